@@ -1,0 +1,408 @@
+/*
+ * ara_oracle.c -- plain, slow, obviously-correct CPU reference for aggregate
+ * risk analysis (Anderson, Rau-Chaplin, Varbanescu et al., "Achieving Speedup
+ * in Aggregate Risk Analysis using Multiple GPUs", arXiv 1308.2572).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library links, loads or
+ * calls this file; only the test-suite, the smoke check and the CPU-baseline
+ * leg of the benchmark do.  It shares no code, header, table or constant with
+ * the HIP implementation.
+ *
+ * Precision: IEEE binary64 throughout after the binary32 ELT loss is read
+ * (the widening is exact).  Build with -ffp-contract=off so that s*l - R is a
+ * separately rounded multiply and subtract.
+ *
+ * Parity pins (checked by tests/test_oracle_*.py, never by this file):
+ *   - hand-worked example derived from Algorithm 1 (tests/golden/)
+ *   - closed forms: zero retentions / infinite limits, one-event trials,
+ *     AggR = 0 with AggL = inf
+ *   - invariants: bounds, monotonicity, permutation invariance, additivity
+ *   - brute force on tiny inputs through an independent formulation
+ *   - Euler's identity for positively homogeneous metrics (backward)
+ *   - central finite differences at certified kink-free points (backward)
+ *
+ * Readings of points the paper leaves open (all stated again in the design
+ * notes):
+ *   R1  ApplyFinancialTerms (Section II, step two) is read as
+ *       g_k(l) = min(max(s_k*l - R_k, 0), L_k): a per-ELT scale (currency
+ *       rate) then a per-ELT retention and limit.
+ *   R2  every "min(max(v - R, 0), L)" is evaluated as
+ *         y = v - R;  a = (y > 0) ? y : 0;  out = (a < L) ? a : L
+ *       and L = +infinity means "no limit".
+ *   R3  an event absent from an ELT has loss 0 (direct-access tables,
+ *       Section III).
+ *   R4  lo and lr start at 0 for every (layer, trial); the differencing step
+ *       uses lo_0 := 0 and runs from the last occurrence down to the first.
+ *   R5  hits(layer, trial) = number of (occurrence, ELT) pairs whose table
+ *       entry is non-zero.
+ *   R6  tail metrics: r = N - floor(p*N + 1e-9) clamped to [1, N];
+ *       PML_p = r-th largest year loss, TVaR_p = mean of the r largest,
+ *       AAL = mean year loss.
+ *   R7  subgradients follow the evaluated branch: d out/d v = [y>0 && a<L],
+ *       d out/d R = -[y>0 && a<L], d out/d L = [a >= L].
+ *   R8  ties at the PML threshold share the weight equally.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+enum { OR_OK = 0, OR_E_INVAL = 1, OR_E_RANGE = 2, OR_E_DUP = 3, OR_E_NOMEM = 4 };
+
+/* min(max(v - R, 0), L) in the evaluation order of reading R2. */
+static double clamp_xl(double v, double R, double L)
+{
+    double y = v - R;
+    double a = (y > 0.0) ? y : 0.0;
+    return (a < L) ? a : L;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Preprocessing stage (Section II; direct-access tables, Section III):      */
+/* one dense binary32 array per ELT over the whole catalogue, 0 = absent.     */
+/* ------------------------------------------------------------------------ */
+int oracle_build_tables(int32_t n_elts, int32_t catalog,
+                        const int64_t *rec_off, const int32_t *rec_ids,
+                        const float *rec_loss, float *tables)
+{
+    if (n_elts < 0 || catalog <= 0) return OR_E_INVAL;
+    unsigned char *seen = (unsigned char *)malloc((size_t)catalog);
+    if (!seen) return OR_E_NOMEM;
+    int rc = OR_OK;
+    for (int32_t k = 0; k < n_elts && rc == OR_OK; ++k) {
+        float *tab = tables + (size_t)k * (size_t)catalog;
+        memset(seen, 0, (size_t)catalog);
+        for (int32_t e = 0; e < catalog; ++e) tab[e] = 0.0f;
+        if (rec_off[k + 1] < rec_off[k]) { rc = OR_E_RANGE; break; }
+        for (int64_t i = rec_off[k]; i < rec_off[k + 1]; ++i) {
+            int32_t id = rec_ids[i];
+            if (id < 0 || id >= catalog) { rc = OR_E_RANGE; break; }
+            if (seen[id]) { rc = OR_E_DUP; break; }
+            seen[id] = 1;
+            tab[id] = rec_loss[i];
+        }
+    }
+    free(seen);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Algorithm 1, literally: layer -> trial -> ELT -> occurrence, four steps.   */
+/* ------------------------------------------------------------------------ */
+/*
+ * tables      [n_elts][catalog]  binary32 losses (0 = absent)
+ * offsets     [n_trials+1]       CSR over ids; trial t is ids[offsets[t]..offsets[t+1])
+ * layer_off   [n_layers+1]       CSR over layer_elts (ELT indices, listed order)
+ * elt_terms   [n_elts][3]        {s_k, R_k, L_k}
+ * layer_terms [n_layers][4]      {OccR, OccL, AggR, AggL}
+ * outputs (each [n_layers][t1-t0], any may be NULL):
+ *   ylt   year loss lr of the literal algorithm
+ *   s_pre S = last prefix sum of occurrence losses (0 for an empty trial)
+ *   hits  reading R5
+ *   ylt_closed  f_agg(S), the telescoped closed form of steps 18-28
+ * n_threads: 1 = strictly sequential; >1 splits trials over OpenMP threads
+ * (each trial is computed by the same sequential code, so results are
+ * bit-identical to the single-thread run).
+ */
+int oracle_forward(int32_t n_elts, int32_t catalog, const float *tables,
+                   int64_t n_trials, const int64_t *offsets, const int32_t *ids,
+                   int32_t n_layers, const int32_t *layer_off, const int32_t *layer_elts,
+                   const double *elt_terms, const double *layer_terms,
+                   int64_t t0, int64_t t1, int32_t n_threads,
+                   double *ylt, double *s_pre, int32_t *hits, double *ylt_closed)
+{
+    if (t0 < 0 || t1 < t0 || t1 > n_trials) return OR_E_INVAL;
+    int64_t nt = t1 - t0;
+    int64_t max_len = 0;
+    for (int64_t t = t0; t < t1; ++t) {
+        int64_t len = offsets[t + 1] - offsets[t];
+        if (len < 0) return OR_E_RANGE;
+        if (len > max_len) max_len = len;
+    }
+    for (int64_t t = t0; t < t1; ++t)
+        for (int64_t i = offsets[t]; i < offsets[t + 1]; ++i)
+            if (ids[i] < 0 || ids[i] >= catalog) return OR_E_RANGE;
+    for (int32_t a = 0; a < n_layers; ++a)
+        for (int32_t c = layer_off[a]; c < layer_off[a + 1]; ++c)
+            if (layer_elts[c] < 0 || layer_elts[c] >= n_elts) return OR_E_RANGE;
+    int rc = OR_OK;
+#ifdef _OPENMP
+    if (n_threads < 1) n_threads = 1;
+#pragma omp parallel num_threads(n_threads)
+#endif
+    {
+        /* per-thread work arrays: x_d (looked-up loss), l_d (net of
+         * financial terms) and lo_d (accumulated occurrence loss) */
+        double *x = (double *)malloc(sizeof(double) * (size_t)(max_len + 1));
+        double *l = (double *)malloc(sizeof(double) * (size_t)(max_len + 1));
+        double *lo = (double *)malloc(sizeof(double) * (size_t)(max_len + 1));
+        if (!x || !l || !lo) {
+#ifdef _OPENMP
+#pragma omp atomic write
+#endif
+            rc = OR_E_NOMEM;
+        } else {
+            for (int32_t a = 0; a < n_layers; ++a) {               /* for all layers */
+                const double OccR = layer_terms[4 * a + 0], OccL = layer_terms[4 * a + 1];
+                const double AggR = layer_terms[4 * a + 2], AggL = layer_terms[4 * a + 3];
+#ifdef _OPENMP
+#pragma omp for schedule(static)
+#endif
+                for (int64_t b = t0; b < t1; ++b) {                 /* for all trials */
+                    const int32_t *ev = ids + offsets[b];
+                    const int64_t n = offsets[b + 1] - offsets[b];
+                    int32_t h = 0;
+                    for (int64_t d = 0; d < n; ++d) lo[d] = 0.0;    /* reading R4 */
+                    for (int32_t c = layer_off[a]; c < layer_off[a + 1]; ++c) {  /* ELTs */
+                        const int32_t k = layer_elts[c];
+                        const float *tab = tables + (size_t)k * (size_t)catalog;
+                        const double s = elt_terms[3 * k + 0];
+                        const double R = elt_terms[3 * k + 1];
+                        const double L = elt_terms[3 * k + 2];
+                        /* step one: look up each occurrence's loss in this ELT */
+                        for (int64_t d = 0; d < n; ++d) {
+                            float v = tab[ev[d]];
+                            x[d] = (double)v;
+                            h += (v != 0.0f);
+                        }
+                        /* step two: financial terms of this ELT (reading R1) */
+                        for (int64_t d = 0; d < n; ++d) {
+                            double scaled = s * x[d];
+                            l[d] = clamp_xl(scaled, R, L);
+                        }
+                        /* accumulate across the layer's ELTs */
+                        for (int64_t d = 0; d < n; ++d) lo[d] = lo[d] + l[d];
+                    }
+                    /* step three: occurrence retention and limit */
+                    for (int64_t d = 0; d < n; ++d) lo[d] = clamp_xl(lo[d], OccR, OccL);
+                    /* cumulative sum over the trial, in occurrence order */
+                    for (int64_t d = 1; d < n; ++d) lo[d] = lo[d] + lo[d - 1];
+                    const double S = (n > 0) ? lo[n - 1] : 0.0;
+                    /* step four: aggregate terms on each running total ... */
+                    for (int64_t d = 0; d < n; ++d) lo[d] = clamp_xl(lo[d], AggR, AggL);
+                    /* ... back to per-occurrence increments (lo_0 := 0, descending) */
+                    for (int64_t d = n - 1; d >= 1; --d) lo[d] = lo[d] - lo[d - 1];
+                    /* ... and summed into the year loss */
+                    double lr = 0.0;
+                    for (int64_t d = 0; d < n; ++d) lr = lr + lo[d];
+                    const size_t o = (size_t)a * (size_t)nt + (size_t)(b - t0);
+                    if (ylt) ylt[o] = lr;
+                    if (s_pre) s_pre[o] = S;
+                    if (hits) hits[o] = h;
+                    if (ylt_closed) ylt_closed[o] = clamp_xl(S, AggR, AggL);
+                }
+            }
+        }
+        free(x); free(l); free(lo);
+    }
+    return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Portfolio risk metrics from the YLT (named in Section I; reading R6).     */
+/* ------------------------------------------------------------------------ */
+int64_t oracle_tail_count(int64_t n, double p)
+{
+    int64_t r = n - (int64_t)floor(p * (double)n + 1e-9);
+    if (r < 1) r = 1;
+    if (r > n) r = n;
+    return r;
+}
+
+static int cmp_desc(const void *a, const void *b)
+{
+    double x = *(const double *)a, y = *(const double *)b;
+    return (x < y) - (x > y);
+}
+
+/* out[3*j + {0,1,2}] = {AAL, PML_p, TVaR_p} for each of n_layers rows of n. */
+int oracle_metrics(const double *ylt, int32_t n_layers, int64_t n, double p, double *out)
+{
+    if (n <= 0 || !(p > 0.0 && p < 1.0)) return OR_E_INVAL;
+    double *v = (double *)malloc(sizeof(double) * (size_t)n);
+    if (!v) return OR_E_NOMEM;
+    const int64_t r = oracle_tail_count(n, p);
+    for (int32_t j = 0; j < n_layers; ++j) {
+        const double *y = ylt + (size_t)j * (size_t)n;
+        double sum = 0.0;
+        for (int64_t t = 0; t < n; ++t) sum += y[t];
+        memcpy(v, y, sizeof(double) * (size_t)n);
+        qsort(v, (size_t)n, sizeof(double), cmp_desc);
+        double top = 0.0;
+        for (int64_t i = 0; i < r; ++i) top += v[i];
+        out[3 * j + 0] = sum / (double)n;
+        out[3 * j + 1] = v[r - 1];
+        out[3 * j + 2] = top / (double)r;
+    }
+    free(v);
+    return OR_OK;
+}
+
+/* dMetric/dY for each metric (reading R8): w[m][j][t], m = AAL, PML, TVaR. */
+int oracle_metric_weights(const double *ylt, int32_t n_layers, int64_t n, double p, double *w)
+{
+    if (n <= 0 || !(p > 0.0 && p < 1.0)) return OR_E_INVAL;
+    double *v = (double *)malloc(sizeof(double) * (size_t)n);
+    if (!v) return OR_E_NOMEM;
+    const int64_t r = oracle_tail_count(n, p);
+    for (int32_t j = 0; j < n_layers; ++j) {
+        const double *y = ylt + (size_t)j * (size_t)n;
+        memcpy(v, y, sizeof(double) * (size_t)n);
+        qsort(v, (size_t)n, sizeof(double), cmp_desc);
+        const double thr = v[r - 1];
+        int64_t n_gt = 0, n_eq = 0;
+        for (int64_t t = 0; t < n; ++t) { n_gt += (y[t] > thr); n_eq += (y[t] == thr); }
+        double *wa = w + ((size_t)0 * n_layers + j) * (size_t)n;
+        double *wp = w + ((size_t)1 * n_layers + j) * (size_t)n;
+        double *wt = w + ((size_t)2 * n_layers + j) * (size_t)n;
+        for (int64_t t = 0; t < n; ++t) {
+            wa[t] = 1.0 / (double)n;
+            wp[t] = (y[t] == thr) ? 1.0 / (double)n_eq : 0.0;
+            if (y[t] > thr) wt[t] = 1.0 / (double)r;
+            else if (y[t] == thr) wt[t] = (double)(r - n_gt) / ((double)r * (double)n_eq);
+            else wt[t] = 0.0;
+        }
+    }
+    free(v);
+    return OR_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Reverse sweep of Algorithm 1 (not in the paper; the adjoint of steps one  */
+/* to four, walked backwards occurrence by occurrence, reading R7).          */
+/* ------------------------------------------------------------------------ */
+/*
+ * cot        [n_cot][n_layers][t1-t0]  cotangent on each year loss
+ * grad_elt   [n_cot][n_elts][3]        d/d{s_k, R_k, L_k}   (overwritten)
+ * grad_layer [n_cot][n_layers][4]      d/d{OccR,OccL,AggR,AggL} (overwritten)
+ * Sequential (single thread), trial order.
+ */
+int oracle_backward(int32_t n_elts, int32_t catalog, const float *tables,
+                    int64_t n_trials, const int64_t *offsets, const int32_t *ids,
+                    int32_t n_layers, const int32_t *layer_off, const int32_t *layer_elts,
+                    const double *elt_terms, const double *layer_terms,
+                    int64_t t0, int64_t t1, int32_t n_cot, const double *cot,
+                    double *grad_elt, double *grad_layer)
+{
+    if (t0 < 0 || t1 < t0 || t1 > n_trials || n_cot < 0) return OR_E_INVAL;
+    const int64_t nt = t1 - t0;
+    int64_t max_len = 0;
+    for (int64_t t = t0; t < t1; ++t) {
+        int64_t len = offsets[t + 1] - offsets[t];
+        if (len < 0) return OR_E_RANGE;
+        if (len > max_len) max_len = len;
+    }
+    for (int64_t t = t0; t < t1; ++t)
+        for (int64_t i = offsets[t]; i < offsets[t + 1]; ++i)
+            if (ids[i] < 0 || ids[i] >= catalog) return OR_E_RANGE;
+    int32_t max_j = 0;
+    for (int32_t a = 0; a < n_layers; ++a) {
+        if (layer_off[a + 1] - layer_off[a] > max_j) max_j = layer_off[a + 1] - layer_off[a];
+        for (int32_t c = layer_off[a]; c < layer_off[a + 1]; ++c)
+            if (layer_elts[c] < 0 || layer_elts[c] >= n_elts) return OR_E_RANGE;
+    }
+    memset(grad_elt, 0, sizeof(double) * (size_t)n_cot * (size_t)n_elts * 3);
+    memset(grad_layer, 0, sizeof(double) * (size_t)n_cot * (size_t)n_layers * 4);
+    const size_t m = (size_t)(max_len + 1);
+    const size_t mj = (size_t)(max_j > 0 ? max_j : 1);
+    double *xk = (double *)malloc(sizeof(double) * m * mj);   /* looked-up losses per ELT */
+    double *pre = (double *)malloc(sizeof(double) * m * mj);  /* s*x - R per ELT          */
+    double *lsum = (double *)malloc(sizeof(double) * m);      /* lo after step two        */
+    double *o = (double *)malloc(sizeof(double) * m);         /* after occurrence terms   */
+    double *c = (double *)malloc(sizeof(double) * m);         /* running totals           */
+    double *f = (double *)malloc(sizeof(double) * m);         /* after aggregate terms    */
+    double *adj_f = (double *)malloc(sizeof(double) * m);
+    double *adj_c = (double *)malloc(sizeof(double) * m);
+    double *adj_o = (double *)malloc(sizeof(double) * m);
+    int rc = OR_OK;
+    if (!xk || !pre || !lsum || !o || !c || !f || !adj_f || !adj_c || !adj_o) { rc = OR_E_NOMEM; goto done; }
+    for (int32_t a = 0; a < n_layers; ++a) {
+        const double OccR = layer_terms[4 * a + 0], OccL = layer_terms[4 * a + 1];
+        const double AggR = layer_terms[4 * a + 2], AggL = layer_terms[4 * a + 3];
+        const int32_t J = layer_off[a + 1] - layer_off[a];
+        for (int64_t b = t0; b < t1; ++b) {
+            const int32_t *ev = ids + offsets[b];
+            const int64_t n = offsets[b + 1] - offsets[b];
+            /* forward, keeping every intermediate */
+            for (int64_t d = 0; d < n; ++d) lsum[d] = 0.0;
+            for (int32_t q = 0; q < J; ++q) {
+                const int32_t k = layer_elts[layer_off[a] + q];
+                const float *tab = tables + (size_t)k * (size_t)catalog;
+                const double s = elt_terms[3 * k + 0], R = elt_terms[3 * k + 1], L = elt_terms[3 * k + 2];
+                for (int64_t d = 0; d < n; ++d) {
+                    double xv = (double)tab[ev[d]];
+                    xk[(size_t)q * m + (size_t)d] = xv;
+                    double sc = s * xv;
+                    pre[(size_t)q * m + (size_t)d] = sc - R;
+                    lsum[d] = lsum[d] + clamp_xl(sc, R, L);
+                }
+            }
+            for (int64_t d = 0; d < n; ++d) o[d] = clamp_xl(lsum[d], OccR, OccL);
+            for (int64_t d = 0; d < n; ++d) c[d] = (d == 0) ? o[0] : c[d - 1] + o[d];
+            for (int64_t d = 0; d < n; ++d) f[d] = clamp_xl(c[d], AggR, AggL);
+            for (int32_t g = 0; g < n_cot; ++g) {
+                const double w = cot[((size_t)g * n_layers + a) * (size_t)nt + (size_t)(b - t0)];
+                double *ge = grad_elt + (size_t)g * (size_t)n_elts * 3;
+                double *gl = grad_layer + ((size_t)g * n_layers + a) * 4;
+                if (w == 0.0 || n == 0) continue;
+                /* lr = sum_d (f_d - f_{d-1}), f_0 := 0: adjoint of the
+                 * summation gives w on every increment; the adjoint of the
+                 * differencing moves w onto f_d and -w onto f_{d-1}. */
+                for (int64_t d = 0; d < n; ++d) adj_f[d] = 0.0;
+                for (int64_t d = 0; d < n; ++d) {
+                    adj_f[d] += w;
+                    if (d >= 1) adj_f[d - 1] -= w;
+                }
+                /* aggregate terms on each running total */
+                for (int64_t d = 0; d < n; ++d) {
+                    double y = c[d] - AggR;
+                    double aa = (y > 0.0) ? y : 0.0;
+                    int lin = (y > 0.0) && (aa < AggL);
+                    adj_c[d] = lin ? adj_f[d] : 0.0;
+                    if (lin) gl[2] -= adj_f[d];
+                    if (aa >= AggL) gl[3] += adj_f[d];
+                }
+                /* running total: o_i feeds every c_d with d >= i */
+                double run = 0.0;
+                for (int64_t d = n - 1; d >= 0; --d) { run += adj_c[d]; adj_o[d] = run; }
+                /* occurrence terms, then financial terms per ELT */
+                for (int64_t d = 0; d < n; ++d) {
+                    double y = lsum[d] - OccR;
+                    double aa = (y > 0.0) ? y : 0.0;
+                    int lin = (y > 0.0) && (aa < OccL);
+                    if (lin) gl[0] -= adj_o[d];
+                    if (aa >= OccL) gl[1] += adj_o[d];
+                    const double adj_l = lin ? adj_o[d] : 0.0;
+                    if (adj_l == 0.0) continue;
+                    for (int32_t q = 0; q < J; ++q) {
+                        const int32_t k = layer_elts[layer_off[a] + q];
+                        const double L = elt_terms[3 * k + 2];
+                        const double pv = pre[(size_t)q * m + (size_t)d];
+                        const double av = (pv > 0.0) ? pv : 0.0;
+                        if ((pv > 0.0) && (av < L)) {
+                            ge[3 * k + 0] += adj_l * xk[(size_t)q * m + (size_t)d];
+                            ge[3 * k + 1] -= adj_l;
+                        }
+                        if (av >= L) ge[3 * k + 2] += adj_l;
+                    }
+                }
+            }
+        }
+    }
+done:
+    free(xk); free(pre); free(lsum); free(o); free(c); free(f);
+    free(adj_f); free(adj_c); free(adj_o);
+    return rc;
+}
+
+int oracle_num_threads_available(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
