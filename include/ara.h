@@ -1,0 +1,234 @@
+/*
+ * ara.h -- C ABI of the MI355X (gfx950) aggregate-risk-analysis library.
+ *
+ * The operation is the aggregate analysis of Anderson, Rau-Chaplin,
+ * Varbanescu et al. (arXiv 1308.2572), Section II and Algorithm 1: for every
+ * layer and every trial of a Year Event Table (YET), look up each event
+ * occurrence's loss in the layer's Event Loss Tables (ELTs), apply each ELT's
+ * financial terms, sum across the layer's ELTs, apply the layer's occurrence
+ * retention and limit, then apply the aggregate retention and limit to the
+ * trial's running total; the result per (layer, trial) is the year loss, the
+ * rows of the Year Loss Table (YLT).  Tail metrics (mean annual loss, PML,
+ * TVaR; named in Section I) and their gradients complete the surface.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Every function returns an int32_t status (ARA_OK on success).  On error
+ *    ara_last_error() gives a thread-local detail string.  No C++ exception
+ *    crosses this boundary.
+ *  - Bulk memory is caller-owned DEVICE memory unless a field says "host".
+ *    The library never allocates device memory: each operation that needs
+ *    scratch space has a *_bytes query, and the caller passes a device buffer
+ *    of at least that size (256-byte aligned).
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).  Work
+ *    is enqueued on it and outputs are valid once the stream has completed,
+ *    except where a function says it synchronises.
+ *  - Event IDs are 0-based int32 in [0, catalog).  Losses are binary32, >= 0
+ *    and finite.  Terms are binary64; retentions are finite and >= 0; limits
+ *    are > 0 or +infinity; scales are finite and > 0.
+ *  - Readings of points the paper leaves open (stated once here):
+ *      financial terms of ELT k:  g_k(l) = min(max(s_k*l - R_k, 0), L_k)
+ *      every min(max(v - R, 0), L) is evaluated as y = v - R;
+ *        a = y > 0 ? y : 0; out = a < L ? a : L   (binary64, no fused ops)
+ *      an event absent from an ELT (or stored with loss 0) loses 0
+ *      hits(layer, trial) = number of (occurrence, ELT) pairs with loss != 0
+ *      tail count r = N - floor(p*N + 1e-9) clamped to [1, N];
+ *        PML_p = r-th largest year loss; TVaR_p = mean of the r largest
+ */
+#ifndef ARA_H
+#define ARA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ARA_ABI_VERSION 1
+
+/* status codes */
+#define ARA_OK        0
+#define ARA_E_INVAL   1   /* null pointer, bad size, bad flag, p outside (0,1), invalid term value */
+#define ARA_E_RANGE   2   /* event ID outside [0, catalog), decreasing offsets, ELT index out of range */
+#define ARA_E_DUP     3   /* the same event twice in one ELT (ELTs are dictionaries, Section III) */
+#define ARA_E_NOSPACE 4   /* caller buffer smaller than the *_bytes query */
+#define ARA_E_HIP     5   /* HIP runtime error */
+#define ARA_E_LIMIT   6   /* size beyond a documented implementation limit */
+
+/* forward flags */
+#define ARA_F_EMIT_HITS   1u  /* also produce per-(layer, trial) hit counts */
+
+/* implementation limits */
+#define ARA_MAX_CATALOG       (1 << 26)   /* events in the catalogue */
+#define ARA_MAX_ELTS_PER_LAYER 128
+#define ARA_MAX_COTANGENTS     4
+
+const char *ara_status_string(int32_t status);
+const char *ara_last_error(void);
+int32_t ara_abi_version(void);
+
+/* ------------------------------------------------------------------------ */
+/* YET: the first input (Section II) -- trials of time-ordered event IDs.    */
+/* ------------------------------------------------------------------------ */
+/*
+ * Preprocessing (the paper's first stage loads the YET into memory; here it
+ * is laid out once for the device).  The prepared YET groups each block of
+ * consecutive trials by catalogue range: for block b, range r (2^range_bits
+ * consecutive event IDs) and trial group g, the occurrences of those trials
+ * whose event lies in range r are stored in trial order, packed as
+ * (trial_in_block << range_bits) | (event_id - r * 2^range_bits), and
+ * distributed over 64 lanes as `seg_run` consecutive entries per lane
+ * (entry s of lane j at seg_base + s*64 + j; unused slots hold 0xFFFFFFFF).
+ * Order of occurrences inside a trial is not kept: the year loss does not
+ * depend on it (the cumulative aggregate steps telescope), but the order of
+ * summation, and so rounding, is fixed by this layout and deterministic.
+ */
+typedef struct ara_yet {
+    int64_t   n_trials;
+    int64_t   nnz;               /* total event occurrences */
+    int32_t   catalog;
+    int32_t   range_bits;        /* 15 */
+    int32_t   n_ranges;          /* ceil(catalog / 2^range_bits) */
+    int32_t   groups;            /* trial groups per block (16, one per wavefront) */
+    int32_t   trials_per_group;
+    int32_t   trials_per_block;  /* groups * trials_per_group, <= 4096 */
+    int32_t   n_blocks;          /* ceil(n_trials / trials_per_block) */
+    int32_t   max_occ;           /* largest number of occurrences of one event */
+    int64_t   n_entries;         /* packed entries including padding */
+    uint32_t *ent;               /* device [n_entries] */
+    int64_t  *seg_base;          /* device [n_blocks][n_ranges][groups] */
+    int32_t  *seg_run;           /* device [n_blocks][n_ranges][groups] */
+} ara_yet;
+
+/* Upper bound of the device buffer ara_yet_prepare needs. */
+int32_t ara_yet_prepare_bytes(int64_t n_trials, int64_t nnz, int32_t catalog, size_t *bytes);
+
+/*
+ * offsets: device int64 [n_trials+1], offsets[0] = 0, non-decreasing; trial t
+ *          holds ids[offsets[t] .. offsets[t+1]).
+ * ids:     device int32 [offsets[n_trials]].
+ * buf:     device buffer of at least ara_yet_prepare_bytes; it holds the
+ *          prepared YET afterwards and must outlive every use of *out.
+ * Validates every ID (ARA_E_RANGE) and every offset.  SYNCHRONISES `stream`
+ * (it sizes the layout from device-side counts); one-time cost.
+ */
+int32_t ara_yet_prepare(const int64_t *offsets, const int32_t *ids, int64_t n_trials,
+                        int32_t catalog, void *buf, size_t buf_bytes, void *stream,
+                        ara_yet *out);
+
+/* ------------------------------------------------------------------------ */
+/* ELTs: the second input (Section II) -- event -> loss dictionaries, held as */
+/* direct-access tables over the whole catalogue (Section III).              */
+/* ------------------------------------------------------------------------ */
+typedef struct ara_tables {
+    int32_t   n_elts;
+    int32_t   catalog;
+    int32_t   words;             /* ceil(catalog / 32) */
+    int32_t   reserved;
+    float    *loss;              /* device [n_elts][catalog]; 0 = absent */
+    uint32_t *present;           /* device [n_elts][words]; bit e%32 of word e/32 set iff loss != 0 */
+} ara_tables;
+
+int32_t ara_build_elt_tables_bytes(int32_t n_elts, int32_t catalog, size_t *bytes);
+
+/*
+ * rec_off:  device int64 [n_elts+1]; ELT k holds records rec_off[k]..rec_off[k+1]
+ * rec_ids:  device int32 event IDs, distinct within one ELT (ARA_E_DUP otherwise)
+ * rec_loss: device binary32 losses (>= 0, finite; ARA_E_INVAL otherwise)
+ * buf:      device buffer of at least ara_build_elt_tables_bytes; holds the
+ *           tables afterwards.  SYNCHRONISES `stream` to report errors.
+ */
+int32_t ara_build_elt_tables(int32_t n_elts, int32_t catalog, const int64_t *rec_off,
+                             const int32_t *rec_ids, const float *rec_loss,
+                             void *buf, size_t buf_bytes, void *stream, ara_tables *out);
+
+/* ------------------------------------------------------------------------ */
+/* Layers: the third input (Section II) -- ELT lists plus layer terms.       */
+/* ------------------------------------------------------------------------ */
+typedef struct ara_layers {
+    int32_t        n_layers;
+    int32_t        reserved;
+    const int32_t *elt_off;      /* HOST [n_layers+1] */
+    const int32_t *elt_ids;      /* HOST [elt_off[n_layers]] ELT indices, listed order */
+} ara_layers;
+
+/* ------------------------------------------------------------------------ */
+/* Forward: Algorithm 1 for trials [trial_begin, trial_end) of every layer.  */
+/* ------------------------------------------------------------------------ */
+int32_t ara_ylt_workspace_bytes(const ara_tables *tables, const ara_yet *yet,
+                                const ara_layers *layers, uint32_t flags, size_t *bytes);
+
+/*
+ * elt_terms:   device binary64 [n_elts][3] = (scale s_k, retention R_k, limit L_k)
+ * layer_terms: device binary64 [n_layers][4] = (OccR, OccL, AggR, AggL)
+ * ylt:         device binary64 [n_layers][n], n = trial_end - trial_begin
+ * s_pre:       device binary64 [n_layers][n] or NULL: the trial's total of
+ *              occurrence losses before aggregate terms (kept for the backward)
+ * hits:        device int32 [n_layers][n] or NULL; requires ARA_F_EMIT_HITS
+ * ws:          device workspace of at least ara_ylt_workspace_bytes
+ * Invalid term values are detected on the device: ara_check_device_error.
+ */
+int32_t ara_ylt_forward(const ara_tables *tables, const ara_yet *yet, const ara_layers *layers,
+                        const double *elt_terms, const double *layer_terms,
+                        int64_t trial_begin, int64_t trial_end, uint32_t flags,
+                        double *ylt, double *s_pre, int32_t *hits,
+                        void *ws, size_t ws_bytes, void *stream);
+
+/* Reads (synchronising `stream`) the error word the device side of the
+ * forward or backward left in `ws`; ARA_OK if none. */
+int32_t ara_check_device_error(const void *ws, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Metrics from the YLT (Section I names PML and TVaR).                      */
+/* ------------------------------------------------------------------------ */
+int32_t ara_metrics_workspace_bytes(int32_t n_layers, int64_t n, size_t *bytes);
+
+/*
+ * ylt:     device binary64 [n_layers][n], every value >= 0
+ * out:     device binary64 [n_layers][3] = (AAL, PML_p, TVaR_p)
+ * weights: device binary64 [3][n_layers][n] = d(AAL, PML, TVaR)/d ylt, or NULL.
+ *          Ties at the PML value share its weight equally; TVaR gives 1/r to
+ *          trials above the PML value and (r - #above)/(r * #tied) to ties.
+ * p in (0, 1).
+ */
+int32_t ara_metrics(const double *ylt, int32_t n_layers, int64_t n, double p,
+                    double *out, double *weights, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * Vector-Jacobian product of the metrics: grad_ylt[j][t] =
+ *   sum_m grad_out[j][m] * weights[m][j][t]   (m = AAL, PML, TVaR)
+ * weights as produced by ara_metrics; grad_out device [n_layers][3];
+ * grad_ylt device [n_layers][n] (overwritten).
+ */
+int32_t ara_metrics_vjp(const double *weights, int32_t n_layers, int64_t n, const double *grad_out,
+                        double *grad_ylt, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Backward: gradients of sum_t grad_ylt[c][j][t] * ylt[j][t] with respect to */
+/* every ELT term and layer term (the reverse sweep of Algorithm 1).        */
+/* ------------------------------------------------------------------------ */
+int32_t ara_ylt_backward_workspace_bytes(const ara_tables *tables, const ara_yet *yet,
+                                         const ara_layers *layers, int32_t n_cot, size_t *bytes);
+
+/*
+ * s_pre:      device [n_layers][n] as produced by ara_ylt_forward for the same
+ *             inputs and trial range
+ * grad_ylt:   device binary64 [n_cot][n_layers][n], n_cot in [1, ARA_MAX_COTANGENTS]
+ * grad_elt:   device binary64 [n_cot][n_elts][3]   (overwritten; ELTs in no layer get 0)
+ * grad_layer: device binary64 [n_cot][n_layers][4] (overwritten)
+ * Subgradients follow the evaluated branch of each min/max: d/dv = [y>0 && a<L],
+ * d/dR = -[y>0 && a<L], d/dL = [a >= L].  Deterministic (fixed-point
+ * accumulation of the per-event weights, fixed-order reductions).
+ */
+int32_t ara_ylt_backward(const ara_tables *tables, const ara_yet *yet, const ara_layers *layers,
+                         const double *elt_terms, const double *layer_terms,
+                         int64_t trial_begin, int64_t trial_end, const double *s_pre,
+                         int32_t n_cot, const double *grad_ylt,
+                         double *grad_elt, double *grad_layer,
+                         void *ws, size_t ws_bytes, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ARA_H */

@@ -1,0 +1,312 @@
+"""Python binding of libara.so, the MI355X aggregate-risk-analysis library.
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels behind the C ABI declared in include/ara.h.  PyTorch supplies device
+memory (caller-owned workspaces) and the current HIP stream.  The binding
+refuses to run without the compiled library; there is no CPU fallback.
+
+Functions named ``ara_*`` are one-to-one wrappers of the C entry points (they
+take raw integers/pointers and raise AraError on a non-zero status); the
+classes and functions below them hold tensors alive and size workspaces.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Tuple
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libara.so")
+
+ARA_OK, ARA_E_INVAL, ARA_E_RANGE, ARA_E_DUP, ARA_E_NOSPACE, ARA_E_HIP, ARA_E_LIMIT = range(7)
+ARA_F_EMIT_HITS = 1
+ARA_MAX_COTANGENTS = 4
+
+_c_i32, _c_i64, _c_u32, _c_f64, _c_p, _c_sz = (ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_double,
+                                               ctypes.c_void_p, ctypes.c_size_t)
+
+
+class AraError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(msg)
+        self.status = status
+
+
+class ara_yet(ctypes.Structure):
+    _fields_ = [("n_trials", _c_i64), ("nnz", _c_i64), ("catalog", _c_i32), ("range_bits", _c_i32),
+                ("n_ranges", _c_i32), ("groups", _c_i32), ("trials_per_group", _c_i32),
+                ("trials_per_block", _c_i32), ("n_blocks", _c_i32), ("max_occ", _c_i32),
+                ("n_entries", _c_i64), ("ent", _c_p), ("seg_base", _c_p), ("seg_run", _c_p)]
+
+
+class ara_tables(ctypes.Structure):
+    _fields_ = [("n_elts", _c_i32), ("catalog", _c_i32), ("words", _c_i32), ("reserved", _c_i32),
+                ("loss", _c_p), ("present", _c_p)]
+
+
+class ara_layers(ctypes.Structure):
+    _fields_ = [("n_layers", _c_i32), ("reserved", _c_i32), ("elt_off", _c_p), ("elt_ids", _c_p)]
+
+
+_P = ctypes.POINTER
+_SIGNATURES = {
+    "ara_status_string": (ctypes.c_char_p, [_c_i32]),
+    "ara_last_error": (ctypes.c_char_p, []),
+    "ara_abi_version": (_c_i32, []),
+    "ara_check_device_error": (_c_i32, [_c_p, _c_p]),
+    "ara_yet_prepare_bytes": (_c_i32, [_c_i64, _c_i64, _c_i32, _P(_c_sz)]),
+    "ara_yet_prepare": (_c_i32, [_c_p, _c_p, _c_i64, _c_i32, _c_p, _c_sz, _c_p, _P(ara_yet)]),
+    "ara_build_elt_tables_bytes": (_c_i32, [_c_i32, _c_i32, _P(_c_sz)]),
+    "ara_build_elt_tables": (_c_i32, [_c_i32, _c_i32, _c_p, _c_p, _c_p, _c_p, _c_sz, _c_p, _P(ara_tables)]),
+    "ara_ylt_workspace_bytes": (_c_i32, [_P(ara_tables), _P(ara_yet), _P(ara_layers), _c_u32, _P(_c_sz)]),
+    "ara_ylt_forward": (_c_i32, [_P(ara_tables), _P(ara_yet), _P(ara_layers), _c_p, _c_p, _c_i64, _c_i64, _c_u32,
+                                 _c_p, _c_p, _c_p, _c_p, _c_sz, _c_p]),
+    "ara_metrics_workspace_bytes": (_c_i32, [_c_i32, _c_i64, _P(_c_sz)]),
+    "ara_metrics": (_c_i32, [_c_p, _c_i32, _c_i64, _c_f64, _c_p, _c_p, _c_p, _c_sz, _c_p]),
+    "ara_metrics_vjp": (_c_i32, [_c_p, _c_i32, _c_i64, _c_p, _c_p, _c_p]),
+    "ara_ylt_backward_workspace_bytes": (_c_i32, [_P(ara_tables), _P(ara_yet), _P(ara_layers), _c_i32, _P(_c_sz)]),
+    "ara_ylt_backward": (_c_i32, [_P(ara_tables), _P(ara_yet), _P(ara_layers), _c_p, _c_p, _c_i64, _c_i64, _c_p,
+                                  _c_i32, _c_p, _c_p, _c_p, _c_p, _c_sz, _c_p]),
+}
+
+_lib = None
+
+
+def library() -> ctypes.CDLL:
+    """Load libara.so; raises if it has not been built (no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1308_2572_amd.build` "
+                              f"(the HIP library is required; there is no CPU path)")
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGNATURES.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def _check(rc: int, what: str) -> None:
+    if rc != ARA_OK:
+        lib = library()
+        raise AraError(rc, f"{what}: {lib.ara_status_string(rc).decode()} ({lib.ara_last_error().decode()})")
+
+
+def _stream() -> int:
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _dptr(t: Optional[torch.Tensor]) -> Optional[int]:
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("device tensor expected")
+    if not t.is_contiguous():
+        raise ValueError("contiguous tensor expected")
+    return t.data_ptr() or None
+
+
+def _workspace(nbytes: int, device) -> torch.Tensor:
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+
+
+# --------------------------------------------------------------------------
+# resident inputs
+# --------------------------------------------------------------------------
+
+class PreparedYet:
+    """A YET laid out on the device by ara_yet_prepare (keeps its buffer alive)."""
+
+    def __init__(self, offsets: torch.Tensor, ids: torch.Tensor, catalog: int):
+        lib = library()
+        if offsets.dtype != torch.int64 or ids.dtype != torch.int32:
+            raise ValueError("offsets must be int64 and ids int32")
+        n_trials = offsets.numel() - 1
+        nnz = ids.numel()
+        nb = _c_sz()
+        _check(lib.ara_yet_prepare_bytes(n_trials, nnz, catalog, ctypes.byref(nb)), "ara_yet_prepare_bytes")
+        self.device = offsets.device
+        self.buf = _workspace(nb.value, self.device)
+        self.handle = ara_yet()
+        _check(lib.ara_yet_prepare(_dptr(offsets), _dptr(ids), n_trials, catalog, _dptr(self.buf), self.buf.numel(),
+                                   _stream(), ctypes.byref(self.handle)), "ara_yet_prepare")
+        self.n_trials = n_trials
+        self.catalog = catalog
+
+    @classmethod
+    def from_numpy(cls, yet, device="cuda"):
+        off = torch.from_numpy(np.ascontiguousarray(yet.offsets, np.int64)).to(device)
+        ids = torch.from_numpy(np.ascontiguousarray(yet.ids, np.int32)).to(device)
+        out = cls(off, ids, int(yet.catalog))
+        return out
+
+
+class EltTables:
+    """Direct-access ELT tables built on the device by ara_build_elt_tables."""
+
+    def __init__(self, rec_off: torch.Tensor, rec_ids: torch.Tensor, rec_loss: torch.Tensor, catalog: int):
+        lib = library()
+        n_elts = rec_off.numel() - 1
+        nb = _c_sz()
+        _check(lib.ara_build_elt_tables_bytes(n_elts, catalog, ctypes.byref(nb)), "ara_build_elt_tables_bytes")
+        self.device = rec_off.device
+        self.buf = _workspace(nb.value, self.device)
+        self.handle = ara_tables()
+        _check(lib.ara_build_elt_tables(n_elts, catalog, _dptr(rec_off), _dptr(rec_ids), _dptr(rec_loss),
+                                        _dptr(self.buf), self.buf.numel(), _stream(), ctypes.byref(self.handle)),
+               "ara_build_elt_tables")
+        self.n_elts = n_elts
+        self.catalog = catalog
+
+    @classmethod
+    def from_numpy(cls, elts, device="cuda"):
+        return cls(torch.from_numpy(np.ascontiguousarray(elts.rec_off, np.int64)).to(device),
+                   torch.from_numpy(np.ascontiguousarray(elts.rec_ids, np.int32)).to(device),
+                   torch.from_numpy(np.ascontiguousarray(elts.rec_loss, np.float32)).to(device),
+                   int(elts.catalog))
+
+
+class Layers:
+    """Host-side layer structure (ELT lists in listed order)."""
+
+    def __init__(self, elt_off, elt_ids):
+        self.elt_off = np.ascontiguousarray(elt_off, dtype=np.int32)
+        self.elt_ids = np.ascontiguousarray(elt_ids, dtype=np.int32)
+        self.handle = ara_layers(int(self.elt_off.shape[0] - 1), 0,
+                                 self.elt_off.ctypes.data_as(_c_p), self.elt_ids.ctypes.data_as(_c_p))
+
+    @property
+    def n_layers(self) -> int:
+        return int(self.elt_off.shape[0] - 1)
+
+
+# --------------------------------------------------------------------------
+# computations
+# --------------------------------------------------------------------------
+
+def ylt_forward(tables: EltTables, yet: PreparedYet, layers: Layers, elt_terms: torch.Tensor,
+                layer_terms: torch.Tensor, trial_begin: int = 0, trial_end: Optional[int] = None,
+                want_s_pre: bool = True, want_hits: bool = False, check: bool = False):
+    """Returns (ylt, s_pre or None, hits or None), each [n_layers, n]."""
+    lib = library()
+    trial_end = yet.n_trials if trial_end is None else trial_end
+    n = trial_end - trial_begin
+    L = layers.n_layers
+    dev = yet.device
+    flags = ARA_F_EMIT_HITS if want_hits else 0
+    nb = _c_sz()
+    _check(lib.ara_ylt_workspace_bytes(ctypes.byref(tables.handle), ctypes.byref(yet.handle),
+                                       ctypes.byref(layers.handle), flags, ctypes.byref(nb)), "ara_ylt_workspace_bytes")
+    ws = _workspace(nb.value, dev)
+    ylt = torch.empty((L, n), dtype=torch.float64, device=dev)
+    s_pre = torch.empty((L, n), dtype=torch.float64, device=dev) if want_s_pre else None
+    hits = torch.empty((L, n), dtype=torch.int32, device=dev) if want_hits else None
+    et = elt_terms.to(device=dev, dtype=torch.float64).contiguous()
+    lt = layer_terms.to(device=dev, dtype=torch.float64).contiguous()
+    _check(lib.ara_ylt_forward(ctypes.byref(tables.handle), ctypes.byref(yet.handle), ctypes.byref(layers.handle),
+                               _dptr(et), _dptr(lt), trial_begin, trial_end, flags, _dptr(ylt), _dptr(s_pre),
+                               _dptr(hits), _dptr(ws), ws.numel(), _stream()), "ara_ylt_forward")
+    if check:
+        _check(lib.ara_check_device_error(_dptr(ws), _stream()), "ara_ylt_forward (device)")
+    return ylt, s_pre, hits
+
+
+def metrics(ylt: torch.Tensor, p: float, want_weights: bool = False):
+    """Returns (out [n_layers, 3] = AAL, PML, TVaR; weights [3, n_layers, n] or None)."""
+    lib = library()
+    ylt = ylt.contiguous()
+    L, n = ylt.shape
+    nb = _c_sz()
+    _check(lib.ara_metrics_workspace_bytes(L, n, ctypes.byref(nb)), "ara_metrics_workspace_bytes")
+    ws = _workspace(nb.value, ylt.device)
+    out = torch.empty((L, 3), dtype=torch.float64, device=ylt.device)
+    w = torch.empty((3, L, n), dtype=torch.float64, device=ylt.device) if want_weights else None
+    _check(lib.ara_metrics(_dptr(ylt), L, n, float(p), _dptr(out), _dptr(w), _dptr(ws), ws.numel(), _stream()),
+           "ara_metrics")
+    return out, w
+
+
+def metrics_vjp(weights: torch.Tensor, grad_out: torch.Tensor) -> torch.Tensor:
+    lib = library()
+    _, L, n = weights.shape
+    g = grad_out.to(dtype=torch.float64).contiguous()
+    out = torch.empty((L, n), dtype=torch.float64, device=weights.device)
+    _check(lib.ara_metrics_vjp(_dptr(weights), L, n, _dptr(g), _dptr(out), _stream()), "ara_metrics_vjp")
+    return out
+
+
+def ylt_backward(tables: EltTables, yet: PreparedYet, layers: Layers, elt_terms: torch.Tensor,
+                 layer_terms: torch.Tensor, s_pre: torch.Tensor, grad_ylt: torch.Tensor, trial_begin: int = 0,
+                 trial_end: Optional[int] = None) -> Tuple[torch.Tensor, torch.Tensor]:
+    """grad_ylt: [n_cot, n_layers, n] (or [n_layers, n]).  Returns
+    (grad_elt [n_cot, n_elts, 3], grad_layer [n_cot, n_layers, 4])."""
+    lib = library()
+    trial_end = yet.n_trials if trial_end is None else trial_end
+    squeeze = grad_ylt.dim() == 2
+    g = (grad_ylt[None] if squeeze else grad_ylt).to(dtype=torch.float64).contiguous()
+    n_cot = g.shape[0]
+    dev = yet.device
+    nb = _c_sz()
+    _check(lib.ara_ylt_backward_workspace_bytes(ctypes.byref(tables.handle), ctypes.byref(yet.handle),
+                                                ctypes.byref(layers.handle), n_cot, ctypes.byref(nb)),
+           "ara_ylt_backward_workspace_bytes")
+    ws = _workspace(nb.value, dev)
+    ge = torch.empty((n_cot, tables.n_elts, 3), dtype=torch.float64, device=dev)
+    gl = torch.empty((n_cot, layers.n_layers, 4), dtype=torch.float64, device=dev)
+    et = elt_terms.to(device=dev, dtype=torch.float64).contiguous()
+    lt = layer_terms.to(device=dev, dtype=torch.float64).contiguous()
+    _check(lib.ara_ylt_backward(ctypes.byref(tables.handle), ctypes.byref(yet.handle), ctypes.byref(layers.handle),
+                                _dptr(et), _dptr(lt), trial_begin, trial_end, _dptr(s_pre.contiguous()), n_cot,
+                                _dptr(g), _dptr(ge), _dptr(gl), _dptr(ws), ws.numel(), _stream()), "ara_ylt_backward")
+    if squeeze:
+        return ge[0], gl[0]
+    return ge, gl
+
+
+# --------------------------------------------------------------------------
+# autograd
+# --------------------------------------------------------------------------
+
+class YLT(torch.autograd.Function):
+    """ylt = YLT.apply(elt_terms, layer_terms, engine) with engine = (tables, yet, layers, t0, t1)."""
+
+    @staticmethod
+    def forward(ctx, elt_terms, layer_terms, engine):
+        tables, yet, layers, t0, t1 = engine
+        ylt, s_pre, _ = ylt_forward(tables, yet, layers, elt_terms, layer_terms, t0, t1, want_s_pre=True)
+        ctx.engine = engine
+        ctx.save_for_backward(elt_terms, layer_terms, s_pre)
+        return ylt
+
+    @staticmethod
+    def backward(ctx, grad_ylt):
+        elt_terms, layer_terms, s_pre = ctx.saved_tensors
+        tables, yet, layers, t0, t1 = ctx.engine
+        ge, gl = ylt_backward(tables, yet, layers, elt_terms, layer_terms, s_pre, grad_ylt, t0, t1)
+        return ge.to(elt_terms.dtype), gl.to(layer_terms.dtype), None
+
+
+class Metrics(torch.autograd.Function):
+    """out = Metrics.apply(ylt, p): [n_layers, 3] = (AAL, PML_p, TVaR_p)."""
+
+    @staticmethod
+    def forward(ctx, ylt, p):
+        out, w = metrics(ylt, p, want_weights=True)
+        ctx.save_for_backward(w)
+        return out
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        (w,) = ctx.saved_tensors
+        return metrics_vjp(w, grad_out), None
+
+
+__all__ = [
+    "AraError", "PreparedYet", "EltTables", "Layers", "ylt_forward", "metrics", "metrics_vjp", "ylt_backward",
+    "YLT", "Metrics", "library", "ara_yet", "ara_tables", "ara_layers", "ARA_F_EMIT_HITS",
+]

@@ -1,0 +1,67 @@
+// Internal declarations shared by the translation units of libara.so.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+#include <string>
+
+#include "ara.h"
+
+namespace ara {
+
+// Layout constants of the prepared YET and the occurrence tables.
+constexpr int kRangeBits = 15;                 // catalogue range of one packed entry
+constexpr int kRange = 1 << kRangeBits;
+constexpr int kGroups = 16;                    // trial groups per block = wavefronts per workgroup
+constexpr int kMaxTrialsPerGroup = 256;
+constexpr int kMaxTrialsPerBlock = kGroups * kMaxTrialsPerGroup;   // 4096
+constexpr int kSrBits = 16;                    // one occurrence-table "super-range" = 2 ranges
+constexpr int kSr = 1 << kSrBits;
+constexpr int kSrWords = kSr / 32;             // 2048 bitmap words per super-range
+constexpr uint32_t kSentinel = 0xFFFFFFFFu;
+constexpr int kWave = 64;
+
+// Error word kept at the head of every workspace.
+struct WsHeader {
+    int32_t error;          // first device-side error (ARA_E_*), 0 if none
+    int32_t pad[63];
+};
+constexpr size_t kWsHeaderBytes = 256;
+
+void set_error(const std::string &msg);
+int32_t fail(int32_t status, const std::string &msg);
+int32_t hip_fail(hipError_t e, const char *what);
+
+__host__ __device__ inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+#define ARA_HIP(call)                                              \
+    do {                                                           \
+        hipError_t _e = (call);                                    \
+        if (_e != hipSuccess) return ::ara::hip_fail(_e, #call);   \
+    } while (0)
+
+// Carve a caller buffer into 256-byte aligned pieces.
+struct Carver {
+    char *base;
+    size_t used = 0;
+    explicit Carver(void *b) : base(static_cast<char *>(b)) {}
+    template <class T>
+    T *take(size_t count) {
+        T *p = reinterpret_cast<T *>(base + used);
+        used = align256(used + count * sizeof(T));
+        return p;
+    }
+    size_t bytes() const { return used; }
+};
+
+int device_cu_count();
+
+// Forward/backward occurrence-table workspace layout for one call.
+struct OccLayout {
+    int n_sr;               // super-ranges
+    size_t br_bytes, vals_bytes, cnt_bytes;
+};
+
+}  // namespace ara

@@ -1,0 +1,268 @@
+// Forward: stream the prepared YET, gather each occurrence's O(e) from the
+// occurrence table held in LDS, accumulate per trial, apply the aggregate
+// terms (Algorithm 1, steps three and four).
+//
+// One workgroup per block of trials; wavefront g owns trial group g of the
+// block.  The per-trial totals live in LDS for the whole pass over the
+// catalogue (one super-range table at a time), so each trial's total is
+// accumulated by a single wavefront in a fixed order: deterministic.
+#include "occ.h"
+
+#include <algorithm>
+#include <string>
+
+namespace ara {
+
+constexpr int kUnroll = 16;
+constexpr int kLdsBytes = 160 * 1024;
+
+struct FwdParams {
+    const uint32_t *ent;
+    const int64_t *seg_base;
+    const int32_t *seg_run;
+    int64_t n_trials;
+    int32_t tg, tb, n_ranges, n_sr;
+    int32_t b_lo;
+    int64_t t0, t1;
+    int32_t n_layers;
+    int32_t cap;               // values held in LDS per super-range
+    const OccTables *tabs;     // [n_layers]
+    const double *layer_terms; // [n_layers][4]
+    double *ylt;
+    double *s_pre;
+    int32_t *hits;
+};
+
+__device__ __forceinline__ uint32_t ld_stream(const uint32_t *p) { return __builtin_nontemporal_load(p); }
+
+template <bool HITS>
+__global__ __launch_bounds__(1024) void k_fwd(FwdParams P) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int tb = P.tb;
+    double *acc = reinterpret_cast<double *>(smem);
+    int32_t *hacc = reinterpret_cast<int32_t *>(smem + static_cast<size_t>(tb) * 8);
+    const size_t tbr_off = align256(static_cast<size_t>(tb) * 8 + (HITS ? static_cast<size_t>(tb) * 4 : 0));
+    uint2 *tbr = reinterpret_cast<uint2 *>(smem + tbr_off);
+    double *tvals = reinterpret_cast<double *>(smem + tbr_off + kSrWords * sizeof(uint2));
+    uint8_t *tcnt = reinterpret_cast<uint8_t *>(tvals + P.cap);
+
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int64_t b = static_cast<int64_t>(P.b_lo) + blockIdx.x;
+    const int64_t gt0 = b * tb + static_cast<int64_t>(w) * P.tg;
+    const int64_t gt1 = min(gt0 + P.tg, P.n_trials);
+    const bool active = gt0 < gt1 && gt1 > P.t0 && gt0 < P.t1;
+    const int G = P.n_ranges;
+    const size_t seg0 = static_cast<size_t>(b) * G * kGroups + w;
+    const int64_t n_out = P.t1 - P.t0;
+
+    for (int j = 0; j < P.n_layers; ++j) {
+        __syncthreads();   // the previous layer's totals have been written out
+        for (int i = tid; i < tb; i += blockDim.x) {
+            acc[i] = 0.0;
+            if (HITS) hacc[i] = 0;
+        }
+        const OccTables T = P.tabs[j];
+
+        // stream cursor over this wave's segments (range rr, step within it)
+        int rr = active ? 0 : G, step = 0, R = 0;
+        int64_t sb = 0;
+        auto seek = [&]() {
+            while (rr < G) {
+                const size_t si = seg0 + static_cast<size_t>(rr) * kGroups;
+                R = P.seg_run[si];
+                sb = P.seg_base[si];
+                if (R > 0) break;
+                ++rr;
+            }
+        };
+        uint32_t X[kUnroll];
+        int chunk_rr = G;
+        auto load = [&]() {
+            chunk_rr = rr;
+            if (rr < G) {
+#pragma unroll
+                for (int u = 0; u < kUnroll; ++u)
+                    X[u] = (step + u < R) ? ld_stream(P.ent + sb + static_cast<int64_t>(step + u) * kWave + lane)
+                                          : kSentinel;
+                step += kUnroll;
+                if (step >= R) {
+                    ++rr;
+                    step = 0;
+                    seek();
+                }
+            }
+        };
+        seek();
+        load();
+
+        for (int s = 0; s < P.n_sr; ++s) {
+            __syncthreads();
+            const int cnt_s = T.count[s];
+            const int inl = min(cnt_s, P.cap);
+            const uint2 *gbr = T.br + static_cast<size_t>(s) * kSrWords;
+            const double *gvals = T.vals + static_cast<size_t>(s) * kSr;
+            const uint8_t *gcnt = HITS ? T.cnt + static_cast<size_t>(s) * kSr : nullptr;
+            for (int i = tid; i < kSrWords; i += blockDim.x) tbr[i] = gbr[i];
+            for (int i = tid; i < inl; i += blockDim.x) tvals[i] = gvals[i];
+            if (HITS)
+                for (int i = tid; i < inl; i += blockDim.x) tcnt[i] = gcnt[i];
+            __syncthreads();
+            const int rr_end = min(2 * s + 2, G);
+            while (chunk_rr < rr_end) {
+                uint32_t Y[kUnroll];
+#pragma unroll
+                for (int u = 0; u < kUnroll; ++u) Y[u] = X[u];
+                const uint32_t hb = static_cast<uint32_t>(chunk_rr & 1) << kRangeBits;
+                load();   // prefetch the next chunk (possibly of the next super-range)
+#pragma unroll
+                for (int u = 0; u < kUnroll; ++u) {
+                    const uint32_t e = Y[u];
+                    if (e != kSentinel) {
+                        const uint32_t tl = e >> kRangeBits;
+                        const uint32_t loc = hb | (e & (kRange - 1));
+                        const uint2 q = tbr[loc >> 5];
+                        const uint32_t bit = loc & 31;
+                        if ((q.x >> bit) & 1u) {
+                            const uint32_t rank = q.y + __popc(q.x & ((1u << bit) - 1u));
+                            const double v = (rank < static_cast<uint32_t>(P.cap)) ? tvals[rank] : gvals[rank];
+                            atomicAdd(&acc[tl], v);
+                            if (HITS) {
+                                const int c = (rank < static_cast<uint32_t>(P.cap)) ? tcnt[rank] : gcnt[rank];
+                                atomicAdd(&hacc[tl], c);
+                            }
+                        }
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        if (active) {
+            const double aggR = P.layer_terms[4 * j + 2], aggL = P.layer_terms[4 * j + 3];
+            const int64_t lo = max(gt0, P.t0), hi = min(gt1, P.t1);
+            for (int64_t t = lo + lane; t < hi; t += kWave) {
+                const int i = static_cast<int>(t - b * tb);
+                const double S = acc[i];
+                const size_t o = static_cast<size_t>(j) * n_out + static_cast<size_t>(t - P.t0);
+                P.ylt[o] = xl(S, aggR, aggL);
+                if (P.s_pre) P.s_pre[o] = S;
+                if (HITS && P.hits) P.hits[o] = hacc[i];
+            }
+        }
+    }
+}
+
+static size_t fwd_workspace(const ara_tables *tables, const ara_layers *layers, bool hits) {
+    const OccLayoutSizes z = occ_sizes(tables->catalog, hits);
+    const int L = layers->n_layers;
+    const int nJ = L > 0 ? layers->elt_off[L] : 0;
+    size_t b = kWsHeaderBytes;
+    b += align256(static_cast<size_t>(L + 1) * sizeof(int32_t));
+    b += align256(static_cast<size_t>(std::max(nJ, 1)) * sizeof(int32_t));
+    b += align256(static_cast<size_t>(std::max(L, 1)) * sizeof(OccTables));
+    b += static_cast<size_t>(L) * z.per_layer;
+    return b;
+}
+
+static int32_t check_pair(const ara_tables *tables, const ara_yet *yet) {
+    if (!tables || !yet) return fail(ARA_E_INVAL, "null tables or yet");
+    if (tables->catalog != yet->catalog) return fail(ARA_E_INVAL, "tables and YET use different catalogues");
+    if (yet->range_bits != kRangeBits || yet->groups != kGroups) return fail(ARA_E_INVAL, "YET not prepared by this library");
+    return ARA_OK;
+}
+
+}  // namespace ara
+
+using namespace ara;
+
+extern "C" int32_t ara_ylt_workspace_bytes(const ara_tables *tables, const ara_yet *yet, const ara_layers *layers,
+                                           uint32_t flags, size_t *bytes) {
+    if (!bytes) return fail(ARA_E_INVAL, "null output");
+    int32_t rc = check_pair(tables, yet);
+    if (rc) return rc;
+    if ((rc = check_layers(layers, tables->n_elts))) return rc;
+    if (flags & ~ARA_F_EMIT_HITS) return fail(ARA_E_INVAL, "unknown flag");
+    *bytes = fwd_workspace(tables, layers, (flags & ARA_F_EMIT_HITS) != 0);
+    return ARA_OK;
+}
+
+extern "C" int32_t ara_ylt_forward(const ara_tables *tables, const ara_yet *yet, const ara_layers *layers,
+                                   const double *elt_terms, const double *layer_terms, int64_t trial_begin,
+                                   int64_t trial_end, uint32_t flags, double *ylt, double *s_pre, int32_t *hits,
+                                   void *ws, size_t ws_bytes, void *stream) {
+    int32_t rc = check_pair(tables, yet);
+    if (rc) return rc;
+    if ((rc = check_layers(layers, tables->n_elts))) return rc;
+    if (flags & ~ARA_F_EMIT_HITS) return fail(ARA_E_INVAL, "unknown flag");
+    const bool want_hits = (flags & ARA_F_EMIT_HITS) != 0;
+    if (hits && !want_hits) return fail(ARA_E_INVAL, "hits output requires ARA_F_EMIT_HITS");
+    if (trial_begin < 0 || trial_end < trial_begin || trial_end > yet->n_trials)
+        return fail(ARA_E_RANGE, "trial range outside the YET");
+    if (!ws) return fail(ARA_E_INVAL, "null workspace");
+    const int L = layers->n_layers;
+    const int64_t n = trial_end - trial_begin;
+    if (L > 0 && n > 0 && (!ylt || !elt_terms || !layer_terms)) return fail(ARA_E_INVAL, "null output or terms");
+    if (ws_bytes < fwd_workspace(tables, layers, want_hits)) return fail(ARA_E_NOSPACE, "forward workspace too small");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    ARA_HIP(hipMemsetAsync(ws, 0, kWsHeaderBytes, st));
+    if (L == 0 || n == 0) return ARA_OK;
+
+    const OccLayoutSizes z = occ_sizes(tables->catalog, want_hits);
+    const int nJ = layers->elt_off[L];
+    Carver c(ws);
+    int32_t *d_err = c.take<int32_t>(kWsHeaderBytes / sizeof(int32_t));
+    int32_t *d_off = c.take<int32_t>(static_cast<size_t>(L + 1));
+    int32_t *d_ids = c.take<int32_t>(static_cast<size_t>(std::max(nJ, 1)));
+    OccTables *d_tabs = c.take<OccTables>(static_cast<size_t>(L));
+    std::vector<OccTables> tabs(static_cast<size_t>(L));
+    for (int j = 0; j < L; ++j) tabs[j] = occ_carve(c, z, want_hits);
+    ARA_HIP(hipMemcpyAsync(d_off, layers->elt_off, (L + 1) * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    if (nJ > 0) ARA_HIP(hipMemcpyAsync(d_ids, layers->elt_ids, nJ * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    ARA_HIP(hipMemcpyAsync(d_tabs, tabs.data(), L * sizeof(OccTables), hipMemcpyHostToDevice, st));
+
+    if ((rc = launch_occ(tables, d_off, d_ids, elt_terms, layer_terms, L, want_hits, d_tabs, z.n_sr, d_err, st)))
+        return rc;
+
+    FwdParams P{};
+    P.ent = yet->ent;
+    P.seg_base = yet->seg_base;
+    P.seg_run = yet->seg_run;
+    P.n_trials = yet->n_trials;
+    P.tg = yet->trials_per_group;
+    P.tb = yet->trials_per_block;
+    P.n_ranges = yet->n_ranges;
+    P.n_sr = z.n_sr;
+    P.b_lo = static_cast<int32_t>(trial_begin / yet->trials_per_block);
+    const int64_t b_hi = (trial_end + yet->trials_per_block - 1) / yet->trials_per_block;
+    P.t0 = trial_begin;
+    P.t1 = trial_end;
+    P.n_layers = L;
+    const size_t fixed = align256(static_cast<size_t>(P.tb) * 8 + (want_hits ? static_cast<size_t>(P.tb) * 4 : 0)) +
+                         kSrWords * sizeof(uint2);
+    P.cap = static_cast<int32_t>((kLdsBytes - fixed) / (want_hits ? 9 : 8));
+    P.tabs = d_tabs;
+    P.layer_terms = layer_terms;
+    P.ylt = ylt;
+    P.s_pre = s_pre;
+    P.hits = hits;
+    const unsigned grid = static_cast<unsigned>(b_hi - P.b_lo);
+    if (want_hits) {
+        static bool attr = false;
+        if (!attr) {
+            ARA_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_fwd<true>),
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes));
+            attr = true;
+        }
+        k_fwd<true><<<grid, 1024, kLdsBytes, st>>>(P);
+    } else {
+        static bool attr = false;
+        if (!attr) {
+            ARA_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_fwd<false>),
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes));
+            attr = true;
+        }
+        k_fwd<false><<<grid, 1024, kLdsBytes, st>>>(P);
+    }
+    ARA_HIP(hipGetLastError());
+    return ARA_OK;
+}

@@ -1,0 +1,73 @@
+// Occurrence tables shared by the forward and the backward.
+//
+// Steps one to three of Algorithm 1 (look up each ELT's loss, apply that
+// ELT's financial terms, sum over the layer's ELTs in listed order, apply the
+// occurrence retention and limit) depend only on the event, not on the trial.
+// They are therefore evaluated once per catalogue event and per call, and the
+// result O(e) is stored compactly per "super-range" of 65,536 events:
+//   br[s][w]   = {bits of word w (events 32w..32w+31 of super-range s),
+//                 number of set bits in words 0..w-1}
+//   vals[s][i] = O of the i-th set event of super-range s (binary64)
+//   cnt[s][i]  = number of the layer's ELTs holding that event (hits mode)
+// The set events are those with O != 0 ("hot"), or, when hit counts are
+// requested, every event present in at least one of the layer's ELTs.
+#pragma once
+
+#include "ara_internal.h"
+
+namespace ara {
+
+constexpr int kMaxJ = ARA_MAX_ELTS_PER_LAYER;
+
+struct OccTables {
+    uint2 *br;          // [n_sr][kSrWords]
+    double *vals;       // [n_sr][kSr]
+    uint8_t *cnt;       // [n_sr][kSr] or null
+    int32_t *count;     // [n_sr]
+};
+
+// min(max(v - R, 0), L), evaluated exactly as the oracle does: a separately
+// rounded subtraction and two selects (no fused operations; the build uses
+// -ffp-contract=off).
+__device__ __forceinline__ double xl(double v, double r, double lim) {
+    const double y = v - r;
+    const double a = (y > 0.0) ? y : 0.0;
+    return (a < lim) ? a : lim;
+}
+
+struct OccLayoutSizes {
+    int n_sr;
+    size_t per_layer;
+    size_t br, vals, cnt, count;
+};
+
+inline OccLayoutSizes occ_sizes(int32_t catalog, bool with_cnt) {
+    OccLayoutSizes z{};
+    z.n_sr = (catalog + kSr - 1) / kSr;
+    z.br = align256(static_cast<size_t>(z.n_sr) * kSrWords * sizeof(uint2));
+    z.vals = align256(static_cast<size_t>(z.n_sr) * kSr * sizeof(double));
+    z.cnt = with_cnt ? align256(static_cast<size_t>(z.n_sr) * kSr) : 0;
+    z.count = align256(static_cast<size_t>(z.n_sr) * sizeof(int32_t));
+    z.per_layer = z.br + z.vals + z.cnt + z.count;
+    return z;
+}
+
+inline OccTables occ_carve(Carver &c, const OccLayoutSizes &z, bool with_cnt) {
+    OccTables t{};
+    t.br = c.take<uint2>(static_cast<size_t>(z.n_sr) * kSrWords);
+    t.vals = c.take<double>(static_cast<size_t>(z.n_sr) * kSr);
+    t.cnt = with_cnt ? c.take<uint8_t>(static_cast<size_t>(z.n_sr) * kSr) : nullptr;
+    t.count = c.take<int32_t>(static_cast<size_t>(z.n_sr));
+    return t;
+}
+
+// Validates the layer list on the host; returns ARA_OK or an error.
+int32_t check_layers(const ara_layers *layers, int32_t n_elts);
+
+// Enqueue the occurrence-table kernel for every layer.  `tabs` has one entry
+// per layer; the layer CSR must already be on the device.
+int32_t launch_occ(const ara_tables *tables, const int32_t *d_elt_off, const int32_t *d_elt_ids,
+                   const double *elt_terms, const double *layer_terms, int32_t n_layers, bool union_mode,
+                   OccTables *d_tabs, int n_sr, int32_t *d_err, hipStream_t st);
+
+}  // namespace ara

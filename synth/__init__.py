@@ -16,7 +16,9 @@ not depend on how many trials were generated in total.
 """
 from __future__ import annotations
 
-from dataclasses import dataclass, field
+import os
+from concurrent.futures import ThreadPoolExecutor
+from dataclasses import dataclass
 from typing import List, Optional, Sequence
 
 import numpy as np
@@ -100,11 +102,36 @@ class Request:
 # building blocks
 # --------------------------------------------------------------------------
 
+TRIAL_CHUNK = 16384   # trials per independently keyed ID stream
+
+
+def _uniform_ids(seed: int, offsets: np.ndarray, catalog: int) -> np.ndarray:
+    """i.i.d. uniform IDs; chunk c of TRIAL_CHUNK trials draws from its own
+    Philox key, so chunks are generated in parallel and any prefix of trials
+    is identical whatever the total."""
+    n_trials = offsets.shape[0] - 1
+    ids = np.empty(int(offsets[-1]), dtype=np.int32)
+    chunks = range((n_trials + TRIAL_CHUNK - 1) // TRIAL_CHUNK)
+
+    def fill(c):
+        a = int(offsets[c * TRIAL_CHUNK])
+        b = int(offsets[min((c + 1) * TRIAL_CHUNK, n_trials)])
+        ids[a:b] = _rng(seed, _S_IDS, c).integers(0, catalog, size=b - a, dtype=np.int32)
+
+    if len(chunks) <= 1:
+        for c in chunks:
+            fill(c)
+    else:
+        with ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+            list(ex.map(fill, chunks))
+    return ids
+
+
 def fixed_length_yet(seed: int, n_trials: int, n_events: int, catalog: int,
                      with_ts: bool = False) -> Yet:
     """n_trials trials of exactly n_events i.i.d. uniform event IDs."""
     offsets = np.arange(n_trials + 1, dtype=np.int64) * n_events
-    ids = _rng(seed, _S_IDS).integers(0, catalog, size=n_trials * n_events, dtype=np.int32)
+    ids = _uniform_ids(seed, offsets, catalog)
     ts = _timestamps(seed, offsets) if with_ts else None
     return Yet(catalog, offsets, ids, ts)
 
@@ -115,7 +142,7 @@ def poisson_yet(seed: int, n_trials: int, mean_events: float, catalog: int,
     lens = _rng(seed, _S_LEN).poisson(mean_events, size=n_trials).astype(np.int64)
     offsets = np.zeros(n_trials + 1, dtype=np.int64)
     np.cumsum(lens, out=offsets[1:])
-    ids = _rng(seed, _S_IDS).integers(0, catalog, size=int(offsets[-1]), dtype=np.int32)
+    ids = _uniform_ids(seed, offsets, catalog)
     ts = _timestamps(seed, offsets) if with_ts else None
     return Yet(catalog, offsets, ids, ts)
 

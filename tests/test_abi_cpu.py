@@ -1,0 +1,106 @@
+"""Host-side checks of the C ABI: the library loads, exports every function
+include/ara.h declares, and rejects bad arguments before any device work.
+No compute call reaches a GPU here."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ara.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ara_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def ara():
+    import paper_1308_2572_amd as ara
+    ara.library()
+    return ara
+
+
+def test_every_declared_symbol_is_exported(ara):
+    lib = ara.library()
+    names = declared_functions()
+    assert len(names) >= 14
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, f"not exported: {missing}"
+    # and the binding wraps each of them with a signature
+    from paper_1308_2572_amd import _SIGNATURES
+    assert sorted(_SIGNATURES) == names
+
+
+def test_status_strings(ara):
+    lib = ara.library()
+    assert lib.ara_status_string(0) == b"ok"
+    assert b"duplicate" in lib.ara_status_string(3)
+    assert lib.ara_status_string(99) == b"unknown status"
+    assert lib.ara_abi_version() == 1
+
+
+def test_size_queries(ara):
+    lib = ara.library()
+    nb = ctypes.c_size_t()
+    assert lib.ara_yet_prepare_bytes(1000, 1_000_000, 200_000, ctypes.byref(nb)) == 0
+    assert nb.value >= 4 * 1_000_000
+    assert lib.ara_build_elt_tables_bytes(15, 2_000_000, ctypes.byref(nb)) == 0
+    assert nb.value >= 15 * 2_000_000 * 4
+    assert lib.ara_metrics_workspace_bytes(2, 1000, ctypes.byref(nb)) == 0
+    assert nb.value >= 2 * 1000 * 8
+    assert lib.ara_yet_prepare_bytes(10, 10, 1 << 27, ctypes.byref(nb)) == 6       # beyond the catalogue limit
+    assert lib.ara_yet_prepare_bytes(-1, 10, 100, ctypes.byref(nb)) == 1
+
+
+def test_argument_validation_before_device_work(ara):
+    lib = ara.library()
+    # p outside (0, 1)
+    assert lib.ara_metrics(None, 1, 10, 1.5, None, None, None, 0, None) == 1
+    assert b"p must" in lib.ara_last_error()
+    # layer referring to an ELT that does not exist
+    tables = ara.ara_tables(n_elts=2, catalog=100, words=4)
+    yet = ara.ara_yet(n_trials=10, catalog=100, range_bits=15, groups=16)
+    lay = ara.Layers([0, 2], [0, 5])
+    nb = ctypes.c_size_t()
+    assert lib.ara_ylt_workspace_bytes(ctypes.byref(tables), ctypes.byref(yet), ctypes.byref(lay.handle), 0,
+                                       ctypes.byref(nb)) == 2
+    # too many ELTs in one layer
+    lay = ara.Layers([0, 130], np.zeros(130, np.int32))
+    assert lib.ara_ylt_workspace_bytes(ctypes.byref(tables), ctypes.byref(yet), ctypes.byref(lay.handle), 0,
+                                       ctypes.byref(nb)) == 6
+    # mismatched catalogues
+    yet2 = ara.ara_yet(n_trials=10, catalog=101, range_bits=15, groups=16)
+    lay = ara.Layers([0, 1], [0])
+    assert lib.ara_ylt_workspace_bytes(ctypes.byref(tables), ctypes.byref(yet2), ctypes.byref(lay.handle), 0,
+                                       ctypes.byref(nb)) == 1
+    # unknown flag, and hits without the flag
+    assert lib.ara_ylt_workspace_bytes(ctypes.byref(tables), ctypes.byref(yet), ctypes.byref(lay.handle), 8,
+                                       ctypes.byref(nb)) == 1
+    assert lib.ara_ylt_forward(ctypes.byref(tables), ctypes.byref(yet), ctypes.byref(lay.handle), None, None, 0, 5,
+                               0, None, None, ctypes.c_void_p(16), None, 0, None) == 1
+    # trial range outside the YET
+    assert lib.ara_ylt_forward(ctypes.byref(tables), ctypes.byref(yet), ctypes.byref(lay.handle), None, None, 0, 11,
+                               0, None, None, None, None, 0, None) == 2
+
+
+def test_product_refuses_to_run_without_library(tmp_path, monkeypatch):
+    import paper_1308_2572_amd as ara
+    monkeypatch.setattr(ara, "LIB_PATH", str(tmp_path / "missing.so"))
+    monkeypatch.setattr(ara, "_lib", None)
+    with pytest.raises(ImportError):
+        ara.library()
+
+
+def test_product_does_not_import_oracle():
+    src_dir = os.path.join(ROOT, "paper_1308_2572_amd")
+    for dirpath, _, files in os.walk(src_dir):
+        for f in files:
+            if f.endswith((".py", ".hip", ".h", ".cpp")):
+                text = open(os.path.join(dirpath, f)).read()
+                assert "import oracle" not in text and "from oracle" not in text, f
+                assert "ara_oracle" not in text, f

@@ -1,0 +1,261 @@
+"""Parity of the HIP forward (prepare, tables, occurrence table, stream) and
+of the metrics kernels against the CPU oracle, through the C ABI.
+
+Tolerances (the method reaches an exact result; only the order of the
+per-trial summation differs between the two sides):
+  hits            bit-exact
+  year loss Y     |Y_gpu - Y_ref| <= 1e-9 * max(Y_ref, S_ref)   (S = total
+                  before aggregate terms; near the aggregate retention a
+                  plain relative error is ill-conditioned)
+  S               1e-9 relative
+  AAL, PML, TVaR  1e-9 relative (PML exact when computed from the same YLT)
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from _indep import load_hand_example
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-9
+
+
+def _say(msg):
+    print(f"[gpu-forward] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ara():
+    import torch
+    assert torch.cuda.is_available(), "GPU test needs a device"
+    import paper_1308_2572_amd as ara
+    ara.library()
+    return ara
+
+
+class Engine:
+    def __init__(self, ara, w, device="cuda"):
+        import torch
+        self.ara = ara
+        self.w = w
+        self.tables = ara.EltTables.from_numpy(w.elts, device)
+        self.yet = ara.PreparedYet.from_numpy(w.yet, device)
+        self.layers = ara.Layers(w.layers.elt_off, w.layers.elt_ids)
+        self.et = torch.tensor(w.elts.terms, dtype=torch.float64, device=device)
+        self.lt = torch.tensor(w.layers.terms, dtype=torch.float64, device=device)
+
+    def forward(self, t0=0, t1=None, hits=True, et=None, lt=None):
+        y, s, h = self.ara.ylt_forward(self.tables, self.yet, self.layers, self.et if et is None else et,
+                                       self.lt if lt is None else lt, t0, t1, want_s_pre=True, want_hits=hits,
+                                       check=True)
+        return (y.cpu().numpy(), s.cpu().numpy(), None if h is None else h.cpu().numpy())
+
+
+def assert_ylt(y, s, ref):
+    bound = TOL * np.maximum(np.abs(ref["ylt"]), ref["s_pre"])
+    bad = np.abs(y - ref["ylt"]) > bound
+    assert not bad.any(), f"{bad.sum()} year losses off; worst {np.abs(y - ref['ylt'])[bad].max()}"
+    sb = np.abs(s - ref["s_pre"]) > TOL * ref["s_pre"]
+    assert not sb.any(), f"{sb.sum()} totals off"
+
+
+def oracle_ref(w, t0=0, t1=None, threads=1):
+    tb = oracle.build_tables(w.elts)
+    return oracle.forward(tb, w.yet, w.layers, w.elts.terms, w.layers.terms, t0, t1, n_threads=threads)
+
+
+# ------------------------------------------------------------------ small cases
+def test_hand_example_exact(ara):
+    w, g = load_hand_example()
+    e = Engine(ara, w)
+    y, s, h = e.forward()
+    assert y[0].tolist() == g["ylt"]
+    assert s[0].tolist() == g["s_pre"]
+    assert h[0].tolist() == g["hits"]
+    import torch
+    for p, m in g["metrics"].items():
+        out, _ = ara.metrics(torch.tensor(y, device="cuda"), float(p))
+        assert out.cpu().numpy()[0].tolist() == [m["aal"], m["pml"], m["tvar"]]
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_tiny_random_vs_oracle(ara, seed):
+    w = synth.tiny_random(seed, n_trials=37 + 13 * seed, max_events=30, catalog=48 + 40 * seed, n_layers=3)
+    _say(f"tiny seed {seed}")
+    e = Engine(ara, w)
+    ref = oracle_ref(w)
+    y, s, h = e.forward()
+    assert np.array_equal(h, ref["hits"])
+    assert_ylt(y, s, ref)
+    # without hits the (smaller) hot-only table must give the same totals
+    y2, s2, _ = e.forward(hits=False)
+    assert np.array_equal(y2, y) or np.allclose(y2, y, rtol=1e-13, atol=0)
+    assert_ylt(y2, s2, ref)
+
+
+def test_catalogue_spanning_many_ranges(ara):
+    """Catalogue of 300,000 events (5 occurrence-table super-ranges, a ragged
+    last one), 3000 trials with lengths 0..400."""
+    g = np.random.default_rng(5)
+    lens = g.integers(0, 401, size=3000)
+    lens[::97] = 0
+    off = np.zeros(3001, np.int64)
+    np.cumsum(lens, out=off[1:])
+    ids = g.integers(0, 300_000, size=int(off[-1]), dtype=np.int32)
+    ids[:50] = 299_999
+    ids[50:100] = 0
+    elts = synth.lognormal_elts(77, [30_000, 5_000, 60_000, 1], 300_000, mu=11.0)
+    elts.rec_ids[elts.rec_off[3]] = 299_999
+    layers = synth.Layers(np.array([0, 4, 6, 6], np.int32), np.array([2, 0, 1, 3, 3, 2], np.int32),
+                          np.array([[1e4, 5e6, 1e5, 5e7], [0.0, np.inf, 0.0, np.inf], [1e4, 1e6, 0, 1e7]]))
+    w = synth.Workload("ranges", synth.Yet(300_000, off, ids), elts, layers, 0.9)
+    e = Engine(ara, w)
+    ref = oracle_ref(w)
+    y, s, h = e.forward()
+    assert np.array_equal(h, ref["hits"])
+    assert_ylt(y, s, ref)
+    assert np.all(y[2] == 0.0) and np.all(h[2] == 0)          # a layer with no ELTs
+
+
+def test_trial_subsets_match_full_run(ara):
+    w = synth.config(2, n_trials=9000)
+    e = Engine(ara, w)
+    y, s, h = e.forward()
+    for t0, t1 in [(0, 1), (17, 4099), (4096, 4097), (8000, 9000), (123, 123)]:
+        ys, ss, hs = e.forward(t0, t1)
+        assert np.array_equal(ys, y[:, t0:t1]) and np.array_equal(ss, s[:, t0:t1]) and np.array_equal(hs, h[:, t0:t1])
+
+
+def test_run_twice_bitwise_identical(ara):
+    w = synth.config(0, n_trials=3000)
+    e = Engine(ara, w)
+    a = e.forward()
+    b = e.forward()
+    for x, z in zip(a, b):
+        assert np.array_equal(x, z)
+
+
+def test_empty_yet_and_empty_trials(ara):
+    w = synth.tiny_random(1, n_trials=5)
+    w.yet = synth.Yet(w.yet.catalog, np.zeros(6, np.int64), np.zeros(0, np.int32))
+    e = Engine(ara, w)
+    y, s, h = e.forward()
+    assert np.all(y == 0) and np.all(s == 0) and np.all(h == 0)
+
+
+# ------------------------------------------------------------------ errors
+def test_invalid_inputs_are_rejected(ara):
+    import torch
+    w = synth.tiny_random(2)
+    ids = w.yet.ids.copy()
+    ids[3] = w.yet.catalog
+    with pytest.raises(ara.AraError) as ex:
+        ara.PreparedYet.from_numpy(synth.Yet(w.yet.catalog, w.yet.offsets, ids))
+    assert ex.value.status == 2
+    el = w.elts
+    dup = el.rec_ids.copy()
+    k = int(np.argmax(np.diff(el.rec_off) >= 2))
+    dup[el.rec_off[k] + 1] = dup[el.rec_off[k]]
+    with pytest.raises(ara.AraError) as ex:
+        ara.EltTables.from_numpy(synth.Elts(el.catalog, el.rec_off, dup, el.rec_loss, el.terms))
+    assert ex.value.status == 3
+    e = Engine(ara, w)
+    lt = e.lt.clone()
+    lt[0, 0] = -1.0
+    with pytest.raises(ara.AraError) as ex:
+        e.forward(lt=lt)
+    assert ex.value.status == 1
+    et = e.et.clone()
+    et[0, 0] = float("nan")
+    with pytest.raises(ara.AraError):
+        e.forward(et=et)
+
+
+# ------------------------------------------------------------------ metrics
+@pytest.mark.parametrize("seed", range(6))
+def test_metrics_vs_oracle(ara, seed):
+    import torch
+    g = np.random.default_rng(seed)
+    n = [1, 7, 1000, 10_000, 123_457, 400_000][seed]
+    L = 1 + seed % 3
+    y = g.lognormal(15, 2, size=(L, n))
+    if seed % 2:
+        y = np.round(y / 1e5) * 1e5             # many ties
+    y[:, : n // 10] = 0.0
+    for p in [0.5, 0.9, 0.99, 0.999]:
+        out, wts = ara.metrics(torch.tensor(y, device="cuda"), p, want_weights=True)
+        out, wts = out.cpu().numpy(), wts.cpu().numpy()
+        ref = oracle.metrics(y, p)
+        assert np.array_equal(out[:, 1], ref[:, 1])
+        np.testing.assert_allclose(out[:, [0, 2]], ref[:, [0, 2]], rtol=TOL, atol=0)
+        np.testing.assert_array_equal(wts, oracle.metric_weights(y, p))
+
+
+def test_metrics_constant_and_vjp(ara):
+    import torch
+    y = torch.full((2, 50_000), 1e8, dtype=torch.float64, device="cuda")
+    out, _ = ara.metrics(y, 0.99)
+    assert np.all(out.cpu().numpy() == 1e8)
+    yr = torch.tensor(np.random.default_rng(0).exponential(10.0, (2, 1000)), device="cuda", requires_grad=True)
+    m = ara.Metrics.apply(yr, 0.9)
+    gout = torch.tensor([[1.0, 2.0, 3.0], [0.5, -1.0, 0.25]], dtype=torch.float64, device="cuda")
+    (m * gout).sum().backward()
+    wref = oracle.metric_weights(yr.detach().cpu().numpy(), 0.9)
+    expect = np.einsum("lm,mlt->lt", gout.cpu().numpy(), wref)
+    np.testing.assert_allclose(yr.grad.cpu().numpy(), expect, rtol=1e-15, atol=1e-18)
+
+
+# ------------------------------------------------------------------ named workloads
+def test_config0_full(ara):
+    _say("workload 0 (10k x 1000, 15 ELTs)")
+    w = synth.config(0)
+    e = Engine(ara, w)
+    ref = oracle_ref(w, threads=4)
+    y, s, h = e.forward()
+    assert np.array_equal(h, ref["hits"])
+    assert_ylt(y, s, ref)
+    import torch
+    out, _ = ara.metrics(torch.tensor(y, device="cuda"), w.p)
+    np.testing.assert_allclose(out.cpu().numpy(), oracle.metrics(ref["ylt"], w.p), rtol=TOL)
+
+
+def test_config2_prefix_four_layers(ara):
+    _say("workload 2 prefix (20k x Poisson(1000), 4 layers)")
+    w = synth.config(2, n_trials=20_000)
+    e = Engine(ara, w)
+    ref = oracle_ref(w, threads=8)
+    y, s, h = e.forward()
+    assert np.array_equal(h, ref["hits"])
+    assert_ylt(y, s, ref)
+
+
+def test_config1_full_size_sampled(ara):
+    """1,000,000 trials x 1,000 events, 15 ELTs over a 2,000,000-event
+    catalogue, in the configuration the benchmark times: every year loss
+    from the GPU; a random sample recomputed by the oracle one trial at a
+    time; metrics checked on the full GPU YLT."""
+    import torch
+    _say("workload 1: generating 1M x 1000")
+    w = synth.config(1)
+    e = Engine(ara, w)
+    _say("workload 1: forward")
+    y, s, _ = e.forward(hits=False)
+    g = np.random.default_rng(1)
+    sample = np.unique(np.concatenate([g.integers(0, w.yet.n_trials, 300), [0, 1, w.yet.n_trials - 1]]))
+    tb = oracle.build_tables(w.elts)
+    for t in sample:
+        ref = oracle.forward(tb, w.yet, w.layers, w.elts.terms, w.layers.terms, int(t), int(t) + 1)
+        assert abs(y[0, t] - ref["ylt"][0, 0]) <= TOL * max(ref["ylt"][0, 0], ref["s_pre"][0, 0])
+        assert abs(s[0, t] - ref["s_pre"][0, 0]) <= TOL * ref["s_pre"][0, 0]
+    # hits on the sample through the hit-count path, over a trial sub-range
+    yh, sh, hh = e.forward(int(sample[1]), int(sample[1]) + 1, hits=True)
+    refh = oracle.forward(tb, w.yet, w.layers, w.elts.terms, w.layers.terms, int(sample[1]), int(sample[1]) + 1)
+    assert np.array_equal(hh, refh["hits"])
+    _say("workload 1: metrics")
+    out, _ = ara.metrics(torch.tensor(y, device="cuda"), w.p)
+    np.testing.assert_allclose(out.cpu().numpy(), oracle.metrics(y, w.p), rtol=TOL)
+    assert np.all(y >= 0) and np.all(y <= w.layers.terms[0, 3])
