@@ -228,6 +228,24 @@ int32_t ara_ylt_backward(const ara_tables *tables, const ara_yet *yet, const ara
                          double *grad_elt, double *grad_layer,
                          void *ws, size_t ws_bytes, void *stream);
 
+/* ------------------------------------------------------------------------ */
+/* Observability: optional per-kernel timing with HIP events recorded on the */
+/* caller's stream around each internal launch.                              */
+/* ------------------------------------------------------------------------ */
+#define ARA_PROF_OCC      0   /* occurrence-table kernel                     */
+#define ARA_PROF_FWD      1   /* forward streaming kernel                    */
+#define ARA_PROF_METRICS  2   /* all metric kernels of one ara_metrics call  */
+#define ARA_PROF_BWD      3   /* backward streaming kernel                   */
+#define ARA_PROF_BWD_RED  4   /* backward reductions                         */
+#define ARA_PROF_KINDS    8
+
+/* on != 0 starts recording (process-wide); 0 stops. */
+int32_t ara_profile_enable(int32_t on);
+/* Synchronises outstanding events of `kind` and returns their total elapsed
+ * milliseconds and launch count since the last reset. */
+int32_t ara_profile_read(int32_t kind, double *total_ms, int64_t *launches);
+int32_t ara_profile_reset(void);
+
 #ifdef __cplusplus
 }
 #endif

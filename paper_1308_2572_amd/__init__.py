@@ -67,6 +67,9 @@ _SIGNATURES = {
     "ara_metrics_workspace_bytes": (_c_i32, [_c_i32, _c_i64, _P(_c_sz)]),
     "ara_metrics": (_c_i32, [_c_p, _c_i32, _c_i64, _c_f64, _c_p, _c_p, _c_p, _c_sz, _c_p]),
     "ara_metrics_vjp": (_c_i32, [_c_p, _c_i32, _c_i64, _c_p, _c_p, _c_p]),
+    "ara_profile_enable": (_c_i32, [_c_i32]),
+    "ara_profile_read": (_c_i32, [_c_i32, _P(_c_f64), _P(_c_i64)]),
+    "ara_profile_reset": (_c_i32, []),
     "ara_ylt_backward_workspace_bytes": (_c_i32, [_P(ara_tables), _P(ara_yet), _P(ara_layers), _c_i32, _P(_c_sz)]),
     "ara_ylt_backward": (_c_i32, [_P(ara_tables), _P(ara_yet), _P(ara_layers), _c_p, _c_p, _c_i64, _c_i64, _c_p,
                                   _c_i32, _c_p, _c_p, _c_p, _c_p, _c_sz, _c_p]),
@@ -266,6 +269,24 @@ def ylt_backward(tables: EltTables, yet: PreparedYet, layers: Layers, elt_terms:
     if squeeze:
         return ge[0], gl[0]
     return ge, gl
+
+
+PROF_OCC, PROF_FWD, PROF_METRICS, PROF_BWD, PROF_BWD_RED = range(5)
+
+
+def profile_enable(on: bool = True) -> None:
+    _check(library().ara_profile_enable(1 if on else 0), "ara_profile_enable")
+
+
+def profile_reset() -> None:
+    _check(library().ara_profile_reset(), "ara_profile_reset")
+
+
+def profile_read(kind: int) -> Tuple[float, int]:
+    """(total milliseconds, launches) recorded for one kernel kind."""
+    ms, n = _c_f64(), _c_i64()
+    _check(library().ara_profile_read(kind, ctypes.byref(ms), ctypes.byref(n)), "ara_profile_read")
+    return ms.value, n.value
 
 
 # --------------------------------------------------------------------------

@@ -58,6 +58,19 @@ struct Carver {
 
 int device_cu_count();
 
+// Records a start/stop HIP event pair around the enclosed launches when
+// profiling is enabled (ara_profile_enable); no-op otherwise.
+class ProfScope {
+   public:
+    ProfScope(int kind, hipStream_t st);
+    ~ProfScope();
+
+   private:
+    int kind_;
+    hipStream_t st_;
+    hipEvent_t start_ = nullptr;
+};
+
 // Forward/backward occurrence-table workspace layout for one call.
 struct OccLayout {
     int n_sr;               // super-ranges

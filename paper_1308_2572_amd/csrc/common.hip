@@ -2,6 +2,8 @@
 #include "ara_internal.h"
 
 #include <cstdio>
+#include <mutex>
+#include <vector>
 
 namespace ara {
 
@@ -27,9 +29,80 @@ int device_cu_count() {
     return n;
 }
 
+struct ProfPending {
+    int kind;
+    hipEvent_t start, stop;
+};
+
+static std::mutex g_prof_mu;
+static bool g_prof_on = false;
+static std::vector<ProfPending> g_prof_pending;
+static double g_prof_ms[ARA_PROF_KINDS];
+static int64_t g_prof_n[ARA_PROF_KINDS];
+
+ProfScope::ProfScope(int kind, hipStream_t st) : kind_(kind), st_(st) {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    if (!g_prof_on) return;
+    if (hipEventCreate(&start_) != hipSuccess) {
+        start_ = nullptr;
+        return;
+    }
+    hipEventRecord(start_, st_);
+}
+
+ProfScope::~ProfScope() {
+    if (!start_) return;
+    hipEvent_t stop = nullptr;
+    if (hipEventCreate(&stop) != hipSuccess) {
+        hipEventDestroy(start_);
+        return;
+    }
+    hipEventRecord(stop, st_);
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_prof_pending.push_back({kind_, start_, stop});
+}
+
+static void prof_drain_locked() {
+    for (auto &p : g_prof_pending) {
+        float ms = 0.f;
+        if (hipEventSynchronize(p.stop) == hipSuccess && hipEventElapsedTime(&ms, p.start, p.stop) == hipSuccess) {
+            g_prof_ms[p.kind] += ms;
+            g_prof_n[p.kind] += 1;
+        }
+        hipEventDestroy(p.start);
+        hipEventDestroy(p.stop);
+    }
+    g_prof_pending.clear();
+}
+
 }  // namespace ara
 
 extern "C" {
+
+int32_t ara_profile_enable(int32_t on) {
+    std::lock_guard<std::mutex> lk(ara::g_prof_mu);
+    ara::g_prof_on = on != 0;
+    return ARA_OK;
+}
+
+int32_t ara_profile_read(int32_t kind, double *total_ms, int64_t *launches) {
+    if (kind < 0 || kind >= ARA_PROF_KINDS) return ara::fail(ARA_E_INVAL, "ara_profile_read: unknown kind");
+    std::lock_guard<std::mutex> lk(ara::g_prof_mu);
+    ara::prof_drain_locked();
+    if (total_ms) *total_ms = ara::g_prof_ms[kind];
+    if (launches) *launches = ara::g_prof_n[kind];
+    return ARA_OK;
+}
+
+int32_t ara_profile_reset(void) {
+    std::lock_guard<std::mutex> lk(ara::g_prof_mu);
+    ara::prof_drain_locked();
+    for (int k = 0; k < ARA_PROF_KINDS; ++k) {
+        ara::g_prof_ms[k] = 0.0;
+        ara::g_prof_n[k] = 0;
+    }
+    return ARA_OK;
+}
 
 const char *ara_status_string(int32_t status) {
     switch (status) {

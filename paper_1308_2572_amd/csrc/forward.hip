@@ -220,8 +220,11 @@ extern "C" int32_t ara_ylt_forward(const ara_tables *tables, const ara_yet *yet,
     if (nJ > 0) ARA_HIP(hipMemcpyAsync(d_ids, layers->elt_ids, nJ * sizeof(int32_t), hipMemcpyHostToDevice, st));
     ARA_HIP(hipMemcpyAsync(d_tabs, tabs.data(), L * sizeof(OccTables), hipMemcpyHostToDevice, st));
 
-    if ((rc = launch_occ(tables, d_off, d_ids, elt_terms, layer_terms, L, want_hits, d_tabs, z.n_sr, d_err, st)))
-        return rc;
+    {
+        ProfScope prof(ARA_PROF_OCC, st);
+        if ((rc = launch_occ(tables, d_off, d_ids, elt_terms, layer_terms, L, want_hits, d_tabs, z.n_sr, d_err, st)))
+            return rc;
+    }
 
     FwdParams P{};
     P.ent = yet->ent;
@@ -246,6 +249,7 @@ extern "C" int32_t ara_ylt_forward(const ara_tables *tables, const ara_yet *yet,
     P.s_pre = s_pre;
     P.hits = hits;
     const unsigned grid = static_cast<unsigned>(b_hi - P.b_lo);
+    ProfScope prof(ARA_PROF_FWD, st);
     if (want_hits) {
         static bool attr = false;
         if (!attr) {

@@ -367,6 +367,7 @@ extern "C" int32_t ara_metrics(const double *ylt, int32_t n_layers, int64_t n, d
     int64_t r = n - static_cast<int64_t>(std::floor(p * static_cast<double>(n) + 1e-9));
     r = std::max<int64_t>(1, std::min<int64_t>(n, r));
     dim3 grid(static_cast<unsigned>(nwg), static_cast<unsigned>(n_layers));
+    ProfScope prof(ARA_PROF_METRICS, st);
     k_met_hist1<<<grid, kMetThreads, 0, st>>>(ylt, n, nwg, hist1, part);
     k_met_cand<<<grid, kMetThreads, 0, st>>>(ylt, n, nwg, hist1, hist2, cand, state, r);
     k_met_select<<<n_layers, kMetThreads, 0, st>>>(n, hist2, cand, state);
