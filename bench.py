@@ -183,11 +183,18 @@ def main() -> int:
         except ara.AraError as ex:
             result["fwd_bwd"] = {"error": str(ex)}
     if not args.no_serving:
-        try:
-            import serve_bench
-            result["serving"] = serve_bench.run(ara, tables, yet, w, args.serving_requests)
-        except (ImportError, ara.AraError) as ex:
-            result["serving"] = {"error": str(ex)}
+        log("serving: resident 1M x Poisson(1000) YET, 200 ELTs, Poisson arrivals at 50/s")
+        from paper_1308_2572_amd import serve
+        w4 = synth.config(4, n_trials=args.trials)
+        tables4 = ara.EltTables.from_numpy(w4.elts, dev)
+        yet4 = ara.PreparedYet.from_numpy(w4.yet, dev)
+        et4 = torch.tensor(w4.elts.terms, dtype=torch.float64, device=dev)
+        reqs = synth.serving_requests(args.serving_requests, w4.yet.n_trials, n_elts=w4.elts.n_elts)
+        result["serving"] = serve.run_benchmark(tables4, yet4, et4, reqs, p=0.99)
+        result["serving"]["workload"] = ("resident 1,000,000 trials x Poisson(1000) events, 200 ELTs of "
+                                         "10,000-30,000 events; quotes of 5-25 ELTs over 100k-1M trials, "
+                                         "half with gradients, Poisson arrivals at 50/s")
+        del yet4, tables4
     if not args.no_cpu_baseline:
         log("CPU baseline (oracle)")
         result["cpu_baseline"] = cpu_baseline(w)

@@ -55,6 +55,7 @@ extern "C" {
 #define ARA_E_NOSPACE 4   /* caller buffer smaller than the *_bytes query */
 #define ARA_E_HIP     5   /* HIP runtime error */
 #define ARA_E_LIMIT   6   /* size beyond a documented implementation limit */
+#define ARA_E_BUSY    7   /* not an error: the quote is not finished yet (poll, cancel) */
 
 /* forward flags */
 #define ARA_F_EMIT_HITS   1u  /* also produce per-(layer, trial) hit counts */
@@ -227,6 +228,57 @@ int32_t ara_ylt_backward(const ara_tables *tables, const ara_yet *yet, const ara
                          int32_t n_cot, const double *grad_ylt,
                          double *grad_elt, double *grad_layer,
                          void *ws, size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Quote server: continuous batching of pricing requests over the resident   */
+/* YET and ELT tables (the paper motivates real-time pricing, Sections I, V). */
+/* ------------------------------------------------------------------------ */
+/*
+ * A quote is a candidate layer over the resident ELTs with its own terms,
+ * over a contiguous trial range.  A scheduler thread admits quotes in arrival
+ * order as soon as a slot and enough arena memory are free, and every
+ * iteration packs blocks of every active quote into one forward launch, so
+ * quotes arriving while others run join at the next iteration.  Results do
+ * not depend on the mix.  All device memory comes from the caller's arena.
+ */
+typedef struct ara_quote {
+    int32_t        n_elts;
+    int32_t        want_grad;       /* also return d(AAL, PML, TVaR)/d(every term) */
+    const int32_t *elt_ids;         /* HOST [n_elts] indices into the resident ELT set, listed order */
+    double         layer_terms[4];  /* OccR, OccL, AggR, AggL */
+    int64_t        trial_begin, trial_end;
+    double         p;               /* tail probability of PML and TVaR, in (0, 1) */
+} ara_quote;
+
+typedef struct ara_quote_result {
+    int32_t status;
+    int32_t n_elts;
+    double  metrics[3];             /* AAL, PML_p, TVaR_p */
+    double  grad_layer[3][4];       /* [metric][OccR, OccL, AggR, AggL] (want_grad) */
+    double *grad_elt;               /* caller's HOST [3][n_elts][3] (scale, retention, limit), or NULL */
+    double  t_submit_ms, t_admit_ms, t_done_ms;   /* host steady clock */
+} ara_quote_result;
+
+/* Arena bytes that hold `quotes_with_grad` full-range quotes with gradients. */
+int32_t ara_server_arena_bytes(const ara_tables *tables, const ara_yet *yet, int32_t quotes_with_grad,
+                               size_t *bytes);
+/* elt_terms: device [n_elts][3] terms of the resident ELTs; arena: device
+ * buffer owned by the caller for the server's lifetime; max_slots <= 256. */
+int32_t ara_server_create(const ara_tables *tables, const ara_yet *yet, const double *elt_terms,
+                          void *arena, size_t arena_bytes, int32_t max_slots, void **server);
+/* Validates and enqueues; ARA_E_NOSPACE if the quote can never fit the arena. */
+int32_t ara_server_submit(void *server, const ara_quote *quote, int64_t *ticket);
+/* ARA_OK and *out filled when finished (the ticket is then retired), ARA_E_BUSY otherwise. */
+int32_t ara_server_poll(void *server, int64_t ticket, ara_quote_result *out);
+/* Blocks until the quote is finished; fills *out and retires the ticket. */
+int32_t ara_server_wait(void *server, int64_t ticket, ara_quote_result *out);
+/* Cancels a quote still in the queue (ARA_E_BUSY once it is on the device). */
+int32_t ara_server_cancel(void *server, int64_t ticket);
+/* stats[6] = iterations, packed forward launches, most quotes in one launch,
+ * queued, active, free arena bytes. */
+int32_t ara_server_stats(void *server, int64_t *stats);
+/* Stops admitting, drains the active quotes, frees host resources. */
+int32_t ara_server_destroy(void *server);
 
 /* ------------------------------------------------------------------------ */
 /* Observability: optional per-kernel timing with HIP events recorded on the */

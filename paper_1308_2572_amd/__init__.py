@@ -21,7 +21,7 @@ import torch
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libara.so")
 
-ARA_OK, ARA_E_INVAL, ARA_E_RANGE, ARA_E_DUP, ARA_E_NOSPACE, ARA_E_HIP, ARA_E_LIMIT = range(7)
+ARA_OK, ARA_E_INVAL, ARA_E_RANGE, ARA_E_DUP, ARA_E_NOSPACE, ARA_E_HIP, ARA_E_LIMIT, ARA_E_BUSY = range(8)
 ARA_F_EMIT_HITS = 1
 ARA_MAX_COTANGENTS = 4
 
@@ -51,6 +51,16 @@ class ara_layers(ctypes.Structure):
     _fields_ = [("n_layers", _c_i32), ("reserved", _c_i32), ("elt_off", _c_p), ("elt_ids", _c_p)]
 
 
+class ara_quote(ctypes.Structure):
+    _fields_ = [("n_elts", _c_i32), ("want_grad", _c_i32), ("elt_ids", _c_p), ("layer_terms", _c_f64 * 4),
+                ("trial_begin", _c_i64), ("trial_end", _c_i64), ("p", _c_f64)]
+
+
+class ara_quote_result(ctypes.Structure):
+    _fields_ = [("status", _c_i32), ("n_elts", _c_i32), ("metrics", _c_f64 * 3), ("grad_layer", (_c_f64 * 4) * 3),
+                ("grad_elt", _c_p), ("t_submit_ms", _c_f64), ("t_admit_ms", _c_f64), ("t_done_ms", _c_f64)]
+
+
 _P = ctypes.POINTER
 _SIGNATURES = {
     "ara_status_string": (ctypes.c_char_p, [_c_i32]),
@@ -67,6 +77,14 @@ _SIGNATURES = {
     "ara_metrics_workspace_bytes": (_c_i32, [_c_i32, _c_i64, _P(_c_sz)]),
     "ara_metrics": (_c_i32, [_c_p, _c_i32, _c_i64, _c_f64, _c_p, _c_p, _c_p, _c_sz, _c_p]),
     "ara_metrics_vjp": (_c_i32, [_c_p, _c_i32, _c_i64, _c_p, _c_p, _c_p]),
+    "ara_server_arena_bytes": (_c_i32, [_P(ara_tables), _P(ara_yet), _c_i32, _P(_c_sz)]),
+    "ara_server_create": (_c_i32, [_P(ara_tables), _P(ara_yet), _c_p, _c_p, _c_sz, _c_i32, _P(_c_p)]),
+    "ara_server_submit": (_c_i32, [_c_p, _P(ara_quote), _P(_c_i64)]),
+    "ara_server_poll": (_c_i32, [_c_p, _c_i64, _P(ara_quote_result)]),
+    "ara_server_wait": (_c_i32, [_c_p, _c_i64, _P(ara_quote_result)]),
+    "ara_server_cancel": (_c_i32, [_c_p, _c_i64]),
+    "ara_server_stats": (_c_i32, [_c_p, _P(_c_i64)]),
+    "ara_server_destroy": (_c_i32, [_c_p]),
     "ara_profile_enable": (_c_i32, [_c_i32]),
     "ara_profile_read": (_c_i32, [_c_i32, _P(_c_f64), _P(_c_i64)]),
     "ara_profile_reset": (_c_i32, []),
@@ -290,6 +308,93 @@ def profile_read(kind: int) -> Tuple[float, int]:
 
 
 # --------------------------------------------------------------------------
+# quote server
+# --------------------------------------------------------------------------
+
+class QuoteServer:
+    """Continuous-batching quote server over a resident YET and ELT set (the
+    scheduler runs in libara.so; this object owns the device arena)."""
+
+    def __init__(self, tables: EltTables, yet: PreparedYet, elt_terms: torch.Tensor, arena_bytes: Optional[int] = None,
+                 quotes_with_grad: int = 16, max_slots: int = 64):
+        lib = library()
+        if arena_bytes is None:
+            nb = _c_sz()
+            _check(lib.ara_server_arena_bytes(ctypes.byref(tables.handle), ctypes.byref(yet.handle), quotes_with_grad,
+                                              ctypes.byref(nb)), "ara_server_arena_bytes")
+            arena_bytes = nb.value
+        self.tables, self.yet = tables, yet
+        self.elt_terms = elt_terms.to(device=yet.device, dtype=torch.float64).contiguous()
+        self.arena = _workspace(arena_bytes, yet.device)
+        torch.cuda.synchronize(yet.device)
+        self.handle = ctypes.c_void_p()
+        _check(lib.ara_server_create(ctypes.byref(tables.handle), ctypes.byref(yet.handle), _dptr(self.elt_terms),
+                                     _dptr(self.arena), self.arena.numel(), max_slots, ctypes.byref(self.handle)),
+               "ara_server_create")
+        self._keep = {}
+
+    def submit(self, elt_ids, layer_terms, trial_begin: int, trial_end: int, p: float = 0.99,
+               want_grad: bool = False) -> int:
+        ids = np.ascontiguousarray(elt_ids, dtype=np.int32)
+        q = ara_quote(int(ids.shape[0]), 1 if want_grad else 0, ids.ctypes.data_as(_c_p),
+                      (_c_f64 * 4)(*[float(v) for v in layer_terms]), int(trial_begin), int(trial_end), float(p))
+        t = _c_i64()
+        _check(library().ara_server_submit(self.handle, ctypes.byref(q), ctypes.byref(t)), "ara_server_submit")
+        self._keep[t.value] = (int(ids.shape[0]), bool(want_grad))
+        return t.value
+
+    def _result(self, ticket: int, blocking: bool):
+        n_elts, want_grad = self._keep[ticket]
+        ge = np.zeros((3, n_elts, 3), np.float64)
+        r = ara_quote_result()
+        r.grad_elt = ge.ctypes.data_as(_c_p) if want_grad else None
+        lib = library()
+        rc = lib.ara_server_wait(self.handle, ticket, ctypes.byref(r)) if blocking else \
+            lib.ara_server_poll(self.handle, ticket, ctypes.byref(r))
+        if rc == ARA_E_BUSY:
+            return None
+        _check(rc, "ara_server_wait" if blocking else "ara_server_poll")
+        del self._keep[ticket]
+        out = {"metrics": np.array(r.metrics[:]), "t_submit_ms": r.t_submit_ms, "t_admit_ms": r.t_admit_ms,
+               "t_done_ms": r.t_done_ms}
+        if want_grad:
+            out["grad_layer"] = np.array([r.grad_layer[m][:] for m in range(3)])
+            out["grad_elt"] = ge
+        return out
+
+    def wait(self, ticket: int):
+        return self._result(ticket, True)
+
+    def poll(self, ticket: int):
+        return self._result(ticket, False)
+
+    def cancel(self, ticket: int) -> bool:
+        rc = library().ara_server_cancel(self.handle, ticket)
+        if rc == ARA_E_BUSY:
+            return False
+        _check(rc, "ara_server_cancel")
+        self._keep.pop(ticket, None)
+        return True
+
+    def stats(self):
+        st = (_c_i64 * 6)()
+        _check(library().ara_server_stats(self.handle, st), "ara_server_stats")
+        keys = ["iterations", "packed_launches", "max_quotes_per_launch", "queued", "active", "free_arena_bytes"]
+        return dict(zip(keys, list(st)))
+
+    def close(self):
+        if self.handle:
+            library().ara_server_destroy(self.handle)
+            self.handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# --------------------------------------------------------------------------
 # autograd
 # --------------------------------------------------------------------------
 
@@ -329,5 +434,5 @@ class Metrics(torch.autograd.Function):
 
 __all__ = [
     "AraError", "PreparedYet", "EltTables", "Layers", "ylt_forward", "metrics", "metrics_vjp", "ylt_backward",
-    "YLT", "Metrics", "library", "ara_yet", "ara_tables", "ara_layers", "ARA_F_EMIT_HITS",
+    "YLT", "Metrics", "QuoteServer", "library", "ara_yet", "ara_tables", "ara_layers", "ARA_F_EMIT_HITS",
 ]

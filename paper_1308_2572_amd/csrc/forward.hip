@@ -22,15 +22,8 @@ struct FwdParams {
     const int32_t *seg_run;
     int64_t n_trials;
     int32_t tg, tb, n_ranges, n_sr;
-    int32_t b_lo;
-    int64_t t0, t1;
-    int32_t n_layers;
     int32_t cap;               // values held in LDS per super-range
-    const OccTables *tabs;     // [n_layers]
-    const double *layer_terms; // [n_layers][4]
-    double *ylt;
-    double *s_pre;
-    int32_t *hits;
+    const FwdItem *items;      // one (layer, block of trials) per workgroup
 };
 
 __device__ __forceinline__ uint32_t ld_stream(const uint32_t *p) { return __builtin_nontemporal_load(p); }
@@ -46,113 +39,147 @@ __global__ __launch_bounds__(1024) void k_fwd(FwdParams P) {
     double *tvals = reinterpret_cast<double *>(smem + tbr_off + kSrWords * sizeof(uint2));
     uint8_t *tcnt = reinterpret_cast<uint8_t *>(tvals + P.cap);
 
+    const FwdItem I = P.items[blockIdx.x];
     const int tid = threadIdx.x, lane = tid & 63;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int64_t b = static_cast<int64_t>(P.b_lo) + blockIdx.x;
+    const int64_t b = I.block;
     const int64_t gt0 = b * tb + static_cast<int64_t>(w) * P.tg;
     const int64_t gt1 = min(gt0 + P.tg, P.n_trials);
-    const bool active = gt0 < gt1 && gt1 > P.t0 && gt0 < P.t1;
+    const bool active = gt0 < gt1 && gt1 > I.t0 && gt0 < I.t1;
     const int G = P.n_ranges;
     const size_t seg0 = static_cast<size_t>(b) * G * kGroups + w;
-    const int64_t n_out = P.t1 - P.t0;
 
-    for (int j = 0; j < P.n_layers; ++j) {
-        __syncthreads();   // the previous layer's totals have been written out
-        for (int i = tid; i < tb; i += blockDim.x) {
-            acc[i] = 0.0;
-            if (HITS) hacc[i] = 0;
+    for (int i = tid; i < tb; i += blockDim.x) {
+        acc[i] = 0.0;
+        if (HITS) hacc[i] = 0;
+    }
+    const OccTables T = *I.tab;
+
+    // stream cursor over this wave's segments (range rr, step within it)
+    int rr = active ? 0 : G, step = 0, R = 0;
+    int64_t sb = 0;
+    auto seek = [&]() {
+        while (rr < G) {
+            const size_t si = seg0 + static_cast<size_t>(rr) * kGroups;
+            R = P.seg_run[si];
+            sb = P.seg_base[si];
+            if (R > 0) break;
+            ++rr;
         }
-        const OccTables T = P.tabs[j];
-
-        // stream cursor over this wave's segments (range rr, step within it)
-        int rr = active ? 0 : G, step = 0, R = 0;
-        int64_t sb = 0;
-        auto seek = [&]() {
-            while (rr < G) {
-                const size_t si = seg0 + static_cast<size_t>(rr) * kGroups;
-                R = P.seg_run[si];
-                sb = P.seg_base[si];
-                if (R > 0) break;
+    };
+    uint32_t X[kUnroll];
+    int chunk_rr = G;
+    auto load = [&]() {
+        chunk_rr = rr;
+        if (rr < G) {
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u)
+                X[u] = (step + u < R) ? ld_stream(P.ent + sb + static_cast<int64_t>(step + u) * kWave + lane)
+                                      : kSentinel;
+            step += kUnroll;
+            if (step >= R) {
                 ++rr;
+                step = 0;
+                seek();
             }
-        };
-        uint32_t X[kUnroll];
-        int chunk_rr = G;
-        auto load = [&]() {
-            chunk_rr = rr;
-            if (rr < G) {
-#pragma unroll
-                for (int u = 0; u < kUnroll; ++u)
-                    X[u] = (step + u < R) ? ld_stream(P.ent + sb + static_cast<int64_t>(step + u) * kWave + lane)
-                                          : kSentinel;
-                step += kUnroll;
-                if (step >= R) {
-                    ++rr;
-                    step = 0;
-                    seek();
-                }
-            }
-        };
-        seek();
-        load();
+        }
+    };
+    seek();
+    load();
 
-        for (int s = 0; s < P.n_sr; ++s) {
-            __syncthreads();
-            const int cnt_s = T.count[s];
-            const int inl = min(cnt_s, P.cap);
-            const uint2 *gbr = T.br + static_cast<size_t>(s) * kSrWords;
-            const double *gvals = T.vals + static_cast<size_t>(s) * kSr;
-            const uint8_t *gcnt = HITS ? T.cnt + static_cast<size_t>(s) * kSr : nullptr;
-            for (int i = tid; i < kSrWords; i += blockDim.x) tbr[i] = gbr[i];
-            for (int i = tid; i < inl; i += blockDim.x) tvals[i] = gvals[i];
-            if (HITS)
-                for (int i = tid; i < inl; i += blockDim.x) tcnt[i] = gcnt[i];
-            __syncthreads();
-            const int rr_end = min(2 * s + 2, G);
-            while (chunk_rr < rr_end) {
-                uint32_t Y[kUnroll];
+    for (int s = 0; s < P.n_sr; ++s) {
+        __syncthreads();
+        const int cnt_s = T.count[s];
+        const int inl = min(cnt_s, P.cap);
+        const uint2 *gbr = T.br + static_cast<size_t>(s) * kSrWords;
+        const double *gvals = T.vals + static_cast<size_t>(s) * kSr;
+        const uint8_t *gcnt = HITS ? T.cnt + static_cast<size_t>(s) * kSr : nullptr;
+        for (int i = tid; i < kSrWords; i += blockDim.x) tbr[i] = gbr[i];
+        for (int i = tid; i < inl; i += blockDim.x) tvals[i] = gvals[i];
+        if (HITS)
+            for (int i = tid; i < inl; i += blockDim.x) tcnt[i] = gcnt[i];
+        __syncthreads();
+        const int rr_end = min(2 * s + 2, G);
+        while (chunk_rr < rr_end) {
+            uint32_t Y[kUnroll];
 #pragma unroll
-                for (int u = 0; u < kUnroll; ++u) Y[u] = X[u];
-                const uint32_t hb = static_cast<uint32_t>(chunk_rr & 1) << kRangeBits;
-                load();   // prefetch the next chunk (possibly of the next super-range)
+            for (int u = 0; u < kUnroll; ++u) Y[u] = X[u];
+            const uint32_t hb = static_cast<uint32_t>(chunk_rr & 1) << kRangeBits;
+            load();   // prefetch the next chunk (possibly of the next super-range)
 #pragma unroll
-                for (int u = 0; u < kUnroll; ++u) {
-                    const uint32_t e = Y[u];
-                    if (e != kSentinel) {
-                        const uint32_t tl = e >> kRangeBits;
-                        const uint32_t loc = hb | (e & (kRange - 1));
-                        const uint2 q = tbr[loc >> 5];
-                        const uint32_t bit = loc & 31;
-                        if ((q.x >> bit) & 1u) {
-                            const uint32_t rank = q.y + __popc(q.x & ((1u << bit) - 1u));
-                            const double v = (rank < static_cast<uint32_t>(P.cap)) ? tvals[rank] : gvals[rank];
-                            atomicAdd(&acc[tl], v);
-                            if (HITS) {
-                                const int c = (rank < static_cast<uint32_t>(P.cap)) ? tcnt[rank] : gcnt[rank];
-                                atomicAdd(&hacc[tl], c);
-                            }
+            for (int u = 0; u < kUnroll; ++u) {
+                const uint32_t e = Y[u];
+                if (e != kSentinel) {
+                    const uint32_t tl = e >> kRangeBits;
+                    const uint32_t loc = hb | (e & (kRange - 1));
+                    const uint2 q = tbr[loc >> 5];
+                    const uint32_t bit = loc & 31;
+                    if ((q.x >> bit) & 1u) {
+                        const uint32_t rank = q.y + __popc(q.x & ((1u << bit) - 1u));
+                        const double v = (rank < static_cast<uint32_t>(P.cap)) ? tvals[rank] : gvals[rank];
+                        atomicAdd(&acc[tl], v);
+                        if (HITS) {
+                            const int c = (rank < static_cast<uint32_t>(P.cap)) ? tcnt[rank] : gcnt[rank];
+                            atomicAdd(&hacc[tl], c);
                         }
                     }
                 }
             }
         }
-        __syncthreads();
-        if (active) {
-            const double aggR = P.layer_terms[4 * j + 2], aggL = P.layer_terms[4 * j + 3];
-            const int64_t lo = max(gt0, P.t0), hi = min(gt1, P.t1);
-            for (int64_t t = lo + lane; t < hi; t += kWave) {
-                const int i = static_cast<int>(t - b * tb);
-                const double S = acc[i];
-                const size_t o = static_cast<size_t>(j) * n_out + static_cast<size_t>(t - P.t0);
-                P.ylt[o] = xl(S, aggR, aggL);
-                if (P.s_pre) P.s_pre[o] = S;
-                if (HITS && P.hits) P.hits[o] = hacc[i];
-            }
+    }
+    __syncthreads();
+    if (active) {
+        const double aggR = I.lterm[2], aggL = I.lterm[3];
+        const int64_t lo = max(gt0, I.t0), hi = min(gt1, I.t1);
+        for (int64_t t = lo + lane; t < hi; t += kWave) {
+            const int i = static_cast<int>(t - b * tb);
+            const double S = acc[i];
+            const size_t o = static_cast<size_t>(t - I.t0);
+            I.ylt[o] = xl(S, aggR, aggL);
+            if (I.s_pre) I.s_pre[o] = S;
+            if (HITS && I.hits) I.hits[o] = hacc[i];
         }
     }
 }
 
-static size_t fwd_workspace(const ara_tables *tables, const ara_layers *layers, bool hits) {
+int32_t launch_forward(const ara_yet *yet, int n_sr, bool hits, const FwdItem *d_items, int n_items, hipStream_t st) {
+    if (n_items <= 0) return ARA_OK;
+    FwdParams P{};
+    P.ent = yet->ent;
+    P.seg_base = yet->seg_base;
+    P.seg_run = yet->seg_run;
+    P.n_trials = yet->n_trials;
+    P.tg = yet->trials_per_group;
+    P.tb = yet->trials_per_block;
+    P.n_ranges = yet->n_ranges;
+    P.n_sr = n_sr;
+    const size_t fixed = align256(static_cast<size_t>(P.tb) * 8 + (hits ? static_cast<size_t>(P.tb) * 4 : 0)) +
+                         kSrWords * sizeof(uint2);
+    P.cap = static_cast<int32_t>((kLdsBytes - fixed) / (hits ? 9 : 8));
+    P.items = d_items;
+    ProfScope prof(ARA_PROF_FWD, st);
+    if (hits) {
+        static bool attr = false;
+        if (!attr) {
+            ARA_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_fwd<true>),
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes));
+            attr = true;
+        }
+        k_fwd<true><<<n_items, 1024, kLdsBytes, st>>>(P);
+    } else {
+        static bool attr = false;
+        if (!attr) {
+            ARA_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_fwd<false>),
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes));
+            attr = true;
+        }
+        k_fwd<false><<<n_items, 1024, kLdsBytes, st>>>(P);
+    }
+    ARA_HIP(hipGetLastError());
+    return ARA_OK;
+}
+
+static size_t fwd_workspace(const ara_tables *tables, const ara_yet *yet, const ara_layers *layers, bool hits) {
     const OccLayoutSizes z = occ_sizes(tables->catalog, hits);
     const int L = layers->n_layers;
     const int nJ = L > 0 ? layers->elt_off[L] : 0;
@@ -160,6 +187,7 @@ static size_t fwd_workspace(const ara_tables *tables, const ara_layers *layers, 
     b += align256(static_cast<size_t>(L + 1) * sizeof(int32_t));
     b += align256(static_cast<size_t>(std::max(nJ, 1)) * sizeof(int32_t));
     b += align256(static_cast<size_t>(std::max(L, 1)) * sizeof(OccTables));
+    b += align256(static_cast<size_t>(std::max(L, 1)) * std::max(yet->n_blocks, 1) * sizeof(FwdItem));
     b += static_cast<size_t>(L) * z.per_layer;
     return b;
 }
@@ -182,7 +210,7 @@ extern "C" int32_t ara_ylt_workspace_bytes(const ara_tables *tables, const ara_y
     if (rc) return rc;
     if ((rc = check_layers(layers, tables->n_elts))) return rc;
     if (flags & ~ARA_F_EMIT_HITS) return fail(ARA_E_INVAL, "unknown flag");
-    *bytes = fwd_workspace(tables, layers, (flags & ARA_F_EMIT_HITS) != 0);
+    *bytes = fwd_workspace(tables, yet, layers, (flags & ARA_F_EMIT_HITS) != 0);
     return ARA_OK;
 }
 
@@ -202,7 +230,7 @@ extern "C" int32_t ara_ylt_forward(const ara_tables *tables, const ara_yet *yet,
     const int L = layers->n_layers;
     const int64_t n = trial_end - trial_begin;
     if (L > 0 && n > 0 && (!ylt || !elt_terms || !layer_terms)) return fail(ARA_E_INVAL, "null output or terms");
-    if (ws_bytes < fwd_workspace(tables, layers, want_hits)) return fail(ARA_E_NOSPACE, "forward workspace too small");
+    if (ws_bytes < fwd_workspace(tables, yet, layers, want_hits)) return fail(ARA_E_NOSPACE, "forward workspace too small");
     hipStream_t st = static_cast<hipStream_t>(stream);
     ARA_HIP(hipMemsetAsync(ws, 0, kWsHeaderBytes, st));
     if (L == 0 || n == 0) return ARA_OK;
@@ -214,59 +242,34 @@ extern "C" int32_t ara_ylt_forward(const ara_tables *tables, const ara_yet *yet,
     int32_t *d_off = c.take<int32_t>(static_cast<size_t>(L + 1));
     int32_t *d_ids = c.take<int32_t>(static_cast<size_t>(std::max(nJ, 1)));
     OccTables *d_tabs = c.take<OccTables>(static_cast<size_t>(L));
+    const int64_t b_lo = trial_begin / yet->trials_per_block;
+    const int64_t b_hi = (trial_end + yet->trials_per_block - 1) / yet->trials_per_block;
+    const int nb = static_cast<int>(b_hi - b_lo);
+    FwdItem *d_items = c.take<FwdItem>(static_cast<size_t>(L) * std::max(yet->n_blocks, 1));
     std::vector<OccTables> tabs(static_cast<size_t>(L));
     for (int j = 0; j < L; ++j) tabs[j] = occ_carve(c, z, want_hits);
+    std::vector<FwdItem> items(static_cast<size_t>(L) * nb);
+    for (int j = 0; j < L; ++j)
+        for (int i = 0; i < nb; ++i) {
+            FwdItem &it = items[static_cast<size_t>(j) * nb + i];
+            it.tab = d_tabs + j;
+            it.lterm = layer_terms + 4 * j;
+            it.block = static_cast<int32_t>(b_lo + i);
+            it.t0 = trial_begin;
+            it.t1 = trial_end;
+            it.ylt = ylt + static_cast<size_t>(j) * n;
+            it.s_pre = s_pre ? s_pre + static_cast<size_t>(j) * n : nullptr;
+            it.hits = hits ? hits + static_cast<size_t>(j) * n : nullptr;
+        }
     ARA_HIP(hipMemcpyAsync(d_off, layers->elt_off, (L + 1) * sizeof(int32_t), hipMemcpyHostToDevice, st));
     if (nJ > 0) ARA_HIP(hipMemcpyAsync(d_ids, layers->elt_ids, nJ * sizeof(int32_t), hipMemcpyHostToDevice, st));
     ARA_HIP(hipMemcpyAsync(d_tabs, tabs.data(), L * sizeof(OccTables), hipMemcpyHostToDevice, st));
+    ARA_HIP(hipMemcpyAsync(d_items, items.data(), items.size() * sizeof(FwdItem), hipMemcpyHostToDevice, st));
 
     {
         ProfScope prof(ARA_PROF_OCC, st);
         if ((rc = launch_occ(tables, d_off, d_ids, elt_terms, layer_terms, L, want_hits, d_tabs, z.n_sr, d_err, st)))
             return rc;
     }
-
-    FwdParams P{};
-    P.ent = yet->ent;
-    P.seg_base = yet->seg_base;
-    P.seg_run = yet->seg_run;
-    P.n_trials = yet->n_trials;
-    P.tg = yet->trials_per_group;
-    P.tb = yet->trials_per_block;
-    P.n_ranges = yet->n_ranges;
-    P.n_sr = z.n_sr;
-    P.b_lo = static_cast<int32_t>(trial_begin / yet->trials_per_block);
-    const int64_t b_hi = (trial_end + yet->trials_per_block - 1) / yet->trials_per_block;
-    P.t0 = trial_begin;
-    P.t1 = trial_end;
-    P.n_layers = L;
-    const size_t fixed = align256(static_cast<size_t>(P.tb) * 8 + (want_hits ? static_cast<size_t>(P.tb) * 4 : 0)) +
-                         kSrWords * sizeof(uint2);
-    P.cap = static_cast<int32_t>((kLdsBytes - fixed) / (want_hits ? 9 : 8));
-    P.tabs = d_tabs;
-    P.layer_terms = layer_terms;
-    P.ylt = ylt;
-    P.s_pre = s_pre;
-    P.hits = hits;
-    const unsigned grid = static_cast<unsigned>(b_hi - P.b_lo);
-    ProfScope prof(ARA_PROF_FWD, st);
-    if (want_hits) {
-        static bool attr = false;
-        if (!attr) {
-            ARA_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_fwd<true>),
-                                        hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes));
-            attr = true;
-        }
-        k_fwd<true><<<grid, 1024, kLdsBytes, st>>>(P);
-    } else {
-        static bool attr = false;
-        if (!attr) {
-            ARA_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_fwd<false>),
-                                        hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes));
-            attr = true;
-        }
-        k_fwd<false><<<grid, 1024, kLdsBytes, st>>>(P);
-    }
-    ARA_HIP(hipGetLastError());
-    return ARA_OK;
+    return launch_forward(yet, z.n_sr, want_hits, d_items, L * nb, st);
 }

@@ -2,11 +2,13 @@
 // loss) and TVaR_p (mean of the r largest), r = N - floor(p*N + 1e-9).
 //
 // Selection is a radix select on the binary64 bit patterns (year losses are
-// >= 0, so the unsigned order of the bits is the numeric order): 11-bit
-// digits from the top, one grid pass for the first digit, one grid pass that
-// also collects the candidates sharing it, then a single workgroup per layer
-// finishes on the candidates.  Sums use a fixed partition of the trials and
-// fixed-order trees, so every result is deterministic.
+// >= 0, so the unsigned order of the bits is the numeric order), with digits
+// of 11 bits from the top.  Two grid passes fix the exponent and the leading
+// mantissa digit; if few values share that 23-bit prefix they are gathered
+// and one workgroup finishes in LDS, otherwise (heavy ties) four more grid
+// passes finish (they exit at once when the small path already finished).
+// Sums use a fixed partition of the trials and fixed-order trees, so every
+// result is deterministic.
 #include "ara_internal.h"
 
 #include <algorithm>
@@ -14,17 +16,22 @@
 
 namespace ara {
 
-constexpr int kDigit = 11;
-constexpr int kBins = 1 << kDigit;
 constexpr int kMetThreads = 1024;
+constexpr int kBins = 2048;
+constexpr int kPassesMet = 6;
+constexpr int kCandCap = 16384;     // candidates finished inside one workgroup's LDS
+// digit d covers bits [kShift[d], kShift[d] + kWidth[d]) of the key; bit 63
+// (the sign) is 0 for every year loss
+__constant__ int kShift[kPassesMet] = {52, 41, 30, 19, 8, 0};
+__constant__ int kWidth[kPassesMet] = {11, 11, 11, 11, 11, 8};
 
 struct MetState {
-    uint64_t prefix;       // selected high bits so far
-    int64_t need;          // rank (1-based from the top) still to find below the prefix
-    int64_t cand_n;        // candidates collected
-    uint64_t thr_bits;
-    int64_t cnt_gt, cnt_eq;
+    uint64_t prefix[kPassesMet + 1];   // bits fixed before digit d (prefix[d] has 64 - kShift[d] - kWidth[d] bits)
+    int64_t need[kPassesMet + 1];      // rank (1-based from the top) to find among values with prefix[d]
+    int64_t cand_n;
+    int32_t small, done;
     double thr;
+    int64_t cnt_gt, cnt_eq;
     int64_t r;
 };
 
@@ -43,7 +50,7 @@ __device__ __forceinline__ void chunk_of(int64_t n, int nwg, int wg, int64_t &lo
     hi = std::min<int64_t>(n, lo + c);
 }
 
-// Fixed-order block sum of one double per thread.
+// Fixed-order block reductions (value valid in thread 0).
 __device__ double block_sum(double v, double *red) {
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o);
@@ -53,7 +60,7 @@ __device__ double block_sum(double v, double *red) {
     if (tid == 0)
         for (int i = 0; i < static_cast<int>(blockDim.x >> 6); ++i) t += red[i];
     __syncthreads();
-    return t;   // valid in thread 0
+    return t;
 }
 
 __device__ int64_t block_count(int64_t v, int64_t *red) {
@@ -68,87 +75,130 @@ __device__ int64_t block_count(int64_t v, int64_t *red) {
     return t;
 }
 
-// Scan bins from the top until `need` is reached: returns the digit, and the
-// rank still needed inside that bin.  Runs in thread 0.
-__device__ void pick_digit(const uint32_t *h, int bins, int64_t need, int &digit, int64_t &need_in) {
-    int64_t acc = 0;
-    digit = 0;
-    need_in = need;
-    for (int d = bins - 1; d >= 0; --d) {
-        const int64_t c = h[d];
-        if (acc + c >= need) {
-            digit = d;
-            need_in = need - acc;
-            return;
-        }
-        acc += c;
+struct FindShared {
+    int64_t wtot[16];
+    int digit;
+    int64_t need;
+};
+
+// Locate the bin holding the need-th largest value (counting from the top) in
+// histogram h[0..bins); every thread of the block takes part (1024 threads,
+// two bins each).  Result in fs.digit / fs.need (the rank inside that bin).
+__device__ void find_digit(const uint32_t *h, int bins, int64_t need, FindShared &fs) {
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    if (t == 0) {   // defaults (never used when the histogram holds `need` values)
+        fs.digit = 0;
+        fs.need = 1;
     }
+    const int64_t c_lo = (2 * t < bins) ? h[2 * t] : 0;
+    const int64_t c_hi = (2 * t + 1 < bins) ? h[2 * t + 1] : 0;
+    const int64_t v = c_lo + c_hi;
+    // inclusive suffix sum over threads t' >= t
+    int64_t suf = v;
+    for (int o = 1; o < 64; o <<= 1) {
+        const int64_t x = __shfl_down(suf, o);
+        if (lane + o < 64) suf += x;
+    }
+    if (lane == 0) fs.wtot[w] = suf;
+    __syncthreads();
+    int64_t higher = 0;
+    for (int i = w + 1; i < static_cast<int>(blockDim.x >> 6); ++i) higher += fs.wtot[i];
+    const int64_t above = suf - v + higher;   // values in bins above 2t+1
+    if (above < need && need <= above + c_hi) {
+        fs.digit = 2 * t + 1;
+        fs.need = need - above;
+    } else if (above + c_hi < need && need <= above + v) {
+        fs.digit = 2 * t;
+        fs.need = need - above - c_hi;
+    }
+    __syncthreads();
 }
 
-__global__ __launch_bounds__(kMetThreads) void k_met_hist1(const double *__restrict__ ylt, int64_t n, int nwg,
-                                                          uint32_t *__restrict__ hist1, MetPart *__restrict__ part) {
+// Digit pass d over the whole YLT row: histogram of digit d among the values
+// whose higher bits equal the prefix selected so far.  Pass 0 also forms the
+// fixed-partition partial sums for the mean.
+__global__ __launch_bounds__(kMetThreads) void k_met_pass(const double *__restrict__ ylt, int64_t n, int nwg, int d,
+                                                         uint32_t *__restrict__ hist, MetState *__restrict__ st,
+                                                         MetPart *__restrict__ part, int64_t r) {
     __shared__ uint32_t h[kBins];
+    __shared__ FindShared fs;
     __shared__ double red[16];
     const int l = blockIdx.y, wg = blockIdx.x;
+    MetState &S = st[l];
+    uint64_t prefix = 0;
+    int64_t need = r;
+    if (d > 0) {
+        if (S.done) return;
+        const uint32_t *hp = hist + (static_cast<size_t>(d - 1) * gridDim.y + l) * kBins;
+        for (int i = threadIdx.x; i < kBins; i += blockDim.x) h[i] = hp[i];
+        __syncthreads();
+        find_digit(h, 1 << kWidth[d - 1], S.need[d - 1], fs);
+        prefix = (S.prefix[d - 1] << kWidth[d - 1]) | static_cast<uint64_t>(fs.digit);
+        need = fs.need;
+    }
+    if (wg == 0 && threadIdx.x == 0) {
+        S.prefix[d] = prefix;
+        S.need[d] = need;
+        if (d == 0) S.r = r;
+    }
     for (int i = threadIdx.x; i < kBins; i += blockDim.x) h[i] = 0;
     __syncthreads();
+    const int sh = kShift[d], hb = kShift[d] + kWidth[d];
+    const uint32_t mask = (1u << kWidth[d]) - 1u;
     int64_t lo, hi;
     chunk_of(n, nwg, wg, lo, hi);
     const double *y = ylt + static_cast<size_t>(l) * n;
     double s = 0.0;
     for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
         const double v = y[i];
-        s += v;
-        atomicAdd(&h[key_of(v) >> (64 - kDigit)], 1u);
+        const uint64_t u = key_of(v);
+        if (d == 0) s += v;
+        if (hb >= 64 || (u >> hb) == prefix) atomicAdd(&h[(u >> sh) & mask], 1u);
     }
-    const double tot = block_sum(s, red);
-    if (threadIdx.x == 0) part[static_cast<size_t>(l) * nwg + wg].sum = tot;
+    if (d == 0) {
+        const double tot = block_sum(s, red);
+        if (threadIdx.x == 0) part[static_cast<size_t>(l) * nwg + wg].sum = tot;
+    }
+    __syncthreads();
+    uint32_t *hd = hist + (static_cast<size_t>(d) * gridDim.y + l) * kBins;
     for (int i = threadIdx.x; i < kBins; i += blockDim.x)
-        if (h[i]) atomicAdd(&hist1[static_cast<size_t>(l) * kBins + i], h[i]);
+        if (h[i]) atomicAdd(&hd[i], h[i]);
 }
 
-__global__ __launch_bounds__(kMetThreads) void k_met_cand(const double *__restrict__ ylt, int64_t n, int nwg,
-                                                         const uint32_t *__restrict__ hist1, uint32_t *__restrict__ hist2,
-                                                         uint64_t *__restrict__ cand, MetState *__restrict__ st,
-                                                         int64_t r) {
+// After pass 1: if at most kCandCap values share the 23-bit prefix, gather
+// them (one reservation per workgroup) so a single workgroup can finish.
+__global__ __launch_bounds__(kMetThreads) void k_met_collect(const double *__restrict__ ylt, int64_t n, int nwg,
+                                                            const uint32_t *__restrict__ hist, MetState *__restrict__ st,
+                                                            uint64_t *__restrict__ cand) {
     __shared__ uint32_t h[kBins];
-    __shared__ int sd;
-    __shared__ int64_t sneed;
+    __shared__ FindShared fs;
     __shared__ int64_t wcnt[16], wbase[16];
     const int l = blockIdx.y, wg = blockIdx.x;
-    for (int i = threadIdx.x; i < kBins; i += blockDim.x) h[i] = hist1[static_cast<size_t>(l) * kBins + i];
+    MetState &S = st[l];
+    const uint32_t *hp = hist + (static_cast<size_t>(1) * gridDim.y + l) * kBins;
+    for (int i = threadIdx.x; i < kBins; i += blockDim.x) h[i] = hp[i];
     __syncthreads();
-    if (threadIdx.x == 0) {
-        int d;
-        int64_t need_in;
-        pick_digit(h, kBins, r, d, need_in);
-        sd = d;
-        sneed = need_in;
-        if (wg == 0) {
-            st[l].prefix = static_cast<uint64_t>(d);
-            st[l].need = need_in;
-            st[l].r = r;
-        }
-    }
-    __syncthreads();
-    for (int i = threadIdx.x; i < kBins; i += blockDim.x) h[i] = 0;
-    __syncthreads();
-    const uint64_t d1 = static_cast<uint64_t>(sd);
+    find_digit(h, 1 << kWidth[1], S.need[1], fs);
+    const uint64_t prefix = (S.prefix[1] << kWidth[1]) | static_cast<uint64_t>(fs.digit);
+    const int64_t in_bin = h[fs.digit];
+    const bool small = in_bin <= kCandCap;
+    if (wg == 0 && threadIdx.x == 0) S.small = small ? 1 : 0;
+    if (!small) return;
+    const int hb = kShift[1];
     int64_t lo, hi;
     chunk_of(n, nwg, wg, lo, hi);
     const double *y = ylt + static_cast<size_t>(l) * n;
-    uint64_t *c = cand + static_cast<size_t>(l) * n;
+    uint64_t *c = cand + static_cast<size_t>(l) * kCandCap;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    // pass 1: candidates per wavefront; one global reservation per workgroup
     int64_t mine = 0;
-    for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) mine += ((key_of(y[i]) >> (64 - kDigit)) == d1);
+    for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) mine += ((key_of(y[i]) >> hb) == prefix);
     for (int o = 32; o > 0; o >>= 1) mine += __shfl_down(mine, o);
     if (lane == 0) wcnt[w] = mine;
     __syncthreads();
     if (threadIdx.x == 0) {
         int64_t tot = 0;
         for (int i = 0; i < static_cast<int>(blockDim.x >> 6); ++i) tot += wcnt[i];
-        int64_t base = tot ? static_cast<int64_t>(atomicAdd(reinterpret_cast<unsigned long long *>(&st[l].cand_n),
+        int64_t base = tot ? static_cast<int64_t>(atomicAdd(reinterpret_cast<unsigned long long *>(&S.cand_n),
                                                            static_cast<unsigned long long>(tot)))
                            : 0;
         for (int i = 0; i < static_cast<int>(blockDim.x >> 6); ++i) {
@@ -157,79 +207,80 @@ __global__ __launch_bounds__(kMetThreads) void k_met_cand(const double *__restri
         }
     }
     __syncthreads();
-    // pass 2: write them, each wavefront from its own base, in index order
     int64_t off = wbase[w];
     for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
         const uint64_t u = key_of(y[i]);
-        const bool is = (u >> (64 - kDigit)) == d1;
+        const bool is = (u >> hb) == prefix;
         const uint64_t m = __ballot(is);
         if (is) {
             const uint32_t pos = __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(m >> 32),
                                                            __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(m), 0u));
             c[off + pos] = u;
-            atomicAdd(&h[(u >> (64 - 2 * kDigit)) & (kBins - 1)], 1u);
         }
         off += __popcll(m);
     }
-    __syncthreads();
-    for (int i = threadIdx.x; i < kBins; i += blockDim.x)
-        if (h[i]) atomicAdd(&hist2[static_cast<size_t>(l) * kBins + i], h[i]);
 }
 
-// One workgroup per layer: second digit from hist2, remaining digits over the
-// candidate list.
-__global__ __launch_bounds__(kMetThreads) void k_met_select(int64_t n, const uint32_t *__restrict__ hist2,
-                                                           const uint64_t *__restrict__ cand, MetState *__restrict__ st) {
+// One workgroup per layer finishes digits 2..5 on the collected candidates.
+__global__ __launch_bounds__(kMetThreads) void k_met_small(const uint32_t *__restrict__ hist, MetState *__restrict__ st,
+                                                          const uint64_t *__restrict__ cand) {
+    __shared__ uint64_t cs[kCandCap];
     __shared__ uint32_t h[kBins];
-    __shared__ uint64_t sprefix;
-    __shared__ int64_t sneed;
+    __shared__ FindShared fs;
     const int l = blockIdx.x;
-    const uint64_t *c = cand + static_cast<size_t>(l) * n;
-    const int64_t cn = st[l].cand_n;
-    for (int i = threadIdx.x; i < kBins; i += blockDim.x) h[i] = hist2[static_cast<size_t>(l) * kBins + i];
+    MetState &S = st[l];
+    if (!S.small) return;
+    const int64_t cn = S.cand_n;
+    for (int64_t i = threadIdx.x; i < cn; i += blockDim.x) cs[i] = cand[static_cast<size_t>(l) * kCandCap + i];
+    const uint32_t *hp = hist + (static_cast<size_t>(1) * gridDim.x + l) * kBins;
+    for (int i = threadIdx.x; i < kBins; i += blockDim.x) h[i] = hp[i];
     __syncthreads();
-    if (threadIdx.x == 0) {
-        int d;
-        int64_t need_in;
-        pick_digit(h, kBins, st[l].need, d, need_in);
-        sprefix = (st[l].prefix << kDigit) | static_cast<uint64_t>(d);
-        sneed = need_in;
-    }
-    __syncthreads();
-    int known = 2 * kDigit;   // high bits fixed so far
-    while (known < 64) {
-        const int width = std::min(kDigit, 64 - known);
-        const int shift = 64 - known - width;
-        const uint64_t prefix = sprefix;
+    find_digit(h, 1 << kWidth[1], S.need[1], fs);
+    uint64_t prefix = (S.prefix[1] << kWidth[1]) | static_cast<uint64_t>(fs.digit);
+    int64_t need = fs.need;
+    for (int d = 2; d < kPassesMet; ++d) {
         for (int i = threadIdx.x; i < kBins; i += blockDim.x) h[i] = 0;
         __syncthreads();
+        const int sh = kShift[d], hb = kShift[d] + kWidth[d];
+        const uint32_t mask = (1u << kWidth[d]) - 1u;
         for (int64_t i = threadIdx.x; i < cn; i += blockDim.x) {
-            const uint64_t u = c[i];
-            if ((u >> (64 - known)) == prefix) atomicAdd(&h[(u >> shift) & ((1u << width) - 1u)], 1u);
+            const uint64_t u = cs[i];
+            if ((u >> hb) == prefix) atomicAdd(&h[(u >> sh) & mask], 1u);
         }
         __syncthreads();
-        if (threadIdx.x == 0) {
-            int d;
-            int64_t need_in;
-            pick_digit(h, 1 << width, sneed, d, need_in);
-            sprefix = (prefix << width) | static_cast<uint64_t>(d);
-            sneed = need_in;
-        }
-        __syncthreads();
-        known += width;
+        find_digit(h, 1 << kWidth[d], need, fs);
+        prefix = (prefix << kWidth[d]) | static_cast<uint64_t>(fs.digit);
+        need = fs.need;
     }
     if (threadIdx.x == 0) {
-        st[l].thr_bits = sprefix;
-        st[l].thr = __longlong_as_double(static_cast<long long>(sprefix));
+        S.thr = __longlong_as_double(static_cast<long long>(prefix));
+        S.done = 1;
     }
 }
 
+// Counts and sum above the PML value (fixed partition, fixed-order trees).
 __global__ __launch_bounds__(kMetThreads) void k_met_tail(const double *__restrict__ ylt, int64_t n, int nwg,
-                                                         const MetState *__restrict__ st, MetPart *__restrict__ part) {
+                                                         const uint32_t *__restrict__ hist, MetState *__restrict__ st,
+                                                         MetPart *__restrict__ part) {
+    __shared__ uint32_t h[kBins];
+    __shared__ FindShared fs;
     __shared__ double red[16];
     __shared__ int64_t redi[16];
     const int l = blockIdx.y, wg = blockIdx.x;
-    const double thr = st[l].thr;
+    MetState &S = st[l];
+    double thr;
+    if (S.done) {
+        thr = S.thr;
+    } else {
+        const int d = kPassesMet - 1;
+        const uint32_t *hp = hist + (static_cast<size_t>(d) * gridDim.y + l) * kBins;
+        for (int i = threadIdx.x; i < kBins; i += blockDim.x) h[i] = hp[i];
+        __syncthreads();
+        find_digit(h, 1 << kWidth[d], S.need[d], fs);
+        const uint64_t bits = (S.prefix[d] << kWidth[d]) | static_cast<uint64_t>(fs.digit);
+        thr = __longlong_as_double(static_cast<long long>(bits));
+        if (wg == 0 && threadIdx.x == 0) S.thr = thr;
+    }
     int64_t lo, hi;
     chunk_of(n, nwg, wg, lo, hi);
     const double *y = ylt + static_cast<size_t>(l) * n;
@@ -327,11 +378,10 @@ static size_t met_bytes(int32_t L, int64_t n) {
     const int nwg = met_nwg(n);
     Carver c(nullptr);
     c.take<int32_t>(kWsHeaderBytes / 4);
-    c.take<uint32_t>(static_cast<size_t>(L) * kBins);
-    c.take<uint32_t>(static_cast<size_t>(L) * kBins);
+    c.take<uint32_t>(static_cast<size_t>(kPassesMet) * L * kBins);
     c.take<MetState>(static_cast<size_t>(L));
     c.take<MetPart>(static_cast<size_t>(L) * nwg);
-    c.take<uint64_t>(static_cast<size_t>(L) * n);
+    c.take<uint64_t>(static_cast<size_t>(L) * kCandCap);
     return c.bytes();
 }
 
@@ -355,12 +405,11 @@ extern "C" int32_t ara_metrics(const double *ylt, int32_t n_layers, int64_t n, d
     const int nwg = met_nwg(n);
     Carver c(ws);
     int32_t *hdr = c.take<int32_t>(kWsHeaderBytes / 4);
-    uint32_t *hist1 = c.take<uint32_t>(static_cast<size_t>(n_layers) * kBins);
-    uint32_t *hist2 = c.take<uint32_t>(static_cast<size_t>(n_layers) * kBins);
+    uint32_t *hist = c.take<uint32_t>(static_cast<size_t>(kPassesMet) * n_layers * kBins);
     MetState *state = c.take<MetState>(static_cast<size_t>(n_layers));
     MetPart *part = c.take<MetPart>(static_cast<size_t>(n_layers) * nwg);
-    uint64_t *cand = c.take<uint64_t>(static_cast<size_t>(n_layers) * n);
-    // header, both histograms and the states are contiguous: clear them at once
+    uint64_t *cand = c.take<uint64_t>(static_cast<size_t>(n_layers) * kCandCap);
+    // header, histograms and states are contiguous: clear them at once
     const size_t clear = reinterpret_cast<char *>(part) - reinterpret_cast<char *>(hdr);
     ARA_HIP(hipMemsetAsync(hdr, 0, clear, st));
     if (n_layers == 0) return ARA_OK;
@@ -368,10 +417,12 @@ extern "C" int32_t ara_metrics(const double *ylt, int32_t n_layers, int64_t n, d
     r = std::max<int64_t>(1, std::min<int64_t>(n, r));
     dim3 grid(static_cast<unsigned>(nwg), static_cast<unsigned>(n_layers));
     ProfScope prof(ARA_PROF_METRICS, st);
-    k_met_hist1<<<grid, kMetThreads, 0, st>>>(ylt, n, nwg, hist1, part);
-    k_met_cand<<<grid, kMetThreads, 0, st>>>(ylt, n, nwg, hist1, hist2, cand, state, r);
-    k_met_select<<<n_layers, kMetThreads, 0, st>>>(n, hist2, cand, state);
-    k_met_tail<<<grid, kMetThreads, 0, st>>>(ylt, n, nwg, state, part);
+    k_met_pass<<<grid, kMetThreads, 0, st>>>(ylt, n, nwg, 0, hist, state, part, r);
+    k_met_pass<<<grid, kMetThreads, 0, st>>>(ylt, n, nwg, 1, hist, state, part, r);
+    k_met_collect<<<grid, kMetThreads, 0, st>>>(ylt, n, nwg, hist, state, cand);
+    k_met_small<<<n_layers, kMetThreads, 0, st>>>(hist, state, cand);
+    for (int d = 2; d < kPassesMet; ++d) k_met_pass<<<grid, kMetThreads, 0, st>>>(ylt, n, nwg, d, hist, state, part, r);
+    k_met_tail<<<grid, kMetThreads, 0, st>>>(ylt, n, nwg, hist, state, part);
     k_met_final<<<n_layers, kMetThreads, 0, st>>>(n, nwg, part, state, out);
     if (weights) {
         const unsigned gx = static_cast<unsigned>(std::min<int64_t>((n + 255) / 256, 4096));

@@ -24,6 +24,9 @@ struct OccTables {
     double *vals;       // [n_sr][kSr]
     uint8_t *cnt;       // [n_sr][kSr] or null
     int32_t *count;     // [n_sr]
+    uint32_t *bits;     // [n_sr][kSrWords]  set-event bitmap (phase one)
+    double *dense;      // [n_sr][kSr]       O by event (phase one; set events only)
+    uint8_t *dense_nb;  // [n_sr][kSr]       ELT count by event (hits mode)
 };
 
 // min(max(v - R, 0), L), evaluated exactly as the oracle does: a separately
@@ -38,7 +41,7 @@ __device__ __forceinline__ double xl(double v, double r, double lim) {
 struct OccLayoutSizes {
     int n_sr;
     size_t per_layer;
-    size_t br, vals, cnt, count;
+    size_t br, vals, cnt, count, bits, dense, dense_nb;
 };
 
 inline OccLayoutSizes occ_sizes(int32_t catalog, bool with_cnt) {
@@ -48,7 +51,10 @@ inline OccLayoutSizes occ_sizes(int32_t catalog, bool with_cnt) {
     z.vals = align256(static_cast<size_t>(z.n_sr) * kSr * sizeof(double));
     z.cnt = with_cnt ? align256(static_cast<size_t>(z.n_sr) * kSr) : 0;
     z.count = align256(static_cast<size_t>(z.n_sr) * sizeof(int32_t));
-    z.per_layer = z.br + z.vals + z.cnt + z.count;
+    z.bits = align256(static_cast<size_t>(z.n_sr) * kSrWords * sizeof(uint32_t));
+    z.dense = align256(static_cast<size_t>(z.n_sr) * kSr * sizeof(double));
+    z.dense_nb = with_cnt ? align256(static_cast<size_t>(z.n_sr) * kSr) : 0;
+    z.per_layer = z.br + z.vals + z.cnt + z.count + z.bits + z.dense + z.dense_nb;
     return z;
 }
 
@@ -58,8 +64,27 @@ inline OccTables occ_carve(Carver &c, const OccLayoutSizes &z, bool with_cnt) {
     t.vals = c.take<double>(static_cast<size_t>(z.n_sr) * kSr);
     t.cnt = with_cnt ? c.take<uint8_t>(static_cast<size_t>(z.n_sr) * kSr) : nullptr;
     t.count = c.take<int32_t>(static_cast<size_t>(z.n_sr));
+    t.bits = c.take<uint32_t>(static_cast<size_t>(z.n_sr) * kSrWords);
+    t.dense = c.take<double>(static_cast<size_t>(z.n_sr) * kSr);
+    t.dense_nb = with_cnt ? c.take<uint8_t>(static_cast<size_t>(z.n_sr) * kSr) : nullptr;
     return t;
 }
+
+// One unit of forward work: one layer over one block of trials, with the
+// trial range [t0, t1) whose outputs are written (row bases indexed t - t0).
+struct FwdItem {
+    const OccTables *tab;      // device pointer to the layer's occurrence tables
+    const double *lterm;       // device pointer to the layer's (OccR, OccL, AggR, AggL)
+    int32_t block;
+    int32_t pad;
+    int64_t t0, t1;
+    double *ylt;
+    double *s_pre;             // or null
+    int32_t *hits;             // or null
+};
+
+// Enqueue the forward streaming kernel over a device array of items.
+int32_t launch_forward(const ara_yet *yet, int n_sr, bool hits, const FwdItem *d_items, int n_items, hipStream_t st);
 
 // Validates the layer list on the host; returns ARA_OK or an error.
 int32_t check_layers(const ara_layers *layers, int32_t n_elts);

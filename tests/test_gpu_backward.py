@@ -1,0 +1,207 @@
+"""Parity of the HIP backward (reverse sweep of Algorithm 1) against the
+oracle's literal reverse sweep, plus properties that hold at full size:
+Euler's identity for the positively homogeneous metrics, the aggregate-term
+gradients as counts, central differences for the aggregate terms, bitwise
+repeatability.  Gradients: 1e-9 relative to the largest magnitude of the
+row (the sums are of same-sign terms except where a cotangent mixes signs).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from _indep import load_hand_example
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-9
+
+
+def _say(msg):
+    print(f"[gpu-backward] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ara():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_1308_2572_amd as ara
+    ara.library()
+    return ara
+
+
+class Engine:
+    def __init__(self, ara, w, device="cuda"):
+        import torch
+        self.ara, self.w = ara, w
+        self.tables = ara.EltTables.from_numpy(w.elts, device)
+        self.yet = ara.PreparedYet.from_numpy(w.yet, device)
+        self.layers = ara.Layers(w.layers.elt_off, w.layers.elt_ids)
+        self.et = torch.tensor(w.elts.terms, dtype=torch.float64, device=device)
+        self.lt = torch.tensor(w.layers.terms, dtype=torch.float64, device=device)
+
+    def forward(self, t0=0, t1=None, et=None, lt=None):
+        return self.ara.ylt_forward(self.tables, self.yet, self.layers, self.et if et is None else et,
+                                    self.lt if lt is None else lt, t0, t1, want_s_pre=True, check=True)
+
+    def backward(self, s_pre, cot, t0=0, t1=None, et=None, lt=None):
+        import torch
+        c = torch.tensor(cot, dtype=torch.float64, device="cuda") if isinstance(cot, np.ndarray) else cot
+        ge, gl = self.ara.ylt_backward(self.tables, self.yet, self.layers, self.et if et is None else et,
+                                       self.lt if lt is None else lt, s_pre, c, t0, t1)
+        return ge.cpu().numpy(), gl.cpu().numpy()
+
+
+def close(got, ref, tol=TOL):
+    scale = np.maximum(np.abs(ref).max(axis=tuple(range(1, ref.ndim)), keepdims=True), 1e-300)
+    err = np.abs(got - ref) / scale
+    assert err.max() <= tol, f"max scaled error {err.max():.3e}"
+
+
+def test_hand_example_gradients(ara):
+    w, g = load_hand_example()
+    e = Engine(ara, w)
+    ylt, s_pre, _ = e.forward()
+    _, wts = ara.metrics(ylt, g["grad_p"], want_weights=True)
+    ge, gl = e.backward(s_pre, wts)
+    for i, name in enumerate(["aal", "pml", "tvar"]):
+        np.testing.assert_allclose(ge[i], np.array(g["grad"][name]["elt"]), rtol=0, atol=1e-12)
+        np.testing.assert_allclose(gl[i, 0], np.array(g["grad"][name]["layer"]), rtol=0, atol=1e-12)
+
+
+@pytest.mark.parametrize("seed", range(10))
+def test_tiny_random_vs_oracle_sweep(ara, seed):
+    w = synth.tiny_random(seed + 40, n_trials=60 + 17 * seed, max_events=25, catalog=48 + 61 * seed, n_layers=3)
+    _say(f"tiny seed {seed}")
+    e = Engine(ara, w)
+    ylt, s_pre, _ = e.forward()
+    tb = oracle.build_tables(w.elts)
+    ref = oracle.forward(tb, w.yet, w.layers, w.elts.terms, w.layers.terms)
+    g = np.random.default_rng(seed)
+    cots = np.concatenate([oracle.metric_weights(ref["ylt"], w.p),
+                           g.normal(size=(1,) + ref["ylt"].shape)], axis=0)     # 4 rows, one of mixed sign
+    ge, gl = e.backward(s_pre, cots)
+    rge, rgl = oracle.backward(tb, w.yet, w.layers, w.elts.terms, w.layers.terms, cots)
+    close(ge, rge)
+    close(gl, rgl)
+
+
+def test_trial_subrange_vs_oracle(ara):
+    w = synth.config(2, n_trials=6000)
+    e = Engine(ara, w)
+    t0, t1 = 1234, 5000
+    ylt, s_pre, _ = e.forward(t0, t1)
+    tb = oracle.build_tables(w.elts)
+    ref = oracle.forward(tb, w.yet, w.layers, w.elts.terms, w.layers.terms, t0, t1, n_threads=8)
+    cot = oracle.metric_weights(ref["ylt"], 0.9)
+    ge, gl = e.backward(s_pre, cot, t0, t1)
+    rge, rgl = oracle.backward(tb, w.yet, w.layers, w.elts.terms, w.layers.terms, cot, t0, t1)
+    close(ge, rge)
+    close(gl, rgl)
+
+
+def test_config0_all_capped(ara):
+    """Every trial of the 10k x 1000 case exceeds the aggregate limit: only
+    the aggregate limit has a non-zero AAL gradient (= 1)."""
+    w = synth.config(0)
+    e = Engine(ara, w)
+    ylt, s_pre, _ = e.forward()
+    _, wts = ara.metrics(ylt, w.p, want_weights=True)
+    ge, gl = e.backward(s_pre, wts)
+    assert np.all(ge[0] == 0.0)
+    assert gl[0, 0].tolist() == [0.0, 0.0, 0.0, 1.0]
+
+
+def _euler(ara, e, ge, gl, m, w):
+    for c in range(3):
+        tot = 0.0
+        for k in range(w.elts.n_elts):
+            for col in range(3):
+                if np.isfinite(w.elts.terms[k, col]):
+                    tot += w.elts.terms[k, col] * ge[c, k, col]
+        for col in range(4):
+            if np.isfinite(w.layers.terms[0, col]):
+                tot += w.layers.terms[0, col] * gl[c, 0, col]
+        assert abs(tot - m[c]) <= 1e-9 * abs(m[c]), (c, tot, m[c])
+
+
+def test_config3_prefix_vs_oracle_and_euler(ara):
+    _say("workload 3 prefix (30k trials)")
+    w = synth.config(3, n_trials=30_000)
+    e = Engine(ara, w)
+    ylt, s_pre, _ = e.forward()
+    m, wts = ara.metrics(ylt, w.p, want_weights=True)
+    ge, gl = e.backward(s_pre, wts)
+    tb = oracle.build_tables(w.elts)
+    ref = oracle.forward(tb, w.yet, w.layers, w.elts.terms, w.layers.terms, n_threads=8)
+    rge, rgl = oracle.backward(tb, w.yet, w.layers, w.elts.terms, w.layers.terms,
+                               oracle.metric_weights(ref["ylt"], w.p))
+    close(ge, rge)
+    close(gl, rgl)
+    _euler(ara, e, ge, gl, m.cpu().numpy()[0], w)
+
+
+def test_config3_full_size_properties(ara):
+    """1M x 1000 x 15 with perturbed terms: Euler's identity, aggregate-term
+    gradients as counts, central differences for AggR and AggL (a kink-sparse
+    direction), and a bitwise-identical second run."""
+    import torch
+    _say("workload 3 full size")
+    w = synth.config(3)
+    e = Engine(ara, w)
+    ylt, s_pre, _ = e.forward()
+    m, wts = ara.metrics(ylt, w.p, want_weights=True)
+    ge, gl = e.backward(s_pre, wts)
+    ge2, gl2 = e.backward(s_pre, wts)
+    assert np.array_equal(ge, ge2) and np.array_equal(gl, gl2)
+    mm = m.cpu().numpy()[0]
+    _euler(ara, e, ge, gl, mm, w)
+    S = s_pre.cpu().numpy()[0]
+    aggR, aggL = w.layers.terms[0, 2], w.layers.terms[0, 3]
+    z = S - aggR
+    a = np.where(z > 0, z, 0.0)
+    n = S.shape[0]
+    assert gl[0, 0, 2] == pytest.approx(-np.count_nonzero((z > 0) & (a < aggL)) / n, rel=1e-12)
+    assert gl[0, 0, 3] == pytest.approx(np.count_nonzero(a >= aggL) / n, rel=1e-12, abs=1e-15)
+    for col in (2, 3):
+        h = 1e-4 * w.layers.terms[0, col]
+        vals = []
+        for sgn in (+1, -1):
+            lt = e.lt.clone()
+            lt[0, col] += sgn * h
+            y2, _, _ = e.forward(lt=lt)
+            vals.append(ara.metrics(y2, w.p)[0].cpu().numpy()[0])
+        fd = (vals[0] - vals[1]) / (2 * h)
+        for c in range(3):
+            scale = max(abs(fd[c]), abs(gl[c, 0, col]), 1e-12)
+            assert abs(fd[c] - gl[c, 0, col]) <= 2e-2 * scale + 1e-9, (col, c, fd[c], gl[c, 0, col])
+
+
+def test_autograd_matches_direct_call(ara):
+    import torch
+    w = synth.config(2, n_trials=3000)
+    e = Engine(ara, w)
+    et = e.et.clone().requires_grad_(True)
+    lt = e.lt.clone().requires_grad_(True)
+    ylt = ara.YLT.apply(et, lt, (e.tables, e.yet, e.layers, 0, w.yet.n_trials))
+    m = ara.Metrics.apply(ylt, 0.95)
+    coef = torch.tensor([[1.0, 0.5, 2.0]] * w.layers.n_layers, dtype=torch.float64, device="cuda")
+    (m * coef).sum().backward()
+    y, s, _ = e.forward()
+    _, wts = ara.metrics(y, 0.95, want_weights=True)
+    cot = (coef[:, 0:1] * wts[0] + coef[:, 1:2] * wts[1] + coef[:, 2:3] * wts[2]).contiguous()
+    ge, gl = e.backward(s, cot)
+    np.testing.assert_allclose(et.grad.cpu().numpy(), ge, rtol=1e-12, atol=1e-15)
+    np.testing.assert_allclose(lt.grad.cpu().numpy(), gl, rtol=1e-12, atol=1e-15)
+
+
+def test_cotangent_row_limit(ara):
+    import torch
+    w = synth.tiny_random(3)
+    e = Engine(ara, w)
+    _, s_pre, _ = e.forward()
+    with pytest.raises(ara.AraError) as ex:
+        e.backward(s_pre, torch.zeros((5, w.layers.n_layers, w.yet.n_trials), dtype=torch.float64, device="cuda"))
+    assert ex.value.status == 6
