@@ -353,8 +353,8 @@ class QuoteServer:
             lib.ara_server_poll(self.handle, ticket, ctypes.byref(r))
         if rc == ARA_E_BUSY:
             return None
-        _check(rc, "ara_server_wait" if blocking else "ara_server_poll")
         del self._keep[ticket]
+        _check(rc, "ara_server_wait" if blocking else "ara_server_poll")
         out = {"metrics": np.array(r.metrics[:]), "t_submit_ms": r.t_submit_ms, "t_admit_ms": r.t_admit_ms,
                "t_done_ms": r.t_done_ms}
         if want_grad:
@@ -373,7 +373,6 @@ class QuoteServer:
         if rc == ARA_E_BUSY:
             return False
         _check(rc, "ara_server_cancel")
-        self._keep.pop(ticket, None)
         return True
 
     def stats(self):

@@ -404,7 +404,10 @@ extern "C" int32_t ara_server_poll(void *server, int64_t ticket, ara_quote_resul
     auto it = S->jobs.find(ticket);
     if (it == S->jobs.end()) return fail(ARA_E_RANGE, "unknown ticket");
     const Job &j = *it->second;
-    if (j.stage == kCancelled) return fail(ARA_E_INVAL, "quote was cancelled");
+    if (j.stage == kCancelled) {
+        S->jobs.erase(it);
+        return fail(ARA_E_INVAL, "quote was cancelled");
+    }
     if (j.stage != kDone) return ARA_E_BUSY;
     fill_result(S, j, out);
     S->jobs.erase(it);
@@ -419,7 +422,10 @@ extern "C" int32_t ara_server_wait(void *server, int64_t ticket, ara_quote_resul
     if (it == S->jobs.end()) return fail(ARA_E_RANGE, "unknown ticket");
     std::shared_ptr<Job> j = it->second;
     S->cv_done.wait(lk, [&] { return j->stage == kDone || j->stage == kCancelled || S->fatal != ARA_OK; });
-    if (j->stage == kCancelled) return fail(ARA_E_INVAL, "quote was cancelled");
+    if (j->stage == kCancelled) {
+        S->jobs.erase(j->ticket);
+        return fail(ARA_E_INVAL, "quote was cancelled");
+    }
     if (j->stage != kDone) return fail(S->fatal, "server stopped after a device error");
     fill_result(S, *j, out);
     S->jobs.erase(j->ticket);

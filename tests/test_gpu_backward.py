@@ -111,7 +111,8 @@ def test_config0_all_capped(ara):
     _, wts = ara.metrics(ylt, w.p, want_weights=True)
     ge, gl = e.backward(s_pre, wts)
     assert np.all(ge[0] == 0.0)
-    assert gl[0, 0].tolist() == [0.0, 0.0, 0.0, 1.0]
+    assert gl[0, 0, :3].tolist() == [0.0, 0.0, 0.0]
+    assert gl[0, 0, 3] == pytest.approx(1.0, rel=1e-12)     # sum of 10,000 weights of 1e-4
 
 
 def _euler(ara, e, ge, gl, m, w):
