@@ -20,7 +20,9 @@ constexpr int kMaxTrialsPerBlock = kGroups * kMaxTrialsPerGroup;   // 4096
 constexpr int kSrBits = 16;                    // one occurrence-table "super-range" = 2 ranges
 constexpr int kSr = 1 << kSrBits;
 constexpr int kSrWords = kSr / 32;             // 2048 bitmap words per super-range
-constexpr uint32_t kSentinel = 0xFFFFFFFFu;
+// Padding entry of a block with `tb` trials: trial slot tb (one past the
+// block's trials) and event 0 of the range.
+__host__ __device__ inline uint32_t pad_entry(int tb) { return static_cast<uint32_t>(tb) << kRangeBits; }
 constexpr int kWave = 64;
 
 // Error word kept at the head of every workspace.

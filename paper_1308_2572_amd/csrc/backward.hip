@@ -153,7 +153,14 @@ struct BwdStream {
     size_t wg_stride;             // n_sr * kSr
 };
 
-// (4) W(e) += v_t for every occurrence (t, e) of a hot event.
+// (4) W(e) += v_t for every occurrence (t, e) of a hot event.  The blocks of
+// one part are processed in phases of half a block (8 trial groups): the
+// weights of the next phase are loaded into registers while the current one
+// streams, and each wavefront prefetches the first entries of its next
+// segment before the phase barrier.
+constexpr int kBwdUnroll = 16;
+constexpr int kVqRegs = 8;   // n_cot * 8 * tg / 1024 <= 4 * 2048 / 1024
+
 __global__ __launch_bounds__(kBwdThreads) void k_bwd_stream(BwdStream P) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int half_trials = 8 * P.tg;
@@ -183,60 +190,114 @@ __global__ __launch_bounds__(kBwdThreads) void k_bwd_stream(BwdStream P) {
     const size_t cstride = static_cast<size_t>(P.n_parts) * P.wg_stride;
     for (int c = 0; c < P.n_cot; ++c)
         for (uint32_t i = inl + tid; i < hot; i += blockDim.x) wgp[c * cstride + i] = 0;
-    __syncthreads();
 
     const int nb = P.b_hi - P.b_lo;
     const int per = (nb + P.n_parts - 1) / P.n_parts;
     const int pb0 = P.b_lo + part * per, pb1 = min(P.b_hi, pb0 + per);
+    const int nph = 2 * max(0, pb1 - pb0);
     const int G = P.n_ranges;
-    for (int b = pb0; b < pb1; ++b) {
-        for (int h = 0; h < 2; ++h) {
-            __syncthreads();
-            const int64_t tfirst = static_cast<int64_t>(b) * P.tb + static_cast<int64_t>(8 * h) * P.tg;
-            for (int c = 0; c < P.n_cot; ++c) {
-                const int64_t *vr = P.vq + (static_cast<size_t>(c) * P.n_layers + j) * P.n;
-                for (int i = tid; i < half_trials; i += blockDim.x) {
-                    const int64_t t = tfirst + i;
-                    vql[c * half_trials + i] = (t >= P.t0 && t < P.t1) ? vr[t - P.t0] : 0;
-                }
-            }
-            __syncthreads();
-            // wave w: segment of group 8h + w/2, odd/even half of its steps
-            const int g = 8 * h + (w >> 1);
-            const size_t si = (static_cast<size_t>(b) * G + r) * kGroups + g;
-            const int R = P.seg_run[si];
-            const int64_t sb = P.seg_base[si];
-            const int mid = (R + 1) >> 1;
-            const int s0 = (w & 1) ? mid : 0, s1 = (w & 1) ? R : mid;
-            const uint32_t tl0 = static_cast<uint32_t>(8 * h) * P.tg;
-            for (int st = s0; st < s1; st += 8) {
-                uint32_t X[8];
+    const int nv = P.n_cot * half_trials;
+
+    // weights of phase q into registers
+    int64_t vreg[kVqRegs];
+    auto load_vq = [&](int q) {
+        const int64_t tfirst = static_cast<int64_t>(pb0 + q / 2) * P.tb + static_cast<int64_t>(8 * (q & 1)) * P.tg;
 #pragma unroll
-                for (int u = 0; u < 8; ++u)
-                    X[u] = (st + u < s1) ? __builtin_nontemporal_load(P.ent + sb + static_cast<int64_t>(st + u) * kWave + lane)
-                                         : kSentinel;
-#pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    const uint32_t e = X[u];
-                    if (e == kSentinel) continue;
-                    const uint32_t loc = e & (kRange - 1);
-                    const uint2 q = tbr[loc >> 5];
-                    const uint32_t bit = loc & 31;
-                    if (!((q.x >> bit) & 1u)) continue;
-                    const uint32_t rk = q.y + __popc(q.x & ((1u << bit) - 1u));
-                    const uint32_t ti = (e >> kRangeBits) - tl0;
-                    for (int c = 0; c < P.n_cot; ++c) {
-                        const int64_t v = vql[c * half_trials + ti];
-                        if (v == 0) continue;
-                        if (rk < static_cast<uint32_t>(P.capw))
-                            atomicAdd(&wl[c * P.capw + rk], static_cast<unsigned long long>(v));
-                        else
-                            atomicAdd(reinterpret_cast<unsigned long long *>(&wgp[c * cstride + rk]),
-                                      static_cast<unsigned long long>(v));
-                    }
-                }
+        for (int k = 0; k < kVqRegs; ++k) {
+            const int idx = tid + k * kBwdThreads;
+            int64_t v = 0;
+            if (idx < nv) {
+                const int c = idx / half_trials, i = idx - c * half_trials;
+                const int64_t t = tfirst + i;
+                if (t >= P.t0 && t < P.t1) v = P.vq[(static_cast<size_t>(c) * P.n_layers + j) * P.n + (t - P.t0)];
             }
+            vreg[k] = v;
         }
+    };
+    // this wavefront's share of phase q: half the steps of one segment
+    auto meta = [&](int q, int64_t &sbq, int &a, int &bnd) {
+        const int bq = pb0 + q / 2, g = 8 * (q & 1) + (w >> 1);
+        const size_t si = (static_cast<size_t>(bq) * G + r) * kGroups + g;
+        const int R = P.seg_run[si];
+        sbq = P.seg_base[si];
+        const int mid = (R + 1) >> 1;
+        a = (w & 1) ? mid : 0;
+        bnd = (w & 1) ? R : mid;
+    };
+    const uint32_t pad = pad_entry(P.tb);
+    uint32_t X[kBwdUnroll];
+    auto chunk = [&](int64_t sbq, int from, int to) {
+#pragma unroll
+        for (int u = 0; u < kBwdUnroll; ++u)
+            X[u] = (from + u < to) ? __builtin_nontemporal_load(P.ent + sbq + static_cast<int64_t>(from + u) * kWave + lane)
+                                   : pad;
+    };
+    const bool all_lds = hot <= static_cast<uint32_t>(P.capw);   // uniform over the workgroup
+
+    int64_t sb_c = 0, sb_n = 0;
+    int a_c = 0, b_c = 0, a_n = 0, b_n = 0;
+    if (nph > 0) {
+        meta(0, sb_c, a_c, b_c);
+        chunk(sb_c, a_c, b_c);
+        load_vq(0);
+    }
+    for (int ph = 0; ph < nph; ++ph) {
+        if (ph + 1 < nph) meta(ph + 1, sb_n, a_n, b_n);
+        __syncthreads();   // every wave is done with the previous phase's weights
+#pragma unroll
+        for (int k = 0; k < kVqRegs; ++k) {
+            const int idx = tid + k * kBwdThreads;
+            if (idx < nv) vql[idx] = vreg[k];
+        }
+        __syncthreads();
+        if (ph + 1 < nph) load_vq(ph + 1);
+        const uint32_t tl0 = static_cast<uint32_t>(8 * (ph & 1)) * P.tg;
+        int st = a_c;
+        bool prefetched_next = false;
+        while (st < b_c) {
+            uint32_t Y[kBwdUnroll];
+#pragma unroll
+            for (int u = 0; u < kBwdUnroll; ++u) Y[u] = X[u];
+            const int nst = st + kBwdUnroll;
+            if (nst < b_c) {
+                chunk(sb_c, nst, b_c);
+            } else if (ph + 1 < nph) {
+                chunk(sb_n, a_n, b_n);
+                prefetched_next = true;
+            }
+            // branch-free lookups of all entries, then the masked accumulation
+            uint2 q[kBwdUnroll];
+#pragma unroll
+            for (int u = 0; u < kBwdUnroll; ++u) q[u] = tbr[(Y[u] & (kRange - 1)) >> 5];
+            uint32_t rk[kBwdUnroll], ti[kBwdUnroll];
+            bool on[kBwdUnroll];
+#pragma unroll
+            for (int u = 0; u < kBwdUnroll; ++u) {
+                const uint32_t bit = Y[u] & 31;
+                ti[u] = (Y[u] >> kRangeBits) - tl0;
+                on[u] = ((q[u].x >> bit) & 1u) && ti[u] < static_cast<uint32_t>(half_trials);   // padding is off
+                rk[u] = q[u].y + __popc(q[u].x & ((1u << bit) - 1u));
+            }
+            for (int c = 0; c < P.n_cot; ++c) {
+                int64_t v[kBwdUnroll];
+#pragma unroll
+                for (int u = 0; u < kBwdUnroll; ++u) v[u] = vql[c * half_trials + (on[u] ? ti[u] : 0)];
+#pragma unroll
+                for (int u = 0; u < kBwdUnroll; ++u) {
+                    if (!(on[u] && v[u] != 0)) continue;
+                    if (all_lds || rk[u] < static_cast<uint32_t>(P.capw))
+                        atomicAdd(&wl[c * P.capw + rk[u]], static_cast<unsigned long long>(v[u]));
+                    else
+                        atomicAdd(reinterpret_cast<unsigned long long *>(&wgp[c * cstride + rk[u]]),
+                                  static_cast<unsigned long long>(v[u]));
+                }
+            }
+            st = nst;
+        }
+        if (!prefetched_next && ph + 1 < nph) chunk(sb_n, a_n, b_n);
+        sb_c = sb_n;
+        a_c = a_n;
+        b_c = b_n;
     }
     __syncthreads();
     for (int c = 0; c < P.n_cot; ++c)
@@ -287,7 +348,9 @@ __global__ __launch_bounds__(kBwdThreads) void k_bwd_grad(BwdGrad P) {
     const int64_t ev0 = static_cast<int64_t>(s) * kSr + p * (kChunkWords * 32);
     __syncthreads();
 
-    // the thread's four events: weight per row and occurrence-clamp branch
+    // the thread's four events: weight per row and occurrence-clamp branch.
+    // O = min(max(x - OccR, 0), OccL) is non-zero for these events, and it is
+    // below OccL exactly when the occurrence clamp is in its linear branch.
     double W[4][kMaxCot];
     bool lin_occ[4];
     int local[4];
@@ -301,6 +364,7 @@ __global__ __launch_bounds__(kBwdThreads) void k_bwd_grad(BwdGrad P) {
         for (int c = 0; c < kMaxCot; ++c) W[it][c] = 0.0;
         if (!((q.x >> bit) & 1u)) continue;
         const uint32_t rk = q.y + __popc(q.x & ((1u << bit) - 1u));
+        const double O = T.vals[static_cast<size_t>(s) * kSr + rk];
         for (int c = 0; c < P.n_cot; ++c) {
             const int64_t *wc = P.wg + (static_cast<size_t>(j) * P.n_cot + c) * P.n_parts * P.wg_stride +
                                 static_cast<size_t>(s) * kSr + rk;
@@ -308,22 +372,10 @@ __global__ __launch_bounds__(kBwdThreads) void k_bwd_grad(BwdGrad P) {
             for (int pt = 0; pt < P.n_parts; ++pt) acc += wc[static_cast<size_t>(pt) * P.wg_stride];
             W[it][c] = ldexp(static_cast<double>(acc), -P.vs[j * P.n_cot + c].sigma);
         }
-        // x_e in listed ELT order, as the forward
-        double x = 0.0;
-        for (int qq = 0; qq < J; ++qq) {
-            if ((stage[qq * kChunkWords + wip] >> bit) & 1u) {
-                const double l = static_cast<double>(P.loss[static_cast<size_t>(lk[qq]) * P.catalog + ev0 + local[it]]);
-                const double scaled = ls[qq] * l;
-                x = x + xl(scaled, lr[qq], ll[qq]);
-            }
-        }
-        const double y = x - occR;
-        const double av = (y > 0.0) ? y : 0.0;
-        lin_occ[it] = (y > 0.0) && (av < occL);
-        const bool capo = av >= occL;
+        lin_occ[it] = O < occL;
         for (int c = 0; c < P.n_cot; ++c) {
             if (lin_occ[it]) po[c][0] -= W[it][c];
-            if (capo) po[c][1] += W[it][c];
+            else po[c][1] += W[it][c];
         }
     }
     // occurrence-term partials
@@ -345,12 +397,20 @@ __global__ __launch_bounds__(kBwdThreads) void k_bwd_grad(BwdGrad P) {
     for (int qq = 0; qq < J; ++qq) {
         double pe[kMaxCot][3];
         for (int c = 0; c < kMaxCot; ++c) pe[c][0] = pe[c][1] = pe[c][2] = 0.0;
+        float lv[4];
+        bool on[4];
+#pragma unroll
         for (int it = 0; it < 4; ++it) {
-            if (!lin_occ[it]) continue;
             const int wip = local[it] >> 5, bit = local[it] & 31;
-            if (!((stage[qq * kChunkWords + wip] >> bit) & 1u)) continue;
-            const double l = static_cast<double>(P.loss[static_cast<size_t>(lk[qq]) * P.catalog + ev0 + local[it]]);
-            const double pre = ls[qq] * l - lr[qq];
+            on[it] = lin_occ[it] && ((stage[qq * kChunkWords + wip] >> bit) & 1u);
+            const size_t idx = on[it] ? static_cast<size_t>(lk[qq]) * P.catalog + ev0 + local[it] : 0;
+            lv[it] = P.loss[idx];   // element 0 (always valid) for events without the ELT
+        }
+        for (int it = 0; it < 4; ++it) {
+            if (!on[it]) continue;
+            const double l = static_cast<double>(lv[it]);
+            const double scaled = ls[qq] * l;
+            const double pre = scaled - lr[qq];
             const double av = (pre > 0.0) ? pre : 0.0;
             const bool lin = (pre > 0.0) && (av < ll[qq]);
             const bool cap = av >= ll[qq];
@@ -379,34 +439,50 @@ __global__ __launch_bounds__(kBwdThreads) void k_bwd_grad(BwdGrad P) {
     }
 }
 
-// (6) fixed-order sums into the outputs.
-__global__ void k_bwd_final(const int32_t *__restrict__ elt_off, const int32_t *__restrict__ elt_ids, int n_layers,
-                            int n_elts, int n_cot, int n_chunks, int nwg_v, const double *__restrict__ part_elt,
-                            const double *__restrict__ part_occ, const double *__restrict__ aggpart,
-                            double *__restrict__ grad_elt, double *__restrict__ grad_layer) {
-    const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+// (6) fixed-order sums into the outputs: one workgroup per output value,
+// each thread a fixed stride of the partials, then a fixed-order tree.
+__global__ __launch_bounds__(256) void k_bwd_final(const int32_t *__restrict__ elt_off, const int32_t *__restrict__ elt_ids,
+                                                  int n_layers, int n_elts, int n_cot, int n_chunks, int nwg_v,
+                                                  const double *__restrict__ part_elt, const double *__restrict__ part_occ,
+                                                  const double *__restrict__ aggpart, double *__restrict__ grad_elt,
+                                                  double *__restrict__ grad_layer) {
+    __shared__ double red[256];
+    const int o = blockIdx.x, tid = threadIdx.x;
     const int n_e = n_cot * n_elts * 3;
-    if (tid < n_e) {
-        const int c = tid / (n_elts * 3), k = (tid / 3) % n_elts, m = tid % 3;
-        double v = 0.0;
+    double v = 0.0;
+    if (o < n_e) {
+        const int c = o / (n_elts * 3), k = (o / 3) % n_elts, m = o % 3;
         for (int j = 0; j < n_layers; ++j)
             for (int q = elt_off[j]; q < elt_off[j + 1]; ++q) {
                 if (elt_ids[q] != k) continue;
                 const int qq = q - elt_off[j];
-                for (int ch = 0; ch < n_chunks; ++ch)
+                for (int ch = tid; ch < n_chunks; ch += blockDim.x)
                     v += part_elt[(((static_cast<size_t>(j) * n_chunks + ch) * kMaxJ + qq) * n_cot + c) * 3 + m];
             }
-        grad_elt[tid] = v;
-    } else if (tid < n_e + n_cot * n_layers * 4) {
-        const int i = tid - n_e;
+    } else {
+        const int i = o - n_e;
         const int c = i / (n_layers * 4), j = (i / 4) % n_layers, m = i % 4;
-        double v = 0.0;
         if (m < 2) {
-            for (int ch = 0; ch < n_chunks; ++ch) v += part_occ[((static_cast<size_t>(j) * n_chunks + ch) * n_cot + c) * 2 + m];
+            for (int ch = tid; ch < n_chunks; ch += blockDim.x)
+                v += part_occ[((static_cast<size_t>(j) * n_chunks + ch) * n_cot + c) * 2 + m];
         } else {
-            for (int wg = 0; wg < nwg_v; ++wg) v += aggpart[((static_cast<size_t>(j) * n_cot + c) * nwg_v + wg) * 2 + (m - 2)];
+            for (int wg = tid; wg < nwg_v; wg += blockDim.x)
+                v += aggpart[((static_cast<size_t>(j) * n_cot + c) * nwg_v + wg) * 2 + (m - 2)];
         }
-        grad_layer[(static_cast<size_t>(c) * n_layers + j) * 4 + m] = v;
+    }
+    red[tid] = v;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (tid < h) red[tid] += red[tid + h];
+        __syncthreads();
+    }
+    if (tid == 0) {
+        if (o < n_e) grad_elt[o] = red[0];
+        else {
+            const int i = o - n_e;
+            const int c = i / (n_layers * 4), j = (i / 4) % n_layers, m = i % 4;
+            grad_layer[(static_cast<size_t>(c) * n_layers + j) * 4 + m] = red[0];
+        }
     }
 }
 
@@ -428,7 +504,8 @@ static BwdLayout bwd_layout(const ara_tables *tables, const ara_yet *yet, const 
     const int L = layers->n_layers;
     const int nJ = L > 0 ? layers->elt_off[L] : 0;
     const int cu = device_cu_count();
-    B.n_parts = std::max(1, std::min(std::max(yet->n_blocks, 1), (2 * cu + yet->n_ranges - 1) / std::max(yet->n_ranges, 1)));
+    // one workgroup per CU at most (they need all of its LDS): parts = CUs / ranges
+    B.n_parts = std::max(1, std::min(std::max(yet->n_blocks, 1), cu / std::max(yet->n_ranges, 1)));
     B.nwg_v = bwd_nwg_v(n);
     B.n_chunks = B.z.n_sr * kChunks;
     B.wg_stride = static_cast<size_t>(B.z.n_sr) * kSr;
@@ -581,8 +658,8 @@ extern "C" int32_t ara_ylt_backward(const ara_tables *tables, const ara_yet *yet
         ProfScope prof(ARA_PROF_BWD_RED, st);
         k_bwd_grad<<<dim3(B.n_chunks, L), kBwdThreads, 0, st>>>(Gp);
         const int outs = n_cot * tables->n_elts * 3 + n_cot * L * 4;
-        k_bwd_final<<<(outs + 255) / 256, 256, 0, st>>>(d_off, d_ids, L, tables->n_elts, n_cot, B.n_chunks, nwg_v,
-                                                          part_elt, part_occ, aggpart, grad_elt, grad_layer);
+        k_bwd_final<<<outs, 256, 0, st>>>(d_off, d_ids, L, tables->n_elts, n_cot, B.n_chunks, nwg_v, part_elt,
+                                          part_occ, aggpart, grad_elt, grad_layer);
         ARA_HIP(hipGetLastError());
     }
     return ARA_OK;

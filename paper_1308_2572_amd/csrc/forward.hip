@@ -28,13 +28,20 @@ struct FwdParams {
 
 __device__ __forceinline__ uint32_t ld_stream(const uint32_t *p) { return __builtin_nontemporal_load(p); }
 
+// LDS bytes before the values: per-trial totals (and hit counts) including
+// the padding slot, then the super-range's bitmap words with ranks.
+__host__ __device__ inline size_t fwd_fixed_lds(int tb, bool hits) {
+    return align256(static_cast<size_t>(tb + 1) * 8 + (hits ? static_cast<size_t>(tb + 1) * 4 : 0)) +
+           kSrWords * sizeof(uint2);
+}
+
 template <bool HITS>
 __global__ __launch_bounds__(1024) void k_fwd(FwdParams P) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int tb = P.tb;
-    double *acc = reinterpret_cast<double *>(smem);
-    int32_t *hacc = reinterpret_cast<int32_t *>(smem + static_cast<size_t>(tb) * 8);
-    const size_t tbr_off = align256(static_cast<size_t>(tb) * 8 + (HITS ? static_cast<size_t>(tb) * 4 : 0));
+    double *acc = reinterpret_cast<double *>(smem);                                     // [tb + 1]
+    int32_t *hacc = reinterpret_cast<int32_t *>(smem + static_cast<size_t>(tb + 1) * 8);   // [tb + 1]
+    const size_t tbr_off = fwd_fixed_lds(tb, HITS) - kSrWords * sizeof(uint2);
     uint2 *tbr = reinterpret_cast<uint2 *>(smem + tbr_off);
     double *tvals = reinterpret_cast<double *>(smem + tbr_off + kSrWords * sizeof(uint2));
     uint8_t *tcnt = reinterpret_cast<uint8_t *>(tvals + P.cap);
@@ -43,13 +50,14 @@ __global__ __launch_bounds__(1024) void k_fwd(FwdParams P) {
     const int tid = threadIdx.x, lane = tid & 63;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int64_t b = I.block;
+    const uint32_t pad = pad_entry(tb);
     const int64_t gt0 = b * tb + static_cast<int64_t>(w) * P.tg;
     const int64_t gt1 = min(gt0 + P.tg, P.n_trials);
     const bool active = gt0 < gt1 && gt1 > I.t0 && gt0 < I.t1;
     const int G = P.n_ranges;
     const size_t seg0 = static_cast<size_t>(b) * G * kGroups + w;
 
-    for (int i = tid; i < tb; i += blockDim.x) {
+    for (int i = tid; i <= tb; i += blockDim.x) {   // slot tb collects the padding
         acc[i] = 0.0;
         if (HITS) hacc[i] = 0;
     }
@@ -74,8 +82,7 @@ __global__ __launch_bounds__(1024) void k_fwd(FwdParams P) {
         if (rr < G) {
 #pragma unroll
             for (int u = 0; u < kUnroll; ++u)
-                X[u] = (step + u < R) ? ld_stream(P.ent + sb + static_cast<int64_t>(step + u) * kWave + lane)
-                                      : kSentinel;
+                X[u] = (step + u < R) ? ld_stream(P.ent + sb + static_cast<int64_t>(step + u) * kWave + lane) : pad;
             step += kUnroll;
             if (step >= R) {
                 ++rr;
@@ -100,30 +107,53 @@ __global__ __launch_bounds__(1024) void k_fwd(FwdParams P) {
             for (int i = tid; i < inl; i += blockDim.x) tcnt[i] = gcnt[i];
         __syncthreads();
         const int rr_end = min(2 * s + 2, G);
+        const bool all_lds = cnt_s <= P.cap;     // uniform over the workgroup
         while (chunk_rr < rr_end) {
             uint32_t Y[kUnroll];
 #pragma unroll
             for (int u = 0; u < kUnroll; ++u) Y[u] = X[u];
             const uint32_t hb = static_cast<uint32_t>(chunk_rr & 1) << kRangeBits;
             load();   // prefetch the next chunk (possibly of the next super-range)
+            // lookups first, without branches, so the LDS reads of all
+            // entries are in flight together; then the masked accumulation
+            uint2 q[kUnroll];
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) q[u] = tbr[(hb | (Y[u] & (kRange - 1))) >> 5];
+            uint32_t rank[kUnroll];
+            bool hit[kUnroll];
 #pragma unroll
             for (int u = 0; u < kUnroll; ++u) {
-                const uint32_t e = Y[u];
-                if (e != kSentinel) {
-                    const uint32_t tl = e >> kRangeBits;
-                    const uint32_t loc = hb | (e & (kRange - 1));
-                    const uint2 q = tbr[loc >> 5];
-                    const uint32_t bit = loc & 31;
-                    if ((q.x >> bit) & 1u) {
-                        const uint32_t rank = q.y + __popc(q.x & ((1u << bit) - 1u));
-                        const double v = (rank < static_cast<uint32_t>(P.cap)) ? tvals[rank] : gvals[rank];
-                        atomicAdd(&acc[tl], v);
-                        if (HITS) {
-                            const int c = (rank < static_cast<uint32_t>(P.cap)) ? tcnt[rank] : gcnt[rank];
-                            atomicAdd(&hacc[tl], c);
-                        }
+                const uint32_t bit = Y[u] & 31;
+                hit[u] = (q[u].x >> bit) & 1u;
+                rank[u] = q[u].y + __popc(q[u].x & ((1u << bit) - 1u));
+            }
+            if (all_lds) {
+                double v[kUnroll];
+#pragma unroll
+                for (int u = 0; u < kUnroll; ++u) v[u] = tvals[hit[u] ? rank[u] : 0];
+#pragma unroll
+                for (int u = 0; u < kUnroll; ++u)
+                    if (hit[u]) {
+                        atomicAdd(&acc[Y[u] >> kRangeBits], v[u]);
+                        if (HITS) atomicAdd(&hacc[Y[u] >> kRangeBits], static_cast<int>(tcnt[rank[u]]));
                     }
-                }
+            } else {
+#pragma unroll
+                for (int u = 0; u < kUnroll; ++u)
+                    if (hit[u]) {
+                        const bool in = rank[u] < static_cast<uint32_t>(P.cap);
+                        double v;
+                        int c = 0;
+                        if (in) {
+                            v = tvals[rank[u]];
+                            if (HITS) c = tcnt[rank[u]];
+                        } else {
+                            v = gvals[rank[u]];
+                            if (HITS) c = gcnt[rank[u]];
+                        }
+                        atomicAdd(&acc[Y[u] >> kRangeBits], v);
+                        if (HITS) atomicAdd(&hacc[Y[u] >> kRangeBits], c);
+                    }
             }
         }
     }
@@ -153,8 +183,7 @@ int32_t launch_forward(const ara_yet *yet, int n_sr, bool hits, const FwdItem *d
     P.tb = yet->trials_per_block;
     P.n_ranges = yet->n_ranges;
     P.n_sr = n_sr;
-    const size_t fixed = align256(static_cast<size_t>(P.tb) * 8 + (hits ? static_cast<size_t>(P.tb) * 4 : 0)) +
-                         kSrWords * sizeof(uint2);
+    const size_t fixed = fwd_fixed_lds(P.tb, hits);
     P.cap = static_cast<int32_t>((kLdsBytes - fixed) / (hits ? 9 : 8));
     P.items = d_items;
     ProfScope prof(ARA_PROF_FWD, st);

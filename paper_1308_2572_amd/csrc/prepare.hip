@@ -128,7 +128,7 @@ __global__ __launch_bounds__(1024) void k_prep_scatter(const int64_t *__restrict
 __global__ __launch_bounds__(1024) void k_prep_max_occ(const uint32_t *__restrict__ ent,
                                                        const int64_t *__restrict__ seg_base,
                                                        const int32_t *__restrict__ seg_run, int n_blocks,
-                                                       int n_ranges, int32_t *__restrict__ max_occ) {
+                                                       int n_ranges, int tb, int32_t *__restrict__ max_occ) {
     __shared__ uint32_t hist[kRange];
     __shared__ uint32_t red[16];
     for (int i = threadIdx.x; i < kRange; i += blockDim.x) hist[i] = 0;
@@ -141,7 +141,7 @@ __global__ __launch_bounds__(1024) void k_prep_max_occ(const uint32_t *__restric
             const int64_t n = static_cast<int64_t>(seg_run[sidx]) * kWave;
             for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
                 const uint32_t e = ent[sb + i];
-                if (e != kSentinel) atomicAdd(&hist[e & (kRange - 1)], 1u);
+                if ((e >> kRangeBits) < static_cast<uint32_t>(tb)) atomicAdd(&hist[e & (kRange - 1)], 1u);
             }
         }
     }
@@ -231,11 +231,15 @@ extern "C" int32_t ara_yet_prepare(const int64_t *offsets, const int32_t *ids, i
     if (counted != nnz) return fail(ARA_E_RANGE, "ara_yet_prepare: offsets do not cover the IDs consistently");
     ARA_HIP(hipMemcpyAsync(seg_base, base.data(), g.nseg * sizeof(int64_t), hipMemcpyHostToDevice, st));
     ARA_HIP(hipMemcpyAsync(seg_run, run.data(), g.nseg * sizeof(int32_t), hipMemcpyHostToDevice, st));
-    if (total > 0) ARA_HIP(hipMemsetAsync(ent, 0xFF, static_cast<size_t>(total) * sizeof(uint32_t), st));
+    // padding entries name trial slot `tb` (one past the block) and event 0 of
+    // their range: harmless to every consumer, so no sentinel test is needed
+    if (total > 0)
+        ARA_HIP(hipMemsetD32Async(reinterpret_cast<hipDeviceptr_t>(ent), static_cast<int>(pad_entry(g.tb)),
+                                  static_cast<size_t>(total), st));
     k_prep_scatter<<<g.n_blocks, 1024, 0, st>>>(offsets, ids, n_trials, g.tg, g.tb, g.n_ranges, g.gbits, seg_base,
                                                 seg_run, ent);
     ARA_HIP(hipGetLastError());
-    k_prep_max_occ<<<g.n_ranges, 1024, 0, st>>>(ent, seg_base, seg_run, g.n_blocks, g.n_ranges, misc + 1);
+    k_prep_max_occ<<<g.n_ranges, 1024, 0, st>>>(ent, seg_base, seg_run, g.n_blocks, g.n_ranges, g.tb, misc + 1);
     ARA_HIP(hipGetLastError());
     int32_t mo = 0;
     ARA_HIP(hipMemcpyAsync(&mo, misc + 1, sizeof(int32_t), hipMemcpyDeviceToHost, st));
