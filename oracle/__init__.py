@@ -44,7 +44,7 @@ def _load():
         lib = ctypes.CDLL(LIB)
         lib.oracle_build_tables.argtypes = [_I32, _I32, _P, _P, _P, _P]
         lib.oracle_forward.argtypes = [_I32, _I32, _P, _I64, _P, _P, _I32, _P, _P, _P, _P,
-                                       _I64, _I64, _I32, _P, _P, _P, _P]
+                                       _I64, _I64, _I32, _P, _P, _P, _P, _P, _P]
         lib.oracle_tail_count.argtypes = [_I64, _F64]
         lib.oracle_tail_count.restype = _I64
         lib.oracle_metrics.argtypes = [_P, _I32, _I64, _F64, _P]
@@ -80,8 +80,10 @@ def build_tables(elts) -> np.ndarray:
 
 
 def forward(tables: np.ndarray, yet, layers, elt_terms, layer_terms=None, t0: int = 0,
-            t1: Optional[int] = None, n_threads: int = 1):
+            t1: Optional[int] = None, n_threads: int = 1, want_yelt: bool = False):
     """Literal Algorithm 1.  Returns dict(ylt, s_pre, hits, ylt_closed), each
+    [n_layers, t1-t0]; with want_yelt also yelt [n_layers, occurrences in the
+    trial range] (per-occurrence losses, storage order) and occ_max
     [n_layers, t1-t0]."""
     lib = _load()
     t1 = yet.n_trials if t1 is None else t1
@@ -92,16 +94,23 @@ def forward(tables: np.ndarray, yet, layers, elt_terms, layer_terms=None, t0: in
     s_pre = np.empty((nl, n), np.float64)
     hits = np.empty((nl, n), np.int32)
     closed = np.empty((nl, n), np.float64)
+    nocc = int(yet.offsets[t1] - yet.offsets[t0])
+    yelt = np.empty((nl, nocc), np.float64) if want_yelt else None
+    occ_max = np.empty((nl, n), np.float64) if want_yelt else None
     tb = _c(tables, np.float32)
     off, ids = _c(yet.offsets, np.int64), _c(yet.ids, np.int32)
     lo, le = _c(layers.elt_off, np.int32), _c(layers.elt_ids, np.int32)
     et, lt = _c(elt_terms, np.float64), _c(layer_terms, np.float64)
     rc = lib.oracle_forward(tb.shape[0], tb.shape[1], _ptr(tb), yet.n_trials, _ptr(off), _ptr(ids),
                             nl, _ptr(lo), _ptr(le), _ptr(et), _ptr(lt), t0, t1, n_threads,
-                            _ptr(ylt), _ptr(s_pre), _ptr(hits), _ptr(closed))
+                            _ptr(ylt), _ptr(s_pre), _ptr(hits), _ptr(closed),
+                            _ptr(yelt) if want_yelt else None, _ptr(occ_max) if want_yelt else None)
     if rc != 0:
         raise OracleError(f"oracle_forward status {rc}")
-    return dict(ylt=ylt, s_pre=s_pre, hits=hits, ylt_closed=closed)
+    out = dict(ylt=ylt, s_pre=s_pre, hits=hits, ylt_closed=closed)
+    if want_yelt:
+        out.update(yelt=yelt, occ_max=occ_max)
+    return out
 
 
 def tail_count(n: int, p: float) -> int:

@@ -41,6 +41,11 @@
  *   R7  subgradients follow the evaluated branch: d out/d v = [y>0 && a<L],
  *       d out/d R = -[y>0 && a<L], d out/d L = [a >= L].
  *   R8  ties at the PML threshold share the weight equally.
+ *   R9  the per-occurrence loss (event-level YLT) is the occurrence's
+ *       increment of the aggregate-clamped running total, lo_d after the
+ *       differencing pass; it sums to the year loss.  The per-year maximum
+ *       of these increments is the occurrence loss used for occurrence
+ *       exceedance metrics.
  */
 #include <math.h>
 #include <stdint.h>
@@ -102,7 +107,15 @@ int oracle_build_tables(int32_t n_elts, int32_t catalog,
  *   ylt   year loss lr of the literal algorithm
  *   s_pre S = last prefix sum of occurrence losses (0 for an empty trial)
  *   hits  reading R5
- *   ylt_closed  f_agg(S), the telescoped closed form of steps 18-28
+ *   ylt_closed  f_agg(S), the telescoped closed form of step four's
+ *         running-total, clamp and differencing passes
+ * per-occurrence outputs (any may be NULL):
+ *   yelt    [n_layers][offsets[t1]-offsets[t0]]: the occurrence's share of
+ *           the year loss after step four, i.e. lo_d after the differencing
+ *           pass (reading R9), in storage order
+ *   occ_max [n_layers][t1-t0]: the largest of a trial's yelt values (0 for
+ *           an empty trial) -- the per-year maximum occurrence loss behind
+ *           occurrence-exceedance metrics
  * n_threads: 1 = strictly sequential; >1 splits trials over OpenMP threads
  * (each trial is computed by the same sequential code, so results are
  * bit-identical to the single-thread run).
@@ -112,7 +125,8 @@ int oracle_forward(int32_t n_elts, int32_t catalog, const float *tables,
                    int32_t n_layers, const int32_t *layer_off, const int32_t *layer_elts,
                    const double *elt_terms, const double *layer_terms,
                    int64_t t0, int64_t t1, int32_t n_threads,
-                   double *ylt, double *s_pre, int32_t *hits, double *ylt_closed)
+                   double *ylt, double *s_pre, int32_t *hits, double *ylt_closed,
+                   double *yelt, double *occ_max)
 {
     if (t0 < 0 || t1 < t0 || t1 > n_trials) return OR_E_INVAL;
     int64_t nt = t1 - t0;
@@ -189,6 +203,16 @@ int oracle_forward(int32_t n_elts, int32_t catalog, const float *tables,
                     double lr = 0.0;
                     for (int64_t d = 0; d < n; ++d) lr = lr + lo[d];
                     const size_t o = (size_t)a * (size_t)nt + (size_t)(b - t0);
+                    if (yelt) {
+                        const size_t base = (size_t)a * (size_t)(offsets[t1] - offsets[t0]) +
+                                            (size_t)(offsets[b] - offsets[t0]);
+                        for (int64_t d = 0; d < n; ++d) yelt[base + (size_t)d] = lo[d];
+                    }
+                    if (occ_max) {
+                        double m = 0.0;
+                        for (int64_t d = 0; d < n; ++d) m = (lo[d] > m) ? lo[d] : m;
+                        occ_max[o] = m;
+                    }
                     if (ylt) ylt[o] = lr;
                     if (s_pre) s_pre[o] = S;
                     if (hits) hits[o] = h;

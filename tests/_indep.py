@@ -102,3 +102,37 @@ def brute_metrics(y, p):
     gt = [u for u in y if u > pml]
     tvar = (math.fsum(gt) + (r - len(gt)) * pml) / r
     return math.fsum(y) / n, pml, tvar, r
+
+
+def brute_yelt(w, elt_terms=None, layer_terms=None):
+    """Per-occurrence losses as increments of f_agg over correctly rounded
+    running totals (math.fsum of the occurrence losses so far): a different
+    route from a running sum.  Returns (list per layer of per-occurrence
+    arrays in storage order, per-trial maxima [n_layers, n_trials])."""
+    dicts = elt_dicts(w.elts)
+    et = w.elts.terms if elt_terms is None else elt_terms
+    lt = w.layers.terms if layer_terms is None else layer_terms
+    nl, nt = w.layers.n_layers, w.yet.n_trials
+    out = []
+    mx = np.zeros((nl, nt))
+    for j in range(nl):
+        lst = [int(k) for k in w.layers.elt_ids[w.layers.elt_off[j]:w.layers.elt_off[j + 1]]]
+        occr, occl, aggr, aggl = (float(v) for v in lt[j])
+        row = []
+        for t in range(nt):
+            occ = []
+            for e in w.yet.ids[w.yet.offsets[t]:w.yet.offsets[t + 1]]:
+                x = 0.0
+                for k in lst:
+                    x += xl(et[k][0] * dicts[k].get(int(e), 0.0), et[k][1], et[k][2])
+                occ.append(xl(x, occr, occl))
+            prev = 0.0
+            incs = []
+            for d in range(len(occ)):
+                c = xl(math.fsum(occ[: d + 1]), aggr, aggl)
+                incs.append(c - prev)
+                prev = c
+            row.extend(incs)
+            mx[j, t] = max(incs) if incs else 0.0
+        out.append(np.array(row))
+    return out, mx

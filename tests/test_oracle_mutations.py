@@ -35,6 +35,9 @@ MUTATIONS = {
                         "wt[t] = 1.0 / ((double)r * (double)n_eq);"),
     "elt-limit-grad-dropped": ("if (av >= L) ge[3 * k + 2] += adj_l;", "if (av >= L) ge[3 * k + 2] += 0.0;"),
     "occ-limit-grad-dropped": ("if (aa >= OccL) gl[1] += adj_o[d];", "if (aa >= OccL) gl[1] += 0.0;"),
+    "occ-max-is-last": ("m = (lo[d] > m) ? lo[d] : m;", "m = lo[d];"),
+    "yelt-reversed-order": ("for (int64_t d = 0; d < n; ++d) yelt[base + (size_t)d] = lo[d];",
+                            "for (int64_t d = 0; d < n; ++d) yelt[base + (size_t)d] = lo[n - 1 - d];"),
 }
 
 
@@ -42,8 +45,10 @@ def _battery():
     """True iff every pin in this small battery holds."""
     w, g = load_hand_example()
     tb = oracle.build_tables(w.elts)
-    r = oracle.forward(tb, w.yet, w.layers, w.elts.terms, w.layers.terms)
+    r = oracle.forward(tb, w.yet, w.layers, w.elts.terms, w.layers.terms, want_yelt=True)
     if r["ylt"][0].tolist() != g["ylt"] or r["hits"][0].tolist() != g["hits"]:
+        return False
+    if r["yelt"][0].tolist() != [v for t in g["yelt"] for v in t] or r["occ_max"][0].tolist() != g["occ_max"]:
         return False
     for p, m in g["metrics"].items():
         if oracle.metrics(r["ylt"], float(p))[0].tolist() != [m["aal"], m["pml"], m["tvar"]]:

@@ -9,7 +9,7 @@ import pytest
 
 import oracle
 import synth
-from _indep import brute_forward, brute_metrics, load_hand_example, xl
+from _indep import brute_forward, brute_metrics, brute_yelt, load_hand_example, xl
 
 U = 2.0 ** -53
 
@@ -396,3 +396,84 @@ def test_aggregate_term_gradients_are_counts():
         cap = np.count_nonzero(a >= aggl)
         assert gl[0, j, 2] == pytest.approx(-lin / n, rel=1e-12, abs=1e-15)
         assert gl[0, j, 3] == pytest.approx(cap / n, rel=1e-12, abs=1e-15)
+
+
+# ------------------------------------------------- per-occurrence losses
+def test_hand_example_yelt():
+    w, g = load_hand_example()
+    _, r = run(w, want_yelt=True)
+    flat = [v for t in g["yelt"] for v in t]
+    assert r["yelt"][0].tolist() == flat
+    assert r["occ_max"][0].tolist() == g["occ_max"]
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_yelt_sums_to_year_loss_and_bounds(seed):
+    w = synth.tiny_random(seed, n_trials=40, max_events=30, n_layers=2)
+    _, r = run(w, want_yelt=True)
+    off = w.yet.offsets
+    for j in range(w.layers.n_layers):
+        aggl = w.layers.terms[j, 3]
+        y = r["yelt"][j]
+        assert np.all(y >= 0.0) and np.all(y <= aggl)
+        for t in range(w.yet.n_trials):
+            seg = y[off[t]:off[t + 1]]
+            n = len(seg)
+            S = r["s_pre"][j, t]
+            assert abs(math.fsum(seg) - r["ylt"][j, t]) <= 4 * max(n, 1) * U * S
+            assert r["occ_max"][j, t] == (seg.max() if n else 0.0)
+            assert r["occ_max"][j, t] <= r["ylt"][j, t] or n == 0
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_yelt_bruteforce_running_totals(seed):
+    w = synth.tiny_random(seed, n_trials=30, max_events=25, n_layers=2)
+    _, r = run(w, want_yelt=True)
+    ref, mx = brute_yelt(w)
+    off = w.yet.offsets
+    for j in range(w.layers.n_layers):
+        for t in range(w.yet.n_trials):
+            a, b = off[t], off[t + 1]
+            S = r["s_pre"][j, t]
+            tol = 4 * max(b - a, 1) * U * S
+            assert np.all(np.abs(r["yelt"][j][a:b] - ref[j][a:b]) <= tol)
+            assert abs(r["occ_max"][j, t] - mx[j, t]) <= tol
+
+
+def test_yelt_zero_before_retention_and_after_limit():
+    """An occurrence whose running total stays at or below AggR, or which
+    comes after the running total has used up AggL, adds exactly 0."""
+    w = synth.tiny_random(5, n_trials=50, max_events=40, n_layers=1)
+    lt = w.layers.terms.copy()
+    _, r0 = run(w, layer_terms=lt)
+    S = r0["s_pre"][0]
+    lt[0, 2] = float(np.median(S[S > 0])) * 0.3
+    lt[0, 3] = float(np.median(S[S > 0])) * 0.4
+    _, r = run(w, layer_terms=lt, want_yelt=True)
+    off = w.yet.offsets
+    dicts = None
+    for t in range(w.yet.n_trials):
+        seg = r["yelt"][0][off[t]:off[t + 1]]
+        if len(seg) == 0:
+            continue
+        # running totals of the increments identify the phases
+        run_c = np.cumsum(seg)
+        capped = np.nonzero(run_c >= lt[0, 3])[0]
+        if len(capped):
+            assert np.all(seg[capped[0] + 1:] == 0.0)
+        assert r["occ_max"][0, t] <= lt[0, 3]
+
+
+def test_yelt_without_aggregate_terms_is_occurrence_loss():
+    """AggR = 0 and AggL = inf: each increment is the occurrence loss o_d up to
+    the rounding of the running total."""
+    w = synth.tiny_random(3, n_trials=30, max_events=20, n_layers=1)
+    lt = w.layers.terms.copy()
+    lt[0, 2], lt[0, 3] = 0.0, np.inf
+    _, r = run(w, layer_terms=lt, want_yelt=True)
+    ref, _ = brute_yelt(w, layer_terms=lt)
+    off = w.yet.offsets
+    for t in range(w.yet.n_trials):
+        a, b = off[t], off[t + 1]
+        S = r["s_pre"][0, t]
+        assert np.all(np.abs(r["yelt"][0][a:b] - ref[0][a:b]) <= 4 * max(b - a, 1) * U * S)
