@@ -73,6 +73,21 @@ def cpu_baseline(w, budget_s: float = 10.0):
                       f"{dt:.2f} s with {threads} threads"}
 
 
+def copy_calibration() -> int:
+    """A plain device-to-device copy of known size: what FETCH_SIZE and
+    WRITE_SIZE read for it converts their units into HBM bytes."""
+    import torch
+    n = 1 << 28                                  # 2^28 binary32 = 1 GiB
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibration": "copy", "bytes_read_per_launch": n * 4, "bytes_written_per_launch": n * 4,
+                      "launches": 3}), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -83,7 +98,11 @@ def main() -> int:
     ap.add_argument("--no-backward", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=200)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device copy three times (scales the HBM byte counters)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        return copy_calibration()
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU (asked for {args.gpus}); the multi-GPU trial split is a design "
               f"only -- see the sharding notes -- and no multi-GPU figure is produced.", file=sys.stderr)

@@ -80,10 +80,20 @@ int32_t ara_abi_version(void);
  * whose event lies in range r are stored in trial order, packed as
  * (trial_in_block << range_bits) | (event_id - r * 2^range_bits), and
  * distributed over 64 lanes as `seg_run` consecutive entries per lane
- * (entry s of lane j at seg_base + s*64 + j; unused slots hold 0xFFFFFFFF).
+ * (entry s of lane j at seg_base + s*64 + j; unused slots hold the padding
+ * entry trials_per_block << range_bits, a trial slot one past the block).
  * Order of occurrences inside a trial is not kept: the year loss does not
  * depend on it (the cumulative aggregate steps telescope), but the order of
  * summation, and so rounding, is fixed by this layout and deterministic.
+ *
+ * With ARA_PREP_TRANSPOSED the buffer also holds the event-major copy the
+ * backward needs (the adjoint of the per-trial gather is a per-event
+ * scatter; stored transposed it becomes a gather again).  The trials are
+ * cut into n_slices slices of slice_trials consecutive trials; for slice x
+ * and event e the occurrences are the list
+ *     tr_ent[tr_off[x*catalog + e] .. tr_off[x*catalog + e + 1])
+ * of trial indices local to the slice (trial = x*slice_trials + entry), one
+ * entry per occurrence, in no particular order.
  */
 typedef struct ara_yet {
     int64_t   n_trials;
@@ -100,23 +110,35 @@ typedef struct ara_yet {
     uint32_t *ent;               /* device [n_entries] */
     int64_t  *seg_base;          /* device [n_blocks][n_ranges][groups] */
     int32_t  *seg_run;           /* device [n_blocks][n_ranges][groups] */
+    /* event-major copy (ARA_PREP_TRANSPOSED; n_slices = 0 and NULL otherwise) */
+    int32_t   n_slices;          /* 8 */
+    int32_t   reserved;
+    int64_t   slice_trials;      /* a multiple of trials_per_block */
+    int64_t  *tr_off;            /* device [n_slices * catalog + 1] */
+    uint32_t *tr_ent;            /* device [nnz] */
 } ara_yet;
 
-/* Upper bound of the device buffer ara_yet_prepare needs. */
-int32_t ara_yet_prepare_bytes(int64_t n_trials, int64_t nnz, int32_t catalog, size_t *bytes);
+/* prepare flags */
+#define ARA_PREP_TRANSPOSED 1u   /* also build the event-major copy (needed by ara_ylt_backward) */
+
+/* Upper bound of the device buffer ara_yet_prepare needs for these flags. */
+int32_t ara_yet_prepare_bytes(int64_t n_trials, int64_t nnz, int32_t catalog, uint32_t flags, size_t *bytes);
 
 /*
  * offsets: device int64 [n_trials+1], offsets[0] = 0, non-decreasing; trial t
  *          holds ids[offsets[t] .. offsets[t+1]).
  * ids:     device int32 [offsets[n_trials]].
- * buf:     device buffer of at least ara_yet_prepare_bytes; it holds the
- *          prepared YET afterwards and must outlive every use of *out.
+ * flags:   0 or ARA_PREP_TRANSPOSED.
+ * buf:     device buffer of at least ara_yet_prepare_bytes (same flags); it
+ *          holds the prepared YET afterwards and must outlive every use of *out.
  * Validates every ID (ARA_E_RANGE) and every offset.  SYNCHRONISES `stream`
  * (it sizes the layout from device-side counts); one-time cost.
+ * ARA_E_LIMIT if one (slice, catalogue range) of the event-major copy would
+ * hold 2^32 occurrences or more.
  */
 int32_t ara_yet_prepare(const int64_t *offsets, const int32_t *ids, int64_t n_trials,
-                        int32_t catalog, void *buf, size_t buf_bytes, void *stream,
-                        ara_yet *out);
+                        int32_t catalog, uint32_t flags, void *buf, size_t buf_bytes,
+                        void *stream, ara_yet *out);
 
 /* ------------------------------------------------------------------------ */
 /* ELTs: the second input (Section II) -- event -> loss dictionaries, held as */
@@ -181,6 +203,34 @@ int32_t ara_ylt_forward(const ara_tables *tables, const ara_yet *yet, const ara_
 int32_t ara_check_device_error(const void *ws, void *stream);
 
 /* ------------------------------------------------------------------------ */
+/* Per-occurrence losses: step four of Algorithm 1 taken literally, per      */
+/* occurrence in storage order (the event-level YLT), and the per-year       */
+/* maximum occurrence loss behind occurrence-exceedance metrics.             */
+/* ------------------------------------------------------------------------ */
+int32_t ara_yelt_workspace_bytes(const ara_tables *tables, const ara_layers *layers, size_t *bytes);
+
+/*
+ * offsets, ids: the trial-major YET on the device (as given to
+ *              ara_yet_prepare; storage order matters here), n_trials trials.
+ * occ_begin:   offsets[trial_begin]; occ_count: offsets[trial_end] - occ_begin
+ *              (host values; a mismatch is a device-side ARA_E_RANGE).
+ * yelt:        device binary64 [n_layers][occ_count]: occurrence d of trial t
+ *              gets f_agg(S_{t,d}) - f_agg(S_{t,d-1}), S_{t,d} the running total
+ *              of the trial's occurrence losses (S_{t,0} = 0); a trial's values
+ *              sum to its year loss.
+ * occ_max:     device binary64 [n_layers][trial_end - trial_begin]: the largest
+ *              of the trial's values (0 for an empty trial).
+ * Event IDs outside [0, catalog) are a device-side ARA_E_RANGE
+ * (ara_check_device_error on ws); the running total is summed in wavefront
+ * order, so values agree with a sequential sum to rounding.
+ */
+int32_t ara_yelt_forward(const ara_tables *tables, const int64_t *offsets, const int32_t *ids,
+                         int64_t n_trials, const ara_layers *layers, const double *elt_terms,
+                         const double *layer_terms, int64_t trial_begin, int64_t trial_end,
+                         int64_t occ_begin, int64_t occ_count, double *yelt, double *occ_max,
+                         void *ws, size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------------------ */
 /* Metrics from the YLT (Section I names PML and TVaR).                      */
 /* ------------------------------------------------------------------------ */
 int32_t ara_metrics_workspace_bytes(int32_t n_layers, int64_t n, size_t *bytes);
@@ -221,6 +271,8 @@ int32_t ara_ylt_backward_workspace_bytes(const ara_tables *tables, const ara_yet
  * Subgradients follow the evaluated branch of each min/max: d/dv = [y>0 && a<L],
  * d/dR = -[y>0 && a<L], d/dL = [a >= L].  Deterministic (fixed-point
  * accumulation of the per-event weights, fixed-order reductions).
+ * The YET must have been prepared with ARA_PREP_TRANSPOSED (ARA_E_INVAL
+ * otherwise).
  */
 int32_t ara_ylt_backward(const ara_tables *tables, const ara_yet *yet, const ara_layers *layers,
                          const double *elt_terms, const double *layer_terms,
@@ -266,7 +318,9 @@ int32_t ara_server_arena_bytes(const ara_tables *tables, const ara_yet *yet, int
  * buffer owned by the caller for the server's lifetime; max_slots <= 256. */
 int32_t ara_server_create(const ara_tables *tables, const ara_yet *yet, const double *elt_terms,
                           void *arena, size_t arena_bytes, int32_t max_slots, void **server);
-/* Validates and enqueues; ARA_E_NOSPACE if the quote can never fit the arena. */
+/* Validates and enqueues; ARA_E_NOSPACE if the quote can never fit the arena;
+ * ARA_E_INVAL for a quote with gradients when the resident YET was prepared
+ * without ARA_PREP_TRANSPOSED. */
 int32_t ara_server_submit(void *server, const ara_quote *quote, int64_t *ticket);
 /* ARA_OK and *out filled when finished (the ticket is then retired), ARA_E_BUSY otherwise. */
 int32_t ara_server_poll(void *server, int64_t ticket, ara_quote_result *out);
@@ -289,6 +343,7 @@ int32_t ara_server_destroy(void *server);
 #define ARA_PROF_METRICS  2   /* all metric kernels of one ara_metrics call  */
 #define ARA_PROF_BWD      3   /* backward streaming kernel                   */
 #define ARA_PROF_BWD_RED  4   /* backward reductions                         */
+#define ARA_PROF_YELT     5   /* per-occurrence (event-level) kernel         */
 #define ARA_PROF_KINDS    8
 
 /* on != 0 starts recording (process-wide); 0 stops. */

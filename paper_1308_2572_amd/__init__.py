@@ -23,6 +23,7 @@ LIB_PATH = os.path.join(HERE, "libara.so")
 
 ARA_OK, ARA_E_INVAL, ARA_E_RANGE, ARA_E_DUP, ARA_E_NOSPACE, ARA_E_HIP, ARA_E_LIMIT, ARA_E_BUSY = range(8)
 ARA_F_EMIT_HITS = 1
+PREP_TRANSPOSED = 1          # ARA_PREP_TRANSPOSED
 ARA_MAX_COTANGENTS = 4
 
 _c_i32, _c_i64, _c_u32, _c_f64, _c_p, _c_sz = (ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_double,
@@ -39,7 +40,9 @@ class ara_yet(ctypes.Structure):
     _fields_ = [("n_trials", _c_i64), ("nnz", _c_i64), ("catalog", _c_i32), ("range_bits", _c_i32),
                 ("n_ranges", _c_i32), ("groups", _c_i32), ("trials_per_group", _c_i32),
                 ("trials_per_block", _c_i32), ("n_blocks", _c_i32), ("max_occ", _c_i32),
-                ("n_entries", _c_i64), ("ent", _c_p), ("seg_base", _c_p), ("seg_run", _c_p)]
+                ("n_entries", _c_i64), ("ent", _c_p), ("seg_base", _c_p), ("seg_run", _c_p),
+                ("n_slices", _c_i32), ("reserved", _c_i32), ("slice_trials", _c_i64), ("tr_off", _c_p),
+                ("tr_ent", _c_p)]
 
 
 class ara_tables(ctypes.Structure):
@@ -67,13 +70,16 @@ _SIGNATURES = {
     "ara_last_error": (ctypes.c_char_p, []),
     "ara_abi_version": (_c_i32, []),
     "ara_check_device_error": (_c_i32, [_c_p, _c_p]),
-    "ara_yet_prepare_bytes": (_c_i32, [_c_i64, _c_i64, _c_i32, _P(_c_sz)]),
-    "ara_yet_prepare": (_c_i32, [_c_p, _c_p, _c_i64, _c_i32, _c_p, _c_sz, _c_p, _P(ara_yet)]),
+    "ara_yet_prepare_bytes": (_c_i32, [_c_i64, _c_i64, _c_i32, _c_u32, _P(_c_sz)]),
+    "ara_yet_prepare": (_c_i32, [_c_p, _c_p, _c_i64, _c_i32, _c_u32, _c_p, _c_sz, _c_p, _P(ara_yet)]),
     "ara_build_elt_tables_bytes": (_c_i32, [_c_i32, _c_i32, _P(_c_sz)]),
     "ara_build_elt_tables": (_c_i32, [_c_i32, _c_i32, _c_p, _c_p, _c_p, _c_p, _c_sz, _c_p, _P(ara_tables)]),
     "ara_ylt_workspace_bytes": (_c_i32, [_P(ara_tables), _P(ara_yet), _P(ara_layers), _c_u32, _P(_c_sz)]),
     "ara_ylt_forward": (_c_i32, [_P(ara_tables), _P(ara_yet), _P(ara_layers), _c_p, _c_p, _c_i64, _c_i64, _c_u32,
                                  _c_p, _c_p, _c_p, _c_p, _c_sz, _c_p]),
+    "ara_yelt_workspace_bytes": (_c_i32, [_P(ara_tables), _P(ara_layers), _P(_c_sz)]),
+    "ara_yelt_forward": (_c_i32, [_P(ara_tables), _c_p, _c_p, _c_i64, _P(ara_layers), _c_p, _c_p, _c_i64, _c_i64,
+                                  _c_i64, _c_i64, _c_p, _c_p, _c_p, _c_sz, _c_p]),
     "ara_metrics_workspace_bytes": (_c_i32, [_c_i32, _c_i64, _P(_c_sz)]),
     "ara_metrics": (_c_i32, [_c_p, _c_i32, _c_i64, _c_f64, _c_p, _c_p, _c_p, _c_sz, _c_p]),
     "ara_metrics_vjp": (_c_i32, [_c_p, _c_i32, _c_i64, _c_p, _c_p, _c_p]),
@@ -143,27 +149,31 @@ def _workspace(nbytes: int, device) -> torch.Tensor:
 class PreparedYet:
     """A YET laid out on the device by ara_yet_prepare (keeps its buffer alive)."""
 
-    def __init__(self, offsets: torch.Tensor, ids: torch.Tensor, catalog: int):
+    def __init__(self, offsets: torch.Tensor, ids: torch.Tensor, catalog: int, transposed: bool = True):
+        """transposed: also build the event-major copy that the backward
+        needs (ARA_PREP_TRANSPOSED); leave it off for forward-only use."""
         lib = library()
         if offsets.dtype != torch.int64 or ids.dtype != torch.int32:
             raise ValueError("offsets must be int64 and ids int32")
         n_trials = offsets.numel() - 1
         nnz = ids.numel()
+        flags = PREP_TRANSPOSED if transposed else 0
         nb = _c_sz()
-        _check(lib.ara_yet_prepare_bytes(n_trials, nnz, catalog, ctypes.byref(nb)), "ara_yet_prepare_bytes")
+        _check(lib.ara_yet_prepare_bytes(n_trials, nnz, catalog, flags, ctypes.byref(nb)), "ara_yet_prepare_bytes")
         self.device = offsets.device
         self.buf = _workspace(nb.value, self.device)
         self.handle = ara_yet()
-        _check(lib.ara_yet_prepare(_dptr(offsets), _dptr(ids), n_trials, catalog, _dptr(self.buf), self.buf.numel(),
-                                   _stream(), ctypes.byref(self.handle)), "ara_yet_prepare")
+        _check(lib.ara_yet_prepare(_dptr(offsets), _dptr(ids), n_trials, catalog, flags, _dptr(self.buf),
+                                   self.buf.numel(), _stream(), ctypes.byref(self.handle)), "ara_yet_prepare")
         self.n_trials = n_trials
         self.catalog = catalog
+        self.transposed = transposed
 
     @classmethod
-    def from_numpy(cls, yet, device="cuda"):
+    def from_numpy(cls, yet, device="cuda", transposed: bool = True):
         off = torch.from_numpy(np.ascontiguousarray(yet.offsets, np.int64)).to(device)
         ids = torch.from_numpy(np.ascontiguousarray(yet.ids, np.int32)).to(device)
-        out = cls(off, ids, int(yet.catalog))
+        out = cls(off, ids, int(yet.catalog), transposed=transposed)
         return out
 
 
@@ -209,6 +219,41 @@ class Layers:
 # --------------------------------------------------------------------------
 # computations
 # --------------------------------------------------------------------------
+
+def yelt_forward(tables: EltTables, offsets: torch.Tensor, ids: torch.Tensor, layers: Layers,
+                 elt_terms: torch.Tensor, layer_terms: torch.Tensor, trial_begin: int = 0,
+                 trial_end: Optional[int] = None, check: bool = False):
+    """Per-occurrence losses over the trial-major YET (device int64 offsets,
+    int32 ids, storage order).  Returns (yelt [n_layers, occurrences in the
+    range], occ_max [n_layers, n])."""
+    lib = library()
+    if offsets.dtype != torch.int64 or ids.dtype != torch.int32:
+        raise ValueError("offsets must be int64 and ids int32")
+    n_trials = offsets.numel() - 1
+    trial_end = n_trials if trial_end is None else trial_end
+    if not (0 <= trial_begin <= trial_end <= n_trials):
+        raise AraError(ARA_E_RANGE, "trial range outside the YET")
+    n = trial_end - trial_begin
+    L = layers.n_layers
+    dev = offsets.device
+    occ_begin = int(offsets[trial_begin].item())
+    occ_count = int(offsets[trial_end].item()) - occ_begin
+    nb = _c_sz()
+    _check(lib.ara_yelt_workspace_bytes(ctypes.byref(tables.handle), ctypes.byref(layers.handle), ctypes.byref(nb)),
+           "ara_yelt_workspace_bytes")
+    ws = _workspace(nb.value, dev)
+    yelt = torch.empty((L, max(occ_count, 0)), dtype=torch.float64, device=dev)
+    occ_max = torch.empty((L, n), dtype=torch.float64, device=dev)
+    et = elt_terms.to(device=dev, dtype=torch.float64).contiguous()
+    lt = layer_terms.to(device=dev, dtype=torch.float64).contiguous()
+    _check(lib.ara_yelt_forward(ctypes.byref(tables.handle), _dptr(offsets), _dptr(ids), n_trials,
+                                ctypes.byref(layers.handle), _dptr(et), _dptr(lt), trial_begin, trial_end,
+                                occ_begin, occ_count, _dptr(yelt), _dptr(occ_max), _dptr(ws), ws.numel(),
+                                _stream()), "ara_yelt_forward")
+    if check:
+        _check(lib.ara_check_device_error(_dptr(ws), _stream()), "ara_yelt_forward (device)")
+    return yelt, occ_max
+
 
 def ylt_forward(tables: EltTables, yet: PreparedYet, layers: Layers, elt_terms: torch.Tensor,
                 layer_terms: torch.Tensor, trial_begin: int = 0, trial_end: Optional[int] = None,
@@ -289,7 +334,7 @@ def ylt_backward(tables: EltTables, yet: PreparedYet, layers: Layers, elt_terms:
     return ge, gl
 
 
-PROF_OCC, PROF_FWD, PROF_METRICS, PROF_BWD, PROF_BWD_RED = range(5)
+PROF_OCC, PROF_FWD, PROF_METRICS, PROF_BWD, PROF_BWD_RED, PROF_YELT = range(6)
 
 
 def profile_enable(on: bool = True) -> None:

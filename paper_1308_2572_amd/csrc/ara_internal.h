@@ -24,6 +24,10 @@ constexpr int kSrWords = kSr / 32;             // 2048 bitmap words per super-ra
 // block's trials) and event 0 of the range.
 __host__ __device__ inline uint32_t pad_entry(int tb) { return static_cast<uint32_t>(tb) << kRangeBits; }
 constexpr int kWave = 64;
+// Trial slices of the event-major YET copy: one per XCD of the MI355X, so
+// that a backward workgroup's gathers of per-trial weights stay in the L2 of
+// the XCD it runs on (workgroups are dealt to the XCDs round-robin).
+constexpr int kSlices = 8;
 
 // Error word kept at the head of every workspace.
 struct WsHeader {

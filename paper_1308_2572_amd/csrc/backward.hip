@@ -16,15 +16,19 @@
 //   with O(e) != 0 can have b_e or a binding occurrence limit, so W is kept
 //   for those "hot" events only, indexed by the occurrence table's rank.
 //
+// The forward gathers O(e) per trial; its adjoint scatters v_t per event.
+// Read through the event-major copy of the YET the scatter is a gather
+// again, and only the hot events' occurrence lists are read at all.
+//
 // Kernels: (1) the hot occurrence tables (shared with the forward);
 // (2) v_t per cotangent row, its largest magnitude and the aggregate-term
 // sums; (3) v_t in 64-bit fixed point, scaled so that no partial sum of W
 // can overflow (|W| <= max|v| * largest occurrence count of one event);
-// (4) a stream over the prepared YET, one workgroup per (catalogue range,
-// part of the blocks), adding fixed-point v into LDS accumulators of W --
-// integer addition, so the result does not depend on the order;
-// (5) per 4096-event chunk, W times the per-event derivatives, reduced in a
-// fixed order; (6) a fixed-order sum of the chunk partials into the outputs.
+// (4) the list of hot events; (5) W(e) per hot event, gathered per trial
+// slice over the event-major YET and combined with integer atomics, so the
+// result does not depend on the order; (6) per 4096-event chunk, W times
+// the per-event derivatives, reduced in a fixed order; (7) a fixed-order sum
+// of the chunk partials into the outputs.
 #include "occ.h"
 
 #include <algorithm>
@@ -37,7 +41,6 @@ constexpr int kBwdThreads = 1024;
 constexpr int kMaxCot = ARA_MAX_COTANGENTS;
 constexpr int kChunkWords = 128;                  // 4096 events per reduction workgroup
 constexpr int kChunks = kSrWords / kChunkWords;   // 16 per super-range
-constexpr int kLds = 160 * 1024;
 
 struct VScale {
     unsigned long long maxabs_bits;   // max |v| as binary64 bits (non-negative: order-preserving)
@@ -119,189 +122,134 @@ __device__ __forceinline__ int sigma_of(const VScale &v, int max_occ) {
     return 62 - e;
 }
 
-// (3) fixed-point weights vq[c][j][t] = round(c_t a_t 2^sigma).
+// (3) fixed-point weights vq[j][t][c] = round(c_t a_t 2^sigma), the rows of
+// one trial side by side (cs >= n_cot slots, the spare ones zero) so that one
+// gather fetches every row.
 __global__ void k_bwd_vq(const double *__restrict__ cot, const double *__restrict__ s_pre,
-                         const double *__restrict__ layer_terms, int64_t n, int n_layers, int n_cot, int max_occ,
-                         VScale *__restrict__ vs, int64_t *__restrict__ vq) {
+                         const double *__restrict__ layer_terms, int64_t n, int n_layers, int n_cot, int cs,
+                         int max_occ, VScale *__restrict__ vs, int64_t *__restrict__ vq) {
     const int j = blockIdx.y;
     const double aggR = layer_terms[4 * j + 2], aggL = layer_terms[4 * j + 3];
     const double *S = s_pre + static_cast<size_t>(j) * n;
+    int sg[kMaxCot];
     for (int c = 0; c < n_cot; ++c) {
-        const int sg = sigma_of(vs[j * n_cot + c], max_occ);
-        if (blockIdx.x == 0 && threadIdx.x == 0) vs[j * n_cot + c].sigma = sg;
-        const double *g = cot + (static_cast<size_t>(c) * n_layers + j) * n;
-        int64_t *q = vq + (static_cast<size_t>(c) * n_layers + j) * n;
-        for (int64_t t = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; t < n;
-             t += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-            const double v = agg_linear(S[t], aggR, aggL) ? g[t] : 0.0;
-            q[t] = (v == 0.0) ? 0 : static_cast<int64_t>(__double2ll_rn(ldexp(v, sg)));
+        sg[c] = sigma_of(vs[j * n_cot + c], max_occ);
+        if (blockIdx.x == 0 && threadIdx.x == 0) vs[j * n_cot + c].sigma = sg[c];
+    }
+    int64_t *q = vq + static_cast<size_t>(j) * n * cs;
+    for (int64_t t = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; t < n;
+         t += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        const bool lin = agg_linear(S[t], aggR, aggL);
+        for (int c = 0; c < cs; ++c) {
+            int64_t r = 0;
+            if (c < n_cot && lin) {
+                const double v = cot[(static_cast<size_t>(c) * n_layers + j) * n + t];
+                r = (v == 0.0) ? 0 : static_cast<int64_t>(__double2ll_rn(ldexp(v, sg[c])));
+            }
+            q[static_cast<size_t>(t) * cs + c] = r;
         }
     }
 }
 
-struct BwdStream {
-    const uint32_t *ent;
-    const int64_t *seg_base;
-    const int32_t *seg_run;
-    int64_t t0, t1, n;
-    int32_t tg, tb, n_ranges, n_parts, n_cot, n_layers;
-    int32_t b_lo, b_hi;
-    int32_t capw;                 // W accumulators per row held in LDS
-    const OccTables *tabs;        // hot tables per layer
-    const int64_t *vq;            // [n_cot][n_layers][n]
-    int64_t *wg;                  // [n_layers][n_cot][n_parts][n_sr * kSr]
-    size_t wg_stride;             // n_sr * kSr
+// (4) the layer's hot events (O(e) != 0) as one list, in (super-range,
+// rank) order: hot_ev[g] is the event of hot index g = hot_base[s] + rank;
+// the weight accumulators of every hot index start at zero.
+__global__ __launch_bounds__(256) void k_bwd_hot(const OccTables *__restrict__ tabs, int n_sr, int n_cot,
+                                                 int32_t catalog, int32_t *__restrict__ hot_ev,
+                                                 int32_t *__restrict__ hot_base, int64_t *__restrict__ W) {
+    __shared__ int32_t red[4];
+    const int s = blockIdx.x, j = blockIdx.y, tid = threadIdx.x;
+    const OccTables T = tabs[j];
+    int32_t part = 0;
+    for (int i = tid; i < s; i += blockDim.x) part += T.count[i];
+    for (int o = 32; o > 0; o >>= 1) part += __shfl_down(part, o);
+    if ((tid & 63) == 0) red[tid >> 6] = part;
+    __syncthreads();
+    const int32_t base = red[0] + red[1] + red[2] + red[3];
+    int32_t *hb = hot_base + static_cast<size_t>(j) * (n_sr + 1);
+    if (tid == 0) {
+        hb[s] = base;
+        if (s == n_sr - 1) hb[n_sr] = base + T.count[s];
+    }
+    int32_t *hev = hot_ev + static_cast<size_t>(j) * catalog;
+    int64_t *Wj = W + static_cast<size_t>(j) * n_cot * catalog;
+    for (int i = tid; i < kSrWords; i += blockDim.x) {
+        const uint2 q = T.br[static_cast<size_t>(s) * kSrWords + i];
+        uint32_t m = q.x;
+        int32_t g = base + static_cast<int32_t>(q.y);
+        while (m) {
+            const int bit = __builtin_ctz(m);
+            hev[g] = s * kSr + 32 * i + bit;
+            for (int c = 0; c < n_cot; ++c) Wj[static_cast<size_t>(c) * catalog + g] = 0;
+            ++g;
+            m &= m - 1;
+        }
+    }
+}
+
+struct BwdGather {
+    const int64_t *tr_off;        // event-major YET
+    const uint32_t *tr_ent;
+    int32_t catalog, n_sr, n_cot, pad;
+    int64_t slice_trials;
+    int64_t t0, t1, n;            // trial range of the call
+    const int32_t *hot_ev;        // [n_layers][catalog]
+    const int32_t *hot_base;      // [n_layers][n_sr + 1]
+    const int64_t *vq;            // [n_layers][n][CS]
+    int64_t *W;                   // [n_layers][n_cot][catalog], by hot index
 };
 
-// (4) W(e) += v_t for every occurrence (t, e) of a hot event.  The blocks of
-// one part are processed in phases of half a block (8 trial groups): the
-// weights of the next phase are loaded into registers while the current one
-// streams, and each wavefront prefetches the first entries of its next
-// segment before the phase barrier.
-constexpr int kBwdUnroll = 16;
-constexpr int kVqRegs = 8;   // n_cot * 8 * tg / 1024 <= 4 * 2048 / 1024
-
-__global__ __launch_bounds__(kBwdThreads) void k_bwd_stream(BwdStream P) {
-    extern __shared__ __align__(16) unsigned char smem[];
-    const int half_trials = 8 * P.tg;
-    uint2 *tbr = reinterpret_cast<uint2 *>(smem);                                       // [1024]
-    int64_t *vql = reinterpret_cast<int64_t *>(smem + 1024 * sizeof(uint2));           // [n_cot][half_trials]
-    unsigned long long *wl = reinterpret_cast<unsigned long long *>(
-        smem + 1024 * sizeof(uint2) + static_cast<size_t>(P.n_cot) * half_trials * sizeof(int64_t));   // [n_cot][capw]
-
-    const int r = blockIdx.x / P.n_parts, part = blockIdx.x % P.n_parts, j = blockIdx.y;
-    const int tid = threadIdx.x, lane = tid & 63;
-    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int s = r >> 1, hf = r & 1;
-    const OccTables T = P.tabs[j];
-    const uint2 *gbr = T.br + static_cast<size_t>(s) * kSrWords + hf * 1024;
-    const uint32_t base = gbr[0].y;
-    const uint32_t end = hf ? static_cast<uint32_t>(T.count[s]) : T.br[static_cast<size_t>(s) * kSrWords + 1024].y;
-    const uint32_t hot = end - base;
-    for (int i = tid; i < 1024; i += blockDim.x) {
-        const uint2 q = gbr[i];
-        tbr[i] = make_uint2(q.x, q.y - base);
-    }
-    const uint32_t inl = min(hot, static_cast<uint32_t>(P.capw));
-    for (int c = 0; c < P.n_cot; ++c)
-        for (uint32_t i = tid; i < inl; i += blockDim.x) wl[c * P.capw + i] = 0ull;
-    int64_t *wgp = P.wg + (static_cast<size_t>(j) * P.n_cot * P.n_parts + part) * P.wg_stride +
-                   static_cast<size_t>(s) * kSr + base;
-    const size_t cstride = static_cast<size_t>(P.n_parts) * P.wg_stride;
-    for (int c = 0; c < P.n_cot; ++c)
-        for (uint32_t i = inl + tid; i < hot; i += blockDim.x) wgp[c * cstride + i] = 0;
-
-    const int nb = P.b_hi - P.b_lo;
-    const int per = (nb + P.n_parts - 1) / P.n_parts;
-    const int pb0 = P.b_lo + part * per, pb1 = min(P.b_hi, pb0 + per);
-    const int nph = 2 * max(0, pb1 - pb0);
-    const int G = P.n_ranges;
-    const int nv = P.n_cot * half_trials;
-
-    // weights of phase q into registers
-    int64_t vreg[kVqRegs];
-    auto load_vq = [&](int q) {
-        const int64_t tfirst = static_cast<int64_t>(pb0 + q / 2) * P.tb + static_cast<int64_t>(8 * (q & 1)) * P.tg;
+// (5) W(e) = sum of v_t over the occurrences (t, e), per hot event, as a
+// gather over the event-major YET.  Workgroup i works on trial slice i mod 8
+// only, which keeps its gathers of v in the L2 of one XCD; each thread owns
+// one hot event at a time and sums its list in registers; the eight slice
+// sums meet in one integer atomic add per (event, row), exact in any order.
+template <int CS>
+__global__ __launch_bounds__(256) void k_bwd_w(BwdGather P) {
+    constexpr int kU = 8;
+    const int x = blockIdx.x % kSlices, wi = blockIdx.x / kSlices, nw = gridDim.x / kSlices, j = blockIdx.y;
+    const int64_t tx0 = static_cast<int64_t>(x) * P.slice_trials;
+    const int64_t ulo = max<int64_t>(P.t0 - tx0, 0), uhi = min<int64_t>(P.t1 - tx0, P.slice_trials);
+    if (uhi <= ulo) return;   // the slice lies outside the call's trials
+    const uint32_t u0 = static_cast<uint32_t>(ulo), span = static_cast<uint32_t>(uhi - ulo);
+    const int64_t *vq = P.vq + (static_cast<size_t>(j) * P.n + static_cast<size_t>(tx0 + ulo - P.t0)) * CS;
+    const int H = P.hot_base[static_cast<size_t>(j) * (P.n_sr + 1) + P.n_sr];
+    const int32_t *hev = P.hot_ev + static_cast<size_t>(j) * P.catalog;
+    const int64_t *off = P.tr_off + static_cast<int64_t>(x) * P.catalog;
+    int64_t *Wj = P.W + static_cast<size_t>(j) * P.n_cot * P.catalog;
+    for (int g = wi * blockDim.x + threadIdx.x; g < H; g += nw * blockDim.x) {
+        const int e = hev[g];
+        const int64_t o0 = off[e], o1 = off[e + 1];
+        int64_t acc[CS];
 #pragma unroll
-        for (int k = 0; k < kVqRegs; ++k) {
-            const int idx = tid + k * kBwdThreads;
-            int64_t v = 0;
-            if (idx < nv) {
-                const int c = idx / half_trials, i = idx - c * half_trials;
-                const int64_t t = tfirst + i;
-                if (t >= P.t0 && t < P.t1) v = P.vq[(static_cast<size_t>(c) * P.n_layers + j) * P.n + (t - P.t0)];
-            }
-            vreg[k] = v;
-        }
-    };
-    // this wavefront's share of phase q: half the steps of one segment
-    auto meta = [&](int q, int64_t &sbq, int &a, int &bnd) {
-        const int bq = pb0 + q / 2, g = 8 * (q & 1) + (w >> 1);
-        const size_t si = (static_cast<size_t>(bq) * G + r) * kGroups + g;
-        const int R = P.seg_run[si];
-        sbq = P.seg_base[si];
-        const int mid = (R + 1) >> 1;
-        a = (w & 1) ? mid : 0;
-        bnd = (w & 1) ? R : mid;
-    };
-    const uint32_t pad = pad_entry(P.tb);
-    uint32_t X[kBwdUnroll];
-    auto chunk = [&](int64_t sbq, int from, int to) {
+        for (int c = 0; c < CS; ++c) acc[c] = 0;
+        for (int64_t i = o0; i < o1; i += kU) {
+            uint32_t d[kU];
 #pragma unroll
-        for (int u = 0; u < kBwdUnroll; ++u)
-            X[u] = (from + u < to) ? __builtin_nontemporal_load(P.ent + sbq + static_cast<int64_t>(from + u) * kWave + lane)
-                                   : pad;
-    };
-    const bool all_lds = hot <= static_cast<uint32_t>(P.capw);   // uniform over the workgroup
-
-    int64_t sb_c = 0, sb_n = 0;
-    int a_c = 0, b_c = 0, a_n = 0, b_n = 0;
-    if (nph > 0) {
-        meta(0, sb_c, a_c, b_c);
-        chunk(sb_c, a_c, b_c);
-        load_vq(0);
-    }
-    for (int ph = 0; ph < nph; ++ph) {
-        if (ph + 1 < nph) meta(ph + 1, sb_n, a_n, b_n);
-        __syncthreads();   // every wave is done with the previous phase's weights
+            for (int v = 0; v < kU; ++v) d[v] = (i + v < o1) ? P.tr_ent[i + v] - u0 : span;   // span = skip
 #pragma unroll
-        for (int k = 0; k < kVqRegs; ++k) {
-            const int idx = tid + k * kBwdThreads;
-            if (idx < nv) vql[idx] = vreg[k];
-        }
-        __syncthreads();
-        if (ph + 1 < nph) load_vq(ph + 1);
-        const uint32_t tl0 = static_cast<uint32_t>(8 * (ph & 1)) * P.tg;
-        int st = a_c;
-        bool prefetched_next = false;
-        while (st < b_c) {
-            uint32_t Y[kBwdUnroll];
+            for (int v = 0; v < kU; ++v) {
+                if (d[v] < span) {
+                    const int64_t *q = vq + static_cast<size_t>(d[v]) * CS;
+                    if constexpr (CS == 1) {
+                        acc[0] += q[0];
+                    } else {
 #pragma unroll
-            for (int u = 0; u < kBwdUnroll; ++u) Y[u] = X[u];
-            const int nst = st + kBwdUnroll;
-            if (nst < b_c) {
-                chunk(sb_c, nst, b_c);
-            } else if (ph + 1 < nph) {
-                chunk(sb_n, a_n, b_n);
-                prefetched_next = true;
-            }
-            // branch-free lookups of all entries, then the masked accumulation
-            uint2 q[kBwdUnroll];
-#pragma unroll
-            for (int u = 0; u < kBwdUnroll; ++u) q[u] = tbr[(Y[u] & (kRange - 1)) >> 5];
-            uint32_t rk[kBwdUnroll], ti[kBwdUnroll];
-            bool on[kBwdUnroll];
-#pragma unroll
-            for (int u = 0; u < kBwdUnroll; ++u) {
-                const uint32_t bit = Y[u] & 31;
-                ti[u] = (Y[u] >> kRangeBits) - tl0;
-                on[u] = ((q[u].x >> bit) & 1u) && ti[u] < static_cast<uint32_t>(half_trials);   // padding is off
-                rk[u] = q[u].y + __popc(q[u].x & ((1u << bit) - 1u));
-            }
-            for (int c = 0; c < P.n_cot; ++c) {
-                int64_t v[kBwdUnroll];
-#pragma unroll
-                for (int u = 0; u < kBwdUnroll; ++u) v[u] = vql[c * half_trials + (on[u] ? ti[u] : 0)];
-#pragma unroll
-                for (int u = 0; u < kBwdUnroll; ++u) {
-                    if (!(on[u] && v[u] != 0)) continue;
-                    if (all_lds || rk[u] < static_cast<uint32_t>(P.capw))
-                        atomicAdd(&wl[c * P.capw + rk[u]], static_cast<unsigned long long>(v[u]));
-                    else
-                        atomicAdd(reinterpret_cast<unsigned long long *>(&wgp[c * cstride + rk[u]]),
-                                  static_cast<unsigned long long>(v[u]));
+                        for (int h = 0; h < CS; h += 2) {
+                            const longlong2 t = *reinterpret_cast<const longlong2 *>(q + h);
+                            acc[h] += t.x;
+                            acc[h + 1] += t.y;
+                        }
+                    }
                 }
             }
-            st = nst;
         }
-        if (!prefetched_next && ph + 1 < nph) chunk(sb_n, a_n, b_n);
-        sb_c = sb_n;
-        a_c = a_n;
-        b_c = b_n;
+#pragma unroll
+        for (int c = 0; c < CS; ++c)
+            if (c < P.n_cot && acc[c] != 0)
+                atomicAdd(reinterpret_cast<unsigned long long *>(&Wj[static_cast<size_t>(c) * P.catalog + g]),
+                          static_cast<unsigned long long>(acc[c]));
     }
-    __syncthreads();
-    for (int c = 0; c < P.n_cot; ++c)
-        for (uint32_t i = tid; i < inl; i += blockDim.x) wgp[c * cstride + i] = static_cast<int64_t>(wl[c * P.capw + i]);
 }
 
 struct BwdGrad {
@@ -311,9 +259,9 @@ struct BwdGrad {
     const int32_t *elt_off, *elt_ids;
     const double *elt_terms, *layer_terms;
     const OccTables *tabs;
-    const int64_t *wg;
-    size_t wg_stride;
-    int32_t n_parts, n_cot, n_chunks;   // chunks = n_sr * kChunks
+    const int64_t *W;              // [n_layers][n_cot][catalog] by hot index
+    const int32_t *hot_base;       // [n_layers][n_sr + 1]
+    int32_t n_sr, n_cot, n_chunks;   // chunks = n_sr * kChunks
     const VScale *vs;
     double *part_elt;    // [n_layers][n_chunks][kMaxJ][n_cot][3]
     double *part_occ;    // [n_layers][n_chunks][n_cot][2]
@@ -356,6 +304,7 @@ __global__ __launch_bounds__(kBwdThreads) void k_bwd_grad(BwdGrad P) {
     int local[4];
     double po[kMaxCot][2];
     for (int c = 0; c < kMaxCot; ++c) po[c][0] = po[c][1] = 0.0;
+    const int32_t hb = P.hot_base[static_cast<size_t>(j) * (P.n_sr + 1) + s];
     for (int it = 0; it < 4; ++it) {
         local[it] = it * 1024 + tid;
         const int wip = local[it] >> 5, bit = local[it] & 31;
@@ -366,10 +315,7 @@ __global__ __launch_bounds__(kBwdThreads) void k_bwd_grad(BwdGrad P) {
         const uint32_t rk = q.y + __popc(q.x & ((1u << bit) - 1u));
         const double O = T.vals[static_cast<size_t>(s) * kSr + rk];
         for (int c = 0; c < P.n_cot; ++c) {
-            const int64_t *wc = P.wg + (static_cast<size_t>(j) * P.n_cot + c) * P.n_parts * P.wg_stride +
-                                static_cast<size_t>(s) * kSr + rk;
-            int64_t acc = 0;
-            for (int pt = 0; pt < P.n_parts; ++pt) acc += wc[static_cast<size_t>(pt) * P.wg_stride];
+            const int64_t acc = P.W[(static_cast<size_t>(j) * P.n_cot + c) * P.catalog + hb + rk];
             W[it][c] = ldexp(static_cast<double>(acc), -P.vs[j * P.n_cot + c].sigma);
         }
         lin_occ[it] = O < occL;
@@ -488,8 +434,7 @@ __global__ __launch_bounds__(256) void k_bwd_final(const int32_t *__restrict__ e
 
 struct BwdLayout {
     OccLayoutSizes z;
-    int n_parts, nwg_v, n_chunks;
-    size_t wg_stride;
+    int nwg_v, n_chunks, cs;
     size_t bytes;
 };
 
@@ -497,18 +442,17 @@ static int bwd_nwg_v(int64_t n) {
     return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>((n + 8191) / 8192, 512)));
 }
 
-static BwdLayout bwd_layout(const ara_tables *tables, const ara_yet *yet, const ara_layers *layers, int n_cot,
-                            int64_t n) {
+static int bwd_cs(int n_cot) { return n_cot <= 1 ? 1 : (n_cot <= 2 ? 2 : 4); }
+
+static BwdLayout bwd_layout(const ara_tables *tables, const ara_layers *layers, int n_cot, int64_t n) {
     BwdLayout B{};
     B.z = occ_sizes(tables->catalog, false);
     const int L = layers->n_layers;
     const int nJ = L > 0 ? layers->elt_off[L] : 0;
-    const int cu = device_cu_count();
-    // one workgroup per CU at most (they need all of its LDS): parts = CUs / ranges
-    B.n_parts = std::max(1, std::min(std::max(yet->n_blocks, 1), cu / std::max(yet->n_ranges, 1)));
     B.nwg_v = bwd_nwg_v(n);
     B.n_chunks = B.z.n_sr * kChunks;
-    B.wg_stride = static_cast<size_t>(B.z.n_sr) * kSr;
+    B.cs = bwd_cs(n_cot);
+    const size_t cat = static_cast<size_t>(tables->catalog);
     Carver c(nullptr);
     c.take<int32_t>(kWsHeaderBytes / 4);
     c.take<int32_t>(static_cast<size_t>(L + 1));
@@ -518,8 +462,10 @@ static BwdLayout bwd_layout(const ara_tables *tables, const ara_yet *yet, const 
     Carver d(nullptr);
     d.take<VScale>(static_cast<size_t>(std::max(L * n_cot, 1)));
     d.take<double>(static_cast<size_t>(L) * n_cot * B.nwg_v * 2);
-    d.take<int64_t>(static_cast<size_t>(n_cot) * L * std::max<int64_t>(n, 1));
-    d.take<int64_t>(static_cast<size_t>(L) * n_cot * B.n_parts * B.wg_stride);
+    d.take<int64_t>(static_cast<size_t>(L) * std::max<int64_t>(n, 1) * B.cs);
+    d.take<int32_t>(static_cast<size_t>(L) * cat);
+    d.take<int32_t>(static_cast<size_t>(L) * (B.z.n_sr + 1));
+    d.take<int64_t>(static_cast<size_t>(L) * n_cot * cat);
     d.take<double>(static_cast<size_t>(L) * B.n_chunks * kMaxJ * n_cot * 3);
     d.take<double>(static_cast<size_t>(L) * B.n_chunks * n_cot * 2);
     B.bytes = b + d.bytes();
@@ -530,6 +476,8 @@ static int32_t check_pair_b(const ara_tables *tables, const ara_yet *yet) {
     if (!tables || !yet) return fail(ARA_E_INVAL, "null tables or yet");
     if (tables->catalog != yet->catalog) return fail(ARA_E_INVAL, "tables and YET use different catalogues");
     if (yet->range_bits != kRangeBits || yet->groups != kGroups) return fail(ARA_E_INVAL, "YET not prepared by this library");
+    if (yet->n_slices != kSlices || !yet->tr_off || (yet->nnz > 0 && !yet->tr_ent))
+        return fail(ARA_E_INVAL, "the backward needs a YET prepared with ARA_PREP_TRANSPOSED");
     return ARA_OK;
 }
 
@@ -544,7 +492,7 @@ extern "C" int32_t ara_ylt_backward_workspace_bytes(const ara_tables *tables, co
     if (rc) return rc;
     if ((rc = check_layers(layers, tables->n_elts))) return rc;
     if (n_cot < 1 || n_cot > kMaxCot) return fail(ARA_E_LIMIT, "cotangent rows must be 1..ARA_MAX_COTANGENTS");
-    *bytes = bwd_layout(tables, yet, layers, n_cot, yet->n_trials).bytes;
+    *bytes = bwd_layout(tables, layers, n_cot, yet->n_trials).bytes;
     return ARA_OK;
 }
 
@@ -564,7 +512,7 @@ extern "C" int32_t ara_ylt_backward(const ara_tables *tables, const ara_yet *yet
     if (L > 0 && n > 0 && (!s_pre || !grad_ylt || !elt_terms || !layer_terms))
         return fail(ARA_E_INVAL, "null input");
     // workspace sized for the full trial range is valid for any sub-range
-    const BwdLayout B = bwd_layout(tables, yet, layers, n_cot, yet->n_trials);
+    const BwdLayout B = bwd_layout(tables, layers, n_cot, yet->n_trials);
     if (ws_bytes < B.bytes) return fail(ARA_E_NOSPACE, "backward workspace too small");
     hipStream_t st = static_cast<hipStream_t>(stream);
     ARA_HIP(hipMemsetAsync(ws, 0, kWsHeaderBytes, st));
@@ -582,8 +530,10 @@ extern "C" int32_t ara_ylt_backward(const ara_tables *tables, const ara_yet *yet
     for (int j = 0; j < L; ++j) tabs[j] = occ_carve(c, B.z, false);
     VScale *vs = c.take<VScale>(static_cast<size_t>(L * n_cot));
     double *aggpart = c.take<double>(static_cast<size_t>(L) * n_cot * bwd_nwg_v(n) * 2);
-    int64_t *vq = c.take<int64_t>(static_cast<size_t>(n_cot) * L * n);
-    int64_t *wgb = c.take<int64_t>(static_cast<size_t>(L) * n_cot * B.n_parts * B.wg_stride);
+    int64_t *vq = c.take<int64_t>(static_cast<size_t>(L) * n * B.cs);
+    int32_t *hot_ev = c.take<int32_t>(static_cast<size_t>(L) * tables->catalog);
+    int32_t *hot_base = c.take<int32_t>(static_cast<size_t>(L) * (B.z.n_sr + 1));
+    int64_t *W = c.take<int64_t>(static_cast<size_t>(L) * n_cot * tables->catalog);
     double *part_elt = c.take<double>(static_cast<size_t>(L) * B.n_chunks * kMaxJ * n_cot * 3);
     double *part_occ = c.take<double>(static_cast<size_t>(L) * B.n_chunks * n_cot * 2);
     ARA_HIP(hipMemsetAsync(vs, 0, static_cast<size_t>(L * n_cot) * sizeof(VScale), st));
@@ -601,39 +551,33 @@ extern "C" int32_t ara_ylt_backward(const ara_tables *tables, const ara_yet *yet
         ProfScope prof(ARA_PROF_BWD_RED, st);
         k_bwd_vmax<<<dim3(nwg_v, L), kBwdThreads, 0, st>>>(grad_ylt, s_pre, layer_terms, n, L, n_cot, nwg_v, vs, aggpart);
         const unsigned gx = static_cast<unsigned>(std::min<int64_t>((n + 255) / 256, 2048));
-        k_bwd_vq<<<dim3(gx, L), 256, 0, st>>>(grad_ylt, s_pre, layer_terms, n, L, n_cot, yet->max_occ, vs, vq);
+        k_bwd_vq<<<dim3(gx, L), 256, 0, st>>>(grad_ylt, s_pre, layer_terms, n, L, n_cot, B.cs, yet->max_occ, vs, vq);
+        k_bwd_hot<<<dim3(B.z.n_sr, L), 256, 0, st>>>(d_tabs, B.z.n_sr, n_cot, tables->catalog, hot_ev, hot_base, W);
         ARA_HIP(hipGetLastError());
     }
-    BwdStream S{};
-    S.ent = yet->ent;
-    S.seg_base = yet->seg_base;
-    S.seg_run = yet->seg_run;
+    BwdGather S{};
+    S.tr_off = yet->tr_off;
+    S.tr_ent = yet->tr_ent;
+    S.catalog = tables->catalog;
+    S.n_sr = B.z.n_sr;
+    S.n_cot = n_cot;
+    S.slice_trials = yet->slice_trials;
     S.t0 = trial_begin;
     S.t1 = trial_end;
     S.n = n;
-    S.tg = yet->trials_per_group;
-    S.tb = yet->trials_per_block;
-    S.n_ranges = yet->n_ranges;
-    S.n_parts = B.n_parts;
-    S.n_cot = n_cot;
-    S.n_layers = L;
-    S.b_lo = static_cast<int32_t>(trial_begin / yet->trials_per_block);
-    S.b_hi = static_cast<int32_t>((trial_end + yet->trials_per_block - 1) / yet->trials_per_block);
-    const size_t fixed = 1024 * sizeof(uint2) + static_cast<size_t>(n_cot) * 8 * yet->trials_per_group * sizeof(int64_t);
-    S.capw = static_cast<int32_t>((kLds - fixed) / (static_cast<size_t>(n_cot) * sizeof(int64_t)));
-    S.tabs = d_tabs;
+    S.hot_ev = hot_ev;
+    S.hot_base = hot_base;
     S.vq = vq;
-    S.wg = wgb;
-    S.wg_stride = B.wg_stride;
+    S.W = W;
     {
         ProfScope prof(ARA_PROF_BWD, st);
-        static bool attr = false;
-        if (!attr) {
-            ARA_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_bwd_stream),
-                                        hipFuncAttributeMaxDynamicSharedMemorySize, kLds));
-            attr = true;
-        }
-        k_bwd_stream<<<dim3(yet->n_ranges * B.n_parts, L), kBwdThreads, kLds, st>>>(S);
+        // four 256-thread workgroups per CU, a multiple of the slice count
+        const int cu = device_cu_count();
+        const unsigned gx = static_cast<unsigned>(kSlices * std::max(1, (4 * cu) / kSlices));
+        const dim3 grid(gx, L);
+        if (B.cs == 1) k_bwd_w<1><<<grid, 256, 0, st>>>(S);
+        else if (B.cs == 2) k_bwd_w<2><<<grid, 256, 0, st>>>(S);
+        else k_bwd_w<4><<<grid, 256, 0, st>>>(S);
         ARA_HIP(hipGetLastError());
     }
     BwdGrad Gp{};
@@ -646,9 +590,9 @@ extern "C" int32_t ara_ylt_backward(const ara_tables *tables, const ara_yet *yet
     Gp.elt_terms = elt_terms;
     Gp.layer_terms = layer_terms;
     Gp.tabs = d_tabs;
-    Gp.wg = wgb;
-    Gp.wg_stride = B.wg_stride;
-    Gp.n_parts = B.n_parts;
+    Gp.W = W;
+    Gp.hot_base = hot_base;
+    Gp.n_sr = B.z.n_sr;
     Gp.n_cot = n_cot;
     Gp.n_chunks = B.n_chunks;
     Gp.vs = vs;

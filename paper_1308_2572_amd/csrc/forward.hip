@@ -4,8 +4,12 @@
 //
 // One workgroup per block of trials; wavefront g owns trial group g of the
 // block.  The per-trial totals live in LDS for the whole pass over the
-// catalogue (one super-range table at a time), so each trial's total is
-// accumulated by a single wavefront in a fixed order: deterministic.
+// catalogue, so each trial's total is accumulated by a single wavefront in a
+// fixed order: deterministic.  The catalogue is walked one range (2^15
+// events) at a time; the range's slice of the occurrence table (bitmap words
+// with ranks, then the values) sits in one of two LDS buffers, and the next
+// range's slice is copied into the other buffer by LDS DMA
+// (global_load_lds_dwordx4) while the current range streams.
 #include "occ.h"
 
 #include <algorithm>
@@ -15,25 +19,54 @@ namespace ara {
 
 constexpr int kUnroll = 16;
 constexpr int kLdsBytes = 160 * 1024;
+constexpr int kBrBytes = 1024 * static_cast<int>(sizeof(uint2));   // one range's bitmap words with ranks
 
 struct FwdParams {
     const uint32_t *ent;
     const int64_t *seg_base;
     const int32_t *seg_run;
     int64_t n_trials;
-    int32_t tg, tb, n_ranges, n_sr;
-    int32_t cap;               // values held in LDS per super-range
+    int32_t tg, tb, n_ranges;
+    int32_t capv;              // values per range buffer
+    int32_t buf_bytes;         // bytes per range buffer
     const FwdItem *items;      // one (layer, block of trials) per workgroup
 };
 
 __device__ __forceinline__ uint32_t ld_stream(const uint32_t *p) { return __builtin_nontemporal_load(p); }
 
-// LDS bytes before the values: per-trial totals (and hit counts) including
-// the padding slot, then the super-range's bitmap words with ranks.
-__host__ __device__ inline size_t fwd_fixed_lds(int tb, bool hits) {
-    return align256(static_cast<size_t>(tb + 1) * 8 + (hits ? static_cast<size_t>(tb + 1) * 4 : 0)) +
-           kSrWords * sizeof(uint2);
+// 16 bytes per lane from global memory straight into LDS at lds_base + 16 *
+// lane (lds_base uniform over the wavefront).  Issued as inline assembly so
+// that the compiler does not make the next LDS reads wait for it: the
+// kernel waits for these copies itself (vmcnt(0) before the barrier that
+// publishes the buffer).  The wait counts the compiler computes for its own
+// loads stay sufficient, since an extra outstanding load only makes them
+// stricter.
+__device__ __forceinline__ void lds_dma16(const void *src, uint32_t lds_base) {
+    asm volatile("s_mov_b32 m0, %0\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %1, off"
+                 :
+                 : "s"(__builtin_amdgcn_readfirstlane(lds_base)), "v"(src)
+                 : "memory", "m0");
 }
+
+__device__ __forceinline__ void wait_dma() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+
+// LDS bytes of the per-trial totals (and hit counts), including the padding
+// slot; the table counts of every range; each wavefront's window of 64
+// segment descriptors (run length, base) -- descriptors come from LDS so that
+// moving to the next range never waits on the vector memory counter, which
+// also counts the prefetched stream.
+__host__ __device__ inline size_t fwd_acc_lds(int tb, bool hits) {
+    return align256(static_cast<size_t>(tb + 1) * 8 + (hits ? static_cast<size_t>(tb + 1) * 4 : 0));
+}
+__host__ __device__ inline size_t fwd_meta_lds(int n_ranges) {
+    return align256(static_cast<size_t>(n_ranges) * 8) + align256(static_cast<size_t>(kGroups) * kWave * 12);
+}
+
+// Range r of the catalogue is half (r & 1) of occurrence-table super-range
+// r >> 1; its set events have super-range ranks [base, base + cnt).
+struct RangeInfo {
+    uint32_t base, cnt;
+};
 
 template <bool HITS>
 __global__ __launch_bounds__(1024) void k_fwd(FwdParams P) {
@@ -41,10 +74,13 @@ __global__ __launch_bounds__(1024) void k_fwd(FwdParams P) {
     const int tb = P.tb;
     double *acc = reinterpret_cast<double *>(smem);                                     // [tb + 1]
     int32_t *hacc = reinterpret_cast<int32_t *>(smem + static_cast<size_t>(tb + 1) * 8);   // [tb + 1]
-    const size_t tbr_off = fwd_fixed_lds(tb, HITS) - kSrWords * sizeof(uint2);
-    uint2 *tbr = reinterpret_cast<uint2 *>(smem + tbr_off);
-    double *tvals = reinterpret_cast<double *>(smem + tbr_off + kSrWords * sizeof(uint2));
-    uint8_t *tcnt = reinterpret_cast<uint8_t *>(tvals + P.cap);
+    const int G = P.n_ranges;
+    uint2 *rinfo = reinterpret_cast<uint2 *>(smem + fwd_acc_lds(tb, HITS));                     // [G] (base, cnt)
+    unsigned char *meta2 = smem + fwd_acc_lds(tb, HITS) + align256(static_cast<size_t>(G) * 8);
+    int64_t *wbase_all = reinterpret_cast<int64_t *>(meta2);                                    // [16][64]
+    int32_t *wrun_all = reinterpret_cast<int32_t *>(meta2 + kGroups * kWave * 8);               // [16][64]
+    unsigned char *bufs = smem + fwd_acc_lds(tb, HITS) + fwd_meta_lds(G);
+    const uint32_t bufs_lds = static_cast<uint32_t>(reinterpret_cast<uintptr_t>(bufs));
 
     const FwdItem I = P.items[blockIdx.x];
     const int tid = threadIdx.x, lane = tid & 63;
@@ -54,7 +90,6 @@ __global__ __launch_bounds__(1024) void k_fwd(FwdParams P) {
     const int64_t gt0 = b * tb + static_cast<int64_t>(w) * P.tg;
     const int64_t gt1 = min(gt0 + P.tg, P.n_trials);
     const bool active = gt0 < gt1 && gt1 > I.t0 && gt0 < I.t1;
-    const int G = P.n_ranges;
     const size_t seg0 = static_cast<size_t>(b) * G * kGroups + w;
 
     for (int i = tid; i <= tb; i += blockDim.x) {   // slot tb collects the padding
@@ -63,16 +98,78 @@ __global__ __launch_bounds__(1024) void k_fwd(FwdParams P) {
     }
     const OccTables T = *I.tab;
 
-    // stream cursor over this wave's segments (range rr, step within it)
+    // copy range r's table slice into buffer k, split over the wavefronts
+    auto fetch = [&](int r, RangeInfo ri, int k) {
+        const uint32_t dst = bufs_lds + static_cast<uint32_t>(k * P.buf_bytes);
+        const size_t s = static_cast<size_t>(r >> 1);
+        const unsigned char *gbr = reinterpret_cast<const unsigned char *>(T.br + s * kSrWords + (r & 1) * 1024);
+        for (int c0 = w * kWave; c0 < kBrBytes / 16; c0 += kGroups * kWave)
+            lds_dma16(gbr + static_cast<size_t>(c0 + lane) * 16, dst + c0 * 16);
+        const uint32_t nv = min(ri.cnt + (ri.base & 1u), static_cast<uint32_t>(P.capv));
+        const int nvc = static_cast<int>((nv + 1) / 2);
+        const unsigned char *gv = reinterpret_cast<const unsigned char *>(T.vals + s * kSr + (ri.base & ~1u));
+        for (int c0 = w * kWave; c0 < nvc; c0 += kGroups * kWave)
+            if (c0 + lane < nvc) lds_dma16(gv + static_cast<size_t>(c0 + lane) * 16, dst + kBrBytes + c0 * 16);
+        if (HITS) {
+            const uint32_t nb = min(ri.cnt + (ri.base & 15u), static_cast<uint32_t>(P.capv));
+            const int nbc = static_cast<int>((nb + 15) / 16);
+            const unsigned char *gc = T.cnt + s * kSr + (ri.base & ~15u);
+            const uint32_t cdst = dst + kBrBytes + static_cast<uint32_t>(P.capv) * 8;
+            for (int c0 = w * kWave; c0 < nbc; c0 += kGroups * kWave)
+                if (c0 + lane < nbc) lds_dma16(gc + static_cast<size_t>(c0 + lane) * 16, cdst + c0 * 16);
+        }
+    };
+
+    for (int r = tid; r < G; r += blockDim.x) {
+        const size_t sr = static_cast<size_t>(r >> 1);
+        const uint32_t mid = T.br[sr * kSrWords + 1024].y;
+        const uint32_t tot = static_cast<uint32_t>(T.count[sr]);
+        rinfo[r] = (r & 1) ? make_uint2(mid, tot - mid) : make_uint2(0u, mid);
+    }
+    auto range_info = [&](int r) {   // uniform
+        const uint2 v = rinfo[r];
+        RangeInfo ri;
+        ri.base = __builtin_amdgcn_readfirstlane(v.x);
+        ri.cnt = __builtin_amdgcn_readfirstlane(v.y);
+        return ri;
+    };
+
+    // stream cursor over this wave's segments (range rr, step within it); the
+    // descriptors of 64 consecutive ranges are staged in this wave's LDS window
+    int64_t *wbase = wbase_all + w * kWave;
+    int32_t *wrun = wrun_all + w * kWave;
+    int seg_win = -kWave;
+    uint64_t nonempty = 0;
     int rr = active ? 0 : G, step = 0, R = 0;
     int64_t sb = 0;
-    auto seek = [&]() {
+    auto seek = [&]() {   // first range >= rr in which this wave has entries
         while (rr < G) {
-            const size_t si = seg0 + static_cast<size_t>(rr) * kGroups;
-            R = P.seg_run[si];
-            sb = P.seg_base[si];
-            if (R > 0) break;
-            ++rr;
+            if (rr >= seg_win + kWave) {
+                seg_win = rr & ~(kWave - 1);
+                const int r = seg_win + lane;
+                int32_t run = 0;
+                int64_t base = 0;
+                if (r < G) {
+                    const size_t si = seg0 + static_cast<size_t>(r) * kGroups;
+                    run = P.seg_run[si];
+                    base = P.seg_base[si];
+                }
+                wrun[lane] = run;
+                wbase[lane] = base;
+                nonempty = __ballot(run > 0);
+            }
+            const uint64_t m = nonempty & (~0ull << (rr - seg_win));
+            if (m) {
+                const int l = __builtin_ctzll(m);
+                rr = seg_win + l;
+                R = __builtin_amdgcn_readfirstlane(wrun[l]);
+                const int64_t bv = wbase[l];
+                sb = static_cast<int64_t>(
+                    (static_cast<uint64_t>(__builtin_amdgcn_readfirstlane(static_cast<uint32_t>(static_cast<uint64_t>(bv) >> 32))) << 32) |
+                    __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(bv)));
+                return;
+            }
+            rr = seg_win + kWave;
         }
     };
     uint32_t X[kUnroll];
@@ -91,34 +188,45 @@ __global__ __launch_bounds__(1024) void k_fwd(FwdParams P) {
             }
         }
     };
+
+    __syncthreads();   // range table counts published
+    RangeInfo cur = range_info(0);
+    fetch(0, cur, 0);
     seek();
     load();
+    wait_dma();
+    __syncthreads();
 
-    for (int s = 0; s < P.n_sr; ++s) {
-        __syncthreads();
-        const int cnt_s = T.count[s];
-        const int inl = min(cnt_s, P.cap);
-        const uint2 *gbr = T.br + static_cast<size_t>(s) * kSrWords;
-        const double *gvals = T.vals + static_cast<size_t>(s) * kSr;
-        const uint8_t *gcnt = HITS ? T.cnt + static_cast<size_t>(s) * kSr : nullptr;
-        for (int i = tid; i < kSrWords; i += blockDim.x) tbr[i] = gbr[i];
-        for (int i = tid; i < inl; i += blockDim.x) tvals[i] = gvals[i];
-        if (HITS)
-            for (int i = tid; i < inl; i += blockDim.x) tcnt[i] = gcnt[i];
-        __syncthreads();
-        const int rr_end = min(2 * s + 2, G);
-        const bool all_lds = cnt_s <= P.cap;     // uniform over the workgroup
-        while (chunk_rr < rr_end) {
+    for (int r = 0; r < G; ++r) {
+        const int k = r & 1;
+        unsigned char *buf = bufs + static_cast<size_t>(k) * P.buf_bytes;
+        const uint2 *tbr = reinterpret_cast<const uint2 *>(buf);
+        const double *tvals = reinterpret_cast<const double *>(buf + kBrBytes);
+        const uint8_t *tcnt = buf + kBrBytes + static_cast<size_t>(P.capv) * 8;
+        const size_t s = static_cast<size_t>(r >> 1);
+        const double *gvals = T.vals + s * kSr;
+        const uint8_t *gcnt = HITS ? T.cnt + s * kSr : nullptr;
+        const uint32_t vsh = cur.base & ~1u, csh = cur.base & ~15u;
+        // values with buffer index below vlim (and counts below clim) are in LDS
+        const uint32_t vlim = static_cast<uint32_t>(P.capv), clim = static_cast<uint32_t>(P.capv);
+        const bool all_lds = cur.cnt + (cur.base & 15u) <= static_cast<uint32_t>(P.capv);   // uniform
+        RangeInfo nxt{0, 0};
+        if (r + 1 < G) nxt = range_info(r + 1);
+        bool fetched = r + 1 >= G;
+        while (chunk_rr == r) {
             uint32_t Y[kUnroll];
 #pragma unroll
             for (int u = 0; u < kUnroll; ++u) Y[u] = X[u];
-            const uint32_t hb = static_cast<uint32_t>(chunk_rr & 1) << kRangeBits;
-            load();   // prefetch the next chunk (possibly of the next super-range)
+            load();   // prefetch the next chunk (possibly of a later range)
+            if (!fetched) {   // after the first chunk's loads: the range info has arrived
+                fetch(r + 1, nxt, k ^ 1);
+                fetched = true;
+            }
             // lookups first, without branches, so the LDS reads of all
             // entries are in flight together; then the masked accumulation
             uint2 q[kUnroll];
 #pragma unroll
-            for (int u = 0; u < kUnroll; ++u) q[u] = tbr[(hb | (Y[u] & (kRange - 1))) >> 5];
+            for (int u = 0; u < kUnroll; ++u) q[u] = tbr[(Y[u] & (kRange - 1)) >> 5];
             uint32_t rank[kUnroll];
             bool hit[kUnroll];
 #pragma unroll
@@ -130,34 +238,35 @@ __global__ __launch_bounds__(1024) void k_fwd(FwdParams P) {
             if (all_lds) {
                 double v[kUnroll];
 #pragma unroll
-                for (int u = 0; u < kUnroll; ++u) v[u] = tvals[hit[u] ? rank[u] : 0];
+                for (int u = 0; u < kUnroll; ++u) v[u] = tvals[hit[u] ? rank[u] - vsh : 0];
 #pragma unroll
                 for (int u = 0; u < kUnroll; ++u)
                     if (hit[u]) {
                         atomicAdd(&acc[Y[u] >> kRangeBits], v[u]);
-                        if (HITS) atomicAdd(&hacc[Y[u] >> kRangeBits], static_cast<int>(tcnt[rank[u]]));
+                        if (HITS) atomicAdd(&hacc[Y[u] >> kRangeBits], static_cast<int>(tcnt[rank[u] - csh]));
                     }
             } else {
 #pragma unroll
                 for (int u = 0; u < kUnroll; ++u)
                     if (hit[u]) {
-                        const bool in = rank[u] < static_cast<uint32_t>(P.cap);
                         double v;
                         int c = 0;
-                        if (in) {
-                            v = tvals[rank[u]];
-                            if (HITS) c = tcnt[rank[u]];
-                        } else {
-                            v = gvals[rank[u]];
-                            if (HITS) c = gcnt[rank[u]];
+                        if (rank[u] - vsh < vlim) v = tvals[rank[u] - vsh];
+                        else v = gvals[rank[u]];
+                        if (HITS) {
+                            if (rank[u] - csh < clim) c = tcnt[rank[u] - csh];
+                            else c = gcnt[rank[u]];
                         }
                         atomicAdd(&acc[Y[u] >> kRangeBits], v);
                         if (HITS) atomicAdd(&hacc[Y[u] >> kRangeBits], c);
                     }
             }
         }
+        if (!fetched) fetch(r + 1, nxt, k ^ 1);
+        cur = nxt;
+        wait_dma();
+        __syncthreads();
     }
-    __syncthreads();
     if (active) {
         const double aggR = I.lterm[2], aggL = I.lterm[3];
         const int64_t lo = max(gt0, I.t0), hi = min(gt1, I.t1);
@@ -173,6 +282,7 @@ __global__ __launch_bounds__(1024) void k_fwd(FwdParams P) {
 }
 
 int32_t launch_forward(const ara_yet *yet, int n_sr, bool hits, const FwdItem *d_items, int n_items, hipStream_t st) {
+    (void)n_sr;
     if (n_items <= 0) return ARA_OK;
     FwdParams P{};
     P.ent = yet->ent;
@@ -182,9 +292,12 @@ int32_t launch_forward(const ara_yet *yet, int n_sr, bool hits, const FwdItem *d
     P.tg = yet->trials_per_group;
     P.tb = yet->trials_per_block;
     P.n_ranges = yet->n_ranges;
-    P.n_sr = n_sr;
-    const size_t fixed = fwd_fixed_lds(P.tb, hits);
-    P.cap = static_cast<int32_t>((kLdsBytes - fixed) / (hits ? 9 : 8));
+    // two range buffers: [bitmap words with ranks][values][counts (hits mode)]
+    const size_t per_buf = ((kLdsBytes - fwd_acc_lds(P.tb, hits) - fwd_meta_lds(P.n_ranges)) / 2) & ~size_t(255);
+    size_t capv = hits ? (per_buf - kBrBytes - 16) / 9 : (per_buf - kBrBytes) / 8;
+    capv &= ~size_t(15);
+    P.capv = static_cast<int32_t>(capv);
+    P.buf_bytes = static_cast<int32_t>(per_buf);
     P.items = d_items;
     ProfScope prof(ARA_PROF_FWD, st);
     if (hits) {

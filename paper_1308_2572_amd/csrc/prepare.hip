@@ -10,6 +10,7 @@ namespace ara {
 
 struct Geometry {
     int tg, tb, n_blocks, n_ranges, gbits;
+    int slice_blocks;   // blocks per trial slice of the event-major copy
     size_t nseg;
 };
 
@@ -25,15 +26,21 @@ static Geometry geometry(int64_t n_trials, int32_t catalog) {
     g.gbits = 0;
     while ((1 << g.gbits) < g.n_ranges) ++g.gbits;
     g.nseg = static_cast<size_t>(g.n_blocks) * g.n_ranges * kGroups;
+    g.slice_blocks = std::max(1, (g.n_blocks + kSlices - 1) / kSlices);
     return g;
 }
 
-static size_t prepare_bytes(const Geometry &g, int64_t nnz) {
+static size_t prepare_bytes(const Geometry &g, int64_t nnz, int32_t catalog, uint32_t flags) {
     Carver c(nullptr);
     c.take<uint32_t>(static_cast<size_t>(nnz) + g.nseg * (kWave - 1));
     c.take<int64_t>(g.nseg);
     c.take<int32_t>(g.nseg);
     c.take<int32_t>(64);
+    if (flags & ARA_PREP_TRANSPOSED) {
+        c.take<int64_t>(static_cast<size_t>(kSlices) * catalog + 1);
+        c.take<uint32_t>(static_cast<size_t>(std::max<int64_t>(nnz, 1)));
+        c.take<int64_t>(static_cast<size_t>(kSlices) * g.n_ranges);
+    }
     return c.bytes();
 }
 
@@ -158,23 +165,129 @@ __global__ __launch_bounds__(1024) void k_prep_max_occ(const uint32_t *__restric
     }
 }
 
+// Event-major copy, pass 1: per (catalogue range r, trial slice x) count the
+// occurrences of each event of the range in the slice's blocks; counts go to
+// tr_off[x*catalog + e] and the region's total to rtot[x*n_ranges + r].
+__global__ __launch_bounds__(1024) void k_tr_count(const uint32_t *__restrict__ ent,
+                                                   const int64_t *__restrict__ seg_base,
+                                                   const int32_t *__restrict__ seg_run, int n_blocks, int n_ranges,
+                                                   int tb, int slice_blocks, int32_t catalog,
+                                                   int64_t *__restrict__ tr_off, int64_t *__restrict__ rtot) {
+    __shared__ uint32_t hist[kRange];
+    __shared__ unsigned long long red[16];
+    const int r = blockIdx.x, x = blockIdx.y, tid = threadIdx.x;
+    for (int i = tid; i < kRange; i += blockDim.x) hist[i] = 0;
+    __syncthreads();
+    const int b0 = x * slice_blocks, b1 = min(n_blocks, b0 + slice_blocks);
+    for (int b = b0; b < b1; ++b)
+        for (int g = 0; g < kGroups; ++g) {
+            const size_t sidx = (static_cast<size_t>(b) * n_ranges + r) * kGroups + g;
+            const int64_t sb = seg_base[sidx];
+            const int64_t n = static_cast<int64_t>(seg_run[sidx]) * kWave;
+            for (int64_t i = tid; i < n; i += blockDim.x) {
+                const uint32_t e = ent[sb + i];
+                if ((e >> kRangeBits) < static_cast<uint32_t>(tb)) atomicAdd(&hist[e & (kRange - 1)], 1u);
+            }
+        }
+    __syncthreads();
+    const int64_t e0 = static_cast<int64_t>(r) * kRange;
+    const int nloc = static_cast<int>(min<int64_t>(kRange, catalog - e0));
+    unsigned long long sum = 0;
+    for (int l = tid; l < nloc; l += blockDim.x) {
+        tr_off[static_cast<int64_t>(x) * catalog + e0 + l] = hist[l];
+        sum += hist[l];
+    }
+    for (int o = 32; o > 0; o >>= 1) sum += __shfl_down(sum, o);
+    if ((tid & 63) == 0) red[tid >> 6] = sum;
+    __syncthreads();
+    if (tid == 0) {
+        unsigned long long t = 0;
+        for (int i = 0; i < static_cast<int>(blockDim.x >> 6); ++i) t += red[i];
+        rtot[static_cast<size_t>(x) * n_ranges + r] = static_cast<int64_t>(t);
+    }
+}
+
+// Event-major copy, pass 2: turn the region's counts into list starts (the
+// region begins at rbase[x*n_ranges + r]) and scatter each occurrence's
+// slice-local trial index into its event's list.
+__global__ __launch_bounds__(1024) void k_tr_scatter(const uint32_t *__restrict__ ent,
+                                                     const int64_t *__restrict__ seg_base,
+                                                     const int32_t *__restrict__ seg_run, int n_blocks, int n_ranges,
+                                                     int tb, int slice_blocks, int32_t catalog,
+                                                     const int64_t *__restrict__ rbase, int64_t *__restrict__ tr_off,
+                                                     uint32_t *__restrict__ tr_ent) {
+    constexpr int kPer = kRange / 1024;
+    __shared__ uint32_t cur[kRange];
+    __shared__ uint32_t wsum[16];
+    const int r = blockIdx.x, x = blockIdx.y, tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int64_t e0 = static_cast<int64_t>(r) * kRange;
+    const int nloc = static_cast<int>(min<int64_t>(kRange, catalog - e0));
+    const int64_t rb = rbase[static_cast<size_t>(x) * n_ranges + r];
+    int64_t *off = tr_off + static_cast<int64_t>(x) * catalog + e0;
+    uint32_t c[kPer];
+    uint32_t s = 0;
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+        const int l = tid * kPer + k;
+        c[k] = l < nloc ? static_cast<uint32_t>(off[l]) : 0u;
+        s += c[k];
+    }
+    // exclusive scan of the per-thread sums over the workgroup
+    uint32_t inc = s;
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t v = __shfl_up(inc, o);
+        if (lane >= o) inc += v;
+    }
+    if (lane == 63) wsum[w] = inc;
+    __syncthreads();
+    uint32_t pre = 0;
+    for (int i = 0; i < w; ++i) pre += wsum[i];
+    uint32_t ex = pre + inc - s;
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+        const int l = tid * kPer + k;
+        cur[l] = ex;
+        if (l < nloc) off[l] = rb + ex;
+        ex += c[k];
+    }
+    __syncthreads();
+    const int b0 = x * slice_blocks, b1 = min(n_blocks, b0 + slice_blocks);
+    for (int b = b0; b < b1; ++b)
+        for (int g = 0; g < kGroups; ++g) {
+            const size_t sidx = (static_cast<size_t>(b) * n_ranges + r) * kGroups + g;
+            const int64_t sb = seg_base[sidx];
+            const int64_t n = static_cast<int64_t>(seg_run[sidx]) * kWave;
+            for (int64_t i = tid; i < n; i += blockDim.x) {
+                const uint32_t e = ent[sb + i];
+                const uint32_t tl = e >> kRangeBits;
+                if (tl < static_cast<uint32_t>(tb)) {
+                    const uint32_t pos = atomicAdd(&cur[e & (kRange - 1)], 1u);
+                    tr_ent[rb + pos] = static_cast<uint32_t>(b - b0) * static_cast<uint32_t>(tb) + tl;
+                }
+            }
+        }
+}
+
 }  // namespace ara
 
 using namespace ara;
 
-extern "C" int32_t ara_yet_prepare_bytes(int64_t n_trials, int64_t nnz, int32_t catalog, size_t *bytes) {
+extern "C" int32_t ara_yet_prepare_bytes(int64_t n_trials, int64_t nnz, int32_t catalog, uint32_t flags,
+                                         size_t *bytes) {
     if (!bytes) return fail(ARA_E_INVAL, "ara_yet_prepare_bytes: null output");
     if (n_trials < 0 || nnz < 0 || catalog <= 0) return fail(ARA_E_INVAL, "ara_yet_prepare_bytes: negative size");
     if (catalog > ARA_MAX_CATALOG) return fail(ARA_E_LIMIT, "catalog exceeds ARA_MAX_CATALOG");
-    *bytes = prepare_bytes(geometry(n_trials, catalog), nnz);
+    if (flags & ~ARA_PREP_TRANSPOSED) return fail(ARA_E_INVAL, "ara_yet_prepare_bytes: unknown flag");
+    *bytes = prepare_bytes(geometry(n_trials, catalog), nnz, catalog, flags);
     return ARA_OK;
 }
 
 extern "C" int32_t ara_yet_prepare(const int64_t *offsets, const int32_t *ids, int64_t n_trials, int32_t catalog,
-                                   void *buf, size_t buf_bytes, void *stream, ara_yet *out) {
+                                   uint32_t flags, void *buf, size_t buf_bytes, void *stream, ara_yet *out) {
     if (!offsets || !buf || !out) return fail(ARA_E_INVAL, "ara_yet_prepare: null pointer");
     if (n_trials < 0 || catalog <= 0) return fail(ARA_E_INVAL, "ara_yet_prepare: bad size");
     if (catalog > ARA_MAX_CATALOG) return fail(ARA_E_LIMIT, "catalog exceeds ARA_MAX_CATALOG");
+    if (flags & ~ARA_PREP_TRANSPOSED) return fail(ARA_E_INVAL, "ara_yet_prepare: unknown flag");
     hipStream_t st = static_cast<hipStream_t>(stream);
     const Geometry g = geometry(n_trials, catalog);
     int64_t ends[2] = {0, 0};
@@ -184,13 +297,21 @@ extern "C" int32_t ara_yet_prepare(const int64_t *offsets, const int32_t *ids, i
     if (ends[0] != 0 || ends[1] < 0) return fail(ARA_E_RANGE, "offsets[0] must be 0 and offsets[n] >= 0");
     const int64_t nnz = ends[1];
     if (nnz > 0 && !ids) return fail(ARA_E_INVAL, "ara_yet_prepare: null ids");
-    if (buf_bytes < prepare_bytes(g, nnz)) return fail(ARA_E_NOSPACE, "ara_yet_prepare: buffer too small");
+    if (buf_bytes < prepare_bytes(g, nnz, catalog, flags)) return fail(ARA_E_NOSPACE, "ara_yet_prepare: buffer too small");
 
     Carver c(buf);
     uint32_t *ent = c.take<uint32_t>(static_cast<size_t>(nnz) + g.nseg * (kWave - 1));
     int64_t *seg_base = c.take<int64_t>(g.nseg);
     int32_t *seg_run = c.take<int32_t>(g.nseg);
     int32_t *misc = c.take<int32_t>(64);   // [0] error, [1] max occurrences
+    const bool transposed = (flags & ARA_PREP_TRANSPOSED) != 0;
+    int64_t *tr_off = nullptr, *rtot = nullptr;
+    uint32_t *tr_ent = nullptr;
+    if (transposed) {
+        tr_off = c.take<int64_t>(static_cast<size_t>(kSlices) * catalog + 1);
+        tr_ent = c.take<uint32_t>(static_cast<size_t>(std::max<int64_t>(nnz, 1)));
+        rtot = c.take<int64_t>(static_cast<size_t>(kSlices) * g.n_ranges);
+    }
     ARA_HIP(hipMemsetAsync(misc, 0, 64 * sizeof(int32_t), st));
 
     ara_yet y{};
@@ -206,7 +327,16 @@ extern "C" int32_t ara_yet_prepare(const int64_t *offsets, const int32_t *ids, i
     y.ent = ent;
     y.seg_base = seg_base;
     y.seg_run = seg_run;
+    if (transposed) {
+        y.n_slices = kSlices;
+        y.slice_trials = static_cast<int64_t>(g.slice_blocks) * g.tb;
+        y.tr_off = tr_off;
+        y.tr_ent = tr_ent;
+        // every list is empty until the counting pass has run
+        ARA_HIP(hipMemsetAsync(tr_off, 0, (static_cast<size_t>(kSlices) * catalog + 1) * sizeof(int64_t), st));
+    }
     if (g.n_blocks == 0) {
+        ARA_HIP(hipStreamSynchronize(st));
         *out = y;
         return ARA_OK;
     }
@@ -241,6 +371,32 @@ extern "C" int32_t ara_yet_prepare(const int64_t *offsets, const int32_t *ids, i
     ARA_HIP(hipGetLastError());
     k_prep_max_occ<<<g.n_ranges, 1024, 0, st>>>(ent, seg_base, seg_run, g.n_blocks, g.n_ranges, g.tb, misc + 1);
     ARA_HIP(hipGetLastError());
+    if (transposed) {
+        const dim3 grid(static_cast<unsigned>(g.n_ranges), kSlices);
+        k_tr_count<<<grid, 1024, 0, st>>>(ent, seg_base, seg_run, g.n_blocks, g.n_ranges, g.tb, g.slice_blocks,
+                                          catalog, tr_off, rtot);
+        ARA_HIP(hipGetLastError());
+        const size_t nreg = static_cast<size_t>(kSlices) * g.n_ranges;
+        std::vector<int64_t> tot(nreg);
+        ARA_HIP(hipMemcpyAsync(tot.data(), rtot, nreg * sizeof(int64_t), hipMemcpyDeviceToHost, st));
+        ARA_HIP(hipStreamSynchronize(st));
+        int64_t acc = 0;
+        for (size_t i = 0; i < nreg; ++i) {   // regions in (slice, range) order = list order
+            if (tot[i] >= (int64_t(1) << 32))
+                return fail(ARA_E_LIMIT, "ara_yet_prepare: 2^32 or more occurrences in one (slice, range)");
+            const int64_t t = tot[i];
+            tot[i] = acc;
+            acc += t;
+        }
+        if (acc != nnz) return fail(ARA_E_RANGE, "ara_yet_prepare: event-major copy lost occurrences");
+        ARA_HIP(hipMemcpyAsync(rtot, tot.data(), nreg * sizeof(int64_t), hipMemcpyHostToDevice, st));
+        ARA_HIP(hipMemcpyAsync(tr_off + static_cast<size_t>(kSlices) * catalog, &acc, sizeof(int64_t),
+                               hipMemcpyHostToDevice, st));
+        ARA_HIP(hipStreamSynchronize(st));   // the host sources live in this scope
+        k_tr_scatter<<<grid, 1024, 0, st>>>(ent, seg_base, seg_run, g.n_blocks, g.n_ranges, g.tb, g.slice_blocks,
+                                            catalog, rtot, tr_off, tr_ent);
+        ARA_HIP(hipGetLastError());
+    }
     int32_t mo = 0;
     ARA_HIP(hipMemcpyAsync(&mo, misc + 1, sizeof(int32_t), hipMemcpyDeviceToHost, st));
     ARA_HIP(hipStreamSynchronize(st));

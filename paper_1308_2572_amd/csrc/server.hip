@@ -353,6 +353,8 @@ extern "C" int32_t ara_server_submit(void *server, const ara_quote *q, int64_t *
         return fail(ARA_E_RANGE, "quote trial range outside the YET");
     if (q->trial_end == q->trial_begin) return fail(ARA_E_INVAL, "quote over an empty trial range");
     if (!(q->p > 0.0 && q->p < 1.0)) return fail(ARA_E_INVAL, "quote p must lie in (0, 1)");
+    if (q->want_grad && S->yet.n_slices != kSlices)
+        return fail(ARA_E_INVAL, "gradients need a resident YET prepared with ARA_PREP_TRANSPOSED");
     const double *t = q->layer_terms;
     if (!(t[0] >= 0.0 && t[0] < INFINITY) || !(t[1] > 0.0) || !(t[2] >= 0.0 && t[2] < INFINITY) || !(t[3] > 0.0))
         return fail(ARA_E_INVAL, "quote layer terms invalid");

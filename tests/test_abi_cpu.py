@@ -47,14 +47,18 @@ def test_status_strings(ara):
 def test_size_queries(ara):
     lib = ara.library()
     nb = ctypes.c_size_t()
-    assert lib.ara_yet_prepare_bytes(1000, 1_000_000, 200_000, ctypes.byref(nb)) == 0
+    assert lib.ara_yet_prepare_bytes(1000, 1_000_000, 200_000, 0, ctypes.byref(nb)) == 0
     assert nb.value >= 4 * 1_000_000
+    plain = nb.value
+    assert lib.ara_yet_prepare_bytes(1000, 1_000_000, 200_000, ara.PREP_TRANSPOSED, ctypes.byref(nb)) == 0
+    assert nb.value >= plain + 4 * 1_000_000 + 8 * (8 * 200_000 + 1)     # event-major entries and list offsets
+    assert lib.ara_yet_prepare_bytes(1000, 1_000_000, 200_000, 2, ctypes.byref(nb)) == 1   # unknown flag
     assert lib.ara_build_elt_tables_bytes(15, 2_000_000, ctypes.byref(nb)) == 0
     assert nb.value >= 15 * 2_000_000 * 4
     assert lib.ara_metrics_workspace_bytes(2, 1000, ctypes.byref(nb)) == 0
     assert nb.value >= 2 * 1000 * 8
-    assert lib.ara_yet_prepare_bytes(10, 10, 1 << 27, ctypes.byref(nb)) == 6       # beyond the catalogue limit
-    assert lib.ara_yet_prepare_bytes(-1, 10, 100, ctypes.byref(nb)) == 1
+    assert lib.ara_yet_prepare_bytes(10, 10, 1 << 27, 0, ctypes.byref(nb)) == 6       # beyond the catalogue limit
+    assert lib.ara_yet_prepare_bytes(-1, 10, 100, 0, ctypes.byref(nb)) == 1
 
 
 def test_argument_validation_before_device_work(ara):
@@ -86,6 +90,10 @@ def test_argument_validation_before_device_work(ara):
     # trial range outside the YET
     assert lib.ara_ylt_forward(ctypes.byref(tables), ctypes.byref(yet), ctypes.byref(lay.handle), None, None, 0, 11,
                                0, None, None, None, None, 0, None) == 2
+    # the backward needs the event-major copy of the YET
+    assert lib.ara_ylt_backward_workspace_bytes(ctypes.byref(tables), ctypes.byref(yet), ctypes.byref(lay.handle), 1,
+                                                ctypes.byref(nb)) == 1
+    assert b"ARA_PREP_TRANSPOSED" in lib.ara_last_error()
 
 
 def test_product_refuses_to_run_without_library(tmp_path, monkeypatch):

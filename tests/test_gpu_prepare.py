@@ -1,0 +1,119 @@
+"""The event-major copy of the YET that the backward reads (an index
+transposition: exact).  For every trial slice x and event e the list of
+slice-local trial indices must hold exactly the occurrences of e in the
+slice's trials, with multiplicity; the list offsets are the running counts.
+Checked against a numpy construction from the raw trials.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(f"[gpu-prepare] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ara():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_1308_2572_amd as ara
+    ara.library()
+    return ara
+
+
+def read_dev(yet, ptr, count, dtype):
+    import torch
+    itemsize = torch.tensor([], dtype=dtype).element_size()
+    off = ptr - yet.buf.data_ptr()
+    assert 0 <= off and off + count * itemsize <= yet.buf.numel()
+    return yet.buf[off: off + count * itemsize].view(dtype).cpu().numpy()
+
+
+def expected(yet_np, slice_trials, n_slices):
+    n = yet_np.n_trials
+    lens = np.diff(yet_np.offsets)
+    t = np.repeat(np.arange(n, dtype=np.int64), lens)
+    x = t // slice_trials
+    key = x * yet_np.catalog + yet_np.ids.astype(np.int64)
+    local = t - x * slice_trials
+    counts = np.bincount(key, minlength=n_slices * yet_np.catalog)
+    off = np.zeros(n_slices * yet_np.catalog + 1, np.int64)
+    np.cumsum(counts, out=off[1:])
+    order = np.lexsort((local, key))
+    return off, key[order], local[order]
+
+
+def check(ara, yet_np):
+    import torch
+    _say(f"trials {yet_np.n_trials} nnz {yet_np.nnz} catalog {yet_np.catalog}")
+    py = ara.PreparedYet.from_numpy(yet_np, "cuda")
+    h = py.handle
+    torch.cuda.synchronize()
+    assert h.n_slices == 8
+    assert h.slice_trials % h.trials_per_block == 0 and h.slice_trials * h.n_slices >= yet_np.n_trials
+    off_ref, key_ref, loc_ref = expected(yet_np, h.slice_trials, h.n_slices)
+    off = read_dev(py, h.tr_off, h.n_slices * yet_np.catalog + 1, torch.int64)
+    assert np.array_equal(off, off_ref)
+    if yet_np.nnz == 0:
+        return
+    ent = read_dev(py, h.tr_ent, yet_np.nnz, torch.int32).astype(np.int64)
+    key = np.repeat(np.arange(h.n_slices * yet_np.catalog, dtype=np.int64), np.diff(off))
+    order = np.lexsort((ent, key))
+    assert np.array_equal(key[order], key_ref)
+    assert np.array_equal(ent[order], loc_ref)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_tiny_random(ara, seed):
+    w = synth.tiny_random(seed)
+    check(ara, w.yet)
+
+
+def test_many_ranges_ragged_and_empty_trials(ara):
+    g = np.random.default_rng(11)
+    lens = g.integers(0, 300, size=5000)
+    lens[::7] = 0
+    off = np.zeros(5001, np.int64)
+    np.cumsum(lens, out=off[1:])
+    ids = g.integers(0, 300_000, size=int(off[-1]), dtype=np.int32)
+    ids[:40] = 299_999                     # last event of a ragged last range
+    ids[40:90] = 7                         # one event many times in one trial
+    check(ara, synth.Yet(300_000, off, ids))
+
+
+def test_fewer_blocks_than_slices(ara):
+    g = np.random.default_rng(3)
+    off = np.array([0, 3, 3, 10], np.int64)
+    ids = g.integers(0, 70_000, size=10, dtype=np.int32)
+    check(ara, synth.Yet(70_000, off, ids))
+
+
+def test_no_trials_and_no_occurrences(ara):
+    check(ara, synth.Yet(1000, np.zeros(1, np.int64), np.zeros(0, np.int32)))
+    check(ara, synth.Yet(1000, np.zeros(50, np.int64), np.zeros(0, np.int32)))
+
+
+def test_config0_layout(ara):
+    check(ara, synth.config(0, n_trials=20_000).yet)
+
+
+def test_forward_only_prepare_and_backward_refusal(ara):
+    import torch
+    w = synth.tiny_random(1)
+    yet = ara.PreparedYet.from_numpy(w.yet, "cuda", transposed=False)
+    assert yet.handle.n_slices == 0 and not yet.handle.tr_off
+    tables = ara.EltTables.from_numpy(w.elts, "cuda")
+    layers = ara.Layers(w.layers.elt_off, w.layers.elt_ids)
+    et = torch.tensor(w.elts.terms, dtype=torch.float64, device="cuda")
+    lt = torch.tensor(w.layers.terms, dtype=torch.float64, device="cuda")
+    ylt, s_pre, _ = ara.ylt_forward(tables, yet, layers, et, lt, want_s_pre=True)
+    cot = torch.ones((1,) + tuple(ylt.shape), dtype=torch.float64, device="cuda")
+    with pytest.raises(ara.AraError, match="TRANSPOSED"):
+        ara.ylt_backward(tables, yet, layers, et, lt, s_pre, cot)
