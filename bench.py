@@ -97,6 +97,7 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-backward", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-yelt", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=200)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy three times (scales the HBM byte counters)")
@@ -201,6 +202,11 @@ def main() -> int:
             result["fwd_bwd"] = bench_backward(ara, tables, yet, layers, et, lt, w, args.steps, args.warmup, ms_step)
         except ara.AraError as ex:
             result["fwd_bwd"] = {"error": str(ex)}
+    if not args.no_yelt:
+        try:
+            result["yelt"] = bench_yelt(ara, tables, layers, et, lt, w, args.steps, args.warmup)
+        except ara.AraError as ex:
+            result["yelt"] = {"error": str(ex)}
     if not args.no_serving:
         log("serving: resident 1M x Poisson(1000) YET, 200 ELTs, Poisson arrivals at 50/s")
         from paper_1308_2572_amd import serve
@@ -219,6 +225,42 @@ def main() -> int:
         result["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(result), flush=True)
     return 0
+
+
+def bench_yelt(ara, tables, layers, et, lt, w, steps, warmup):
+    """Per-occurrence losses (event-level YLT) and the per-year maximum
+    occurrence loss over the same workload, from the trial-major YET; the
+    occurrence-exceedance PML/TVaR follow from the maxima."""
+    import numpy as np
+    import torch
+    off = torch.from_numpy(np.ascontiguousarray(w.yet.offsets, np.int64)).cuda()
+    ids = torch.from_numpy(np.ascontiguousarray(w.yet.ids, np.int32)).cuda()
+    N, nnz = w.yet.n_trials, w.yet.nnz
+    for _ in range(max(1, warmup)):
+        y, m = ara.yelt_forward(tables, off, ids, layers, et, lt)
+        del y
+    torch.cuda.synchronize()
+    n_steps = max(1, min(steps, 5))
+    ara.profile_reset()
+    ara.profile_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(n_steps):
+        y, m = ara.yelt_forward(tables, off, ids, layers, et, lt)
+        del y
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ara.profile_enable(False)
+    k_ms, k_n = ara.profile_read(ara.PROF_YELT)
+    k = k_ms / max(k_n, 1)
+    algo = 4.0 * nnz + 8.0 * nnz * w.layers.n_layers + 8.0 * N + 8.0 * N * w.layers.n_layers
+    oep, _ = ara.metrics(m, w.p)
+    o = oep.cpu().numpy()[0]
+    del off, ids, m
+    torch.cuda.empty_cache()
+    return {"ms_per_call": (t1 - t0) * 1e3 / n_steps, "kernel": "k_yelt", "kernel_ms": k,
+            "algorithmic_bytes": algo, "achieved_gbs": algo / (k * 1e-3) / 1e9,
+            "frac_of_hbm_peak": algo / (k * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "oep": {"mean_max_occurrence_loss": float(o[0]), "pml": float(o[1]), "tvar": float(o[2])}}
 
 
 def bench_backward(ara, tables, yet, layers, et, lt, w, steps, warmup, ms_fwd_step):

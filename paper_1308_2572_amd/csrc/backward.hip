@@ -201,12 +201,15 @@ struct BwdGather {
 
 // (5) W(e) = sum of v_t over the occurrences (t, e), per hot event, as a
 // gather over the event-major YET.  Workgroup i works on trial slice i mod 8
-// only, which keeps its gathers of v in the L2 of one XCD; each thread owns
-// one hot event at a time and sums its list in registers; the eight slice
-// sums meet in one integer atomic add per (event, row), exact in any order.
-template <int CS>
+// only, which keeps its gathers of v in the L2 of one XCD; a group of G
+// lanes owns one hot event at a time, reads its list coalesced (G
+// consecutive entries per step, streamed past the cache) and sums the
+// trials' fixed-point weights; the group's sums meet in a lane reduction and
+// the eight slice sums in one integer atomic add per (event, row) -- exact
+// in any order.
+template <int CS, int G>
 __global__ __launch_bounds__(256) void k_bwd_w(BwdGather P) {
-    constexpr int kU = 8;
+    constexpr int kU = 2;
     const int x = blockIdx.x % kSlices, wi = blockIdx.x / kSlices, nw = gridDim.x / kSlices, j = blockIdx.y;
     const int64_t tx0 = static_cast<int64_t>(x) * P.slice_trials;
     const int64_t ulo = max<int64_t>(P.t0 - tx0, 0), uhi = min<int64_t>(P.t1 - tx0, P.slice_trials);
@@ -217,16 +220,19 @@ __global__ __launch_bounds__(256) void k_bwd_w(BwdGather P) {
     const int32_t *hev = P.hot_ev + static_cast<size_t>(j) * P.catalog;
     const int64_t *off = P.tr_off + static_cast<int64_t>(x) * P.catalog;
     int64_t *Wj = P.W + static_cast<size_t>(j) * P.n_cot * P.catalog;
-    for (int g = wi * blockDim.x + threadIdx.x; g < H; g += nw * blockDim.x) {
+    const int sub = threadIdx.x & (G - 1);
+    const int ngrp = nw * static_cast<int>(blockDim.x) / G;
+    for (int g = (wi * static_cast<int>(blockDim.x) + static_cast<int>(threadIdx.x)) / G; g < H; g += ngrp) {
         const int e = hev[g];
         const int64_t o0 = off[e], o1 = off[e + 1];
         int64_t acc[CS];
 #pragma unroll
         for (int c = 0; c < CS; ++c) acc[c] = 0;
-        for (int64_t i = o0; i < o1; i += kU) {
+        for (int64_t i = o0 + sub; i < o1; i += G * kU) {
             uint32_t d[kU];
 #pragma unroll
-            for (int v = 0; v < kU; ++v) d[v] = (i + v < o1) ? P.tr_ent[i + v] - u0 : span;   // span = skip
+            for (int v = 0; v < kU; ++v)
+                d[v] = (i + v * G < o1) ? __builtin_nontemporal_load(P.tr_ent + i + v * G) - u0 : span;   // span = skip
 #pragma unroll
             for (int v = 0; v < kU; ++v) {
                 if (d[v] < span) {
@@ -246,10 +252,22 @@ __global__ __launch_bounds__(256) void k_bwd_w(BwdGather P) {
         }
 #pragma unroll
         for (int c = 0; c < CS; ++c)
-            if (c < P.n_cot && acc[c] != 0)
-                atomicAdd(reinterpret_cast<unsigned long long *>(&Wj[static_cast<size_t>(c) * P.catalog + g]),
-                          static_cast<unsigned long long>(acc[c]));
+            for (int s = G / 2; s > 0; s >>= 1) acc[c] += __shfl_xor(acc[c], s, G);
+        if (sub == 0) {
+#pragma unroll
+            for (int c = 0; c < CS; ++c)
+                if (c < P.n_cot && acc[c] != 0)
+                    atomicAdd(reinterpret_cast<unsigned long long *>(&Wj[static_cast<size_t>(c) * P.catalog + g]),
+                              static_cast<unsigned long long>(acc[c]));
+        }
     }
+}
+
+template <int G>
+static void launch_bwd_w(int cs, dim3 grid, hipStream_t st, const BwdGather &S) {
+    if (cs == 1) k_bwd_w<1, G><<<grid, 256, 0, st>>>(S);
+    else if (cs == 2) k_bwd_w<2, G><<<grid, 256, 0, st>>>(S);
+    else k_bwd_w<4, G><<<grid, 256, 0, st>>>(S);
 }
 
 struct BwdGrad {
@@ -261,19 +279,25 @@ struct BwdGrad {
     const OccTables *tabs;
     const int64_t *W;              // [n_layers][n_cot][catalog] by hot index
     const int32_t *hot_base;       // [n_layers][n_sr + 1]
-    int32_t n_sr, n_cot, n_chunks;   // chunks = n_sr * kChunks
+    int32_t n_sr, n_cot, n_chunks, n_elt_slots;   // chunks = n_sr * kChunks; slots = ELT positions of all layers
     const VScale *vs;
-    double *part_elt;    // [n_layers][n_chunks][kMaxJ][n_cot][3]
-    double *part_occ;    // [n_layers][n_chunks][n_cot][2]
+    double *part_elt;    // [n_chunks * 16 waves][n_elt_slots][n_cot][3]
+    double *part_occ;    // [n_layers][n_chunks * 16 waves][n_cot][2]
 };
 
-// (5) per 4096-event chunk: W(e) times the derivatives of O(e).
+constexpr int kGradWaves = kBwdThreads / kWave;   // 16
+constexpr int kGradBatch = 4;                      // ELTs whose losses are loaded together
+
+// (6) per 4096-event chunk: W(e) times the derivatives of O(e).  Each
+// thread owns four events; each wavefront reduces its lanes in a fixed tree
+// and writes its own partials, so no workgroup barrier sits in the ELT loop
+// and the final sums (a fixed order over chunks and wavefronts) are
+// deterministic.  Every per-row array is indexed by compile-time constants
+// (rows beyond n_cot are zero), so nothing leaves registers.
 __global__ __launch_bounds__(kBwdThreads) void k_bwd_grad(BwdGrad P) {
     __shared__ uint32_t stage[kMaxJ * kChunkWords];
     __shared__ int32_t lk[kMaxJ];
     __shared__ double ls[kMaxJ], lr[kMaxJ], ll[kMaxJ];
-    __shared__ double wpart[16][kMaxCot][3];
-    __shared__ double opart[16][kMaxCot][2];
     const int s = blockIdx.x / kChunks, p = blockIdx.x % kChunks, j = blockIdx.y;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int a = P.elt_off[j];
@@ -292,8 +316,10 @@ __global__ __launch_bounds__(kBwdThreads) void k_bwd_grad(BwdGrad P) {
         stage[idx] = (gw < P.words) ? P.present[static_cast<size_t>(lk[q]) * P.words + gw] : 0u;
     }
     const double occR = P.layer_terms[4 * j + 0], occL = P.layer_terms[4 * j + 1];
+    (void)occR;
     const OccTables T = P.tabs[j];
     const int64_t ev0 = static_cast<int64_t>(s) * kSr + p * (kChunkWords * 32);
+    const int32_t hb = P.hot_base[static_cast<size_t>(j) * (P.n_sr + 1) + s];
     __syncthreads();
 
     // the thread's four events: weight per row and occurrence-clamp branch.
@@ -303,93 +329,102 @@ __global__ __launch_bounds__(kBwdThreads) void k_bwd_grad(BwdGrad P) {
     bool lin_occ[4];
     int local[4];
     double po[kMaxCot][2];
+#pragma unroll
     for (int c = 0; c < kMaxCot; ++c) po[c][0] = po[c][1] = 0.0;
-    const int32_t hb = P.hot_base[static_cast<size_t>(j) * (P.n_sr + 1) + s];
+#pragma unroll
     for (int it = 0; it < 4; ++it) {
         local[it] = it * 1024 + tid;
         const int wip = local[it] >> 5, bit = local[it] & 31;
         const uint2 q = T.br[static_cast<size_t>(s) * kSrWords + p * kChunkWords + wip];
-        lin_occ[it] = false;
-        for (int c = 0; c < kMaxCot; ++c) W[it][c] = 0.0;
-        if (!((q.x >> bit) & 1u)) continue;
+        const bool hot = (q.x >> bit) & 1u;
         const uint32_t rk = q.y + __popc(q.x & ((1u << bit) - 1u));
-        const double O = T.vals[static_cast<size_t>(s) * kSr + rk];
-        for (int c = 0; c < P.n_cot; ++c) {
-            const int64_t acc = P.W[(static_cast<size_t>(j) * P.n_cot + c) * P.catalog + hb + rk];
-            W[it][c] = ldexp(static_cast<double>(acc), -P.vs[j * P.n_cot + c].sigma);
-        }
-        lin_occ[it] = O < occL;
-        for (int c = 0; c < P.n_cot; ++c) {
-            if (lin_occ[it]) po[c][0] -= W[it][c];
-            else po[c][1] += W[it][c];
+        const double O = hot ? T.vals[static_cast<size_t>(s) * kSr + rk] : 0.0;
+        lin_occ[it] = hot && (O < occL);
+#pragma unroll
+        for (int c = 0; c < kMaxCot; ++c) {
+            double wv = 0.0;
+            if (hot && c < P.n_cot) {
+                const int64_t acc = P.W[(static_cast<size_t>(j) * P.n_cot + c) * P.catalog + hb + rk];
+                wv = ldexp(static_cast<double>(acc), -P.vs[j * P.n_cot + c].sigma);
+            }
+            W[it][c] = wv;
+            if (hot) {
+                if (lin_occ[it]) po[c][0] -= wv;
+                else po[c][1] += wv;
+            }
         }
     }
-    // occurrence-term partials
-    for (int c = 0; c < P.n_cot; ++c)
+    const size_t cw = static_cast<size_t>(blockIdx.x) * kGradWaves + w;   // (chunk, wave) partial slot
+    // occurrence-term partials of this wavefront
+#pragma unroll
+    for (int c = 0; c < kMaxCot; ++c)
+#pragma unroll
         for (int m = 0; m < 2; ++m) {
             double v = po[c][m];
             for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o);
-            if (lane == 0) opart[w][c][m] = v;
+            if (lane == 0 && c < P.n_cot)
+                P.part_occ[((static_cast<size_t>(j) * P.n_chunks * kGradWaves + cw) * P.n_cot + c) * 2 + m] = v;
         }
-    __syncthreads();
-    const size_t chunk = static_cast<size_t>(s) * kChunks + p;
-    if (tid < P.n_cot * 2) {
-        const int c = tid >> 1, m = tid & 1;
-        double v = 0.0;
-        for (int i = 0; i < 16; ++i) v += opart[i][c][m];
-        P.part_occ[((static_cast<size_t>(j) * P.n_chunks + chunk) * P.n_cot + c) * 2 + m] = v;
-    }
-    // ELT-term partials, one ELT of the layer at a time
-    for (int qq = 0; qq < J; ++qq) {
-        double pe[kMaxCot][3];
-        for (int c = 0; c < kMaxCot; ++c) pe[c][0] = pe[c][1] = pe[c][2] = 0.0;
-        float lv[4];
-        bool on[4];
+    // ELT-term partials, kGradBatch ELTs' losses in flight at a time
+    for (int q0 = 0; q0 < J; q0 += kGradBatch) {
+        float lv[kGradBatch][4];
+        bool on[kGradBatch][4];
 #pragma unroll
-        for (int it = 0; it < 4; ++it) {
-            const int wip = local[it] >> 5, bit = local[it] & 31;
-            on[it] = lin_occ[it] && ((stage[qq * kChunkWords + wip] >> bit) & 1u);
-            const size_t idx = on[it] ? static_cast<size_t>(lk[qq]) * P.catalog + ev0 + local[it] : 0;
-            lv[it] = P.loss[idx];   // element 0 (always valid) for events without the ELT
+        for (int b = 0; b < kGradBatch; ++b) {
+            const int qq = q0 + b;
+#pragma unroll
+            for (int it = 0; it < 4; ++it) {
+                const int wip = local[it] >> 5, bit = local[it] & 31;
+                on[b][it] = qq < J && lin_occ[it] && ((stage[qq * kChunkWords + wip] >> bit) & 1u);
+                const size_t idx = on[b][it] ? static_cast<size_t>(lk[qq]) * P.catalog + ev0 + local[it] : 0;
+                lv[b][it] = P.loss[idx];   // element 0 (always valid) for events without the ELT
+            }
         }
-        for (int it = 0; it < 4; ++it) {
-            if (!on[it]) continue;
-            const double l = static_cast<double>(lv[it]);
-            const double scaled = ls[qq] * l;
-            const double pre = scaled - lr[qq];
-            const double av = (pre > 0.0) ? pre : 0.0;
-            const bool lin = (pre > 0.0) && (av < ll[qq]);
-            const bool cap = av >= ll[qq];
-            for (int c = 0; c < P.n_cot; ++c) {
-                if (lin) {
-                    pe[c][0] += W[it][c] * l;
-                    pe[c][1] -= W[it][c];
+#pragma unroll
+        for (int b = 0; b < kGradBatch; ++b) {
+            const int qq = q0 + b;
+            if (qq >= J) break;
+            double pe[kMaxCot][3];
+#pragma unroll
+            for (int c = 0; c < kMaxCot; ++c) pe[c][0] = pe[c][1] = pe[c][2] = 0.0;
+#pragma unroll
+            for (int it = 0; it < 4; ++it) {
+                if (!on[b][it]) continue;
+                const double l = static_cast<double>(lv[b][it]);
+                const double scaled = ls[qq] * l;
+                const double pre = scaled - lr[qq];
+                const double av = (pre > 0.0) ? pre : 0.0;
+                const bool lin = (pre > 0.0) && (av < ll[qq]);
+                const bool cap = av >= ll[qq];
+#pragma unroll
+                for (int c = 0; c < kMaxCot; ++c) {
+                    if (lin) {
+                        pe[c][0] += W[it][c] * l;
+                        pe[c][1] -= W[it][c];
+                    }
+                    if (cap) pe[c][2] += W[it][c];
                 }
-                if (cap) pe[c][2] += W[it][c];
             }
-        }
-        __syncthreads();   // wpart is reused per ELT
-        for (int c = 0; c < P.n_cot; ++c)
-            for (int m = 0; m < 3; ++m) {
-                double v = pe[c][m];
-                for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o);
-                if (lane == 0) wpart[w][c][m] = v;
-            }
-        __syncthreads();
-        if (tid < P.n_cot * 3) {
-            const int c = tid / 3, m = tid % 3;
-            double v = 0.0;
-            for (int i = 0; i < 16; ++i) v += wpart[i][c][m];
-            P.part_elt[(((static_cast<size_t>(j) * P.n_chunks + chunk) * kMaxJ + qq) * P.n_cot + c) * 3 + m] = v;
+            double *dst = P.part_elt + (cw * P.n_elt_slots + (a + qq)) * P.n_cot * 3;
+#pragma unroll
+            for (int c = 0; c < kMaxCot; ++c)
+#pragma unroll
+                for (int m = 0; m < 3; ++m) {
+                    double v = pe[c][m];
+                    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o);
+                    if (lane == 0 && c < P.n_cot) dst[c * 3 + m] = v;
+                }
         }
     }
 }
 
-// (6) fixed-order sums into the outputs: one workgroup per output value,
-// each thread a fixed stride of the partials, then a fixed-order tree.
+// (7) fixed-order sums into the outputs: one workgroup per output value,
+// each thread a fixed stride of the (chunk, wavefront) partials, then a
+// fixed-order tree.
 __global__ __launch_bounds__(256) void k_bwd_final(const int32_t *__restrict__ elt_off, const int32_t *__restrict__ elt_ids,
-                                                  int n_layers, int n_elts, int n_cot, int n_chunks, int nwg_v,
-                                                  const double *__restrict__ part_elt, const double *__restrict__ part_occ,
+                                                  int n_layers, int n_elts, int n_cot, int n_cw, int n_elt_slots,
+                                                  int nwg_v, const double *__restrict__ part_elt,
+                                                  const double *__restrict__ part_occ,
                                                   const double *__restrict__ aggpart, double *__restrict__ grad_elt,
                                                   double *__restrict__ grad_layer) {
     __shared__ double red[256];
@@ -401,16 +436,15 @@ __global__ __launch_bounds__(256) void k_bwd_final(const int32_t *__restrict__ e
         for (int j = 0; j < n_layers; ++j)
             for (int q = elt_off[j]; q < elt_off[j + 1]; ++q) {
                 if (elt_ids[q] != k) continue;
-                const int qq = q - elt_off[j];
-                for (int ch = tid; ch < n_chunks; ch += blockDim.x)
-                    v += part_elt[(((static_cast<size_t>(j) * n_chunks + ch) * kMaxJ + qq) * n_cot + c) * 3 + m];
+                for (int cw = tid; cw < n_cw; cw += blockDim.x)
+                    v += part_elt[((static_cast<size_t>(cw) * n_elt_slots + q) * n_cot + c) * 3 + m];
             }
     } else {
         const int i = o - n_e;
         const int c = i / (n_layers * 4), j = (i / 4) % n_layers, m = i % 4;
         if (m < 2) {
-            for (int ch = tid; ch < n_chunks; ch += blockDim.x)
-                v += part_occ[((static_cast<size_t>(j) * n_chunks + ch) * n_cot + c) * 2 + m];
+            for (int cw = tid; cw < n_cw; cw += blockDim.x)
+                v += part_occ[((static_cast<size_t>(j) * n_cw + cw) * n_cot + c) * 2 + m];
         } else {
             for (int wg = tid; wg < nwg_v; wg += blockDim.x)
                 v += aggpart[((static_cast<size_t>(j) * n_cot + c) * nwg_v + wg) * 2 + (m - 2)];
@@ -466,8 +500,8 @@ static BwdLayout bwd_layout(const ara_tables *tables, const ara_layers *layers, 
     d.take<int32_t>(static_cast<size_t>(L) * cat);
     d.take<int32_t>(static_cast<size_t>(L) * (B.z.n_sr + 1));
     d.take<int64_t>(static_cast<size_t>(L) * n_cot * cat);
-    d.take<double>(static_cast<size_t>(L) * B.n_chunks * kMaxJ * n_cot * 3);
-    d.take<double>(static_cast<size_t>(L) * B.n_chunks * n_cot * 2);
+    d.take<double>(static_cast<size_t>(B.n_chunks) * kGradWaves * std::max(nJ, 1) * n_cot * 3);
+    d.take<double>(static_cast<size_t>(L) * B.n_chunks * kGradWaves * n_cot * 2);
     B.bytes = b + d.bytes();
     return B;
 }
@@ -534,8 +568,8 @@ extern "C" int32_t ara_ylt_backward(const ara_tables *tables, const ara_yet *yet
     int32_t *hot_ev = c.take<int32_t>(static_cast<size_t>(L) * tables->catalog);
     int32_t *hot_base = c.take<int32_t>(static_cast<size_t>(L) * (B.z.n_sr + 1));
     int64_t *W = c.take<int64_t>(static_cast<size_t>(L) * n_cot * tables->catalog);
-    double *part_elt = c.take<double>(static_cast<size_t>(L) * B.n_chunks * kMaxJ * n_cot * 3);
-    double *part_occ = c.take<double>(static_cast<size_t>(L) * B.n_chunks * n_cot * 2);
+    double *part_elt = c.take<double>(static_cast<size_t>(B.n_chunks) * kGradWaves * std::max(nJ, 1) * n_cot * 3);
+    double *part_occ = c.take<double>(static_cast<size_t>(L) * B.n_chunks * kGradWaves * n_cot * 2);
     ARA_HIP(hipMemsetAsync(vs, 0, static_cast<size_t>(L * n_cot) * sizeof(VScale), st));
     ARA_HIP(hipMemcpyAsync(d_off, layers->elt_off, (L + 1) * sizeof(int32_t), hipMemcpyHostToDevice, st));
     if (nJ > 0) ARA_HIP(hipMemcpyAsync(d_ids, layers->elt_ids, nJ * sizeof(int32_t), hipMemcpyHostToDevice, st));
@@ -575,9 +609,10 @@ extern "C" int32_t ara_ylt_backward(const ara_tables *tables, const ara_yet *yet
         const int cu = device_cu_count();
         const unsigned gx = static_cast<unsigned>(kSlices * std::max(1, (4 * cu) / kSlices));
         const dim3 grid(gx, L);
-        if (B.cs == 1) k_bwd_w<1><<<grid, 256, 0, st>>>(S);
-        else if (B.cs == 2) k_bwd_w<2><<<grid, 256, 0, st>>>(S);
-        else k_bwd_w<4><<<grid, 256, 0, st>>>(S);
+        // lanes per hot event: about a third of the mean list length, 4 or 16
+        const double mean_list = static_cast<double>(yet->nnz) / (static_cast<double>(kSlices) * tables->catalog);
+        if (mean_list >= 24.0) launch_bwd_w<16>(B.cs, grid, st, S);
+        else launch_bwd_w<4>(B.cs, grid, st, S);
         ARA_HIP(hipGetLastError());
     }
     BwdGrad Gp{};
@@ -595,6 +630,7 @@ extern "C" int32_t ara_ylt_backward(const ara_tables *tables, const ara_yet *yet
     Gp.n_sr = B.z.n_sr;
     Gp.n_cot = n_cot;
     Gp.n_chunks = B.n_chunks;
+    Gp.n_elt_slots = std::max(nJ, 1);
     Gp.vs = vs;
     Gp.part_elt = part_elt;
     Gp.part_occ = part_occ;
@@ -602,8 +638,8 @@ extern "C" int32_t ara_ylt_backward(const ara_tables *tables, const ara_yet *yet
         ProfScope prof(ARA_PROF_BWD_RED, st);
         k_bwd_grad<<<dim3(B.n_chunks, L), kBwdThreads, 0, st>>>(Gp);
         const int outs = n_cot * tables->n_elts * 3 + n_cot * L * 4;
-        k_bwd_final<<<outs, 256, 0, st>>>(d_off, d_ids, L, tables->n_elts, n_cot, B.n_chunks, nwg_v, part_elt,
-                                          part_occ, aggpart, grad_elt, grad_layer);
+        k_bwd_final<<<outs, 256, 0, st>>>(d_off, d_ids, L, tables->n_elts, n_cot, B.n_chunks * kGradWaves,
+                                          std::max(nJ, 1), nwg_v, part_elt, part_occ, aggpart, grad_elt, grad_layer);
         ARA_HIP(hipGetLastError());
     }
     return ARA_OK;
