@@ -177,9 +177,15 @@ __global__ __launch_bounds__(1024) void k_fwd(FwdParams P) {
     auto load = [&]() {
         chunk_rr = rr;
         if (rr < G) {
+            // every load is issued (steps past the segment's end re-read its
+            // last step, same cache lines) and then replaced by padding: no
+            // branch per entry
 #pragma unroll
-            for (int u = 0; u < kUnroll; ++u)
-                X[u] = (step + u < R) ? ld_stream(P.ent + sb + static_cast<int64_t>(step + u) * kWave + lane) : pad;
+            for (int u = 0; u < kUnroll; ++u) {
+                const int su = min(step + u, R - 1);
+                const uint32_t v = ld_stream(P.ent + sb + static_cast<int64_t>(su) * kWave + lane);
+                X[u] = (step + u < R) ? v : pad;
+            }
             step += kUnroll;
             if (step >= R) {
                 ++rr;
