@@ -6,6 +6,7 @@
 #include <cstdint>
 #include <cstring>
 #include <string>
+#include <vector>
 
 #include "ara.h"
 
@@ -63,6 +64,34 @@ struct Carver {
 };
 
 int device_cu_count();
+
+// Host image of the small arrays at the head of a workspace (error header,
+// layer lists, table descriptors, work items), laid out at the offsets the
+// device carving uses and sent in one host-to-device copy, which also clears
+// the error header: one transfer per call instead of one per array.
+class HeadImage {
+   public:
+    explicit HeadImage(void *ws) : ws_(static_cast<char *>(ws)) {}
+    template <class T>
+    void put(const T *dev_dst, const T *src, size_t n) {
+        const size_t off = static_cast<size_t>(reinterpret_cast<const char *>(dev_dst) - ws_);
+        grow(off + n * sizeof(T));
+        if (n) std::memcpy(buf_.data() + off, src, n * sizeof(T));
+    }
+    void cover(const void *dev_end) { grow(static_cast<size_t>(static_cast<const char *>(dev_end) - ws_)); }
+    int32_t send(hipStream_t st) {
+        if (buf_.empty()) return ARA_OK;
+        ARA_HIP(hipMemcpyAsync(ws_, buf_.data(), buf_.size(), hipMemcpyHostToDevice, st));
+        return ARA_OK;
+    }
+
+   private:
+    void grow(size_t n) {
+        if (buf_.size() < n) buf_.resize(n, 0);
+    }
+    char *ws_;
+    std::vector<unsigned char> buf_;
+};
 
 // Records a start/stop HIP event pair around the enclosed launches when
 // profiling is enabled (ara_profile_enable); no-op otherwise.

@@ -549,10 +549,13 @@ extern "C" int32_t ara_ylt_backward(const ara_tables *tables, const ara_yet *yet
     const BwdLayout B = bwd_layout(tables, layers, n_cot, yet->n_trials);
     if (ws_bytes < B.bytes) return fail(ARA_E_NOSPACE, "backward workspace too small");
     hipStream_t st = static_cast<hipStream_t>(stream);
-    ARA_HIP(hipMemsetAsync(ws, 0, kWsHeaderBytes, st));
-    ARA_HIP(hipMemsetAsync(grad_elt, 0, static_cast<size_t>(n_cot) * tables->n_elts * 3 * sizeof(double), st));
-    ARA_HIP(hipMemsetAsync(grad_layer, 0, static_cast<size_t>(n_cot) * L * 4 * sizeof(double), st));
-    if (L == 0 || n == 0) return ARA_OK;
+    if (L == 0 || n == 0) {
+        ARA_HIP(hipMemsetAsync(ws, 0, kWsHeaderBytes, st));
+        ARA_HIP(hipMemsetAsync(grad_elt, 0, static_cast<size_t>(n_cot) * tables->n_elts * 3 * sizeof(double), st));
+        if (L > 0) ARA_HIP(hipMemsetAsync(grad_layer, 0, static_cast<size_t>(n_cot) * L * 4 * sizeof(double), st));
+        return ARA_OK;
+    }
+    // otherwise every output value is written by the final reduction
 
     const int nJ = layers->elt_off[L];
     Carver c(ws);
@@ -560,9 +563,9 @@ extern "C" int32_t ara_ylt_backward(const ara_tables *tables, const ara_yet *yet
     int32_t *d_off = c.take<int32_t>(static_cast<size_t>(L + 1));
     int32_t *d_ids = c.take<int32_t>(static_cast<size_t>(std::max(nJ, 1)));
     OccTables *d_tabs = c.take<OccTables>(static_cast<size_t>(L));
+    VScale *vs = c.take<VScale>(static_cast<size_t>(L * n_cot));
     std::vector<OccTables> tabs(static_cast<size_t>(L));
     for (int j = 0; j < L; ++j) tabs[j] = occ_carve(c, B.z, false);
-    VScale *vs = c.take<VScale>(static_cast<size_t>(L * n_cot));
     double *aggpart = c.take<double>(static_cast<size_t>(L) * n_cot * bwd_nwg_v(n) * 2);
     int64_t *vq = c.take<int64_t>(static_cast<size_t>(L) * n * B.cs);
     int32_t *hot_ev = c.take<int32_t>(static_cast<size_t>(L) * tables->catalog);
@@ -570,10 +573,12 @@ extern "C" int32_t ara_ylt_backward(const ara_tables *tables, const ara_yet *yet
     int64_t *W = c.take<int64_t>(static_cast<size_t>(L) * n_cot * tables->catalog);
     double *part_elt = c.take<double>(static_cast<size_t>(B.n_chunks) * kGradWaves * std::max(nJ, 1) * n_cot * 3);
     double *part_occ = c.take<double>(static_cast<size_t>(L) * B.n_chunks * kGradWaves * n_cot * 2);
-    ARA_HIP(hipMemsetAsync(vs, 0, static_cast<size_t>(L * n_cot) * sizeof(VScale), st));
-    ARA_HIP(hipMemcpyAsync(d_off, layers->elt_off, (L + 1) * sizeof(int32_t), hipMemcpyHostToDevice, st));
-    if (nJ > 0) ARA_HIP(hipMemcpyAsync(d_ids, layers->elt_ids, nJ * sizeof(int32_t), hipMemcpyHostToDevice, st));
-    ARA_HIP(hipMemcpyAsync(d_tabs, tabs.data(), L * sizeof(OccTables), hipMemcpyHostToDevice, st));
+    HeadImage img(ws);   // clears the error header and the weight scales
+    img.put(d_off, layers->elt_off, static_cast<size_t>(L + 1));
+    img.put(d_ids, layers->elt_ids, static_cast<size_t>(nJ));
+    img.put(d_tabs, tabs.data(), tabs.size());
+    img.cover(vs + L * n_cot);
+    if ((rc = img.send(st))) return rc;
 
     {
         ProfScope prof(ARA_PROF_OCC, st);

@@ -380,8 +380,10 @@ extern "C" int32_t ara_ylt_forward(const ara_tables *tables, const ara_yet *yet,
     if (L > 0 && n > 0 && (!ylt || !elt_terms || !layer_terms)) return fail(ARA_E_INVAL, "null output or terms");
     if (ws_bytes < fwd_workspace(tables, yet, layers, want_hits)) return fail(ARA_E_NOSPACE, "forward workspace too small");
     hipStream_t st = static_cast<hipStream_t>(stream);
-    ARA_HIP(hipMemsetAsync(ws, 0, kWsHeaderBytes, st));
-    if (L == 0 || n == 0) return ARA_OK;
+    if (L == 0 || n == 0) {
+        ARA_HIP(hipMemsetAsync(ws, 0, kWsHeaderBytes, st));
+        return ARA_OK;
+    }
 
     const OccLayoutSizes z = occ_sizes(tables->catalog, want_hits);
     const int nJ = layers->elt_off[L];
@@ -409,10 +411,13 @@ extern "C" int32_t ara_ylt_forward(const ara_tables *tables, const ara_yet *yet,
             it.s_pre = s_pre ? s_pre + static_cast<size_t>(j) * n : nullptr;
             it.hits = hits ? hits + static_cast<size_t>(j) * n : nullptr;
         }
-    ARA_HIP(hipMemcpyAsync(d_off, layers->elt_off, (L + 1) * sizeof(int32_t), hipMemcpyHostToDevice, st));
-    if (nJ > 0) ARA_HIP(hipMemcpyAsync(d_ids, layers->elt_ids, nJ * sizeof(int32_t), hipMemcpyHostToDevice, st));
-    ARA_HIP(hipMemcpyAsync(d_tabs, tabs.data(), L * sizeof(OccTables), hipMemcpyHostToDevice, st));
-    ARA_HIP(hipMemcpyAsync(d_items, items.data(), items.size() * sizeof(FwdItem), hipMemcpyHostToDevice, st));
+    HeadImage img(ws);
+    img.cover(d_err + kWsHeaderBytes / sizeof(int32_t));
+    img.put(d_off, layers->elt_off, static_cast<size_t>(L + 1));
+    img.put(d_ids, layers->elt_ids, static_cast<size_t>(nJ));
+    img.put(d_tabs, tabs.data(), tabs.size());
+    img.put(d_items, items.data(), items.size());
+    if ((rc = img.send(st))) return rc;
 
     {
         ProfScope prof(ARA_PROF_OCC, st);

@@ -238,8 +238,10 @@ extern "C" int32_t ara_yelt_forward(const ara_tables *tables, const int64_t *off
         return fail(ARA_E_INVAL, "null input or output");
     if (ws_bytes < yelt_workspace(tables, layers)) return fail(ARA_E_NOSPACE, "workspace too small");
     hipStream_t st = static_cast<hipStream_t>(stream);
-    ARA_HIP(hipMemsetAsync(ws, 0, kWsHeaderBytes, st));
-    if (L == 0 || n == 0) return ARA_OK;
+    if (L == 0 || n == 0) {
+        ARA_HIP(hipMemsetAsync(ws, 0, kWsHeaderBytes, st));
+        return ARA_OK;
+    }
 
     const OccLayoutSizes z = occ_sizes(tables->catalog, false);
     const int nJ = layers->elt_off[L];
@@ -251,9 +253,12 @@ extern "C" int32_t ara_yelt_forward(const ara_tables *tables, const int64_t *off
     uint32_t *d_filter = c.take<uint32_t>(static_cast<size_t>(L) * kFilterWords);
     std::vector<OccTables> tabs(static_cast<size_t>(L));
     for (int j = 0; j < L; ++j) tabs[j] = occ_carve(c, z, false);
-    ARA_HIP(hipMemcpyAsync(d_off, layers->elt_off, (L + 1) * sizeof(int32_t), hipMemcpyHostToDevice, st));
-    if (nJ > 0) ARA_HIP(hipMemcpyAsync(d_ids, layers->elt_ids, nJ * sizeof(int32_t), hipMemcpyHostToDevice, st));
-    ARA_HIP(hipMemcpyAsync(d_tabs, tabs.data(), L * sizeof(OccTables), hipMemcpyHostToDevice, st));
+    HeadImage img(ws);
+    img.cover(d_err + kWsHeaderBytes / sizeof(int32_t));
+    img.put(d_off, layers->elt_off, static_cast<size_t>(L + 1));
+    img.put(d_ids, layers->elt_ids, static_cast<size_t>(nJ));
+    img.put(d_tabs, tabs.data(), tabs.size());
+    if ((rc = img.send(st))) return rc;
     {
         ProfScope prof(ARA_PROF_OCC, st);
         if ((rc = launch_occ(tables, d_off, d_ids, elt_terms, layer_terms, L, false, d_tabs, z.n_sr, d_err, st)))
