@@ -77,14 +77,19 @@ int32_t ara_abi_version(void);
  * is laid out once for the device).  The prepared YET groups each block of
  * consecutive trials by catalogue range: for block b, range r (2^range_bits
  * consecutive event IDs) and trial group g, the occurrences of those trials
- * whose event lies in range r are stored in trial order, packed as
- * (trial_in_block << range_bits) | (event_id - r * 2^range_bits), and
- * distributed over 64 lanes as `seg_run` consecutive entries per lane
- * (entry s of lane j at seg_base + s*64 + j; unused slots hold the padding
- * entry trials_per_block << range_bits, a trial slot one past the block).
- * Order of occurrences inside a trial is not kept: the year loss does not
- * depend on it (the cumulative aggregate steps telescope), but the order of
- * summation, and so rounding, is fixed by this layout and deterministic.
+ * whose event lies in range r form a segment, in trial order, one 16-bit code
+ * per occurrence: bits 0..14 the event's offset in the range, bit 15 "advance
+ * to the next trial of the group first".  The code 0xFFFF advances without an
+ * event: it stands for a trial of the group with no event in the range, for
+ * the advance of an event at offset 0x7FFF that opens a trial (the event then
+ * follows as 0x7FFF), and for padding.  The padded segment is dealt to 64
+ * lanes as runs of seg_run consecutive codes (a multiple of 4); lane j starts
+ * at trial lane_start[j] of its group and its code s sits at
+ * seg_base + (s/4)*256 + 4*j + s%4.
+ * Order of occurrences inside a trial is kept within a segment but not across
+ * ranges: the year loss does not depend on it (the cumulative aggregate steps
+ * telescope), and the order of summation, so rounding, is fixed by this
+ * layout and deterministic.
  *
  * With ARA_PREP_TRANSPOSED the buffer also holds the event-major copy the
  * backward needs (the adjoint of the per-trial gather is a per-event
@@ -106,10 +111,11 @@ typedef struct ara_yet {
     int32_t   trials_per_block;  /* groups * trials_per_group, <= 4096 */
     int32_t   n_blocks;          /* ceil(n_trials / trials_per_block) */
     int32_t   max_occ;           /* largest number of occurrences of one event */
-    int64_t   n_entries;         /* packed entries including padding */
-    uint32_t *ent;               /* device [n_entries] */
-    int64_t  *seg_base;          /* device [n_blocks][n_ranges][groups] */
-    int32_t  *seg_run;           /* device [n_blocks][n_ranges][groups] */
+    int64_t   n_codes;           /* 16-bit codes including gap codes and padding */
+    uint16_t *code;              /* device [n_codes] */
+    int64_t  *seg_base;          /* device [n_blocks][n_ranges][groups]: the segment's first code */
+    int32_t  *seg_run;           /* device [n_blocks][n_ranges][groups]: codes per lane */
+    uint8_t  *lane_start;        /* device [n_blocks][n_ranges][groups][64]: each lane's first trial */
     /* event-major copy (ARA_PREP_TRANSPOSED; n_slices = 0 and NULL otherwise) */
     int32_t   n_slices;          /* 8 */
     int32_t   reserved;

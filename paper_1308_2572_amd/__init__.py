@@ -40,7 +40,7 @@ class ara_yet(ctypes.Structure):
     _fields_ = [("n_trials", _c_i64), ("nnz", _c_i64), ("catalog", _c_i32), ("range_bits", _c_i32),
                 ("n_ranges", _c_i32), ("groups", _c_i32), ("trials_per_group", _c_i32),
                 ("trials_per_block", _c_i32), ("n_blocks", _c_i32), ("max_occ", _c_i32),
-                ("n_entries", _c_i64), ("ent", _c_p), ("seg_base", _c_p), ("seg_run", _c_p),
+                ("n_codes", _c_i64), ("code", _c_p), ("seg_base", _c_p), ("seg_run", _c_p), ("lane_start", _c_p),
                 ("n_slices", _c_i32), ("reserved", _c_i32), ("slice_trials", _c_i64), ("tr_off", _c_p),
                 ("tr_ent", _c_p)]
 

@@ -1,6 +1,6 @@
-// Forward: stream the prepared YET, gather each occurrence's O(e) from the
-// occurrence table held in LDS, accumulate per trial, apply the aggregate
-// terms (Algorithm 1, steps three and four).
+// Forward: stream the prepared YET (16-bit codes), gather each occurrence's
+// O(e) from the occurrence table held in LDS, accumulate per trial, apply
+// the aggregate terms (Algorithm 1, steps three and four).
 //
 // One workgroup per block of trials; wavefront g owns trial group g of the
 // block.  The per-trial totals live in LDS for the whole pass over the
@@ -22,9 +22,10 @@ constexpr int kLdsBytes = 160 * 1024;
 constexpr int kBrBytes = 1024 * static_cast<int>(sizeof(uint2));   // one range's bitmap words with ranks
 
 struct FwdParams {
-    const uint32_t *ent;
+    const uint16_t *code;
     const int64_t *seg_base;
     const int32_t *seg_run;
+    const uint8_t *lane_start;
     int64_t n_trials;
     int32_t tg, tb, n_ranges;
     int32_t capv;              // values per range buffer
@@ -32,7 +33,10 @@ struct FwdParams {
     const FwdItem *items;      // one (layer, block of trials) per workgroup
 };
 
-__device__ __forceinline__ uint32_t ld_stream(const uint32_t *p) { return __builtin_nontemporal_load(p); }
+// Four consecutive codes of one lane, streamed past the cache.
+__device__ __forceinline__ unsigned long long ld_codes(const uint16_t *p) {
+    return __builtin_nontemporal_load(reinterpret_cast<const unsigned long long *>(p));
+}
 
 // 16 bytes per lane from global memory straight into LDS at lds_base + 16 *
 // lane (lds_base uniform over the wavefront).  Issued as inline assembly so
@@ -86,7 +90,6 @@ __global__ __launch_bounds__(1024) void k_fwd(FwdParams P) {
     const int tid = threadIdx.x, lane = tid & 63;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int64_t b = I.block;
-    const uint32_t pad = pad_entry(tb);
     const int64_t gt0 = b * tb + static_cast<int64_t>(w) * P.tg;
     const int64_t gt1 = min(gt0 + P.tg, P.n_trials);
     const bool active = gt0 < gt1 && gt1 > I.t0 && gt0 < I.t1;
@@ -172,19 +175,25 @@ __global__ __launch_bounds__(1024) void k_fwd(FwdParams P) {
             rr = seg_win + kWave;
         }
     };
-    uint32_t X[kUnroll];
+    // a chunk is kUnroll codes per lane (four 8-byte loads); the first chunk
+    // of a segment also brings the lane's starting trial
+    unsigned long long X[kUnroll / 4];
+    int X_start = 0;
+    bool X_first = false;
     int chunk_rr = G;
     auto load = [&]() {
         chunk_rr = rr;
         if (rr < G) {
+            X_first = step == 0;
+            if (X_first) X_start = P.lane_start[(seg0 + static_cast<size_t>(rr) * kGroups) * kWave + lane];
             // every load is issued (steps past the segment's end re-read its
-            // last step, same cache lines) and then replaced by padding: no
-            // branch per entry
+            // last four, same cache lines) and then replaced by padding: no
+            // branch per load
 #pragma unroll
-            for (int u = 0; u < kUnroll; ++u) {
-                const int su = min(step + u, R - 1);
-                const uint32_t v = ld_stream(P.ent + sb + static_cast<int64_t>(su) * kWave + lane);
-                X[u] = (step + u < R) ? v : pad;
+            for (int q = 0; q < kUnroll / 4; ++q) {
+                const int s4 = min(step + 4 * q, R - 4);
+                const unsigned long long v = ld_codes(P.code + sb + static_cast<int64_t>(s4 >> 2) * (4 * kWave) + 4 * lane);
+                X[q] = (step + 4 * q < R) ? v : ~0ull;
             }
             step += kUnroll;
             if (step >= R) {
@@ -195,6 +204,8 @@ __global__ __launch_bounds__(1024) void k_fwd(FwdParams P) {
         }
     };
 
+    const int tbase_w = w * P.tg;   // first trial of this wave's group within the block
+    int tcur = 0;                   // the lane's current trial within its group
     __syncthreads();   // range table counts published
     RangeInfo cur = range_info(0);
     fetch(0, cur, 0);
@@ -219,52 +230,71 @@ __global__ __launch_bounds__(1024) void k_fwd(FwdParams P) {
         RangeInfo nxt{0, 0};
         if (r + 1 < G) nxt = range_info(r + 1);
         bool fetched = r + 1 >= G;
+        // this wave's trial totals (and hit counts), and the values indexed by
+        // super-range rank
+        double *acc_w = acc + tbase_w;
+        int32_t *hacc_w = hacc + tbase_w;
+        const double *tv = tvals - vsh;
+        const uint8_t *tc = tcnt - csh;
         while (chunk_rr == r) {
-            uint32_t Y[kUnroll];
+            // codes of this chunk: four per 8-byte load, low half first
+            if (X_first) tcur = X_start;
+            uint32_t cw[kUnroll];
 #pragma unroll
-            for (int u = 0; u < kUnroll; ++u) Y[u] = X[u];
+            for (int u = 0; u < kUnroll; ++u) {
+                const uint32_t word = static_cast<uint32_t>(X[u >> 2] >> (32 * ((u >> 1) & 1)));
+                cw[u] = __builtin_amdgcn_ubfe(word, 16 * (u & 1), 16);
+            }
             load();   // prefetch the next chunk (possibly of a later range)
             if (!fetched) {   // after the first chunk's loads: the range info has arrived
                 fetch(r + 1, nxt, k ^ 1);
                 fetched = true;
             }
-            // lookups first, without branches, so the LDS reads of all
-            // entries are in flight together; then the masked accumulation
+            // bitmap words of all codes first, without branches, so the LDS
+            // reads are in flight together (offset bits 5..14 pick the word)
             uint2 q[kUnroll];
 #pragma unroll
-            for (int u = 0; u < kUnroll; ++u) q[u] = tbr[(Y[u] & (kRange - 1)) >> 5];
-            uint32_t rank[kUnroll];
-            bool hit[kUnroll];
+            for (int u = 0; u < kUnroll; ++u) q[u] = tbr[__builtin_amdgcn_ubfe(cw[u], 5, 10)];
+            // each code advances the lane's trial by its top bit
+            int tr[kUnroll];
 #pragma unroll
             for (int u = 0; u < kUnroll; ++u) {
-                const uint32_t bit = Y[u] & 31;
-                hit[u] = (q[u].x >> bit) & 1u;
-                rank[u] = q[u].y + __popc(q[u].x & ((1u << bit) - 1u));
+                tcur += static_cast<int>(cw[u] >> 15);
+                tr[u] = tcur;
+            }
+            // an event is set when its bit is; skip codes (0xFFFF) never are
+            bool on[kUnroll];
+            uint32_t rank[kUnroll];
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) {
+                const uint32_t bit = cw[u] & 31;
+                on[u] = (cw[u] != 0xFFFFu) && __builtin_amdgcn_ubfe(q[u].x, bit, 1);
+                rank[u] = __popc(q[u].x & ((1u << bit) - 1u)) + q[u].y;
             }
             if (all_lds) {
                 double v[kUnroll];
 #pragma unroll
-                for (int u = 0; u < kUnroll; ++u) v[u] = tvals[hit[u] ? rank[u] - vsh : 0];
+                for (int u = 0; u < kUnroll; ++u) v[u] = tv[on[u] ? rank[u] : vsh];
 #pragma unroll
                 for (int u = 0; u < kUnroll; ++u)
-                    if (hit[u]) {
-                        atomicAdd(&acc[Y[u] >> kRangeBits], v[u]);
-                        if (HITS) atomicAdd(&hacc[Y[u] >> kRangeBits], static_cast<int>(tcnt[rank[u] - csh]));
+                    if (on[u]) {
+                        atomicAdd(&acc_w[tr[u]], v[u]);
+                        if (HITS) atomicAdd(&hacc_w[tr[u]], static_cast<int>(tc[rank[u]]));
                     }
             } else {
 #pragma unroll
                 for (int u = 0; u < kUnroll; ++u)
-                    if (hit[u]) {
+                    if (on[u]) {
                         double v;
                         int c = 0;
-                        if (rank[u] - vsh < vlim) v = tvals[rank[u] - vsh];
+                        if (rank[u] - vsh < vlim) v = tv[rank[u]];
                         else v = gvals[rank[u]];
                         if (HITS) {
-                            if (rank[u] - csh < clim) c = tcnt[rank[u] - csh];
+                            if (rank[u] - csh < clim) c = tc[rank[u]];
                             else c = gcnt[rank[u]];
                         }
-                        atomicAdd(&acc[Y[u] >> kRangeBits], v);
-                        if (HITS) atomicAdd(&hacc[Y[u] >> kRangeBits], c);
+                        atomicAdd(&acc_w[tr[u]], v);
+                        if (HITS) atomicAdd(&hacc_w[tr[u]], c);
                     }
             }
         }
@@ -291,9 +321,10 @@ int32_t launch_forward(const ara_yet *yet, int n_sr, bool hits, const FwdItem *d
     (void)n_sr;
     if (n_items <= 0) return ARA_OK;
     FwdParams P{};
-    P.ent = yet->ent;
+    P.code = yet->code;
     P.seg_base = yet->seg_base;
     P.seg_run = yet->seg_run;
+    P.lane_start = yet->lane_start;
     P.n_trials = yet->n_trials;
     P.tg = yet->trials_per_group;
     P.tb = yet->trials_per_block;

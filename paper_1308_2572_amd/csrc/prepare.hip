@@ -1,12 +1,31 @@
 // YET preparation: validate the trials and lay them out by (block of trials,
-// catalogue range, trial group) so that the forward and backward kernels can
-// keep one range's occurrence table in LDS while streaming.
+// catalogue range, trial group) so that the forward kernel can keep one
+// range's occurrence table in LDS while streaming, in 16-bit codes; and, on
+// request, the event-major copy that the backward reads.
+//
+// Code stream of one segment (block b, range r, group g): the occurrences of
+// the group's trials whose event lies in range r, in trial order (storage
+// order inside a trial), one 16-bit code each:
+//     bit 15      advance to the next trial of the group before this code
+//     bits 0..14  the event's offset in the range
+// 0xFFFF means "advance, no event": it stands for each trial of the group
+// with no event in the range between two that have some, for the advance of
+// an event at offset 0x7FFF that opens a trial (which then follows as plain
+// 0x7FFF), and for padding.  The padded stream is dealt to the 64 lanes as
+// runs of `run` consecutive codes (run a multiple of 4), lane j starting from
+// trial lane_start[j] of the group; code s of lane j sits at
+//     base + (s / 4) * 256 + 4 * j + s % 4,
+// so a wavefront reads four steps of all its lanes as one 512-byte block.
 #include "ara_internal.h"
 
 #include <algorithm>
 #include <vector>
 
 namespace ara {
+
+constexpr uint16_t kAdvance = 0x8000;
+constexpr uint16_t kSkip = 0xFFFF;
+constexpr int kRangeWindow = 1024;   // ranges tracked at once in a wavefront's LDS state
 
 struct Geometry {
     int tg, tb, n_blocks, n_ranges, gbits;
@@ -30,12 +49,20 @@ static Geometry geometry(int64_t n_trials, int32_t catalog) {
     return g;
 }
 
+// Upper bound of the codes: a segment holds its events, at most tg - 1 gap
+// codes, at most tg - 1 advances for events at offset 0x7FFF, and fewer than
+// 4 * 64 padding codes.
+static int64_t max_codes(const Geometry &g, int64_t nnz) {
+    return nnz + static_cast<int64_t>(g.nseg) * (2 * g.tg + 4 * kWave);
+}
+
 static size_t prepare_bytes(const Geometry &g, int64_t nnz, int32_t catalog, uint32_t flags) {
     Carver c(nullptr);
-    c.take<uint32_t>(static_cast<size_t>(nnz) + g.nseg * (kWave - 1));
+    c.take<uint16_t>(static_cast<size_t>(max_codes(g, nnz)));
     c.take<int64_t>(g.nseg);
     c.take<int32_t>(g.nseg);
-    c.take<int32_t>(64);
+    c.take<uint8_t>(g.nseg * kWave);
+    c.take<int64_t>(32);
     if (flags & ARA_PREP_TRANSPOSED) {
         c.take<int64_t>(static_cast<size_t>(kSlices) * catalog + 1);
         c.take<uint32_t>(static_cast<size_t>(std::max<int64_t>(nnz, 1)));
@@ -44,98 +71,127 @@ static size_t prepare_bytes(const Geometry &g, int64_t nnz, int32_t catalog, uin
     return c.bytes();
 }
 
-// Count, per (block, range, group), the occurrences whose event lies in the
-// range; validate IDs and offsets.
-__global__ __launch_bounds__(1024) void k_prep_count(const int64_t *__restrict__ off,
-                                                     const int32_t *__restrict__ ids, int64_t n_trials,
-                                                     int32_t catalog, int tg, int tb, int n_ranges,
-                                                     int32_t *__restrict__ cnt, int32_t *__restrict__ err) {
-    __shared__ int32_t hist[kGroups * 2048];
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    for (int i = threadIdx.x; i < kGroups * n_ranges; i += blockDim.x) hist[i] = 0;
-    __syncthreads();
-    const int64_t b = blockIdx.x;
-    const int64_t t0 = b * tb + static_cast<int64_t>(w) * tg;
-    const int64_t t1 = std::min<int64_t>(t0 + tg, n_trials);
-    int32_t *h = hist + w * n_ranges;
-    for (int64_t t = t0; t < t1; ++t) {
-        const int64_t o0 = off[t], o1 = off[t + 1];
-        if (o1 < o0 || o0 < 0) {
-            if (lane == 0) atomicCAS(err, 0, ARA_E_RANGE);
-            continue;
-        }
-        for (int64_t i = o0 + lane; i < o1; i += kWave) {
-            const int32_t id = ids[i];
-            if (id < 0 || id >= catalog) {
-                atomicCAS(err, 0, ARA_E_RANGE);
-            } else {
-                atomicAdd(&h[id >> kRangeBits], 1);
-            }
-        }
-    }
-    // each wave publishes its own row; no other wave touches it
-    for (int r = lane; r < n_ranges; r += kWave)
-        cnt[(static_cast<size_t>(b) * n_ranges + r) * kGroups + w] = h[r];
+__device__ __forceinline__ int64_t code_slot(int64_t base, int s, int lane) {
+    return base + static_cast<int64_t>(s >> 2) * (4 * kWave) + 4 * lane + (s & 3);
 }
 
-// Scatter every occurrence into its segment, keeping trial order (and the
-// order inside a trial) within each segment.
-__global__ __launch_bounds__(1024) void k_prep_scatter(const int64_t *__restrict__ off,
-                                                       const int32_t *__restrict__ ids, int64_t n_trials,
-                                                       int tg, int tb, int n_ranges, int gbits,
-                                                       const int64_t *__restrict__ seg_base,
-                                                       const int32_t *__restrict__ seg_run,
-                                                       uint32_t *__restrict__ ent) {
-    __shared__ int32_t cursor[kGroups * 2048];
+// One pass over a wavefront's trial group, in trial order, per window of
+// ranges.  Pass one (SCATTER = false) counts each segment's codes and the
+// events, validating IDs and offsets; pass two writes the codes and the
+// lanes' starting trials.  Within a 64-ID chunk of a trial, the lanes of one
+// range are its occurrences in storage order (a stable multi-split by
+// ballots); the first of them settles what precedes them in the segment: gap
+// codes for skipped trials and the advance flag.
+template <bool SCATTER>
+__global__ __launch_bounds__(1024) void k_prep_codes(const int64_t *__restrict__ off,
+                                                     const int32_t *__restrict__ ids, int64_t n_trials,
+                                                     int32_t catalog, int tg, int tb, int n_ranges, int gbits,
+                                                     int32_t *__restrict__ seg_codes,
+                                                     const int64_t *__restrict__ seg_base,
+                                                     const int32_t *__restrict__ seg_run,
+                                                     uint16_t *__restrict__ code, uint8_t *__restrict__ lane_start,
+                                                     int32_t *__restrict__ err,
+                                                     unsigned long long *__restrict__ events) {
+    __shared__ int32_t cur_all[kGroups * kRangeWindow];   // codes so far per range
+    __shared__ int16_t last_all[kGroups * kRangeWindow];  // last trial seen per range, -1 none
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    int32_t *cur = cursor + w * n_ranges;
-    for (int r = lane; r < n_ranges; r += kWave) cur[r] = 0;
+    int32_t *cur = cur_all + w * kRangeWindow;
+    int16_t *last = last_all + w * kRangeWindow;
     const int64_t b = blockIdx.x;
     const int64_t t0 = b * tb + static_cast<int64_t>(w) * tg;
     const int64_t t1 = std::min<int64_t>(t0 + tg, n_trials);
-    for (int64_t t = t0; t < t1; ++t) {
-        const int64_t o0 = off[t], o1 = off[t + 1];
-        const uint32_t tl = static_cast<uint32_t>(t - b * tb);
-        for (int64_t base = o0; base < o1; base += kWave) {
-            const int64_t i = base + lane;
-            const bool active = i < o1;
-            const int32_t id = active ? ids[i] : 0;
-            const int r = id >> kRangeBits;
-            // lanes holding the same range, in lane order (stable multi-split)
-            uint64_t peers = __ballot(active);
-            for (int bit = 0; bit < gbits; ++bit) {
-                const bool on = (r >> bit) & 1;
-                const uint64_t m = __ballot(active && on);
-                peers &= on ? m : ~m;
-            }
-            const uint32_t rank = __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(peers >> 32),
-                                                            __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(peers), 0u));
-            const int tot = __popcll(peers);
-            int32_t c0 = 0;
-            if (active) c0 = cur[r];
-            __builtin_amdgcn_wave_barrier();
-            if (active && rank == 0) cur[r] = c0 + tot;
-            if (active) {
-                const size_t sidx = (static_cast<size_t>(b) * n_ranges + r) * kGroups + w;
-                const int32_t R = seg_run[sidx];
-                const int64_t sb = seg_base[sidx];
-                const int32_t pos = c0 + static_cast<int32_t>(rank);
-                const int32_t lj = pos / R;
-                const int32_t step = pos - lj * R;
-                ent[sb + static_cast<int64_t>(step) * kWave + lj] =
-                    (tl << kRangeBits) | static_cast<uint32_t>(id & (kRange - 1));
-            }
-            __builtin_amdgcn_wave_barrier();
+    auto seg_of = [&](int r) { return (static_cast<size_t>(b) * n_ranges + r) * kGroups + w; };
+    // position p of range r's segment gets code c; the state before it is trial `start`
+    auto put = [&](int r, int64_t p, uint16_t c, int start) {
+        const size_t si = seg_of(r);
+        const int run = seg_run[si];
+        const int lj = static_cast<int>(p / run);
+        const int s = static_cast<int>(p - static_cast<int64_t>(lj) * run);
+        code[code_slot(seg_base[si], s, lj)] = c;
+        if (s == 0) lane_start[si * kWave + lj] = static_cast<uint8_t>(start);
+    };
+    unsigned long long ev = 0;
+    for (int w0 = 0; w0 < n_ranges; w0 += kRangeWindow) {
+        const int wn = min(kRangeWindow, n_ranges - w0);
+        for (int r = lane; r < wn; r += kWave) {
+            cur[r] = 0;
+            last[r] = -1;
         }
+        __builtin_amdgcn_wave_barrier();
+        for (int64_t t = t0; t < t1; ++t) {
+            const int i = static_cast<int>(t - t0);
+            const int64_t o0 = off[t], o1 = off[t + 1];
+            if (o1 < o0 || o0 < 0) {
+                if (!SCATTER && lane == 0 && w0 == 0) atomicCAS(err, 0, ARA_E_RANGE);
+                continue;
+            }
+            for (int64_t base = o0; base < o1; base += kWave) {
+                const int64_t k = base + lane;
+                const bool in = k < o1;
+                const int32_t id = in ? ids[k] : 0;
+                const bool bad = in && (id < 0 || id >= catalog);
+                if (!SCATTER && bad && w0 == 0) atomicCAS(err, 0, ARA_E_RANGE);
+                const int r = (in && !bad) ? (id >> kRangeBits) : -1;
+                const bool active = r >= w0 && r < w0 + wn;
+                uint64_t peers = __ballot(active);
+                for (int bit = 0; bit < gbits; ++bit) {
+                    const bool on = (r >> bit) & 1;
+                    const uint64_t m = __ballot(active && on);
+                    peers &= on ? m : ~m;
+                }
+                const uint32_t rank = __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(peers >> 32),
+                                                                __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(peers), 0u));
+                const int tot = __popcll(peers);
+                const int leader = active ? __builtin_ctzll(peers) : lane;
+                const uint16_t local = static_cast<uint16_t>(id & (kRange - 1));
+                int p_open = 0, adv_open = 0;
+                if (active && rank == 0) {
+                    const int rl = r - w0;
+                    const int L = last[rl];
+                    int gap = 0;
+                    bool adv = false;
+                    if (L >= 0 && L != i) {       // opens trial i after trial L in this segment
+                        gap = i - L - 1;
+                        adv = true;
+                        if (local == (kRange - 1)) {   // offset 0x7FFF cannot carry the flag
+                            ++gap;
+                            adv = false;
+                        }
+                    }
+                    const int p0 = cur[rl];
+                    if (SCATTER)
+                        for (int q = 0; q < gap; ++q) put(r, p0 + q, kSkip, L + q);   // each advances one trial
+                    cur[rl] = p0 + gap + tot;
+                    last[rl] = static_cast<int16_t>(i);
+                    p_open = p0 + gap;
+                    adv_open = adv ? 1 : 0;
+                }
+                if (!SCATTER) ev += active ? 1u : 0u;
+                p_open = __shfl(p_open, leader);
+                adv_open = __shfl(adv_open, leader);
+                if (SCATTER && active) {
+                    const int a = (rank == 0) ? adv_open : 0;
+                    put(r, p_open + static_cast<int>(rank), static_cast<uint16_t>((a ? kAdvance : 0) | local), i - a);
+                }
+                __builtin_amdgcn_wave_barrier();
+            }
+        }
+        if (!SCATTER)
+            for (int r = lane; r < wn; r += kWave) seg_codes[seg_of(w0 + r)] = cur[r];
+        __builtin_amdgcn_wave_barrier();
+    }
+    if (!SCATTER) {
+        for (int o = 32; o > 0; o >>= 1) ev += __shfl_down(ev, o);
+        if (lane == 0 && ev) atomicAdd(events, ev);
     }
 }
 
 // Largest number of occurrences of any single event (bounds the backward's
 // fixed-point accumulators).
-__global__ __launch_bounds__(1024) void k_prep_max_occ(const uint32_t *__restrict__ ent,
+__global__ __launch_bounds__(1024) void k_prep_max_occ(const uint16_t *__restrict__ code,
                                                        const int64_t *__restrict__ seg_base,
                                                        const int32_t *__restrict__ seg_run, int n_blocks,
-                                                       int n_ranges, int tb, int32_t *__restrict__ max_occ) {
+                                                       int n_ranges, int32_t *__restrict__ max_occ) {
     __shared__ uint32_t hist[kRange];
     __shared__ uint32_t red[16];
     for (int i = threadIdx.x; i < kRange; i += blockDim.x) hist[i] = 0;
@@ -147,8 +203,8 @@ __global__ __launch_bounds__(1024) void k_prep_max_occ(const uint32_t *__restric
             const int64_t sb = seg_base[sidx];
             const int64_t n = static_cast<int64_t>(seg_run[sidx]) * kWave;
             for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
-                const uint32_t e = ent[sb + i];
-                if ((e >> kRangeBits) < static_cast<uint32_t>(tb)) atomicAdd(&hist[e & (kRange - 1)], 1u);
+                const uint16_t c = code[sb + i];
+                if (c != kSkip) atomicAdd(&hist[c & (kRange - 1)], 1u);
             }
         }
     }
@@ -168,11 +224,11 @@ __global__ __launch_bounds__(1024) void k_prep_max_occ(const uint32_t *__restric
 // Event-major copy, pass 1: per (catalogue range r, trial slice x) count the
 // occurrences of each event of the range in the slice's blocks; counts go to
 // tr_off[x*catalog + e] and the region's total to rtot[x*n_ranges + r].
-__global__ __launch_bounds__(1024) void k_tr_count(const uint32_t *__restrict__ ent,
+__global__ __launch_bounds__(1024) void k_tr_count(const uint16_t *__restrict__ code,
                                                    const int64_t *__restrict__ seg_base,
                                                    const int32_t *__restrict__ seg_run, int n_blocks, int n_ranges,
-                                                   int tb, int slice_blocks, int32_t catalog,
-                                                   int64_t *__restrict__ tr_off, int64_t *__restrict__ rtot) {
+                                                   int slice_blocks, int32_t catalog, int64_t *__restrict__ tr_off,
+                                                   int64_t *__restrict__ rtot) {
     __shared__ uint32_t hist[kRange];
     __shared__ unsigned long long red[16];
     const int r = blockIdx.x, x = blockIdx.y, tid = threadIdx.x;
@@ -185,8 +241,8 @@ __global__ __launch_bounds__(1024) void k_tr_count(const uint32_t *__restrict__ 
             const int64_t sb = seg_base[sidx];
             const int64_t n = static_cast<int64_t>(seg_run[sidx]) * kWave;
             for (int64_t i = tid; i < n; i += blockDim.x) {
-                const uint32_t e = ent[sb + i];
-                if ((e >> kRangeBits) < static_cast<uint32_t>(tb)) atomicAdd(&hist[e & (kRange - 1)], 1u);
+                const uint16_t c = code[sb + i];
+                if (c != kSkip) atomicAdd(&hist[c & (kRange - 1)], 1u);
             }
         }
     __syncthreads();
@@ -209,11 +265,13 @@ __global__ __launch_bounds__(1024) void k_tr_count(const uint32_t *__restrict__ 
 
 // Event-major copy, pass 2: turn the region's counts into list starts (the
 // region begins at rbase[x*n_ranges + r]) and scatter each occurrence's
-// slice-local trial index into its event's list.
-__global__ __launch_bounds__(1024) void k_tr_scatter(const uint32_t *__restrict__ ent,
+// slice-local trial index into its event's list.  Wavefront g decodes the
+// segments of trial group g, each lane its own run.
+__global__ __launch_bounds__(1024) void k_tr_scatter(const uint16_t *__restrict__ code,
                                                      const int64_t *__restrict__ seg_base,
-                                                     const int32_t *__restrict__ seg_run, int n_blocks, int n_ranges,
-                                                     int tb, int slice_blocks, int32_t catalog,
+                                                     const int32_t *__restrict__ seg_run,
+                                                     const uint8_t *__restrict__ lane_start, int n_blocks,
+                                                     int n_ranges, int tg, int tb, int slice_blocks, int32_t catalog,
                                                      const int64_t *__restrict__ rbase, int64_t *__restrict__ tr_off,
                                                      uint32_t *__restrict__ tr_ent) {
     constexpr int kPer = kRange / 1024;
@@ -252,20 +310,26 @@ __global__ __launch_bounds__(1024) void k_tr_scatter(const uint32_t *__restrict_
     }
     __syncthreads();
     const int b0 = x * slice_blocks, b1 = min(n_blocks, b0 + slice_blocks);
-    for (int b = b0; b < b1; ++b)
-        for (int g = 0; g < kGroups; ++g) {
-            const size_t sidx = (static_cast<size_t>(b) * n_ranges + r) * kGroups + g;
-            const int64_t sb = seg_base[sidx];
-            const int64_t n = static_cast<int64_t>(seg_run[sidx]) * kWave;
-            for (int64_t i = tid; i < n; i += blockDim.x) {
-                const uint32_t e = ent[sb + i];
-                const uint32_t tl = e >> kRangeBits;
-                if (tl < static_cast<uint32_t>(tb)) {
-                    const uint32_t pos = atomicAdd(&cur[e & (kRange - 1)], 1u);
-                    tr_ent[rb + pos] = static_cast<uint32_t>(b - b0) * static_cast<uint32_t>(tb) + tl;
+    for (int b = b0; b < b1; ++b) {
+        const size_t sidx = (static_cast<size_t>(b) * n_ranges + r) * kGroups + w;
+        const int64_t sb = seg_base[sidx];
+        const int run = seg_run[sidx];
+        const uint32_t tbase = static_cast<uint32_t>(b - b0) * static_cast<uint32_t>(tb) +
+                               static_cast<uint32_t>(w) * static_cast<uint32_t>(tg);
+        int t = lane_start[sidx * kWave + lane];
+        for (int s4 = 0; s4 < run; s4 += 4) {
+            const uint2 q = *reinterpret_cast<const uint2 *>(code + code_slot(sb, s4, lane));
+#pragma unroll
+            for (int h = 0; h < 4; ++h) {
+                const uint32_t cd = ((h < 2 ? q.x : q.y) >> (16 * (h & 1))) & 0xFFFFu;
+                t += static_cast<int>(cd >> 15);
+                if (cd != kSkip) {
+                    const uint32_t pos = atomicAdd(&cur[cd & (kRange - 1)], 1u);
+                    tr_ent[rb + pos] = tbase + static_cast<uint32_t>(t);
                 }
             }
         }
+    }
 }
 
 }  // namespace ara
@@ -300,10 +364,14 @@ extern "C" int32_t ara_yet_prepare(const int64_t *offsets, const int32_t *ids, i
     if (buf_bytes < prepare_bytes(g, nnz, catalog, flags)) return fail(ARA_E_NOSPACE, "ara_yet_prepare: buffer too small");
 
     Carver c(buf);
-    uint32_t *ent = c.take<uint32_t>(static_cast<size_t>(nnz) + g.nseg * (kWave - 1));
+    uint16_t *code = c.take<uint16_t>(static_cast<size_t>(max_codes(g, nnz)));
     int64_t *seg_base = c.take<int64_t>(g.nseg);
     int32_t *seg_run = c.take<int32_t>(g.nseg);
-    int32_t *misc = c.take<int32_t>(64);   // [0] error, [1] max occurrences
+    uint8_t *lane_start = c.take<uint8_t>(g.nseg * kWave);
+    int64_t *misc = c.take<int64_t>(32);   // [0] error (int32), [1] max occurrences (int32), [2] events
+    int32_t *err = reinterpret_cast<int32_t *>(misc);
+    int32_t *max_occ = reinterpret_cast<int32_t *>(misc + 1);
+    unsigned long long *events = reinterpret_cast<unsigned long long *>(misc + 2);
     const bool transposed = (flags & ARA_PREP_TRANSPOSED) != 0;
     int64_t *tr_off = nullptr, *rtot = nullptr;
     uint32_t *tr_ent = nullptr;
@@ -312,7 +380,7 @@ extern "C" int32_t ara_yet_prepare(const int64_t *offsets, const int32_t *ids, i
         tr_ent = c.take<uint32_t>(static_cast<size_t>(std::max<int64_t>(nnz, 1)));
         rtot = c.take<int64_t>(static_cast<size_t>(kSlices) * g.n_ranges);
     }
-    ARA_HIP(hipMemsetAsync(misc, 0, 64 * sizeof(int32_t), st));
+    ARA_HIP(hipMemsetAsync(misc, 0, 32 * sizeof(int64_t), st));
 
     ara_yet y{};
     y.n_trials = n_trials;
@@ -324,9 +392,10 @@ extern "C" int32_t ara_yet_prepare(const int64_t *offsets, const int32_t *ids, i
     y.trials_per_group = g.tg;
     y.trials_per_block = g.tb;
     y.n_blocks = g.n_blocks;
-    y.ent = ent;
+    y.code = code;
     y.seg_base = seg_base;
     y.seg_run = seg_run;
+    y.lane_start = lane_start;
     if (transposed) {
         y.n_slices = kSlices;
         y.slice_trials = static_cast<int64_t>(g.slice_blocks) * g.tb;
@@ -340,41 +409,45 @@ extern "C" int32_t ara_yet_prepare(const int64_t *offsets, const int32_t *ids, i
         *out = y;
         return ARA_OK;
     }
-    k_prep_count<<<g.n_blocks, 1024, 0, st>>>(offsets, ids, n_trials, catalog, g.tg, g.tb, g.n_ranges, seg_run, misc);
+    // pass 1: codes per segment (into seg_run for now)
+    k_prep_codes<false><<<g.n_blocks, 1024, 0, st>>>(offsets, ids, n_trials, catalog, g.tg, g.tb, g.n_ranges,
+                                                     g.gbits, seg_run, nullptr, nullptr, nullptr, nullptr, err,
+                                                     events);
     ARA_HIP(hipGetLastError());
     std::vector<int32_t> cnt(g.nseg);
-    int32_t err = 0;
-    ARA_HIP(hipMemcpyAsync(&err, misc, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    int64_t head[3] = {0, 0, 0};
+    ARA_HIP(hipMemcpyAsync(head, misc, sizeof(head), hipMemcpyDeviceToHost, st));
     ARA_HIP(hipMemcpyAsync(cnt.data(), seg_run, g.nseg * sizeof(int32_t), hipMemcpyDeviceToHost, st));
     ARA_HIP(hipStreamSynchronize(st));
-    if (err) return fail(err, "ara_yet_prepare: an event ID lies outside [0, catalog) or offsets decrease");
+    const int32_t err_h = static_cast<int32_t>(head[0] & 0xffffffff);
+    if (err_h) return fail(err_h, "ara_yet_prepare: an event ID lies outside [0, catalog) or offsets decrease");
+    if (head[2] != nnz) return fail(ARA_E_RANGE, "ara_yet_prepare: offsets do not cover the IDs consistently");
 
     std::vector<int64_t> base(g.nseg);
     std::vector<int32_t> run(g.nseg);
-    int64_t total = 0, counted = 0;
+    int64_t total = 0;
     for (size_t i = 0; i < g.nseg; ++i) {
-        run[i] = (cnt[i] + kWave - 1) / kWave;
+        run[i] = ((cnt[i] + kWave - 1) / kWave + 3) & ~3;   // codes per lane, a multiple of 4
         base[i] = total;
         total += static_cast<int64_t>(run[i]) * kWave;
-        counted += cnt[i];
     }
-    if (counted != nnz) return fail(ARA_E_RANGE, "ara_yet_prepare: offsets do not cover the IDs consistently");
+    if (total > max_codes(g, nnz)) return fail(ARA_E_LIMIT, "ara_yet_prepare: code bound exceeded");
     ARA_HIP(hipMemcpyAsync(seg_base, base.data(), g.nseg * sizeof(int64_t), hipMemcpyHostToDevice, st));
     ARA_HIP(hipMemcpyAsync(seg_run, run.data(), g.nseg * sizeof(int32_t), hipMemcpyHostToDevice, st));
-    // padding entries name trial slot `tb` (one past the block) and event 0 of
-    // their range: harmless to every consumer, so no sentinel test is needed
-    if (total > 0)
-        ARA_HIP(hipMemsetD32Async(reinterpret_cast<hipDeviceptr_t>(ent), static_cast<int>(pad_entry(g.tb)),
-                                  static_cast<size_t>(total), st));
-    k_prep_scatter<<<g.n_blocks, 1024, 0, st>>>(offsets, ids, n_trials, g.tg, g.tb, g.n_ranges, g.gbits, seg_base,
-                                                seg_run, ent);
+    if (total > 0) ARA_HIP(hipMemsetAsync(code, 0xFF, static_cast<size_t>(total) * sizeof(uint16_t), st));   // padding
+    ARA_HIP(hipMemsetAsync(lane_start, 0, g.nseg * kWave, st));
+    // pass 2: the codes themselves
+    k_prep_codes<true><<<g.n_blocks, 1024, 0, st>>>(offsets, ids, n_trials, catalog, g.tg, g.tb, g.n_ranges,
+                                                    g.gbits, nullptr, seg_base, seg_run, code, lane_start, err,
+                                                    nullptr);
     ARA_HIP(hipGetLastError());
-    k_prep_max_occ<<<g.n_ranges, 1024, 0, st>>>(ent, seg_base, seg_run, g.n_blocks, g.n_ranges, g.tb, misc + 1);
+    ARA_HIP(hipStreamSynchronize(st));   // the host copies of base and run live in this scope
+    k_prep_max_occ<<<g.n_ranges, 1024, 0, st>>>(code, seg_base, seg_run, g.n_blocks, g.n_ranges, max_occ);
     ARA_HIP(hipGetLastError());
     if (transposed) {
         const dim3 grid(static_cast<unsigned>(g.n_ranges), kSlices);
-        k_tr_count<<<grid, 1024, 0, st>>>(ent, seg_base, seg_run, g.n_blocks, g.n_ranges, g.tb, g.slice_blocks,
-                                          catalog, tr_off, rtot);
+        k_tr_count<<<grid, 1024, 0, st>>>(code, seg_base, seg_run, g.n_blocks, g.n_ranges, g.slice_blocks, catalog,
+                                          tr_off, rtot);
         ARA_HIP(hipGetLastError());
         const size_t nreg = static_cast<size_t>(kSlices) * g.n_ranges;
         std::vector<int64_t> tot(nreg);
@@ -393,15 +466,15 @@ extern "C" int32_t ara_yet_prepare(const int64_t *offsets, const int32_t *ids, i
         ARA_HIP(hipMemcpyAsync(tr_off + static_cast<size_t>(kSlices) * catalog, &acc, sizeof(int64_t),
                                hipMemcpyHostToDevice, st));
         ARA_HIP(hipStreamSynchronize(st));   // the host sources live in this scope
-        k_tr_scatter<<<grid, 1024, 0, st>>>(ent, seg_base, seg_run, g.n_blocks, g.n_ranges, g.tb, g.slice_blocks,
-                                            catalog, rtot, tr_off, tr_ent);
+        k_tr_scatter<<<grid, 1024, 0, st>>>(code, seg_base, seg_run, lane_start, g.n_blocks, g.n_ranges, g.tg, g.tb,
+                                            g.slice_blocks, catalog, rtot, tr_off, tr_ent);
         ARA_HIP(hipGetLastError());
     }
     int32_t mo = 0;
-    ARA_HIP(hipMemcpyAsync(&mo, misc + 1, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    ARA_HIP(hipMemcpyAsync(&mo, max_occ, sizeof(int32_t), hipMemcpyDeviceToHost, st));
     ARA_HIP(hipStreamSynchronize(st));
     y.max_occ = mo;
-    y.n_entries = total;
+    y.n_codes = total;
     *out = y;
     return ARA_OK;
 }

@@ -58,6 +58,10 @@ struct Job {
     int b_lo = 0, b_hi = 0, next_block = 0;
     hipEvent_t done_ev = nullptr;
     bool finished_host = false;
+    // the quote's results, copied out of its result slot when it completes
+    // (the slot then serves the next quote): 3 metrics, 3x4 layer gradients,
+    // 3 x J x 3 ELT gradients in the quote's ELT order
+    std::vector<double> res;
 };
 
 struct ServerImpl {
@@ -275,6 +279,18 @@ void ServerImpl::loop() {
                     j.t_done = now_ms();
                     j.status = rc;
                     j.stage = kDone;
+                    if (rc == ARA_OK) {
+                        const double *r = h_res + static_cast<size_t>(j.slot) * res_doubles;
+                        const size_t J = j.elt_ids.size();
+                        j.res.assign(15 + 9 * J, 0.0);
+                        std::copy(r, r + 15, j.res.begin());
+                        if (j.q.want_grad)
+                            for (int c = 0; c < 3; ++c)
+                                for (size_t q = 0; q < J; ++q)
+                                    for (int m = 0; m < 3; ++m)
+                                        j.res[15 + (c * J + q) * 3 + m] =
+                                            r[15 + (static_cast<size_t>(c) * tables.n_elts + j.elt_ids[q]) * 3 + m];
+                    }
                     arena.release(j.mem_off, j.mem_bytes);
                     free_slots.push_back(j.slot);
                     it = active.erase(it);
@@ -381,19 +397,19 @@ static void fill_result(ServerImpl *S, const Job &j, ara_quote_result *out) {
     out->t_submit_ms = j.t_submit;
     out->t_admit_ms = j.t_admit;
     out->t_done_ms = j.t_done;
-    const double *r = S->h_res + static_cast<size_t>(j.slot) * S->res_doubles;
+    (void)S;
+    const size_t J = j.elt_ids.size();
+    if (j.res.size() < 15 + 9 * J) {   // failed quote: no results
+        for (int m = 0; m < 3; ++m) out->metrics[m] = 0.0;
+        for (int m = 0; m < 12; ++m) out->grad_layer[m / 4][m % 4] = 0.0;
+        return;
+    }
+    const double *r = j.res.data();
     for (int m = 0; m < 3; ++m) out->metrics[m] = r[m];
     if (j.q.want_grad) {
         for (int m = 0; m < 12; ++m) out->grad_layer[m / 4][m % 4] = r[3 + m];
-        if (out->grad_elt) {
-            // [3][J][3] in the quote's ELT order
-            const int ne = S->tables.n_elts;
-            for (int c = 0; c < 3; ++c)
-                for (size_t q = 0; q < j.elt_ids.size(); ++q)
-                    for (int m = 0; m < 3; ++m)
-                        out->grad_elt[(c * j.elt_ids.size() + q) * 3 + m] =
-                            r[15 + (static_cast<size_t>(c) * ne + j.elt_ids[q]) * 3 + m];
-        }
+        if (out->grad_elt)   // [3][J][3] in the quote's ELT order
+            for (size_t i = 0; i < 9 * J; ++i) out->grad_elt[i] = r[15 + i];
     } else {
         for (int m = 0; m < 12; ++m) out->grad_layer[m / 4][m % 4] = 0.0;
     }

@@ -50,12 +50,51 @@ def expected(yet_np, slice_trials, n_slices):
     return off, key[order], local[order]
 
 
+def check_codes(py, yet_np):
+    """Decode every segment of the 16-bit code stream on the host and compare
+    it with the raw trials: same (trial, offset) sequence, in trial order and
+    storage order inside a trial."""
+    import torch
+    h = py.handle
+    G, groups, tg, tb = h.n_ranges, h.groups, h.trials_per_group, h.trials_per_block
+    nseg = h.n_blocks * G * groups
+    codes = read_dev(py, h.code, max(h.n_codes, 1), torch.int16).view(np.uint16).astype(np.int64)
+    base = read_dev(py, h.seg_base, max(nseg, 1), torch.int64)
+    run = read_dev(py, h.seg_run, max(nseg, 1), torch.int32).astype(np.int64)
+    start = read_dev(py, h.lane_start, max(nseg * 64, 1), torch.uint8).astype(np.int64)
+    n = yet_np.n_trials
+    t = np.repeat(np.arange(n, dtype=np.int64), np.diff(yet_np.offsets))
+    ids = yet_np.ids.astype(np.int64)
+    key = ((t // tb) * G + (ids >> 15)) * groups + (t % tb) // tg
+    order = np.argsort(key, kind="stable")
+    key_s, trial_s, local_s = key[order], (t % tb % tg)[order], (ids & 0x7FFF)[order]
+    bounds = np.searchsorted(key_s, np.arange(nseg + 1))
+    lanes = np.arange(64)
+    for si in range(nseg):
+        R = int(run[si])
+        a, b = bounds[si], bounds[si + 1]
+        if R == 0:
+            assert a == b, f"segment {si}: events but no codes"
+            continue
+        assert R % 4 == 0
+        s = np.arange(R)
+        slot = base[si] + (s[None, :] // 4) * 256 + 4 * lanes[:, None] + s[None, :] % 4   # [64, R]
+        c = codes[slot]
+        tr = start[si * 64: si * 64 + 64][:, None] + np.cumsum(c >> 15, axis=1)
+        valid = c != 0xFFFF
+        got_t, got_l = tr[valid], (c & 0x7FFF)[valid]      # row-major: lane by lane, in order
+        assert np.array_equal(got_t, trial_s[a:b]), f"segment {si}: trials differ"
+        assert np.array_equal(got_l, local_s[a:b]), f"segment {si}: offsets differ"
+    assert h.n_codes >= yet_np.nnz
+
+
 def check(ara, yet_np):
     import torch
     _say(f"trials {yet_np.n_trials} nnz {yet_np.nnz} catalog {yet_np.catalog}")
     py = ara.PreparedYet.from_numpy(yet_np, "cuda")
     h = py.handle
     torch.cuda.synchronize()
+    check_codes(py, yet_np)
     assert h.n_slices == 8
     assert h.slice_trials % h.trials_per_block == 0 and h.slice_trials * h.n_slices >= yet_np.n_trials
     off_ref, key_ref, loc_ref = expected(yet_np, h.slice_trials, h.n_slices)
@@ -102,6 +141,30 @@ def test_no_trials_and_no_occurrences(ara):
 
 def test_config0_layout(ara):
     check(ara, synth.config(0, n_trials=20_000).yet)
+
+
+def test_gap_and_edge_offset_codes(ara):
+    """Trials with no event in a range between trials that have some (gap
+    codes), events at offset 0x7FFF opening a trial (their advance cannot sit
+    on the code), a trial of 300 events in one range (several 64-ID chunks)."""
+    g = np.random.default_rng(17)
+    trials = []
+    for k in range(40_000):   # 10 trials per group, so gaps occur inside segments
+        kind = k % 7
+        if kind == 0:
+            trials.append([])
+        elif kind == 1:
+            trials.append([32767, 32767 + 32768, 5])
+        elif kind == 2:
+            trials.append(list(g.integers(0, 100_000, size=300)))
+        elif kind == 3:
+            trials.append([32767] * 3 + [0])
+        else:
+            trials.append(list(g.integers(0, 100_000, size=int(g.integers(1, 6)))))
+    off = np.zeros(len(trials) + 1, np.int64)
+    np.cumsum([len(x) for x in trials], out=off[1:])
+    ids = np.array([e for x in trials for e in x], np.int32)
+    check(ara, synth.Yet(100_000, off, ids))
 
 
 def test_forward_only_prepare_and_backward_refusal(ara):

@@ -71,6 +71,21 @@ def test_alone_and_in_mix_equal_direct_calls(env):
         same(a, direct(ara, tables, yet, et, r, 0.99))
 
 
+def test_results_survive_slot_reuse(env):
+    """Two result slots, eight quotes, results collected last-first: every
+    quote's result must be its own even after later quotes reused its slot."""
+    ara, w, tables, yet, et, reqs = env
+    srv = ara.QuoteServer(tables, yet, et, quotes_with_grad=6, max_slots=2)
+    try:
+        tickets = [srv.submit(r.elt_ids, r.layer_terms, r.trial_begin, r.trial_end, 0.99, r.want_grad)
+                   for r in reqs[:8]]
+        got = {t: srv.wait(t) for t in reversed(tickets)}
+    finally:
+        srv.close()
+    for r, t in zip(reqs[:8], tickets):
+        same(got[t], direct(ara, tables, yet, et, r, 0.99))
+
+
 def test_quotes_match_oracle(env):
     ara, w, tables, yet, et, reqs = env
     tb = oracle.build_tables(w.elts)
