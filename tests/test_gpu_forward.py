@@ -259,3 +259,29 @@ def test_config1_full_size_sampled(ara):
     out, _ = ara.metrics(torch.tensor(y, device="cuda"), w.p)
     np.testing.assert_allclose(out.cpu().numpy(), oracle.metrics(y, w.p), rtol=TOL)
     assert np.all(y >= 0) and np.all(y <= w.layers.terms[0, 3])
+
+
+def _full_parity(ara, w, label):
+    """Every trial of a full-size workload against the oracle (all host
+    threads): YLT and S to the tolerance, hit counts bit-exact, through both
+    the plain path and the hit-count path (whose larger tables spill out of
+    LDS on the uneven workload)."""
+    _say(f"{label}: oracle over every trial")
+    ref = oracle_ref(w, threads=oracle.num_threads_available())
+    e = Engine(ara, w)
+    _say(f"{label}: forward")
+    y, s, _ = e.forward(hits=False)
+    assert_ylt(y, s, ref)
+    yh, sh, hh = e.forward(hits=True)
+    assert np.array_equal(hh, ref["hits"])
+    assert np.array_equal(yh, y) and np.array_equal(sh, s)
+
+
+def test_config1_full_size_every_trial(ara):
+    _say("workload 1: generating 1M x 1000")
+    _full_parity(ara, synth.config(1), "workload 1")
+
+
+def test_config2_full_size_every_trial(ara):
+    _say("workload 2: generating 1M x Poisson(1000), 4 layers over 55 ELTs")
+    _full_parity(ara, synth.config(2), "workload 2")
