@@ -50,7 +50,7 @@ def _load():
         lib.oracle_metrics.argtypes = [_P, _I32, _I64, _F64, _P]
         lib.oracle_metric_weights.argtypes = [_P, _I32, _I64, _F64, _P]
         lib.oracle_backward.argtypes = [_I32, _I32, _P, _I64, _P, _P, _I32, _P, _P, _P, _P,
-                                        _I64, _I64, _I32, _P, _P, _P]
+                                        _I64, _I64, _I32, _P, _I32, _P, _P]
         lib.oracle_num_threads_available.restype = _I32
         _lib = lib
     return _lib
@@ -140,9 +140,10 @@ def metric_weights(ylt: np.ndarray, p: float) -> np.ndarray:
 
 
 def backward(tables: np.ndarray, yet, layers, elt_terms, layer_terms, cot: np.ndarray,
-             t0: int = 0, t1: Optional[int] = None):
+             t0: int = 0, t1: Optional[int] = None, n_threads: int = 1):
     """Reverse sweep.  cot: [n_cot, n_layers, t1-t0].  Returns
-    (grad_elt [n_cot, n_elts, 3], grad_layer [n_cot, n_layers, 4])."""
+    (grad_elt [n_cot, n_elts, 3], grad_layer [n_cot, n_layers, 4]).
+    n_threads > 1 splits the trials into contiguous shares summed in order."""
     lib = _load()
     t1 = yet.n_trials if t1 is None else t1
     cot = _c(cot, np.float64)
@@ -158,7 +159,7 @@ def backward(tables: np.ndarray, yet, layers, elt_terms, layer_terms, cot: np.nd
     et, lt = _c(elt_terms, np.float64), _c(layer_terms, np.float64)
     rc = lib.oracle_backward(tb.shape[0], tb.shape[1], _ptr(tb), yet.n_trials, _ptr(off), _ptr(ids),
                              nl, _ptr(lo), _ptr(le), _ptr(et), _ptr(lt), t0, t1, nc, _ptr(cot),
-                             _ptr(ge), _ptr(gl))
+                             n_threads, _ptr(ge), _ptr(gl))
     if rc != 0:
         raise OracleError(f"oracle_backward status {rc}")
     return ge, gl

@@ -309,7 +309,7 @@ int oracle_backward(int32_t n_elts, int32_t catalog, const float *tables,
                     int32_t n_layers, const int32_t *layer_off, const int32_t *layer_elts,
                     const double *elt_terms, const double *layer_terms,
                     int64_t t0, int64_t t1, int32_t n_cot, const double *cot,
-                    double *grad_elt, double *grad_layer)
+                    int32_t n_threads, double *grad_elt, double *grad_layer)
 {
     if (t0 < 0 || t1 < t0 || t1 > n_trials || n_cot < 0) return OR_E_INVAL;
     const int64_t nt = t1 - t0;
@@ -328,8 +328,33 @@ int oracle_backward(int32_t n_elts, int32_t catalog, const float *tables,
         for (int32_t c = layer_off[a]; c < layer_off[a + 1]; ++c)
             if (layer_elts[c] < 0 || layer_elts[c] >= n_elts) return OR_E_RANGE;
     }
-    memset(grad_elt, 0, sizeof(double) * (size_t)n_cot * (size_t)n_elts * 3);
-    memset(grad_layer, 0, sizeof(double) * (size_t)n_cot * (size_t)n_layers * 4);
+    const size_t n_ge = (size_t)n_cot * (size_t)n_elts * 3, n_gl = (size_t)n_cot * (size_t)n_layers * 4;
+    memset(grad_elt, 0, sizeof(double) * n_ge);
+    memset(grad_layer, 0, sizeof(double) * n_gl);
+    if (n_threads < 1) n_threads = 1;
+#ifndef _OPENMP
+    n_threads = 1;
+#endif
+    /* each thread sums its own contiguous share of the trials; the shares are
+     * added in thread order afterwards, so a given thread count always gives
+     * the same result (one thread: trial order throughout) */
+    double *part = (double *)calloc((size_t)n_threads * (n_ge + n_gl), sizeof(double));
+    if (!part) return OR_E_NOMEM;
+    int rc = OR_OK;
+#ifdef _OPENMP
+#pragma omp parallel num_threads(n_threads)
+#endif
+    {
+#ifdef _OPENMP
+    const int tid = omp_get_thread_num(), nth = omp_get_num_threads();
+#else
+    const int tid = 0, nth = 1;
+#endif
+    const int64_t chunk = (nt + nth - 1) / nth;
+    const int64_t b0 = t0 + (int64_t)tid * chunk;
+    const int64_t b1 = (b0 + chunk < t1) ? b0 + chunk : t1;
+    double *my_ge = part + (size_t)tid * (n_ge + n_gl);
+    double *my_gl = my_ge + n_ge;
     const size_t m = (size_t)(max_len + 1);
     const size_t mj = (size_t)(max_j > 0 ? max_j : 1);
     double *xk = (double *)malloc(sizeof(double) * m * mj);   /* looked-up losses per ELT */
@@ -341,13 +366,17 @@ int oracle_backward(int32_t n_elts, int32_t catalog, const float *tables,
     double *adj_f = (double *)malloc(sizeof(double) * m);
     double *adj_c = (double *)malloc(sizeof(double) * m);
     double *adj_o = (double *)malloc(sizeof(double) * m);
-    int rc = OR_OK;
-    if (!xk || !pre || !lsum || !o || !c || !f || !adj_f || !adj_c || !adj_o) { rc = OR_E_NOMEM; goto done; }
+    if (!xk || !pre || !lsum || !o || !c || !f || !adj_f || !adj_c || !adj_o) {
+#ifdef _OPENMP
+#pragma omp atomic write
+#endif
+        rc = OR_E_NOMEM;
+    } else
     for (int32_t a = 0; a < n_layers; ++a) {
         const double OccR = layer_terms[4 * a + 0], OccL = layer_terms[4 * a + 1];
         const double AggR = layer_terms[4 * a + 2], AggL = layer_terms[4 * a + 3];
         const int32_t J = layer_off[a + 1] - layer_off[a];
-        for (int64_t b = t0; b < t1; ++b) {
+        for (int64_t b = b0; b < b1; ++b) {
             const int32_t *ev = ids + offsets[b];
             const int64_t n = offsets[b + 1] - offsets[b];
             /* forward, keeping every intermediate */
@@ -369,8 +398,8 @@ int oracle_backward(int32_t n_elts, int32_t catalog, const float *tables,
             for (int64_t d = 0; d < n; ++d) f[d] = clamp_xl(c[d], AggR, AggL);
             for (int32_t g = 0; g < n_cot; ++g) {
                 const double w = cot[((size_t)g * n_layers + a) * (size_t)nt + (size_t)(b - t0)];
-                double *ge = grad_elt + (size_t)g * (size_t)n_elts * 3;
-                double *gl = grad_layer + ((size_t)g * n_layers + a) * 4;
+                double *ge = my_ge + (size_t)g * (size_t)n_elts * 3;
+                double *gl = my_gl + ((size_t)g * n_layers + a) * 4;
                 if (w == 0.0 || n == 0) continue;
                 /* lr = sum_d (f_d - f_{d-1}), f_0 := 0: adjoint of the
                  * summation gives w on every increment; the adjoint of the
@@ -416,9 +445,15 @@ int oracle_backward(int32_t n_elts, int32_t catalog, const float *tables,
             }
         }
     }
-done:
     free(xk); free(pre); free(lsum); free(o); free(c); free(f);
     free(adj_f); free(adj_c); free(adj_o);
+    }
+    for (int th = 0; th < n_threads; ++th) {
+        const double *pg = part + (size_t)th * (n_ge + n_gl);
+        for (size_t i = 0; i < n_ge; ++i) grad_elt[i] += pg[i];
+        for (size_t i = 0; i < n_gl; ++i) grad_layer[i] += pg[n_ge + i];
+    }
+    free(part);
     return rc;
 }
 

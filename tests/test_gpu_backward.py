@@ -180,6 +180,24 @@ def test_config3_full_size_properties(ara):
             assert abs(fd[c] - gl[c, 0, col]) <= 2e-2 * scale + 1e-9, (col, c, fd[c], gl[c, 0, col])
 
 
+def test_config3_full_size_vs_oracle(ara):
+    """1M x 1000 x 15 with perturbed terms: the gradients of AAL, PML and TVaR
+    with respect to every term against the oracle's literal reverse sweep
+    over every trial, fed the same cotangent rows."""
+    _say("workload 3 full size: GPU forward, metrics, backward")
+    w = synth.config(3)
+    e = Engine(ara, w)
+    ylt, s_pre, _ = e.forward()
+    _, wts = ara.metrics(ylt, w.p, want_weights=True)
+    ge, gl = e.backward(s_pre, wts)
+    _say("workload 3 full size: oracle reverse sweep")
+    tb = oracle.build_tables(w.elts)
+    rge, rgl = oracle.backward(tb, w.yet, w.layers, w.elts.terms, w.layers.terms, wts.cpu().numpy(),
+                               n_threads=oracle.num_threads_available())
+    close(ge, rge)
+    close(gl, rgl)
+
+
 def test_autograd_matches_direct_call(ara):
     import torch
     w = synth.config(2, n_trials=3000)

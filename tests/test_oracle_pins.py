@@ -477,3 +477,19 @@ def test_yelt_without_aggregate_terms_is_occurrence_loss():
         a, b = off[t], off[t + 1]
         S = r["s_pre"][0, t]
         assert np.all(np.abs(r["yelt"][0][a:b] - ref[0][a:b]) <= 4 * max(b - a, 1) * U * S)
+
+
+def test_threaded_reverse_sweep_matches_sequential():
+    """The trial split of the reverse sweep changes only the order in which
+    per-trial contributions are added."""
+    w = synth.tiny_random(4, n_trials=400, max_events=40, n_layers=2)
+    tb, r = run(w)
+    cot = np.random.default_rng(9).normal(size=(3,) + r["ylt"].shape)
+    ge1, gl1 = oracle.backward(tb, w.yet, w.layers, w.elts.terms, w.layers.terms, cot)
+    ge4, gl4 = oracle.backward(tb, w.yet, w.layers, w.elts.terms, w.layers.terms, cot, n_threads=4)
+    ge4b, gl4b = oracle.backward(tb, w.yet, w.layers, w.elts.terms, w.layers.terms, cot, n_threads=4)
+    assert np.array_equal(ge4, ge4b) and np.array_equal(gl4, gl4b)
+    scale_e = np.abs(ge1).max() + 1e-300
+    scale_l = np.abs(gl1).max() + 1e-300
+    assert np.abs(ge4 - ge1).max() <= 1e-12 * scale_e
+    assert np.abs(gl4 - gl1).max() <= 1e-12 * scale_l
