@@ -7,9 +7,10 @@
 // catalogue, so each trial's total is accumulated by a single wavefront in a
 // fixed order: deterministic.  The catalogue is walked one range (2^15
 // events) at a time; the range's slice of the occurrence table (bitmap words
-// with ranks, then the values) sits in one of two LDS buffers, and the next
-// range's slice is copied into the other buffer by LDS DMA
-// (global_load_lds_dwordx4) while the current range streams.
+// with ranks, then the values) is copied into LDS by LDS DMA
+// (global_load_lds_dwordx4).  A workgroup takes 80 KB of LDS and at most 64
+// registers per lane, so two workgroups share a CU (8 wavefronts per SIMD):
+// while one waits for its next table slice the other streams.
 #include "occ.h"
 
 #include <algorithm>
@@ -17,8 +18,8 @@
 
 namespace ara {
 
-constexpr int kUnroll = 16;
-constexpr int kLdsBytes = 160 * 1024;
+constexpr int kUnroll = 8;
+constexpr int kLdsBytes = 80 * 1024;
 constexpr int kBrBytes = 1024 * static_cast<int>(sizeof(uint2));   // one range's bitmap words with ranks
 
 struct FwdParams {
@@ -73,7 +74,7 @@ struct RangeInfo {
 };
 
 template <bool HITS>
-__global__ __launch_bounds__(1024) void k_fwd(FwdParams P) {
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_fwd(FwdParams P) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int tb = P.tb;
     double *acc = reinterpret_cast<double *>(smem);                                     // [tb + 1]
@@ -101,9 +102,9 @@ __global__ __launch_bounds__(1024) void k_fwd(FwdParams P) {
     }
     const OccTables T = *I.tab;
 
-    // copy range r's table slice into buffer k, split over the wavefronts
-    auto fetch = [&](int r, RangeInfo ri, int k) {
-        const uint32_t dst = bufs_lds + static_cast<uint32_t>(k * P.buf_bytes);
+    // copy range r's table slice into LDS, split over the wavefronts
+    auto fetch = [&](int r, RangeInfo ri) {
+        const uint32_t dst = bufs_lds;
         const size_t s = static_cast<size_t>(r >> 1);
         const unsigned char *gbr = reinterpret_cast<const unsigned char *>(T.br + s * kSrWords + (r & 1) * 1024);
         for (int c0 = w * kWave; c0 < kBrBytes / 16; c0 += kGroups * kWave)
@@ -208,15 +209,14 @@ __global__ __launch_bounds__(1024) void k_fwd(FwdParams P) {
     int tcur = 0;                   // the lane's current trial within its group
     __syncthreads();   // range table counts published
     RangeInfo cur = range_info(0);
-    fetch(0, cur, 0);
+    fetch(0, cur);
     seek();
     load();
     wait_dma();
     __syncthreads();
 
     for (int r = 0; r < G; ++r) {
-        const int k = r & 1;
-        unsigned char *buf = bufs + static_cast<size_t>(k) * P.buf_bytes;
+        unsigned char *buf = bufs;
         const uint2 *tbr = reinterpret_cast<const uint2 *>(buf);
         const double *tvals = reinterpret_cast<const double *>(buf + kBrBytes);
         const uint8_t *tcnt = buf + kBrBytes + static_cast<size_t>(P.capv) * 8;
@@ -229,7 +229,6 @@ __global__ __launch_bounds__(1024) void k_fwd(FwdParams P) {
         const bool all_lds = cur.cnt + (cur.base & 15u) <= static_cast<uint32_t>(P.capv);   // uniform
         RangeInfo nxt{0, 0};
         if (r + 1 < G) nxt = range_info(r + 1);
-        bool fetched = r + 1 >= G;
         // this wave's trial totals (and hit counts), and the values indexed by
         // super-range rank
         double *acc_w = acc + tbase_w;
@@ -246,10 +245,6 @@ __global__ __launch_bounds__(1024) void k_fwd(FwdParams P) {
                 cw[u] = __builtin_amdgcn_ubfe(word, 16 * (u & 1), 16);
             }
             load();   // prefetch the next chunk (possibly of a later range)
-            if (!fetched) {   // after the first chunk's loads: the range info has arrived
-                fetch(r + 1, nxt, k ^ 1);
-                fetched = true;
-            }
             // bitmap words of all codes first, without branches, so the LDS
             // reads are in flight together (offset bits 5..14 pick the word)
             uint2 q[kUnroll];
@@ -298,8 +293,9 @@ __global__ __launch_bounds__(1024) void k_fwd(FwdParams P) {
                     }
             }
         }
-        if (!fetched) fetch(r + 1, nxt, k ^ 1);
         cur = nxt;
+        __syncthreads();   // every wave is done with the table slice
+        if (r + 1 < G) fetch(r + 1, nxt);
         wait_dma();
         __syncthreads();
     }
@@ -329,8 +325,8 @@ int32_t launch_forward(const ara_yet *yet, int n_sr, bool hits, const FwdItem *d
     P.tg = yet->trials_per_group;
     P.tb = yet->trials_per_block;
     P.n_ranges = yet->n_ranges;
-    // two range buffers: [bitmap words with ranks][values][counts (hits mode)]
-    const size_t per_buf = ((kLdsBytes - fwd_acc_lds(P.tb, hits) - fwd_meta_lds(P.n_ranges)) / 2) & ~size_t(255);
+    // the range's table slice: [bitmap words with ranks][values][counts (hits mode)]
+    const size_t per_buf = (kLdsBytes - fwd_acc_lds(P.tb, hits) - fwd_meta_lds(P.n_ranges)) & ~size_t(255);
     size_t capv = hits ? (per_buf - kBrBytes - 16) / 9 : (per_buf - kBrBytes) / 8;
     capv &= ~size_t(15);
     P.capv = static_cast<int32_t>(capv);

@@ -36,7 +36,8 @@ struct Geometry {
 static Geometry geometry(int64_t n_trials, int32_t catalog) {
     Geometry g{};
     const int64_t cu = device_cu_count();
-    int64_t tg = (n_trials + kGroups * cu - 1) / (kGroups * cu);
+    // two blocks per CU: the forward runs two workgroups on every CU
+    int64_t tg = (n_trials + 2 * kGroups * cu - 1) / (2 * kGroups * cu);
     tg = std::max<int64_t>(1, std::min<int64_t>(tg, kMaxTrialsPerGroup));
     g.tg = static_cast<int>(tg);
     g.tb = kGroups * g.tg;

@@ -84,7 +84,7 @@ struct ServerImpl {
     hipEvent_t item_ev[kRing] = {nullptr, nullptr};
     bool item_used[kRing] = {false, false};
     int ring = 0;
-    int blocks_per_iter = 512;
+    int blocks_per_iter = 1024;
 
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
