@@ -149,11 +149,25 @@ __global__ __launch_bounds__(kMetThreads) void k_met_pass(const double *__restri
     chunk_of(n, nwg, wg, lo, hi);
     const double *y = ylt + static_cast<size_t>(l) * n;
     double s = 0.0;
-    for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
-        const double v = y[i];
+    const int lane = threadIdx.x & 63;
+    for (int64_t i0 = lo; i0 < hi; i0 += blockDim.x) {   // uniform trip count: every lane reaches the ballots
+        const int64_t i = i0 + threadIdx.x;
+        const double v = (i < hi) ? y[i] : 0.0;
         const uint64_t u = key_of(v);
         if (d == 0) s += v;
-        if (hb >= 64 || (u >> hb) == prefix) atomicAdd(&h[(u >> sh) & mask], 1u);
+        const bool want = i < hi && (hb >= 64 || (u >> hb) == prefix);
+        const uint32_t dg = static_cast<uint32_t>((u >> sh) & mask);
+        // year losses of one row crowd into few digits (the exponent above
+        // all): the first lane's digit is counted for all the lanes that
+        // share it with one LDS atomic, the rest count themselves
+        const uint64_t act = __ballot(want);
+        if (act) {
+            const int leader = __builtin_ctzll(act);
+            const uint32_t ld = __builtin_amdgcn_readlane(dg, leader);
+            const uint64_t same = __ballot(want && dg == ld);
+            if (lane == leader) atomicAdd(&h[ld], static_cast<uint32_t>(__popcll(same)));
+            if (want && dg != ld) atomicAdd(&h[dg], 1u);
+        }
     }
     if (d == 0) {
         const double tot = block_sum(s, red);
