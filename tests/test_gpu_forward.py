@@ -285,3 +285,40 @@ def test_config1_full_size_every_trial(ara):
 def test_config2_full_size_every_trial(ara):
     _say("workload 2: generating 1M x Poisson(1000), 4 layers over 55 ELTs")
     _full_parity(ara, synth.config(2), "workload 2")
+
+
+def test_largest_catalogue(ara):
+    """A catalogue of ARA_MAX_CATALOG = 2^26 events: 2048 ranges, so the YET
+    preparation walks its per-range state in two windows and the forward's
+    range table is at its largest; events crowd the first and last ranges and
+    one in the middle, the rest are spread out."""
+    cat = 1 << 26
+    g = np.random.default_rng(31)
+    n = 6000
+    lens = g.integers(0, 120, size=n)
+    off = np.zeros(n + 1, np.int64)
+    np.cumsum(lens, out=off[1:])
+    ids = g.integers(0, cat, size=int(off[-1]), dtype=np.int64)
+    pick = g.random(ids.shape[0])
+    ids[pick < 0.2] = g.integers(0, 40_000, size=int((pick < 0.2).sum()))
+    ids[(pick >= 0.2) & (pick < 0.4)] = g.integers(cat - 40_000, cat, size=int(((pick >= 0.2) & (pick < 0.4)).sum()))
+    ids[(pick >= 0.4) & (pick < 0.5)] = g.integers(1 << 25, (1 << 25) + 30_000, size=int(((pick >= 0.4) & (pick < 0.5)).sum()))
+    ids = ids.astype(np.int32)
+    # ELTs drawn from the same crowded places so that many occurrences hit
+    hot = np.unique(ids)
+    recs = [np.sort(g.choice(hot, size=min(len(hot), k), replace=False)) for k in (20_000, 8_000, 30_000)]
+    rec_off = np.zeros(4, np.int64)
+    np.cumsum([len(r) for r in recs], out=rec_off[1:])
+    rec_ids = np.concatenate(recs).astype(np.int32)
+    rec_loss = np.exp(g.normal(11.0, 1.5, size=rec_ids.shape[0])).astype(np.float32)
+    elts = synth.Elts(cat, rec_off, rec_ids, rec_loss, np.array([[1.0, 5e4, 5e6], [1.5, 1e4, 2e6], [0.8, 0.0, np.inf]]))
+    layers = synth.Layers(np.array([0, 3, 4], np.int32), np.array([0, 1, 2, 1], np.int32),
+                          np.array([[1e4, 2e7, 1e5, 1e8], [0.0, np.inf, 0.0, np.inf]]))
+    w = synth.Workload("max-catalogue", synth.Yet(cat, off, ids), elts, layers, 0.95)
+    _say("largest catalogue: prepare and forward")
+    e = Engine(ara, w)
+    assert e.yet.handle.n_ranges == 2048
+    ref = oracle_ref(w, threads=oracle.num_threads_available())
+    y, s, h = e.forward()
+    assert np.array_equal(h, ref["hits"])
+    assert_ylt(y, s, ref)
