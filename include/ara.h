@@ -112,7 +112,7 @@ typedef struct ara_yet {
     int32_t   n_blocks;          /* ceil(n_trials / trials_per_block) */
     int32_t   max_occ;           /* largest number of occurrences of one event */
     int64_t   n_codes;           /* 16-bit codes including gap codes and padding */
-    uint16_t *code;              /* device [n_codes] */
+    uint16_t *code;              /* device [n_codes + 256]: the last 256 are skip codes (0xFFFF) */
     int64_t  *seg_base;          /* device [n_blocks][n_ranges][groups]: the segment's first code */
     int32_t  *seg_run;           /* device [n_blocks][n_ranges][groups]: codes per lane */
     uint8_t  *lane_start;        /* device [n_blocks][n_ranges][groups][64]: each lane's first trial */

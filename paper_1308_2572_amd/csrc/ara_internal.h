@@ -21,10 +21,11 @@ constexpr int kMaxTrialsPerBlock = kGroups * kMaxTrialsPerGroup;   // 4096
 constexpr int kSrBits = 16;                    // one occurrence-table "super-range" = 2 ranges
 constexpr int kSr = 1 << kSrBits;
 constexpr int kSrWords = kSr / 32;             // 2048 bitmap words per super-range
-// Padding entry of a block with `tb` trials: trial slot tb (one past the
-// block's trials) and event 0 of the range.
-__host__ __device__ inline uint32_t pad_entry(int tb) { return static_cast<uint32_t>(tb) << kRangeBits; }
 constexpr int kWave = 64;
+// Skip codes (0xFFFF) stored after the last code of a prepared YET: one
+// 8-byte load per lane of a wavefront reads them in place of codes past a
+// segment's end.
+constexpr int kPadCodes = 4 * kWave;
 // Trial slices of the event-major YET copy: one per XCD of the MI355X, so
 // that a backward workgroup's gathers of per-trial weights stay in the L2 of
 // the XCD it runs on (workgroups are dealt to the XCDs round-robin).

@@ -15,6 +15,7 @@
 
 #include <algorithm>
 #include <string>
+#include <type_traits>
 
 namespace ara {
 
@@ -24,6 +25,7 @@ constexpr int kBrBytes = 1024 * static_cast<int>(sizeof(uint2));   // one range'
 
 struct FwdParams {
     const uint16_t *code;
+    const uint16_t *pad;       // kPadCodes skip codes
     const int64_t *seg_base;
     const int32_t *seg_run;
     const uint8_t *lane_start;
@@ -55,6 +57,17 @@ __device__ __forceinline__ void lds_dma16(const void *src, uint32_t lds_base) {
 
 __device__ __forceinline__ void wait_dma() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
 
+// a + 8 * (bit POS of x): two instructions.  Written out because the
+// optimiser otherwise turns it into shift, mask and add, or re-derives every
+// address of a chain from a running count (three instructions either way).
+template <int POS>
+__device__ __forceinline__ uint32_t add_bit8(uint32_t a, uint32_t x) {
+    uint32_t b, r;
+    asm("v_bfe_u32 %0, %1, %2, 1" : "=v"(b) : "v"(x), "n"(POS));
+    asm("v_lshl_add_u32 %0, %1, 3, %2" : "=v"(r) : "v"(b), "v"(a));
+    return r;
+}
+
 // LDS bytes of the per-trial totals (and hit counts), including the padding
 // slot; the table counts of every range; each wavefront's window of 64
 // segment descriptors (run length, base) -- descriptors come from LDS so that
@@ -75,16 +88,22 @@ struct RangeInfo {
 
 template <bool HITS>
 __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_fwd(FwdParams P) {
-    extern __shared__ __align__(16) unsigned char smem[];
+    // LDS: [range buffer][trial totals][hit counts][range table][segment windows].
+    // A static array: its addresses are compile-time constants, which the LDS
+    // instructions take as immediate offsets.
+    __shared__ __align__(16) unsigned char smem[kLdsBytes];
     const int tb = P.tb;
-    double *acc = reinterpret_cast<double *>(smem);                                     // [tb + 1]
-    int32_t *hacc = reinterpret_cast<int32_t *>(smem + static_cast<size_t>(tb + 1) * 8);   // [tb + 1]
+    const uint32_t acc_off = static_cast<uint32_t>(P.buf_bytes);
+    const uint32_t hacc_off = acc_off + static_cast<uint32_t>(tb + 1) * 8;
+    double *acc = reinterpret_cast<double *>(smem + acc_off);     // [tb + 1]
+    int32_t *hacc = reinterpret_cast<int32_t *>(smem + hacc_off);  // [tb + 1]
     const int G = P.n_ranges;
-    uint2 *rinfo = reinterpret_cast<uint2 *>(smem + fwd_acc_lds(tb, HITS));                     // [G] (base, cnt)
-    unsigned char *meta2 = smem + fwd_acc_lds(tb, HITS) + align256(static_cast<size_t>(G) * 8);
+    unsigned char *meta = smem + acc_off + fwd_acc_lds(tb, HITS);
+    uint2 *rinfo = reinterpret_cast<uint2 *>(meta);                                             // [G] (base, cnt)
+    unsigned char *meta2 = meta + align256(static_cast<size_t>(G) * 8);
     int64_t *wbase_all = reinterpret_cast<int64_t *>(meta2);                                    // [16][64]
     int32_t *wrun_all = reinterpret_cast<int32_t *>(meta2 + kGroups * kWave * 8);               // [16][64]
-    unsigned char *bufs = smem + fwd_acc_lds(tb, HITS) + fwd_meta_lds(G);
+    unsigned char *bufs = smem;
     const uint32_t bufs_lds = static_cast<uint32_t>(reinterpret_cast<uintptr_t>(bufs));
 
     const FwdItem I = P.items[blockIdx.x];
@@ -176,8 +195,12 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8))) vo
             rr = seg_win + kWave;
         }
     };
-    // a chunk is kUnroll codes per lane (four 8-byte loads); the first chunk
-    // of a segment also brings the lane's starting trial
+    // a chunk is kUnroll codes per lane (two 8-byte loads); the first chunk of
+    // a segment also brings the lane's starting trial.  Runs are multiples of
+    // 4 codes, so only a chunk's second load can lie past the segment's end:
+    // it then reads skip codes from the block after the last code.  Nothing
+    // is selected on the loaded words, so the loads stay in flight while the
+    // previous chunk is processed.
     unsigned long long X[kUnroll / 4];
     int X_start = 0;
     bool X_first = false;
@@ -187,14 +210,11 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8))) vo
         if (rr < G) {
             X_first = step == 0;
             if (X_first) X_start = P.lane_start[(seg0 + static_cast<size_t>(rr) * kGroups) * kWave + lane];
-            // every load is issued (steps past the segment's end re-read its
-            // last four, same cache lines) and then replaced by padding: no
-            // branch per load
 #pragma unroll
             for (int q = 0; q < kUnroll / 4; ++q) {
-                const int s4 = min(step + 4 * q, R - 4);
-                const unsigned long long v = ld_codes(P.code + sb + static_cast<int64_t>(s4 >> 2) * (4 * kWave) + 4 * lane);
-                X[q] = (step + 4 * q < R) ? v : ~0ull;
+                const uint16_t *src = step + 4 * q < R ? P.code + sb + static_cast<int64_t>((step >> 2) + q) * (4 * kWave)
+                                                       : P.pad;   // uniform
+                X[q] = ld_codes(src + 4 * lane);
             }
             step += kUnroll;
             if (step >= R) {
@@ -205,8 +225,10 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8))) vo
         }
     };
 
-    const int tbase_w = w * P.tg;   // first trial of this wave's group within the block
-    int tcur = 0;                   // the lane's current trial within its group
+    // byte offset (from smem) of the lane's current trial total; a trial
+    // advance moves it by one slot
+    const uint32_t accw_off = acc_off + static_cast<uint32_t>(w * P.tg) * 8;
+    uint32_t tofs = accw_off;
     __syncthreads();   // range table counts published
     RangeInfo cur = range_info(0);
     fetch(0, cur);
@@ -216,10 +238,9 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8))) vo
     __syncthreads();
 
     for (int r = 0; r < G; ++r) {
-        unsigned char *buf = bufs;
-        const uint2 *tbr = reinterpret_cast<const uint2 *>(buf);
-        const double *tvals = reinterpret_cast<const double *>(buf + kBrBytes);
-        const uint8_t *tcnt = buf + kBrBytes + static_cast<size_t>(P.capv) * 8;
+        const uint2 *tbr = reinterpret_cast<const uint2 *>(smem);
+        const double *tvals = reinterpret_cast<const double *>(smem + kBrBytes);
+        const uint8_t *tcnt = smem + kBrBytes + static_cast<size_t>(P.capv) * 8;
         const size_t s = static_cast<size_t>(r >> 1);
         const double *gvals = T.vals + s * kSr;
         const uint8_t *gcnt = HITS ? T.cnt + s * kSr : nullptr;
@@ -227,71 +248,87 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8))) vo
         // values with buffer index below vlim (and counts below clim) are in LDS
         const uint32_t vlim = static_cast<uint32_t>(P.capv), clim = static_cast<uint32_t>(P.capv);
         const bool all_lds = cur.cnt + (cur.base & 15u) <= static_cast<uint32_t>(P.capv);   // uniform
+        // skip codes (0xFFFF) read the range's last bitmap bit: only when that
+        // event is set do they have to be told apart from it
+        const bool last_set = (__builtin_amdgcn_readfirstlane(tbr[1023].x) >> 31) != 0u;   // uniform
         RangeInfo nxt{0, 0};
         if (r + 1 < G) nxt = range_info(r + 1);
-        // this wave's trial totals (and hit counts), and the values indexed by
-        // super-range rank
-        double *acc_w = acc + tbase_w;
-        int32_t *hacc_w = hacc + tbase_w;
-        const double *tv = tvals - vsh;
-        const uint8_t *tc = tcnt - csh;
-        while (chunk_rr == r) {
-            // codes of this chunk: four per 8-byte load, low half first
-            if (X_first) tcur = X_start;
-            uint32_t cw[kUnroll];
+        // LDS byte offsets of value and count 0 of the super-range: unsigned
+        // arithmetic, so the offsets wrap, while every address formed from
+        // them lies in the buffer
+        const uint32_t vbase = static_cast<uint32_t>(kBrBytes) - vsh * 8u;
+        const uint32_t cbase = static_cast<uint32_t>(kBrBytes) + static_cast<uint32_t>(P.capv) * 8u - csh;
+        auto chunk = [&](auto skip_tag) {
+            constexpr bool kTellSkip = decltype(skip_tag)::value;
+            if (X_first) tofs = accw_off + 8u * static_cast<uint32_t>(X_start);
+            // codes of this chunk, two per 32-bit word, low half first
+            uint32_t wd[kUnroll / 2];
 #pragma unroll
-            for (int u = 0; u < kUnroll; ++u) {
-                const uint32_t word = static_cast<uint32_t>(X[u >> 2] >> (32 * ((u >> 1) & 1)));
-                cw[u] = __builtin_amdgcn_ubfe(word, 16 * (u & 1), 16);
-            }
+            for (int h = 0; h < kUnroll / 2; ++h) wd[h] = static_cast<uint32_t>(X[h >> 1] >> (32 * (h & 1)));
             load();   // prefetch the next chunk (possibly of a later range)
             // bitmap words of all codes first, without branches, so the LDS
             // reads are in flight together (offset bits 5..14 pick the word)
+            uint32_t cw[kUnroll];
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) cw[u] = (u & 1) ? (wd[u >> 1] >> 16) : wd[u >> 1];
             uint2 q[kUnroll];
 #pragma unroll
             for (int u = 0; u < kUnroll; ++u) q[u] = tbr[__builtin_amdgcn_ubfe(cw[u], 5, 10)];
             // each code advances the lane's trial by its top bit
-            int tr[kUnroll];
+            uint32_t ta[kUnroll];
 #pragma unroll
             for (int u = 0; u < kUnroll; ++u) {
-                tcur += static_cast<int>(cw[u] >> 15);
-                tr[u] = tcur;
+                tofs = (u & 1) ? add_bit8<31>(tofs, wd[u >> 1]) : add_bit8<15>(tofs, wd[u >> 1]);
+                ta[u] = tofs;
             }
-            // an event is set when its bit is; skip codes (0xFFFF) never are
+            // bit and rank: the bit field instructions read only the low five
+            // bits of their offset and width operands, which hold the bit
             bool on[kUnroll];
             uint32_t rank[kUnroll];
 #pragma unroll
             for (int u = 0; u < kUnroll; ++u) {
-                const uint32_t bit = cw[u] & 31;
-                on[u] = (cw[u] != 0xFFFFu) && __builtin_amdgcn_ubfe(q[u].x, bit, 1);
-                rank[u] = __popc(q[u].x & ((1u << bit) - 1u)) + q[u].y;
+                on[u] = __builtin_amdgcn_ubfe(q[u].x, cw[u], 1) != 0u;
+                if (kTellSkip) on[u] = on[u] && (cw[u] & 0xFFFFu) != 0xFFFFu;
+                rank[u] = __popc(__builtin_amdgcn_ubfe(q[u].x, 0, cw[u])) + q[u].y;
             }
             if (all_lds) {
                 double v[kUnroll];
 #pragma unroll
-                for (int u = 0; u < kUnroll; ++u) v[u] = tv[on[u] ? rank[u] : vsh];
+                for (int u = 0; u < kUnroll; ++u)
+                    v[u] = *reinterpret_cast<const double *>(smem + ((on[u] ? rank[u] : vsh) * 8u + vbase));
 #pragma unroll
                 for (int u = 0; u < kUnroll; ++u)
                     if (on[u]) {
-                        atomicAdd(&acc_w[tr[u]], v[u]);
-                        if (HITS) atomicAdd(&hacc_w[tr[u]], static_cast<int>(tc[rank[u]]));
+                        atomicAdd(reinterpret_cast<double *>(smem + ta[u]), v[u]);
+                        if (HITS)
+                            atomicAdd(reinterpret_cast<int32_t *>(smem + hacc_off + ((ta[u] - acc_off) >> 1)),
+                                      static_cast<int>(smem[rank[u] + cbase]));
                     }
             } else {
 #pragma unroll
                 for (int u = 0; u < kUnroll; ++u)
                     if (on[u]) {
+                        // indexes relative to the buffer start, so that every
+                        // address stays inside its array
                         double v;
                         int c = 0;
-                        if (rank[u] - vsh < vlim) v = tv[rank[u]];
+                        const uint32_t iv = rank[u] - vsh;
+                        if (iv < vlim) v = tvals[iv];
                         else v = gvals[rank[u]];
                         if (HITS) {
-                            if (rank[u] - csh < clim) c = tc[rank[u]];
+                            const uint32_t ic = rank[u] - csh;
+                            if (ic < clim) c = tcnt[ic];
                             else c = gcnt[rank[u]];
                         }
-                        atomicAdd(&acc_w[tr[u]], v);
-                        if (HITS) atomicAdd(&hacc_w[tr[u]], c);
+                        atomicAdd(reinterpret_cast<double *>(smem + ta[u]), v);
+                        if (HITS) atomicAdd(reinterpret_cast<int32_t *>(smem + hacc_off + ((ta[u] - acc_off) >> 1)), c);
                     }
             }
+        };
+        if (last_set) {
+            while (chunk_rr == r) chunk(std::true_type{});
+        } else {
+            while (chunk_rr == r) chunk(std::false_type{});
         }
         cur = nxt;
         __syncthreads();   // every wave is done with the table slice
@@ -318,6 +355,7 @@ int32_t launch_forward(const ara_yet *yet, int n_sr, bool hits, const FwdItem *d
     if (n_items <= 0) return ARA_OK;
     FwdParams P{};
     P.code = yet->code;
+    P.pad = yet->code + yet->n_codes;
     P.seg_base = yet->seg_base;
     P.seg_run = yet->seg_run;
     P.lane_start = yet->lane_start;
@@ -333,23 +371,8 @@ int32_t launch_forward(const ara_yet *yet, int n_sr, bool hits, const FwdItem *d
     P.buf_bytes = static_cast<int32_t>(per_buf);
     P.items = d_items;
     ProfScope prof(ARA_PROF_FWD, st);
-    if (hits) {
-        static bool attr = false;
-        if (!attr) {
-            ARA_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_fwd<true>),
-                                        hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes));
-            attr = true;
-        }
-        k_fwd<true><<<n_items, 1024, kLdsBytes, st>>>(P);
-    } else {
-        static bool attr = false;
-        if (!attr) {
-            ARA_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_fwd<false>),
-                                        hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes));
-            attr = true;
-        }
-        k_fwd<false><<<n_items, 1024, kLdsBytes, st>>>(P);
-    }
+    if (hits) k_fwd<true><<<n_items, 1024, 0, st>>>(P);
+    else k_fwd<false><<<n_items, 1024, 0, st>>>(P);
     ARA_HIP(hipGetLastError());
     return ARA_OK;
 }

@@ -59,7 +59,7 @@ static int64_t max_codes(const Geometry &g, int64_t nnz) {
 
 static size_t prepare_bytes(const Geometry &g, int64_t nnz, int32_t catalog, uint32_t flags) {
     Carver c(nullptr);
-    c.take<uint16_t>(static_cast<size_t>(max_codes(g, nnz)));
+    c.take<uint16_t>(static_cast<size_t>(max_codes(g, nnz)) + kPadCodes);
     c.take<int64_t>(g.nseg);
     c.take<int32_t>(g.nseg);
     c.take<uint8_t>(g.nseg * kWave);
@@ -365,7 +365,7 @@ extern "C" int32_t ara_yet_prepare(const int64_t *offsets, const int32_t *ids, i
     if (buf_bytes < prepare_bytes(g, nnz, catalog, flags)) return fail(ARA_E_NOSPACE, "ara_yet_prepare: buffer too small");
 
     Carver c(buf);
-    uint16_t *code = c.take<uint16_t>(static_cast<size_t>(max_codes(g, nnz)));
+    uint16_t *code = c.take<uint16_t>(static_cast<size_t>(max_codes(g, nnz)) + kPadCodes);
     int64_t *seg_base = c.take<int64_t>(g.nseg);
     int32_t *seg_run = c.take<int32_t>(g.nseg);
     uint8_t *lane_start = c.take<uint8_t>(g.nseg * kWave);
@@ -435,7 +435,8 @@ extern "C" int32_t ara_yet_prepare(const int64_t *offsets, const int32_t *ids, i
     if (total > max_codes(g, nnz)) return fail(ARA_E_LIMIT, "ara_yet_prepare: code bound exceeded");
     ARA_HIP(hipMemcpyAsync(seg_base, base.data(), g.nseg * sizeof(int64_t), hipMemcpyHostToDevice, st));
     ARA_HIP(hipMemcpyAsync(seg_run, run.data(), g.nseg * sizeof(int32_t), hipMemcpyHostToDevice, st));
-    if (total > 0) ARA_HIP(hipMemsetAsync(code, 0xFF, static_cast<size_t>(total) * sizeof(uint16_t), st));   // padding
+    // padding, and the block of skip codes after the last code
+    ARA_HIP(hipMemsetAsync(code, 0xFF, static_cast<size_t>(total + kPadCodes) * sizeof(uint16_t), st));
     ARA_HIP(hipMemsetAsync(lane_start, 0, g.nseg * kWave, st));
     // pass 2: the codes themselves
     k_prep_codes<true><<<g.n_blocks, 1024, 0, st>>>(offsets, ids, n_trials, catalog, g.tg, g.tb, g.n_ranges,
