@@ -5,16 +5,19 @@
 // of a trial's increments is its year loss; their maximum is the occurrence
 // loss behind occurrence-exceedance metrics.
 //
-// One wavefront per trial, 256 consecutive occurrences per step: the event
+// One wavefront per trial, 512 consecutive occurrences per step: the event
 // IDs stream from the caller's trial-major YET (storage order is needed
-// here, so the bucketed layout cannot serve).  A lookup per occurrence in
-// the cache would be bound by its request rate, so each workgroup first
-// loads a 1-Mbit filter of the layer's set events into LDS (the set-event
-// bitmap folded onto 2^20 bits by OR); only occurrences whose filter bit is
-// set (the set events plus a few that share a bit) read the bitmap word
-// with its rank and then the value from the cache-resident occurrence table.
-// The running total is a wavefront inclusive scan (DPP, no LDS traffic) with
-// the previous step's total carried in.
+// here, so the bucketed layout cannot serve).  Each workgroup first loads a
+// 1-Mbit filter of the layer's set events into LDS (the set-event bitmap
+// folded onto 2^20 bits by OR); only occurrences whose filter bit is set
+// (the set events plus a few that share a bit) read the bitmap word with its
+// rank, and only set events read their value, from the cache-resident
+// occurrence table.  The address unit serves the active lanes of a gather
+// one at a time, so these reads stay masked to the lanes that need them.
+// The running total is formed on a transposed copy of four 64-occurrence
+// slices (staged in LDS, each lane then holding four consecutive
+// occurrences): a prefix inside the lane, one wavefront scan (DPP) across
+// lanes, the previous slices' total carried in.
 #include "occ.h"
 
 #include <algorithm>
@@ -23,8 +26,9 @@
 namespace ara {
 
 constexpr int kYeltThreads = 1024;
-constexpr int kYeltSteps = 8;
-constexpr int kFilterWords = 1 << 15;   // 2^20 bits = 128 KB of LDS
+constexpr int kYeltSteps = 8;           // 64-occurrence slices per step
+constexpr int kYeltGroup = 4;           // slices per transposed scan
+constexpr int kFilterWords = 1 << 15;   // 2^20 bits = 128 KB of LDS (+ 32 KB of staging)
 
 // Cross-lane moves of a binary64 value by DPP (no LDS traffic): CTRL is the
 // DPP control, lanes whose source is outside the pattern (or whose row is
@@ -91,105 +95,189 @@ __global__ __launch_bounds__(256) void k_yelt_filter(const OccTables *__restrict
     filter[static_cast<size_t>(j) * kFilterWords + w] = f;
 }
 
+// Global-memory views of the occurrence table: pointers loaded from memory
+// are generic, and generic loads are waited for together with LDS traffic.
+template <typename T>
+using gmem = const __attribute__((address_space(1))) T *;
+
 __global__ __launch_bounds__(kYeltThreads) void k_yelt(YeltParams P) {
     __shared__ uint32_t filt[kFilterWords];
+    __shared__ double stage[kYeltThreads / kWave][kYeltGroup * kWave];   // one wavefront's transposed slices
     const int j = blockIdx.y, lane = threadIdx.x & 63;
     for (int i = threadIdx.x; i < kFilterWords; i += blockDim.x)
         filt[i] = P.filter[static_cast<size_t>(j) * kFilterWords + i];
     __syncthreads();
-    const int64_t gw = static_cast<int64_t>(blockIdx.x) * (kYeltThreads / kWave) + (threadIdx.x >> 6);
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    double *st = stage[wv];
+    const int64_t gw = static_cast<int64_t>(blockIdx.x) * (kYeltThreads / kWave) + wv;
     const int64_t nw = static_cast<int64_t>(gridDim.x) * (kYeltThreads / kWave);
     const OccTables T = P.tabs[j];
+    const gmem<unsigned long long> gbr = (gmem<unsigned long long>)T.br;   // (bits, rank) words, one per 32 events
+    const gmem<double> gvals = (gmem<double>)T.vals;
+    const gmem<int32_t> gids = (gmem<int32_t>)P.ids;
+    const gmem<int32_t> gdummy = (gmem<int32_t>)(P.filter + static_cast<size_t>(j) * kFilterWords);
+    const gmem<int64_t> goff = (gmem<int64_t>)P.off;
     const double aggR = P.lterms[4 * j + 2], aggL = P.lterms[4 * j + 3];
     double *Y = P.yelt + static_cast<size_t>(j) * P.occ_count;
     double *M = P.occ_max + static_cast<size_t>(j) * (P.t1 - P.t0);
     constexpr int kStep = kWave * kYeltSteps;
 
-    // cursor: trial t, its occurrence range [a, b) (empty if invalid), step start
-    int64_t t = P.t0 + gw, a = 0, b = 0, base = 0;
-    auto open_trial = [&]() {
-        a = P.off[t];
-        b = P.off[t + 1];
+    // occurrences [lo, hi) of a trial, empty (and flagged) if they fall
+    // outside the caller's occurrence range
+    auto checked = [&](int64_t lo, int64_t hi, int64_t &a, int64_t &b) {
+        a = lo;
+        b = hi;
         if (a < P.occ_begin || b > P.occ_begin + P.occ_count || b < a) {
             if (lane == 0) atomicCAS(P.err, 0, ARA_E_RANGE);
             b = a;   // nothing of this trial is read or written
         }
-        base = a;
     };
+    // cursor (uniform over the wavefront): trial t, its occurrences [a, b),
+    // step start base; na, nb: the offsets of trial t + nw (when it exists),
+    // loaded a trial ahead
+    int64_t t = P.t0 + gw;
+    if (t >= P.t1) return;
+    int64_t a, b;
+    checked(goff[t], goff[t + 1], a, b);
+    int64_t base = a, na = 0, nb = 0;
+    if (t + nw < P.t1) {
+        na = goff[t + nw];
+        nb = goff[t + nw + 1];
+    }
+    // IDs [from, from + kStep) capped at end, lanes past it re-reading the
+    // last one; a wavefront with none reads its filter words instead.  The
+    // loads carry no branch.
     int32_t en[kYeltSteps];
-    auto fetch = [&]() {   // IDs of the step at (t, base)
+    auto fetch = [&](int64_t from, int64_t end) {
+        const int64_t n = min<int64_t>(end - from, kStep);
+        const gmem<int32_t> src = n > 0 ? gids + from : gdummy;
+        const int last = n > 0 ? static_cast<int>(n) - 1 : 0;
+#pragma unroll
+        for (int k = 0; k < kYeltSteps; ++k) en[k] = __builtin_nontemporal_load(src + min(k * kWave + lane, last));
+    };
+    // Waiting for the IDs where they are consumed: at the top of the loop
+    // they are then complete on every path, and the previous step's stores
+    // (issued after them) are not waited for there.
+    auto consume_ids = [&]() {
+#pragma unroll
+        for (int k = 0; k < kYeltSteps; ++k) asm volatile("" ::"v"(en[k]));
+    };
+    fetch(base, b);
+    consume_ids();
+    double carry = 0.0, mx = 0.0;
+    bool first = true;   // the next slice group opens its trial
+    while (true) {
+        const int64_t ct = t, cbase = base;
+        const int crem = static_cast<int>(min<int64_t>(b - base, kStep));   // occurrences in this step
+        int32_t e[kYeltSteps];
+        bool in[kYeltSteps];
+        bool bad = false;
 #pragma unroll
         for (int k = 0; k < kYeltSteps; ++k) {
-            const int64_t i = base + k * kWave + lane;
-            en[k] = (i < b) ? __builtin_nontemporal_load(P.ids + i) : 0;
+            in[k] = k * kWave + lane < crem;
+            const bool ok = static_cast<uint32_t>(en[k]) < static_cast<uint32_t>(P.catalog);
+            bad = bad || (in[k] && !ok);
+            in[k] = in[k] && ok;
+            e[k] = in[k] ? en[k] : 0;
         }
-    };
-    if (t >= P.t1) return;
-    open_trial();
-    fetch();
-    double carry = 0.0, cprev = 0.0, mx = 0.0;
-    while (true) {
-        const int64_t ct = t, cbase = base, cb = b;
-        int32_t e[kYeltSteps];
+        if (__ballot(bad) != 0 && lane == 0) atomicCAS(P.err, 0, ARA_E_RANGE);
+        // filter; the bitmap word (with its rank) of each maybe-set event,
+        // word e/32 of the table
+        bool maybe[kYeltSteps];
 #pragma unroll
-        for (int k = 0; k < kYeltSteps; ++k) e[k] = en[k];
-        // advance the cursor and prefetch the next step's IDs
+        for (int k = 0; k < kYeltSteps; ++k) {
+            const uint32_t f = filt[(static_cast<uint32_t>(e[k]) >> 5) & (kFilterWords - 1)];
+            maybe[k] = in[k] & (__builtin_amdgcn_ubfe(f, static_cast<uint32_t>(e[k]), 1) != 0u);
+        }
+        unsigned long long wq[kYeltSteps];
+#pragma unroll
+        for (int k = 0; k < kYeltSteps; ++k) {
+            wq[k] = 0ull;
+            if (maybe[k]) wq[k] = gbr[static_cast<uint32_t>(e[k]) >> 5];
+        }
+        // the value of each set event: super-range base plus rank
+        bool hit[kYeltSteps];
+        double ov[kYeltSteps];
+#pragma unroll
+        for (int k = 0; k < kYeltSteps; ++k) {
+            const uint32_t ue = static_cast<uint32_t>(e[k]);
+            const uint32_t wx = static_cast<uint32_t>(wq[k]), wr = static_cast<uint32_t>(wq[k] >> 32);
+            hit[k] = maybe[k] & (__builtin_amdgcn_ubfe(wx, ue, 1) != 0u);
+            ov[k] = 0.0;
+            if (hit[k]) ov[k] = gvals[(ue & ~static_cast<uint32_t>(kSr - 1)) + wr + __popc(__builtin_amdgcn_ubfe(wx, 0, ue))];
+        }
+        // the next step (the rest of this trial, or the next trial, whose
+        // offsets are at hand): its IDs are fetched now, to arrive with the
+        // values
         base += kStep;
         const bool last_step = base >= b;
         bool more = true;
         if (last_step) {
             t += nw;
             more = t < P.t1;
-            if (more) open_trial();
+            if (more) {
+                checked(na, nb, a, b);
+                base = a;
+            }
         }
-        if (more) fetch();
+        fetch(more ? base : 0, more ? b : 0);
+        if (last_step && more && t + nw < P.t1) {
+            na = goff[t + nw];
+            nb = goff[t + nw + 1];
+        }
 
-        bool in[kYeltSteps];
+        // step four on each group of kYeltGroup slices (256 occurrences):
+        // lane l takes occurrences 4l .. 4l+3 of the group
 #pragma unroll
-        for (int k = 0; k < kYeltSteps; ++k) {
-            in[k] = cbase + k * kWave + lane < cb;
-            if (in[k] && (e[k] < 0 || e[k] >= P.catalog)) {
-                atomicCAS(P.err, 0, ARA_E_RANGE);
-                in[k] = false;
+        for (int g = 0; g < kYeltSteps / kYeltGroup; ++g) {
+#pragma unroll
+            for (int kk = 0; kk < kYeltGroup; ++kk) st[kk * kWave + lane] = hit[g * kYeltGroup + kk] ? ov[g * kYeltGroup + kk] : 0.0;
+            if (g == 0) consume_ids();
+            __builtin_amdgcn_wave_barrier();
+            double p[kYeltGroup];
+#pragma unroll
+            for (int i = 0; i < kYeltGroup; ++i) p[i] = st[kYeltGroup * lane + i];
+#pragma unroll
+            for (int i = 1; i < kYeltGroup; ++i) p[i] = p[i - 1] + p[i];   // running total inside the lane
+            const double incl = wave_inclusive_sum(p[kYeltGroup - 1]);
+            const double excl = dpp_f64<0x138, 0xf>(incl);   // wave_shr:1, lane 0 reads 0
+            const double bl = carry + excl;                   // total before the lane's first occurrence
+            // the aggregate terms on each running total, then the increments;
+            // the trial's first occurrence starts from 0, as the
+            // differencing pass defines it
+            double cprev = (first && lane == 0) ? 0.0 : xl(bl, aggR, aggL);
+            double inc[kYeltGroup];
+#pragma unroll
+            for (int i = 0; i < kYeltGroup; ++i) {
+                const double c = xl(bl + p[i], aggR, aggL);
+                inc[i] = c - cprev;
+                cprev = c;
+                mx = fmax(mx, inc[i]);   // occurrences past the end add nothing: their increment is exactly 0
             }
-            if (!in[k]) e[k] = 0;
-        }
-        uint2 q[kYeltSteps];
+            carry = lane63(bl + p[kYeltGroup - 1]);
+            first = false;
+            __builtin_amdgcn_wave_barrier();
 #pragma unroll
-        for (int k = 0; k < kYeltSteps; ++k) {
-            const bool maybe = in[k] && ((filt[(e[k] >> 5) & (kFilterWords - 1)] >> (e[k] & 31)) & 1u);
-            q[k] = maybe ? T.br[static_cast<size_t>(e[k] >> kSrBits) * kSrWords + ((e[k] & (kSr - 1)) >> 5)]
-                         : make_uint2(0u, 0u);
-        }
-        double o[kYeltSteps];
+            for (int i = 0; i < kYeltGroup; ++i) st[kYeltGroup * lane + i] = inc[i];
+            __builtin_amdgcn_wave_barrier();
+            double v[kYeltGroup];
 #pragma unroll
-        for (int k = 0; k < kYeltSteps; ++k) {
-            const uint32_t bit = e[k] & 31;
-            const bool hit = in[k] && ((q[k].x >> bit) & 1u);
-            const uint32_t rank = q[k].y + __popc(q[k].x & ((1u << bit) - 1u));
-            o[k] = hit ? T.vals[static_cast<size_t>(e[k] >> kSrBits) * kSr + rank] : 0.0;
-        }
+            for (int kk = 0; kk < kYeltGroup; ++kk) v[kk] = st[kk * kWave + lane];
+            static_assert(kYeltGroup == 4, "the read fence below names four values");
+            asm volatile("" : "+v"(v[0]), "+v"(v[1]), "+v"(v[2]), "+v"(v[3]));   // all reads before the (masked) stores
 #pragma unroll
-        for (int k = 0; k < kYeltSteps; ++k) {
-            const double x = wave_inclusive_sum(o[k]);
-            const double run = carry + x;                 // running total after this occurrence
-            const double c = xl(run, aggR, aggL);
-            double cl = dpp_f64<0x138, 0xf>(c);           // wave_shr:1, the previous lane's value
-            if (lane == 0) cl = cprev;
-            const double inc = c - cl;
-            if (in[k]) {
-                __builtin_nontemporal_store(inc, Y + (cbase + k * kWave + lane - P.occ_begin));
-                mx = fmax(mx, inc);
+            for (int kk = 0; kk < kYeltGroup; ++kk) {
+                const int k = g * kYeltGroup + kk;
+                if (in[k]) __builtin_nontemporal_store(v[kk], Y + (cbase + k * kWave + lane - P.occ_begin));
             }
-            carry = lane63(run);   // lanes past the end add 0
-            cprev = lane63(c);
+            __builtin_amdgcn_wave_barrier();
         }
         if (last_step) {
             for (int sh = 32; sh > 0; sh >>= 1) mx = fmax(mx, __shfl_xor(mx, sh));
             if (lane == 0) M[ct - P.t0] = mx;
             carry = 0.0;
-            cprev = 0.0;
             mx = 0.0;
+            first = true;
         }
         if (!more) break;
     }
