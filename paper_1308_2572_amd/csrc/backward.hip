@@ -30,6 +30,7 @@
 // the per-event derivatives, reduced in a fixed order; (7) a fixed-order sum
 // of the chunk partials into the outputs.
 #include "occ.h"
+#include "wave.h"
 
 #include <algorithm>
 #include <cmath>
@@ -60,57 +61,68 @@ __device__ __forceinline__ bool agg_capped(double S, double aggR, double aggL) {
     return a >= aggL;
 }
 
-__device__ double bsum(double v, double *red) {
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o);
-    if (lane == 0) red[w] = v;
-    __syncthreads();
-    double t = 0.0;
-    if (tid == 0)
-        for (int i = 0; i < static_cast<int>(blockDim.x >> 6); ++i) t += red[i];
-    __syncthreads();
-    return t;
-}
-
 __device__ __forceinline__ void chunk_range(int64_t n, int nwg, int wg, int64_t &lo, int64_t &hi) {
     const int64_t c = (n + nwg - 1) / nwg;
     lo = std::min<int64_t>(n, static_cast<int64_t>(wg) * c);
     hi = std::min<int64_t>(n, lo + c);
 }
 
-// (2) largest |c_t a_t| per (layer, row); aggregate-term partial sums.
+// (2) largest |c_t a_t| per (layer, row); aggregate-term partial sums.  One
+// pass over the trials of the workgroup's chunk reads S once for every row;
+// the sums meet in fixed order (each thread's trials, DPP across the
+// wavefront, the wavefronts in index order).
 __global__ __launch_bounds__(kBwdThreads) void k_bwd_vmax(const double *__restrict__ cot, const double *__restrict__ s_pre,
                                                          const double *__restrict__ layer_terms, int64_t n, int n_layers,
                                                          int n_cot, int nwg, VScale *__restrict__ vs,
                                                          double *__restrict__ aggpart) {
-    __shared__ double red[16];
+    __shared__ double red[kBwdThreads / 64][kMaxCot][3];
     const int wg = blockIdx.x, j = blockIdx.y;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const double aggR = layer_terms[4 * j + 2], aggL = layer_terms[4 * j + 3];
     int64_t lo, hi;
     chunk_range(n, nwg, wg, lo, hi);
     const double *S = s_pre + static_cast<size_t>(j) * n;
-    for (int c = 0; c < n_cot; ++c) {
-        const double *g = cot + (static_cast<size_t>(c) * n_layers + j) * n;
-        double m = 0.0, sr = 0.0, sl = 0.0;
-        for (int64_t t = lo + threadIdx.x; t < hi; t += blockDim.x) {
-            const double w = g[t], st = S[t];
-            const bool lin = agg_linear(st, aggR, aggL);
-            if (lin) {
-                sr += w;
-                m = fmax(m, fabs(w));
+    double m[kMaxCot], sr[kMaxCot], sl[kMaxCot];
+#pragma unroll
+    for (int c = 0; c < kMaxCot; ++c) m[c] = sr[c] = sl[c] = 0.0;
+    for (int64_t t = lo + tid; t < hi; t += blockDim.x) {
+        const double st = S[t];
+        const bool lin = agg_linear(st, aggR, aggL), cap = agg_capped(st, aggR, aggL);
+#pragma unroll
+        for (int c = 0; c < kMaxCot; ++c)
+            if (c < n_cot) {
+                const double g = cot[(static_cast<size_t>(c) * n_layers + j) * n + t];
+                if (lin) {
+                    sr[c] += g;
+                    m[c] = fmax(m[c], fabs(g));
+                }
+                if (cap) sl[c] += g;
             }
-            if (agg_capped(st, aggR, aggL)) sl += w;
+    }
+#pragma unroll
+    for (int c = 0; c < kMaxCot; ++c)
+        if (c < n_cot) {
+            double mc = m[c];
+            for (int o = 32; o > 0; o >>= 1) mc = fmax(mc, __shfl_down(mc, o));
+            const double tr = wave_inclusive_sum(sr[c]), tl = wave_inclusive_sum(sl[c]);
+            if (lane == 0) red[w][c][2] = mc;
+            if (lane == 63) {
+                red[w][c][0] = tr;
+                red[w][c][1] = tl;
+            }
         }
-        for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_down(m, o));
-        if ((threadIdx.x & 63) == 0 && m > 0.0)
-            atomicMax(&vs[j * n_cot + c].maxabs_bits, static_cast<unsigned long long>(__double_as_longlong(m)));
-        const double tr = bsum(sr, red);
-        const double tl = bsum(sl, red);
-        if (threadIdx.x == 0) {
-            double *ap = aggpart + ((static_cast<size_t>(j) * n_cot + c) * nwg + wg) * 2;
-            ap[0] = -tr;
-            ap[1] = tl;
-        }
+    __syncthreads();
+    if (tid < n_cot * 2) {
+        const int c = tid >> 1, h = tid & 1;
+        double t = 0.0;
+        for (int i = 0; i < static_cast<int>(blockDim.x >> 6); ++i) t += red[i][c][h];
+        aggpart[((static_cast<size_t>(j) * n_cot + c) * nwg + wg) * 2 + h] = h ? t : -t;
+    } else if (tid >= 64 && tid < 64 + n_cot) {   // one atomic per (workgroup, row)
+        const int c = tid - 64;
+        double mc = 0.0;
+        for (int i = 0; i < static_cast<int>(blockDim.x >> 6); ++i) mc = fmax(mc, red[i][c][2]);
+        if (mc > 0.0)
+            atomicMax(&vs[j * n_cot + c].maxabs_bits, static_cast<unsigned long long>(__double_as_longlong(mc)));
     }
 }
 
@@ -356,14 +368,16 @@ __global__ __launch_bounds__(kBwdThreads) void k_bwd_grad(BwdGrad P) {
     }
     const size_t cw = static_cast<size_t>(blockIdx.x) * kGradWaves + w;   // (chunk, wave) partial slot
     // occurrence-term partials of this wavefront
+    // (wavefront sums by DPP: lane 63 holds the total, in a fixed order)
 #pragma unroll
     for (int c = 0; c < kMaxCot; ++c)
+        if (c < P.n_cot) {
 #pragma unroll
-        for (int m = 0; m < 2; ++m) {
-            double v = po[c][m];
-            for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o);
-            if (lane == 0 && c < P.n_cot)
-                P.part_occ[((static_cast<size_t>(j) * P.n_chunks * kGradWaves + cw) * P.n_cot + c) * 2 + m] = v;
+            for (int m = 0; m < 2; ++m) {
+                const double v = wave_inclusive_sum(po[c][m]);
+                if (lane == 63)
+                    P.part_occ[((static_cast<size_t>(j) * P.n_chunks * kGradWaves + cw) * P.n_cot + c) * 2 + m] = v;
+            }
         }
     // ELT-term partials, kGradBatch ELTs' losses in flight at a time
     for (int q0 = 0; q0 < J; q0 += kGradBatch) {
@@ -408,11 +422,12 @@ __global__ __launch_bounds__(kBwdThreads) void k_bwd_grad(BwdGrad P) {
             double *dst = P.part_elt + (cw * P.n_elt_slots + (a + qq)) * P.n_cot * 3;
 #pragma unroll
             for (int c = 0; c < kMaxCot; ++c)
+                if (c < P.n_cot) {
 #pragma unroll
-                for (int m = 0; m < 3; ++m) {
-                    double v = pe[c][m];
-                    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o);
-                    if (lane == 0 && c < P.n_cot) dst[c * 3 + m] = v;
+                    for (int m = 0; m < 3; ++m) {
+                        const double v = wave_inclusive_sum(pe[c][m]);
+                        if (lane == 63) dst[c * 3 + m] = v;
+                    }
                 }
         }
     }
@@ -472,8 +487,8 @@ struct BwdLayout {
     size_t bytes;
 };
 
-static int bwd_nwg_v(int64_t n) {
-    return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>((n + 8191) / 8192, 512)));
+static int bwd_nwg_v(int64_t n) {   // about two trials per thread, at most 512 workgroups
+    return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>((n + 2047) / 2048, 512)));
 }
 
 static int bwd_cs(int n_cot) { return n_cot <= 1 ? 1 : (n_cot <= 2 ? 2 : 4); }

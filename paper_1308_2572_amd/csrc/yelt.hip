@@ -19,6 +19,7 @@
 // occurrences): a prefix inside the lane, one wavefront scan (DPP) across
 // lanes, the previous slices' total carried in.
 #include "occ.h"
+#include "wave.h"
 
 #include <algorithm>
 #include <vector>
@@ -29,39 +30,6 @@ constexpr int kYeltThreads = 1024;
 constexpr int kYeltSteps = 8;           // 64-occurrence slices per step
 constexpr int kYeltGroup = 4;           // slices per transposed scan
 constexpr int kFilterWords = 1 << 15;   // 2^20 bits = 128 KB of LDS (+ 32 KB of staging)
-
-// Cross-lane moves of a binary64 value by DPP (no LDS traffic): CTRL is the
-// DPP control, lanes whose source is outside the pattern (or whose row is
-// masked off) read 0.
-template <int CTRL, int ROW_MASK>
-__device__ __forceinline__ double dpp_f64(double x) {
-    const unsigned long long b = static_cast<unsigned long long>(__double_as_longlong(x));
-    const int lo = __builtin_amdgcn_update_dpp(0, static_cast<int>(b), CTRL, ROW_MASK, 0xf, true);
-    const int hi = __builtin_amdgcn_update_dpp(0, static_cast<int>(b >> 32), CTRL, ROW_MASK, 0xf, true);
-    return __longlong_as_double(static_cast<long long>((static_cast<unsigned long long>(static_cast<uint32_t>(hi)) << 32) |
-                                                       static_cast<uint32_t>(lo)));
-}
-
-// Inclusive prefix sum over the 64 lanes: shifts of 1, 2, 4, 8 inside each
-// row of 16 lanes, then row 0's total into row 1 and row 2's into row 3
-// (row_bcast:15), then the first two rows' total into rows 2 and 3
-// (row_bcast:31).
-__device__ __forceinline__ double wave_inclusive_sum(double x) {
-    x += dpp_f64<0x111, 0xf>(x);   // row_shr:1
-    x += dpp_f64<0x112, 0xf>(x);   // row_shr:2
-    x += dpp_f64<0x114, 0xf>(x);   // row_shr:4
-    x += dpp_f64<0x118, 0xf>(x);   // row_shr:8
-    x += dpp_f64<0x142, 0xa>(x);   // row_bcast:15
-    x += dpp_f64<0x143, 0xc>(x);   // row_bcast:31
-    return x;
-}
-
-__device__ __forceinline__ double lane63(double x) {
-    const unsigned long long b = static_cast<unsigned long long>(__double_as_longlong(x));
-    const uint32_t lo = __builtin_amdgcn_readlane(static_cast<uint32_t>(b), 63);
-    const uint32_t hi = __builtin_amdgcn_readlane(static_cast<uint32_t>(b >> 32), 63);
-    return __longlong_as_double(static_cast<long long>((static_cast<unsigned long long>(hi) << 32) | lo));
-}
 
 struct YeltParams {
     const int64_t *off;
