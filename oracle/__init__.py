@@ -52,6 +52,11 @@ def _load():
         lib.oracle_backward.argtypes = [_I32, _I32, _P, _I64, _P, _P, _I32, _P, _P, _P, _P,
                                         _I64, _I64, _I32, _P, _I32, _P, _P]
         lib.oracle_num_threads_available.restype = _I32
+        lib.oracle_philox4x64_10.argtypes = [_P, _P, _P]
+        lib.oracle_su_draw.argtypes = [_F64, _F64, ctypes.c_uint64, _I64, _I32]
+        lib.oracle_su_draw.restype = _F64
+        lib.oracle_forward_su.argtypes = [_I32, _I32, _P, _P, _I64, _P, _P, _I32, _P, _P, _P, _P,
+                                          ctypes.c_uint64, _I64, _I64, _I32, _P, _P]
         _lib = lib
     return _lib
 
@@ -163,6 +168,54 @@ def backward(tables: np.ndarray, yet, layers, elt_terms, layer_terms, cot: np.nd
     if rc != 0:
         raise OracleError(f"oracle_backward status {rc}")
     return ge, gl
+
+
+def philox4x64_10(ctr, key) -> np.ndarray:
+    """One Philox4x64-10 block (uint64 [4]) of counter ctr[4] under key[2]."""
+    c = _c(ctr, np.uint64)
+    k = _c(key, np.uint64)
+    out = np.empty(4, np.uint64)
+    _load().oracle_philox4x64_10(_ptr(c), _ptr(k), _ptr(out))
+    return out
+
+
+def su_draw(mu: float, sigma: float, seed: int, occ: int, elt: int) -> float:
+    """The loss drawn for occurrence `occ` in ELT `elt` (reading R10/R11)."""
+    return float(_load().oracle_su_draw(float(mu), float(sigma), int(seed), int(occ), int(elt)))
+
+
+def build_sigma_tables(elts, rec_sigma) -> np.ndarray:
+    """Dense binary32 standard deviations [n_elts, catalog], laid out like
+    the loss tables (0 where the ELT has no record)."""
+    lib = _load()
+    out = np.empty((elts.n_elts, elts.catalog), dtype=np.float32)
+    ro, ri, rs = _c(elts.rec_off, np.int64), _c(elts.rec_ids, np.int32), _c(rec_sigma, np.float32)
+    rc = lib.oracle_build_tables(elts.n_elts, elts.catalog, _ptr(ro), _ptr(ri), _ptr(rs), _ptr(out))
+    if rc != 0:
+        raise OracleError(f"oracle_build_tables (sigma) status {rc}")
+    return out
+
+
+def forward_su(tables: np.ndarray, sigma_tables: np.ndarray, yet, layers, elt_terms, layer_terms, seed: int,
+               t0: int = 0, t1: Optional[int] = None, n_threads: int = 1):
+    """Algorithm 1 with secondary uncertainty (readings R10/R11).  Returns
+    dict(ylt, s_pre), each [n_layers, t1-t0]."""
+    lib = _load()
+    t1 = yet.n_trials if t1 is None else t1
+    nl = layers.n_layers
+    n = t1 - t0
+    ylt = np.empty((nl, n), np.float64)
+    s_pre = np.empty((nl, n), np.float64)
+    tb, sg = _c(tables, np.float32), _c(sigma_tables, np.float32)
+    off, ids = _c(yet.offsets, np.int64), _c(yet.ids, np.int32)
+    lo, le = _c(layers.elt_off, np.int32), _c(layers.elt_ids, np.int32)
+    et, lt = _c(elt_terms, np.float64), _c(layer_terms, np.float64)
+    rc = lib.oracle_forward_su(tb.shape[0], tb.shape[1], _ptr(tb), _ptr(sg), yet.n_trials, _ptr(off), _ptr(ids),
+                               nl, _ptr(lo), _ptr(le), _ptr(et), _ptr(lt), int(seed), t0, t1, n_threads,
+                               _ptr(ylt), _ptr(s_pre))
+    if rc != 0:
+        raise OracleError(f"oracle_forward_su status {rc}")
+    return {"ylt": ylt, "s_pre": s_pre}
 
 
 def num_threads_available() -> int:

@@ -46,6 +46,24 @@
  *       differencing pass; it sums to the year loss.  The per-year maximum
  *       of these increments is the occurrence loss used for occurrence
  *       exceedance metrics.
+ *   R10 secondary uncertainty (named as future work in Section V, not
+ *       defined there): an ELT record carries a standard deviation sigma
+ *       beside its mean loss mu, and every (occurrence, ELT) pair draws its
+ *       loss from the lognormal distribution with that mean and standard
+ *       deviation; sigma = 0 draws mu itself.  The draw replaces the table
+ *       lookup of step one; steps two to four are unchanged.
+ *   R11 the draw of occurrence i (its index in the YET) in ELT k: the
+ *       Philox4x64-10 block (Salmon, Moraes, Dror and Shaw, SC'11) of
+ *       counter (i, k, 0, 0) under key (seed, 0); its first two words give
+ *       u_j = ((w_j >> 12) + 1/2) 2^-52, z = sqrt(-2 ln u_1) cos(2 pi u_2)
+ *       (Box-Muller), x = exp(m + s z) with s^2 = ln(1 + sigma^2/mu^2) and
+ *       m = ln mu - s^2/2.  The same occurrence and ELT draw the same loss in
+ *       every layer.
+ *
+ * Secondary-uncertainty pins: the generator against numpy's Philox
+ * (a library implementation of the same published generator), sigma = 0
+ * against the deterministic path bit for bit, and the moments of the draws
+ * (mean mu, standard deviation sigma, log-mean m, log-variance s^2).
  */
 #include <math.h>
 #include <stdint.h>
@@ -465,3 +483,150 @@ int oracle_num_threads_available(void)
     return 1;
 #endif
 }
+
+/* ------------------------------------------------------------------------ */
+/* Secondary uncertainty (readings R10, R11).                                */
+/* ------------------------------------------------------------------------ */
+
+/* Philox4x64-10: ten rounds of two 64x64->128-bit multiplies (constants
+ * 0xD2E7470EE14C6C93 and 0xCA5A826395121157) with the key bumped by the
+ * Weyl constants 0x9E3779B97F4A7C15 and 0xBB67AE8584CAA73B between rounds. */
+static void philox4x64_10(const uint64_t ctr_in[4], const uint64_t key_in[2], uint64_t out[4])
+{
+    uint64_t c[4] = {ctr_in[0], ctr_in[1], ctr_in[2], ctr_in[3]};
+    uint64_t k0 = key_in[0], k1 = key_in[1];
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) {
+            k0 += 0x9E3779B97F4A7C15ull;
+            k1 += 0xBB67AE8584CAA73Bull;
+        }
+        const unsigned __int128 p0 = (unsigned __int128)0xD2E7470EE14C6C93ull * c[0];
+        const unsigned __int128 p1 = (unsigned __int128)0xCA5A826395121157ull * c[2];
+        const uint64_t hi0 = (uint64_t)(p0 >> 64), lo0 = (uint64_t)p0;
+        const uint64_t hi1 = (uint64_t)(p1 >> 64), lo1 = (uint64_t)p1;
+        const uint64_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+        c[0] = n0;
+        c[1] = lo1;
+        c[2] = n2;
+        c[3] = lo0;
+    }
+    out[0] = c[0];
+    out[1] = c[1];
+    out[2] = c[2];
+    out[3] = c[3];
+}
+
+int oracle_philox4x64_10(const uint64_t *ctr, const uint64_t *key, uint64_t *out)
+{
+    philox4x64_10(ctr, key, out);
+    return OR_OK;
+}
+
+/* One draw of reading R11. */
+double oracle_su_draw(double mu, double sigma, uint64_t seed, int64_t occ, int32_t elt)
+{
+    if (sigma == 0.0) return mu;
+    const uint64_t ctr[4] = {(uint64_t)occ, (uint64_t)(uint32_t)elt, 0, 0};
+    const uint64_t key[2] = {seed, 0};
+    uint64_t w[4];
+    philox4x64_10(ctr, key, w);
+    const double u1 = ((double)(w[0] >> 12) + 0.5) * 0x1p-52;
+    const double u2 = ((double)(w[1] >> 12) + 0.5) * 0x1p-52;
+    const double two_pi = 6.283185307179586476925286766559; /* the binary64 nearest 2 pi */
+    const double z = sqrt(-2.0 * log(u1)) * cos(two_pi * u2);
+    const double r = sigma / mu;
+    const double s2 = log1p(r * r);
+    const double m = log(mu) - 0.5 * s2;
+    return exp(m + sqrt(s2) * z);
+}
+
+/*
+ * Algorithm 1 with secondary uncertainty: as oracle_forward (steps two to
+ * four literally), the lookup of step one replaced by the draw of R10/R11.
+ * sigma_tables: dense binary64-widened-from-binary32 standard deviations
+ * laid out like `tables`.  Outputs ylt and s_pre [n_layers][t1-t0] (either
+ * may be NULL).
+ */
+int oracle_forward_su(int32_t n_elts, int32_t catalog, const float *tables, const float *sigma_tables,
+                      int64_t n_trials, const int64_t *offsets, const int32_t *ids,
+                      int32_t n_layers, const int32_t *layer_off, const int32_t *layer_elts,
+                      const double *elt_terms, const double *layer_terms, uint64_t seed,
+                      int64_t t0, int64_t t1, int32_t n_threads, double *ylt, double *s_pre)
+{
+    if (t0 < 0 || t1 < t0 || t1 > n_trials) return OR_E_INVAL;
+    const int64_t nt = t1 - t0;
+    int64_t max_len = 0;
+    for (int64_t t = t0; t < t1; ++t) {
+        const int64_t len = offsets[t + 1] - offsets[t];
+        if (len < 0) return OR_E_RANGE;
+        if (len > max_len) max_len = len;
+    }
+    for (int64_t t = t0; t < t1; ++t)
+        for (int64_t i = offsets[t]; i < offsets[t + 1]; ++i)
+            if (ids[i] < 0 || ids[i] >= catalog) return OR_E_RANGE;
+    for (int32_t a = 0; a < n_layers; ++a)
+        for (int32_t c = layer_off[a]; c < layer_off[a + 1]; ++c)
+            if (layer_elts[c] < 0 || layer_elts[c] >= n_elts) return OR_E_RANGE;
+    int rc = OR_OK;
+#ifdef _OPENMP
+    if (n_threads < 1) n_threads = 1;
+#pragma omp parallel num_threads(n_threads)
+#endif
+    {
+        double *net = (double *)malloc(sizeof(double) * (size_t)(max_len + 1));
+        double *occ = (double *)malloc(sizeof(double) * (size_t)(max_len + 1));
+        if (!net || !occ) {
+#ifdef _OPENMP
+#pragma omp atomic write
+#endif
+            rc = OR_E_NOMEM;
+        } else {
+            for (int32_t a = 0; a < n_layers; ++a) {
+                const double OccR = layer_terms[4 * a + 0], OccL = layer_terms[4 * a + 1];
+                const double AggR = layer_terms[4 * a + 2], AggL = layer_terms[4 * a + 3];
+#ifdef _OPENMP
+#pragma omp for schedule(static)
+#endif
+                for (int64_t b = t0; b < t1; ++b) {
+                    const int32_t *ev = ids + offsets[b];
+                    const int64_t n = offsets[b + 1] - offsets[b];
+                    for (int64_t d = 0; d < n; ++d) occ[d] = 0.0;
+                    for (int32_t c = layer_off[a]; c < layer_off[a + 1]; ++c) {
+                        const int32_t k = layer_elts[c];
+                        const float *tab = tables + (size_t)k * (size_t)catalog;
+                        const float *sig = sigma_tables + (size_t)k * (size_t)catalog;
+                        const double s = elt_terms[3 * k + 0];
+                        const double R = elt_terms[3 * k + 1];
+                        const double L = elt_terms[3 * k + 2];
+                        /* step one, with secondary uncertainty: a draw per
+                         * occurrence of an event the ELT holds (R10) */
+                        for (int64_t d = 0; d < n; ++d) {
+                            const double mu = (double)tab[ev[d]];
+                            const double x = (mu != 0.0)
+                                ? oracle_su_draw(mu, (double)sig[ev[d]], seed, offsets[b] + d, k) : 0.0;
+                            /* step two */
+                            net[d] = clamp_xl(s * x, R, L);
+                        }
+                        for (int64_t d = 0; d < n; ++d) occ[d] = occ[d] + net[d];
+                    }
+                    /* step three */
+                    for (int64_t d = 0; d < n; ++d) occ[d] = clamp_xl(occ[d], OccR, OccL);
+                    /* step four: running totals, aggregate terms, increments, sum */
+                    for (int64_t d = 1; d < n; ++d) occ[d] = occ[d] + occ[d - 1];
+                    const double S = (n > 0) ? occ[n - 1] : 0.0;
+                    for (int64_t d = 0; d < n; ++d) occ[d] = clamp_xl(occ[d], AggR, AggL);
+                    for (int64_t d = n - 1; d >= 1; --d) occ[d] = occ[d] - occ[d - 1];
+                    double lr = 0.0;
+                    for (int64_t d = 0; d < n; ++d) lr = lr + occ[d];
+                    const size_t o = (size_t)a * (size_t)nt + (size_t)(b - t0);
+                    if (ylt) ylt[o] = lr;
+                    if (s_pre) s_pre[o] = S;
+                }
+            }
+        }
+        free(net);
+        free(occ);
+    }
+    return rc;
+}
+

@@ -26,7 +26,7 @@ import numpy as np
 SEED_BASE = 1308257200
 
 # stream ids (the second Philox key word) for the independent draws
-_S_LEN, _S_IDS, _S_TS, _S_ELT, _S_TERMS, _S_REQ = 1, 2, 3, 4, 5, 6
+_S_LEN, _S_IDS, _S_TS, _S_ELT, _S_TERMS, _S_REQ, _S_SIGMA = 1, 2, 3, 4, 5, 6, 7
 
 
 def _rng(seed: int, stream: int, sub: int = 0) -> np.random.Generator:
@@ -177,6 +177,21 @@ def lognormal_elts(seed: int, sizes: Sequence[int], catalog: int, mu: float = 12
         rec_loss[rec_off[k]:rec_off[k + 1]] = g.lognormal(mu, sigma, size=int(sz)).astype(np.float32)
     terms = np.tile(np.array([scale, retention, limit], dtype=np.float64), (n, 1))
     return Elts(catalog, rec_off, rec_ids, rec_loss, terms)
+
+
+def record_sigmas(seed: int, elts: Elts, cv_lo: float = 0.25, cv_hi: float = 1.5,
+                  zero_frac: float = 0.1) -> np.ndarray:
+    """Standard deviations of the ELT records for secondary uncertainty:
+    sigma = cv * loss with cv ~ U[cv_lo, cv_hi] per record, and a fraction
+    zero_frac of the records with sigma = 0 (no uncertainty), binary32."""
+    out = np.empty(elts.rec_loss.shape[0], dtype=np.float32)
+    for k in range(elts.n_elts):
+        a, b = int(elts.rec_off[k]), int(elts.rec_off[k + 1])
+        g = _rng(seed, _S_SIGMA, k)
+        cv = g.uniform(cv_lo, cv_hi, size=b - a)
+        cv[g.random(b - a) < zero_frac] = 0.0
+        out[a:b] = (cv * elts.rec_loss[a:b].astype(np.float64)).astype(np.float32)
+    return out
 
 
 def log_uniform(g: np.random.Generator, lo: float, hi: float, size=None):

@@ -109,8 +109,66 @@ def _battery():
     return True
 
 
+SU_MUTATIONS = {
+    "su-philox-multiplier": ("(unsigned __int128)0xD2E7470EE14C6C93ull * c[0]",
+                             "(unsigned __int128)0xD2E7470EE14C6C95ull * c[0]"),
+    "su-philox-key-bump": ("k1 += 0xBB67AE8584CAA73Bull;", "k1 += 0xBB67AE8584CAA73Aull;"),
+    "su-philox-word-order": ("c[1] = lo1;\n        c[2] = n2;", "c[1] = n2;\n        c[2] = lo1;"),
+    "su-no-half-variance": ("const double m = log(mu) - 0.5 * s2;", "const double m = log(mu);"),
+    "su-sigma-not-relative": ("const double r = sigma / mu;", "const double r = sigma;"),
+    "su-draw-ignores-elt": ("(uint64_t)(uint32_t)elt, 0, 0};", "0, 0, 0};"),
+    "su-sigma-zero-not-special": ("if (sigma == 0.0) return mu;", "if (sigma < 0.0) return mu;"),
+    "su-lookup-not-drawn": ("? oracle_su_draw(mu, (double)sig[ev[d]], seed, offsets[b] + d, k) : 0.0;",
+                            "? mu : 0.0;"),
+    "su-same-uniform-twice": ("const double u2 = ((double)(w[1] >> 12) + 0.5) * 0x1p-52;",
+                              "const double u2 = ((double)(w[0] >> 12) + 0.5) * 0x1p-52;"),
+}
+
+
+def _battery_su():
+    """True iff every pin of the secondary-uncertainty path holds (small
+    versions of tests/test_oracle_su.py)."""
+    for key, ctr in [((12345, 0), (8, 0, 0, 0)), ((0x0123456789ABCDEF, 0xFEDCBA9876543210), (6, 3, 0, 0))]:
+        start = np.array([ctr[0] - 1, ctr[1], ctr[2], ctr[3]], dtype=np.uint64)
+        ref = np.random.Philox(key=np.array(key, dtype=np.uint64), counter=start).random_raw(4)
+        if oracle.philox4x64_10(np.array(ctr, np.uint64), np.array(key, np.uint64)).tolist() != [int(v) for v in ref]:
+            return False
+    w = synth.tiny_random(1, n_trials=30, max_events=12, n_layers=2)
+    tb = oracle.build_tables(w.elts)
+    ref = oracle.forward(tb, w.yet, w.layers, w.elts.terms, w.layers.terms)
+    su = oracle.forward_su(tb, np.zeros_like(tb), w.yet, w.layers, w.elts.terms, w.layers.terms, seed=4)
+    if not np.array_equal(su["ylt"], ref["ylt"]):
+        return False
+    n = 20_000
+    for mu, sg in [(100.0, 40.0), (5e5, 5e5)]:
+        x = np.array([oracle.su_draw(mu, sg, 2024, i, 3) for i in range(n)])
+        s2 = np.log1p((sg / mu) ** 2)
+        if not np.all(np.isfinite(x)) or not np.all(x > 0):
+            return False
+        lx = np.log(x)
+        if abs(lx.mean() - (np.log(mu) - s2 / 2)) > 6 * np.sqrt(s2 / n) or abs(lx.var() - s2) > 6 * s2 * np.sqrt(2 / n):
+            return False
+    za = np.log([oracle.su_draw(1.0, 0.5, 7, i, 0) for i in range(n)])
+    zb = np.log([oracle.su_draw(1.0, 0.5, 7, i, 1) for i in range(n)])
+    if abs(np.corrcoef(za, zb)[0, 1]) > 6 / np.sqrt(n):
+        return False
+    # linear terms: the year loss's spread is that of the draws
+    cat, nt = 16, 4000
+    elts = synth.Elts(cat, np.array([0, 2], np.int64), np.array([3, 9], np.int32),
+                      np.array([1000.0, 400.0], np.float32), np.array([[1.0, 0.0, np.inf]]))
+    layers = synth.Layers(np.array([0, 1], np.int32), np.array([0], np.int32), np.array([[0.0, np.inf, 0.0, np.inf]]))
+    yet = synth.Yet(cat, np.arange(nt + 1, dtype=np.int64) * 2, np.tile(np.array([3, 9], np.int32), nt))
+    y = oracle.forward_su(oracle.build_tables(elts), oracle.build_sigma_tables(elts, np.array([300.0, 100.0], np.float32)),
+                          yet, layers, elts.terms, layers.terms, seed=2)["ylt"][0]
+    sd = np.hypot(300.0, 100.0)
+    if abs(y.mean() - 1400.0) > 6 * sd / np.sqrt(nt) or abs(y.std() / sd - 1.0) > 0.15:
+        return False
+    return True
+
+
 def test_real_oracle_passes_battery():
     assert _battery()
+    assert _battery_su()
 
 
 @pytest.fixture(scope="module")
@@ -119,9 +177,9 @@ def workdir():
         yield d
 
 
-@pytest.mark.parametrize("name", sorted(MUTATIONS))
+@pytest.mark.parametrize("name", sorted(MUTATIONS) + sorted(SU_MUTATIONS))
 def test_mutant_is_caught(name, workdir):
-    old, new = MUTATIONS[name]
+    old, new = MUTATIONS[name] if name in MUTATIONS else SU_MUTATIONS[name]
     src = open(oracle.SRC).read()
     assert src.count(old) == 1, f"mutation anchor for {name} not unique"
     path_c = os.path.join(workdir, f"{name}.c")
@@ -131,5 +189,5 @@ def test_mutant_is_caught(name, workdir):
     subprocess.check_call(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared",
                            "-o", path_so, path_c, "-lm"])
     with oracle.use_library(path_so):
-        caught = not _battery()
+        caught = not (_battery() and _battery_su())
     assert caught, f"mutant {name} survived every pin"
