@@ -98,6 +98,7 @@ def main() -> int:
     ap.add_argument("--no-backward", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-yelt", action="store_true")
+    ap.add_argument("--no-su", action="store_true", help="skip the secondary-uncertainty forward")
     ap.add_argument("--serving-requests", type=int, default=200)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy three times (scales the HBM byte counters)")
@@ -207,6 +208,11 @@ def main() -> int:
             result["yelt"] = bench_yelt(ara, tables, layers, et, lt, w, args.steps, args.warmup)
         except ara.AraError as ex:
             result["yelt"] = {"error": str(ex)}
+    if not args.no_su:
+        try:
+            result["secondary_uncertainty"] = bench_su(ara, tables, yet, layers, et, lt, w, args.steps, args.warmup)
+        except ara.AraError as ex:
+            result["secondary_uncertainty"] = {"error": str(ex)}
     if not args.no_serving:
         log("serving: resident 1M x Poisson(1000) YET, 200 ELTs, Poisson arrivals at 50/s")
         from paper_1308_2572_amd import serve
@@ -261,6 +267,49 @@ def bench_yelt(ara, tables, layers, et, lt, w, steps, warmup):
             "algorithmic_bytes": algo, "achieved_gbs": algo / (k * 1e-3) / 1e9,
             "frac_of_hbm_peak": algo / (k * 1e-3) / 1e9 / HBM_PEAK_GBS,
             "oep": {"mean_max_occurrence_loss": float(o[0]), "pml": float(o[1]), "tvar": float(o[2])}}
+
+
+def bench_su(ara, tables, yet, layers, et, lt, w, steps, warmup):
+    """Algorithm 1 with secondary uncertainty on the same workload: every
+    record gets a standard deviation (cv ~ U[0.25, 1.5], 10% exact), and every
+    (occurrence, ELT) pair the layer holds draws a lognormal loss."""
+    import numpy as np
+    import torch
+    import synth
+    log("secondary uncertainty: draws per (occurrence, ELT)")
+    sg = synth.record_sigmas(synth.SEED_BASE + 1, w.elts)
+    sigma = ara.SigmaTables.from_numpy(tables, sg)
+    off = torch.from_numpy(np.ascontiguousarray(w.yet.offsets, np.int64)).cuda()
+    ids = torch.from_numpy(np.ascontiguousarray(w.yet.ids, np.int32)).cuda()
+    N, nnz = w.yet.n_trials, w.yet.nnz
+    J = int(w.layers.elt_off[-1])
+    _, _, hits = ara.ylt_forward(tables, yet, layers, et, lt, 0, N, want_s_pre=False, want_hits=True)
+    draws = int(hits.sum().item())          # (occurrence, ELT) pairs whose ELT holds the event
+    del hits
+    for _ in range(max(1, warmup)):
+        y, _ = ara.ylt_forward_su(tables, sigma, off, ids, layers, et, lt, 7, want_s_pre=False)
+    torch.cuda.synchronize()
+    n_steps = max(1, min(steps, 5))
+    ara.profile_reset()
+    ara.profile_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(n_steps):
+        y, _ = ara.ylt_forward_su(tables, sigma, off, ids, layers, et, lt, 7, want_s_pre=False)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ara.profile_enable(False)
+    k_ms, k_n = ara.profile_read(ara.PROF_SU)
+    k = k_ms / max(k_n, 1)
+    ms = (t1 - t0) * 1e3 / n_steps
+    m, _ = ara.metrics(y, w.p)
+    mm = m.cpu().numpy()[0]
+    algo = 4.0 * nnz + 8.0 * N + 8.0 * N * w.layers.n_layers
+    del off, ids, y, sigma
+    torch.cuda.empty_cache()
+    return {"ms_per_call": ms, "kernel": "k_su_fwd", "kernel_ms": k, "draws": draws,
+            "draws_per_s": draws / (k * 1e-3), "lookups_per_s": nnz * J / (ms * 1e-3),
+            "algorithmic_bytes": algo, "frac_of_hbm_peak": algo / (k * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "metrics": {"aal": float(mm[0]), "pml": float(mm[1]), "tvar": float(mm[2])}}
 
 
 def bench_backward(ara, tables, yet, layers, et, lt, w, steps, warmup, ms_fwd_step):

@@ -288,6 +288,61 @@ int32_t ara_ylt_backward(const ara_tables *tables, const ara_yet *yet, const ara
                          void *ws, size_t ws_bytes, void *stream);
 
 /* ------------------------------------------------------------------------ */
+/* Secondary uncertainty (named as future work in Section V): every          */
+/* (occurrence, ELT) pair draws its loss instead of looking up the mean.     */
+/* ------------------------------------------------------------------------ */
+/*
+ * The model (the paper gives none): an ELT record carries a standard
+ * deviation sigma beside its mean loss mu; occurrence i (its index in the
+ * trial-major YET) of an event the ELT holds draws
+ *   x = mu                      if sigma = 0,
+ *   x = exp(m + s z)            otherwise, s^2 = ln(1 + sigma^2/mu^2),
+ *                               m = ln mu - s^2/2 (lognormal, mean mu, sd sigma),
+ *   z = sqrt(-2 ln u1) cos(2 pi u2),  u_j = ((w_j >> 12) + 1/2) 2^-52,
+ *   (w_0, w_1, ...) = Philox4x64-10 block of counter (i, k, 0, 0) under key
+ *   (seed, 0), k the ELT's index (Salmon, Moraes, Dror, Shaw, SC'11),
+ * and x replaces the table lookup of step one of Algorithm 1; steps two to
+ * four are unchanged.  The same occurrence and ELT draw the same loss in
+ * every layer and every call with the same seed.
+ */
+
+/*
+ * rec_off, rec_ids: the device CSR given to ara_build_elt_tables
+ * rec_sigma:        device binary32 standard deviations, one per record
+ *                   (>= 0 and finite; ARA_E_INVAL otherwise)
+ * sigma:            caller's device binary32 [n_elts][catalog], filled here
+ *                   (0 for events the ELT does not hold)
+ * SYNCHRONISES `stream` to report errors.
+ */
+int32_t ara_build_elt_sigma(const ara_tables *tables, const int64_t *rec_off, const int32_t *rec_ids,
+                            const float *rec_sigma, float *sigma, void *stream);
+
+/* elt_records: HOST int64 [n_elts], the records of each ELT (bounds the
+ * (event, ELT) pairs each layer draws for). */
+int32_t ara_su_workspace_bytes(const ara_tables *tables, const ara_layers *layers, const int64_t *elt_records,
+                               size_t *bytes);
+
+/*
+ * offsets, ids: the trial-major YET on the device, n_trials trials (the
+ *              occurrence index keys the draws, so storage order matters).
+ * occ_begin, occ_count: as for ara_yelt_forward.
+ * ylt, s_pre:  device binary64 [n_layers][trial_end - trial_begin] (s_pre may
+ *              be NULL): Algorithm 1 with the draws above.
+ * ws:          device workspace of at least ara_su_workspace_bytes for the same
+ *              elt_records (ARA_E_NOSPACE otherwise; an ELT holding more
+ *              events than its elt_records is a device-side ARA_E_LIMIT).
+ * Per trial the occurrence losses are summed in wavefront order, so S and
+ * the YLT agree with a sequential sum to rounding; everything else follows
+ * the definition step by step in binary64.
+ */
+int32_t ara_ylt_forward_su(const ara_tables *tables, const float *sigma, const int64_t *offsets,
+                           const int32_t *ids, int64_t n_trials, const ara_layers *layers,
+                           const int64_t *elt_records, const double *elt_terms, const double *layer_terms,
+                           uint64_t seed, int64_t trial_begin, int64_t trial_end, int64_t occ_begin,
+                           int64_t occ_count, double *ylt, double *s_pre, void *ws, size_t ws_bytes,
+                           void *stream);
+
+/* ------------------------------------------------------------------------ */
 /* Quote server: continuous batching of pricing requests over the resident   */
 /* YET and ELT tables (the paper motivates real-time pricing, Sections I, V). */
 /* ------------------------------------------------------------------------ */
@@ -350,6 +405,7 @@ int32_t ara_server_destroy(void *server);
 #define ARA_PROF_BWD      3   /* backward streaming kernel                   */
 #define ARA_PROF_BWD_RED  4   /* backward reductions                         */
 #define ARA_PROF_YELT     5   /* per-occurrence (event-level) kernel         */
+#define ARA_PROF_SU       6   /* secondary-uncertainty streaming kernel      */
 #define ARA_PROF_KINDS    8
 
 /* on != 0 starts recording (process-wide); 0 stops. */

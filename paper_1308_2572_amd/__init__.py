@@ -80,6 +80,10 @@ _SIGNATURES = {
     "ara_yelt_workspace_bytes": (_c_i32, [_P(ara_tables), _P(ara_layers), _P(_c_sz)]),
     "ara_yelt_forward": (_c_i32, [_P(ara_tables), _c_p, _c_p, _c_i64, _P(ara_layers), _c_p, _c_p, _c_i64, _c_i64,
                                   _c_i64, _c_i64, _c_p, _c_p, _c_p, _c_sz, _c_p]),
+    "ara_build_elt_sigma": (_c_i32, [_P(ara_tables), _c_p, _c_p, _c_p, _c_p, _c_p]),
+    "ara_su_workspace_bytes": (_c_i32, [_P(ara_tables), _P(ara_layers), _c_p, _P(_c_sz)]),
+    "ara_ylt_forward_su": (_c_i32, [_P(ara_tables), _c_p, _c_p, _c_p, _c_i64, _P(ara_layers), _c_p, _c_p, _c_p,
+                                    ctypes.c_uint64, _c_i64, _c_i64, _c_i64, _c_i64, _c_p, _c_p, _c_p, _c_sz, _c_p]),
     "ara_metrics_workspace_bytes": (_c_i32, [_c_i32, _c_i64, _P(_c_sz)]),
     "ara_metrics": (_c_i32, [_c_p, _c_i32, _c_i64, _c_f64, _c_p, _c_p, _c_p, _c_sz, _c_p]),
     "ara_metrics_vjp": (_c_i32, [_c_p, _c_i32, _c_i64, _c_p, _c_p, _c_p]),
@@ -193,6 +197,11 @@ class EltTables:
                "ara_build_elt_tables")
         self.n_elts = n_elts
         self.catalog = catalog
+        # the CSR is kept for the standard-deviation tables of secondary uncertainty
+        self.rec_off = rec_off
+        self.rec_ids = rec_ids
+        off_h = rec_off.cpu().numpy().astype(np.int64)
+        self.records = np.ascontiguousarray(off_h[1:] - off_h[:-1], dtype=np.int64)
 
     @classmethod
     def from_numpy(cls, elts, device="cuda"):
@@ -200,6 +209,22 @@ class EltTables:
                    torch.from_numpy(np.ascontiguousarray(elts.rec_ids, np.int32)).to(device),
                    torch.from_numpy(np.ascontiguousarray(elts.rec_loss, np.float32)).to(device),
                    int(elts.catalog))
+
+
+class SigmaTables:
+    """Standard deviations of the ELT records (secondary uncertainty), dense
+    binary32 [n_elts, catalog] on the device, built by ara_build_elt_sigma."""
+
+    def __init__(self, tables: EltTables, rec_sigma: torch.Tensor):
+        lib = library()
+        rec_sigma = rec_sigma.to(device=tables.device, dtype=torch.float32).contiguous()
+        self.sigma = torch.empty((tables.n_elts, tables.catalog), dtype=torch.float32, device=tables.device)
+        _check(lib.ara_build_elt_sigma(ctypes.byref(tables.handle), _dptr(tables.rec_off), _dptr(tables.rec_ids),
+                                       _dptr(rec_sigma), _dptr(self.sigma), _stream()), "ara_build_elt_sigma")
+
+    @classmethod
+    def from_numpy(cls, tables: EltTables, rec_sigma):
+        return cls(tables, torch.from_numpy(np.ascontiguousarray(rec_sigma, np.float32)))
 
 
 class Layers:
@@ -253,6 +278,43 @@ def yelt_forward(tables: EltTables, offsets: torch.Tensor, ids: torch.Tensor, la
     if check:
         _check(lib.ara_check_device_error(_dptr(ws), _stream()), "ara_yelt_forward (device)")
     return yelt, occ_max
+
+
+def ylt_forward_su(tables: EltTables, sigma: SigmaTables, offsets: torch.Tensor, ids: torch.Tensor, layers: Layers,
+                   elt_terms: torch.Tensor, layer_terms: torch.Tensor, seed: int, trial_begin: int = 0,
+                   trial_end: Optional[int] = None, want_s_pre: bool = True, check: bool = False):
+    """Algorithm 1 with secondary uncertainty (a lognormal draw per occurrence
+    and ELT) over the trial-major YET.  Returns (ylt, s_pre or None), each
+    [n_layers, n]."""
+    lib = library()
+    if offsets.dtype != torch.int64 or ids.dtype != torch.int32:
+        raise ValueError("offsets must be int64 and ids int32")
+    n_trials = offsets.numel() - 1
+    trial_end = n_trials if trial_end is None else trial_end
+    if not (0 <= trial_begin <= trial_end <= n_trials):
+        raise AraError(ARA_E_RANGE, "trial range outside the YET")
+    n = trial_end - trial_begin
+    L = layers.n_layers
+    dev = offsets.device
+    occ_begin = int(offsets[trial_begin].item())
+    occ_count = int(offsets[trial_end].item()) - occ_begin
+    rec = tables.records
+    nb = _c_sz()
+    _check(lib.ara_su_workspace_bytes(ctypes.byref(tables.handle), ctypes.byref(layers.handle),
+                                      rec.ctypes.data_as(_c_p), ctypes.byref(nb)), "ara_su_workspace_bytes")
+    ws = _workspace(nb.value, dev)
+    ylt = torch.empty((L, n), dtype=torch.float64, device=dev)
+    s_pre = torch.empty((L, n), dtype=torch.float64, device=dev) if want_s_pre else None
+    et = elt_terms.to(device=dev, dtype=torch.float64).contiguous()
+    lt = layer_terms.to(device=dev, dtype=torch.float64).contiguous()
+    _check(lib.ara_ylt_forward_su(ctypes.byref(tables.handle), _dptr(sigma.sigma), _dptr(offsets), _dptr(ids),
+                                  n_trials, ctypes.byref(layers.handle), rec.ctypes.data_as(_c_p), _dptr(et),
+                                  _dptr(lt), int(seed) & 0xFFFFFFFFFFFFFFFF, trial_begin, trial_end, occ_begin,
+                                  occ_count, _dptr(ylt), _dptr(s_pre), _dptr(ws), ws.numel(), _stream()),
+           "ara_ylt_forward_su")
+    if check:
+        _check(lib.ara_check_device_error(_dptr(ws), _stream()), "ara_ylt_forward_su (device)")
+    return ylt, s_pre
 
 
 def ylt_forward(tables: EltTables, yet: PreparedYet, layers: Layers, elt_terms: torch.Tensor,
@@ -334,7 +396,7 @@ def ylt_backward(tables: EltTables, yet: PreparedYet, layers: Layers, elt_terms:
     return ge, gl
 
 
-PROF_OCC, PROF_FWD, PROF_METRICS, PROF_BWD, PROF_BWD_RED, PROF_YELT = range(6)
+PROF_OCC, PROF_FWD, PROF_METRICS, PROF_BWD, PROF_BWD_RED, PROF_YELT, PROF_SU = range(7)
 
 
 def profile_enable(on: bool = True) -> None:
@@ -477,6 +539,7 @@ class Metrics(torch.autograd.Function):
 
 
 __all__ = [
-    "AraError", "PreparedYet", "EltTables", "Layers", "ylt_forward", "metrics", "metrics_vjp", "ylt_backward",
+    "AraError", "PreparedYet", "EltTables", "SigmaTables", "Layers", "ylt_forward", "ylt_forward_su", "yelt_forward",
+    "metrics", "metrics_vjp", "ylt_backward",
     "YLT", "Metrics", "QuoteServer", "library", "ara_yet", "ara_tables", "ara_layers", "ARA_F_EMIT_HITS",
 ]

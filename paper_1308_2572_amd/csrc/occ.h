@@ -86,6 +86,11 @@ struct FwdItem {
 // Enqueue the forward streaming kernel over a device array of items.
 int32_t launch_forward(const ara_yet *yet, int n_sr, bool hits, const FwdItem *d_items, int n_items, hipStream_t st);
 
+// A layer's set-event bitmap folded onto 2^20 bits by OR (128 KB, staged in
+// LDS by the kernels that stream the trial-major YET): one filter per layer.
+constexpr int kFilterWords = 1 << 15;
+int32_t launch_set_filter(const OccTables *d_tabs, int n_words, uint32_t *filter, int n_layers, hipStream_t st);
+
 // Validates the layer list on the host; returns ARA_OK or an error.
 int32_t check_layers(const ara_layers *layers, int32_t n_elts);
 

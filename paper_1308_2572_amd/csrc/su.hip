@@ -1,0 +1,508 @@
+// Secondary uncertainty (named as future work in Section V): Algorithm 1 with
+// the table lookup of step one replaced by a draw per (occurrence, ELT) from
+// the lognormal distribution with the record's mean and standard deviation.
+//
+// Per call and layer:
+//   * the occurrence table in union mode gives the layer's union of ELT
+//     events as a bitmap with ranks, and the number of the layer's ELTs
+//     holding each union event;
+//   * a scan of those counts and a fill pass lay out, per union event and in
+//     the layer's listed ELT order, one entry per ELT holding it: the
+//     lognormal's parameters (m, s), the mean, the ELT's position and index;
+//   * the streaming kernel walks the trial-major YET (the occurrence index
+//     keys the draws, so storage order matters): one wavefront per trial, a
+//     1-Mbit LDS filter of the union, then for each union occurrence the
+//     draws of its entries, the ELT terms (step two) summed in listed order,
+//     the occurrence terms (step three); the trial's occurrence losses meet
+//     in a DPP wavefront sum and the aggregate terms give the year loss (step
+//     four, telescoped).
+// The draw: Philox4x64-10 (Salmon, Moraes, Dror and Shaw, SC'11) block of
+// counter (occurrence, ELT index, 0, 0) under key (seed, 0); uniforms from
+// the top 52 bits of the first two words, Box-Muller, x = exp(m + s z).
+#include "occ.h"
+#include "wave.h"
+
+#include <algorithm>
+#include <vector>
+
+namespace ara {
+
+constexpr int kSuThreads = 1024;
+constexpr int kSuMaxJ = ARA_MAX_ELTS_PER_LAYER;
+constexpr int kSuScanPer = kSr / kSuThreads;   // 64 ranks per thread in the count scan
+
+// One (union event, ELT of the layer) pair; 32 bytes.
+struct SuEntry {
+    double m, s;       // lognormal parameters of the draw
+    float mu;          // the record's mean loss
+    int32_t q;         // the ELT's position in the layer's list
+    int32_t k;         // the ELT's index (keys the draw)
+    int32_t exact;     // sigma = 0: the draw is mu itself
+};
+static_assert(sizeof(SuEntry) == 32, "entry layout");
+
+// ---------------------------------------------------------------------------
+// Standard-deviation tables.
+
+// Records already checked on the host.
+__global__ void k_sigma_scatter(const int64_t *__restrict__ rec_off, const int32_t *__restrict__ rec_ids,
+                                const float *__restrict__ rec_sigma, int32_t catalog, float *__restrict__ sigma) {
+    const int k = blockIdx.y;
+    const int64_t a = rec_off[k], b = rec_off[k + 1];
+    for (int64_t i = a + blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < b;
+         i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+        sigma[static_cast<size_t>(k) * catalog + rec_ids[i]] = rec_sigma[i];
+}
+
+// ---------------------------------------------------------------------------
+// Entry layout.
+
+// Per (super-range, layer): exclusive scan of the union events' ELT counts
+// in rank order -> eoff (relative to the super-range), total -> etot.
+__global__ __launch_bounds__(kSuThreads) void k_su_scan(const OccTables *__restrict__ tabs, int n_sr,
+                                                        uint32_t *__restrict__ eoff, uint32_t *__restrict__ etot) {
+    __shared__ uint32_t wsum[kSuThreads / kWave];
+    const int s = blockIdx.x, j = blockIdx.y, tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const OccTables T = tabs[j];
+    const int cnt_s = T.count[s];
+    const uint8_t *c = T.cnt + static_cast<size_t>(s) * kSr;
+    uint32_t *eo = eoff + (static_cast<size_t>(j) * n_sr + s) * kSr;
+    const int r0 = tid * kSuScanPer;
+    uint32_t mine = 0;
+    for (int r = r0; r < min(r0 + kSuScanPer, cnt_s); ++r) mine += c[r];
+    uint32_t incl = mine;
+    for (int o = 1; o < kWave; o <<= 1) {
+        const uint32_t v = __shfl_up(incl, o);
+        if (lane >= o) incl += v;
+    }
+    if (lane == kWave - 1) wsum[w] = incl;
+    __syncthreads();
+    uint32_t before = incl - mine;
+    for (int i = 0; i < w; ++i) before += wsum[i];
+    for (int r = r0; r < min(r0 + kSuScanPer, cnt_s); ++r) {
+        eo[r] = before;
+        before += c[r];
+    }
+    if (tid == kSuThreads - 1) etot[static_cast<size_t>(j) * n_sr + s] = before;
+}
+
+// Per layer: super-range bases (exclusive scan of etot); the layer's total
+// must fit its entry capacity.
+__global__ __launch_bounds__(kSuThreads) void k_su_base(const uint32_t *__restrict__ etot, int n_sr,
+                                                        const uint64_t *__restrict__ ecap,
+                                                        uint64_t *__restrict__ ebase, int32_t *__restrict__ err) {
+    __shared__ uint64_t wsum[kSuThreads / kWave];
+    const int j = blockIdx.x, tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const uint32_t *et = etot + static_cast<size_t>(j) * n_sr;
+    uint64_t *eb = ebase + static_cast<size_t>(j) * (n_sr + 1);
+    const int per = (n_sr + kSuThreads - 1) / kSuThreads;
+    const int s0 = tid * per;
+    uint64_t mine = 0;
+    for (int s = s0; s < min(s0 + per, n_sr); ++s) mine += et[s];
+    uint64_t incl = mine;
+    for (int o = 1; o < kWave; o <<= 1) {
+        const uint64_t v = __shfl_up(incl, o);
+        if (lane >= o) incl += v;
+    }
+    if (lane == kWave - 1) wsum[w] = incl;
+    __syncthreads();
+    uint64_t before = incl - mine;
+    for (int i = 0; i < w; ++i) before += wsum[i];
+    for (int s = s0; s < min(s0 + per, n_sr); ++s) {
+        eb[s] = before;
+        before += et[s];
+    }
+    if (tid == kSuThreads - 1) {
+        eb[n_sr] = before;
+        if (before > ecap[j]) atomicCAS(err, 0, ARA_E_LIMIT);
+    }
+}
+
+// Per (4096-event chunk, layer): the entries of every union event, in the
+// layer's listed ELT order.
+constexpr int kSuFillWords = 128;                  // 4096 events per workgroup
+constexpr int kSuFillChunks = kSrWords / kSuFillWords;
+
+__global__ __launch_bounds__(kSuThreads) void k_su_fill(const float *__restrict__ loss, const float *__restrict__ sigma,
+                                                        const uint32_t *__restrict__ present, int32_t catalog,
+                                                        int32_t words, const int32_t *__restrict__ elt_off,
+                                                        const int32_t *__restrict__ elt_ids,
+                                                        const OccTables *__restrict__ tabs, int n_sr,
+                                                        const uint32_t *__restrict__ eoff,
+                                                        const uint64_t *__restrict__ ebase,
+                                                        const uint64_t *__restrict__ ecap,
+                                                        const uint64_t *__restrict__ eregion,
+                                                        SuEntry *__restrict__ ent) {
+    __shared__ int32_t lk[kSuMaxJ];
+    const int s = blockIdx.x / kSuFillChunks, p = blockIdx.x % kSuFillChunks, j = blockIdx.y;
+    const int tid = threadIdx.x;
+    const int a = elt_off[j], J = elt_off[j + 1] - a;
+    for (int q = tid; q < J; q += blockDim.x) lk[q] = elt_ids[a + q];
+    __syncthreads();
+    const OccTables T = tabs[j];
+    const uint64_t base_s = ebase[static_cast<size_t>(j) * (n_sr + 1) + s];
+    const uint64_t cap = ecap[j];
+    SuEntry *E = ent + eregion[j];
+    const uint32_t *eo = eoff + (static_cast<size_t>(j) * n_sr + s) * kSr;
+    for (int it = 0; it < 4; ++it) {
+        const int local = p * (kSuFillWords * 32) + it * kSuThreads + tid;   // event within the super-range
+        const int64_t ev = static_cast<int64_t>(s) * kSr + local;
+        if (ev >= catalog) continue;
+        const uint2 q2 = T.br[static_cast<size_t>(s) * kSrWords + (local >> 5)];
+        const int bit = local & 31;
+        if (!((q2.x >> bit) & 1u)) continue;
+        const uint32_t r = q2.y + __popc(q2.x & ((1u << bit) - 1u));
+        uint64_t o = base_s + eo[r];
+        for (int q = 0; q < J; ++q) {
+            const int k = lk[q];
+            if (!((present[static_cast<size_t>(k) * words + (ev >> 5)] >> (ev & 31)) & 1u)) continue;
+            if (o >= cap) break;   // flagged by k_su_base
+            const float mu = loss[static_cast<size_t>(k) * catalog + ev];
+            const float sg = sigma[static_cast<size_t>(k) * catalog + ev];
+            SuEntry e;
+            e.mu = mu;
+            e.q = q;
+            e.k = k;
+            e.exact = (sg == 0.0f) ? 1 : 0;
+            if (e.exact) {
+                e.m = 0.0;
+                e.s = 0.0;
+            } else {
+                const double rr = static_cast<double>(sg) / static_cast<double>(mu);
+                const double s2 = log1p(rr * rr);
+                e.m = log(static_cast<double>(mu)) - 0.5 * s2;
+                e.s = sqrt(s2);
+            }
+            E[o++] = e;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// The draw.
+
+__device__ __forceinline__ void philox4x64_10(uint64_t c[4], uint64_t k0, uint64_t k1) {
+    constexpr uint64_t kM0 = 0xD2E7470EE14C6C93ull, kM1 = 0xCA5A826395121157ull;
+    constexpr uint64_t kW0 = 0x9E3779B97F4A7C15ull, kW1 = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) {
+            k0 += kW0;
+            k1 += kW1;
+        }
+        const uint64_t hi0 = __umul64hi(kM0, c[0]), lo0 = kM0 * c[0];
+        const uint64_t hi1 = __umul64hi(kM1, c[2]), lo1 = kM1 * c[2];
+        const uint64_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+        c[0] = n0;
+        c[1] = lo1;
+        c[2] = n2;
+        c[3] = lo0;
+    }
+}
+
+__device__ __forceinline__ double su_draw(const SuEntry &e, uint64_t seed, int64_t occ) {
+    if (e.exact) return static_cast<double>(e.mu);
+    uint64_t c[4] = {static_cast<uint64_t>(occ), static_cast<uint64_t>(static_cast<uint32_t>(e.k)), 0ull, 0ull};
+    philox4x64_10(c, seed, 0ull);
+    const double u1 = (static_cast<double>(c[0] >> 12) + 0.5) * 0x1p-52;
+    const double u2 = (static_cast<double>(c[1] >> 12) + 0.5) * 0x1p-52;
+    const double two_pi = 6.283185307179586476925286766559;   // the binary64 nearest 2 pi
+    const double z = sqrt(-2.0 * log(u1)) * cos(two_pi * u2);
+    return exp(e.m + e.s * z);
+}
+
+// ---------------------------------------------------------------------------
+// Streaming kernel: one wavefront per trial.
+
+constexpr int kSuSlices = 4;   // 64-occurrence slices per step
+
+struct SuParams {
+    const int64_t *off;
+    const int32_t *ids;
+    int32_t catalog, n_sr;
+    int64_t t0, t1;
+    int64_t occ_begin, occ_count;
+    const OccTables *tabs;
+    const uint32_t *filter;      // [n_layers][kFilterWords]
+    const uint32_t *eoff;        // [n_layers][n_sr][kSr]
+    const uint64_t *ebase;       // [n_layers][n_sr + 1]
+    const uint64_t *eregion;     // [n_layers]
+    const SuEntry *ent;
+    const int32_t *elt_off, *elt_ids;
+    const double *elt_terms, *layer_terms;
+    uint64_t seed;
+    double *ylt, *s_pre;
+    int32_t *err;
+};
+
+__global__ __launch_bounds__(kSuThreads) void k_su_fwd(SuParams P) {
+    __shared__ uint32_t filt[kFilterWords];
+    __shared__ double ls[kSuMaxJ], lr[kSuMaxJ], ll[kSuMaxJ];
+    const int j = blockIdx.y, tid = threadIdx.x, lane = tid & 63;
+    const int a0 = P.elt_off[j], J = P.elt_off[j + 1] - a0;
+    for (int q = tid; q < J; q += blockDim.x) {
+        const int k = P.elt_ids[a0 + q];
+        ls[q] = P.elt_terms[3 * k + 0];
+        lr[q] = P.elt_terms[3 * k + 1];
+        ll[q] = P.elt_terms[3 * k + 2];
+    }
+    for (int i = tid; i < kFilterWords; i += blockDim.x) filt[i] = P.filter[static_cast<size_t>(j) * kFilterWords + i];
+    __syncthreads();
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int64_t nw = static_cast<int64_t>(gridDim.x) * (kSuThreads / kWave);
+    const OccTables T = P.tabs[j];
+    const uint32_t *eo = P.eoff + static_cast<size_t>(j) * P.n_sr * kSr;
+    const uint64_t *eb = P.ebase + static_cast<size_t>(j) * (P.n_sr + 1);
+    const SuEntry *E = P.ent + P.eregion[j];
+    const double occR = P.layer_terms[4 * j + 0], occL = P.layer_terms[4 * j + 1];
+    const double aggR = P.layer_terms[4 * j + 2], aggL = P.layer_terms[4 * j + 3];
+    const int64_t n = P.t1 - P.t0;
+
+    for (int64_t t = P.t0 + static_cast<int64_t>(blockIdx.x) * (kSuThreads / kWave) + wv; t < P.t1; t += nw) {
+        int64_t a = P.off[t], b = P.off[t + 1];
+        if (a < P.occ_begin || b > P.occ_begin + P.occ_count || b < a) {
+            if (lane == 0) atomicCAS(P.err, 0, ARA_E_RANGE);
+            b = a;
+        }
+        double acc = 0.0;   // this lane's occurrence losses, in its order
+        for (int64_t base = a; base < b; base += kSuSlices * kWave) {
+            int32_t ev[kSuSlices];
+#pragma unroll
+            for (int k = 0; k < kSuSlices; ++k) {
+                const int64_t i = base + k * kWave + lane;
+                ev[k] = (i < b) ? P.ids[i] : -1;
+            }
+#pragma unroll
+            for (int k = 0; k < kSuSlices; ++k) {
+                const int64_t i = base + k * kWave + lane;
+                const int32_t e = ev[k];
+                if (i >= b) continue;
+                if (e < 0 || e >= P.catalog) {
+                    atomicCAS(P.err, 0, ARA_E_RANGE);
+                    continue;
+                }
+                if (!((filt[(static_cast<uint32_t>(e) >> 5) & (kFilterWords - 1)] >> (e & 31)) & 1u)) continue;
+                const uint2 w = T.br[static_cast<uint32_t>(e) >> 5];
+                const uint32_t bit = e & 31;
+                if (!((w.x >> bit) & 1u)) continue;
+                const uint32_t sr = static_cast<uint32_t>(e) >> kSrBits;
+                const uint32_t r = w.y + __popc(w.x & ((1u << bit) - 1u));
+                const int nb = T.cnt[static_cast<size_t>(sr) * kSr + r];
+                const SuEntry *pe = E + eb[sr] + eo[static_cast<size_t>(sr) * kSr + r];
+                // steps one and two for each ELT holding the event, summed in
+                // listed order; step three
+                double x = 0.0;
+                for (int h = 0; h < nb; ++h) {
+                    const SuEntry en = pe[h];
+                    const double v = su_draw(en, P.seed, i);
+                    x = x + xl(ls[en.q] * v, lr[en.q], ll[en.q]);
+                }
+                acc += xl(x, occR, occL);
+            }
+        }
+        // step four, telescoped: the aggregate terms on the trial's total
+        const double S = lane63(wave_inclusive_sum(acc));
+        if (lane == 0) {
+            const size_t o = static_cast<size_t>(j) * n + static_cast<size_t>(t - P.t0);
+            P.ylt[o] = xl(S, aggR, aggL);
+            if (P.s_pre) P.s_pre[o] = S;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Workspace.
+
+struct SuLayout {
+    OccLayoutSizes z;
+    std::vector<uint64_t> cap, region;   // per layer: entry capacity and first entry
+    uint64_t n_ent = 0;
+};
+
+static int32_t su_layout(const ara_tables *tables, const ara_layers *layers, const int64_t *elt_records, SuLayout &S) {
+    S.z = occ_sizes(tables->catalog, true);
+    const int L = layers->n_layers;
+    S.cap.assign(static_cast<size_t>(L), 0);
+    S.region.assign(static_cast<size_t>(L), 0);
+    for (int j = 0; j < L; ++j) {
+        uint64_t c = 0;
+        for (int q = layers->elt_off[j]; q < layers->elt_off[j + 1]; ++q) {
+            const int64_t r = elt_records[layers->elt_ids[q]];
+            if (r < 0) return fail(ARA_E_INVAL, "negative record count");
+            c += static_cast<uint64_t>(std::min<int64_t>(r, tables->catalog));
+        }
+        S.cap[j] = c;
+        S.region[j] = S.n_ent;
+        S.n_ent += c;
+    }
+    return ARA_OK;
+}
+
+static size_t su_workspace(const ara_tables *tables, const ara_layers *layers, const SuLayout &S) {
+    const int L = layers->n_layers;
+    const int nJ = L > 0 ? layers->elt_off[L] : 0;
+    const size_t n_sr = static_cast<size_t>(S.z.n_sr);
+    Carver c(nullptr);
+    c.take<int32_t>(kWsHeaderBytes / sizeof(int32_t));
+    c.take<int32_t>(static_cast<size_t>(L + 1));
+    c.take<int32_t>(static_cast<size_t>(std::max(nJ, 1)));
+    c.take<OccTables>(static_cast<size_t>(std::max(L, 1)));
+    c.take<uint64_t>(static_cast<size_t>(std::max(L, 1)));   // capacities
+    c.take<uint64_t>(static_cast<size_t>(std::max(L, 1)));   // regions
+    size_t b = c.bytes();
+    b += static_cast<size_t>(L) * S.z.per_layer;
+    b += align256(static_cast<size_t>(L) * n_sr * kSr * sizeof(uint32_t));            // eoff
+    b += align256(static_cast<size_t>(std::max(L, 1)) * n_sr * sizeof(uint32_t));     // etot
+    b += align256(static_cast<size_t>(std::max(L, 1)) * (n_sr + 1) * sizeof(uint64_t));   // ebase
+    b += align256(static_cast<size_t>(std::max(L, 1)) * kFilterWords * sizeof(uint32_t));
+    b += align256(static_cast<size_t>(std::max<uint64_t>(S.n_ent, 1)) * sizeof(SuEntry));
+    return b;
+}
+
+}  // namespace ara
+
+using namespace ara;
+
+extern "C" int32_t ara_build_elt_sigma(const ara_tables *tables, const int64_t *rec_off, const int32_t *rec_ids,
+                                       const float *rec_sigma, float *sigma, void *stream) {
+    if (!tables || !rec_off || !sigma) return fail(ARA_E_INVAL, "ara_build_elt_sigma: null pointer");
+    const int32_t K = tables->n_elts, C = tables->catalog;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    // the records are checked on the host (a one-time build), then scattered
+    std::vector<int64_t> off(static_cast<size_t>(K) + 1);
+    ARA_HIP(hipMemcpyAsync(off.data(), rec_off, off.size() * sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    ARA_HIP(hipStreamSynchronize(st));
+    int64_t most = 0;
+    for (int32_t k = 0; k < K; ++k) {
+        if (off[k + 1] < off[k] || off[k] < 0) return fail(ARA_E_RANGE, "ara_build_elt_sigma: decreasing record offsets");
+        most = std::max<int64_t>(most, off[k + 1] - off[k]);
+    }
+    const int64_t nrec = K > 0 ? off[K] - off[0] : 0;
+    if (nrec > 0) {
+        if (!rec_ids || !rec_sigma) return fail(ARA_E_INVAL, "ara_build_elt_sigma: null records");
+        std::vector<int32_t> id(static_cast<size_t>(nrec));
+        std::vector<float> sg(static_cast<size_t>(nrec));
+        ARA_HIP(hipMemcpyAsync(id.data(), rec_ids + off[0], id.size() * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        ARA_HIP(hipMemcpyAsync(sg.data(), rec_sigma + off[0], sg.size() * sizeof(float), hipMemcpyDeviceToHost, st));
+        ARA_HIP(hipStreamSynchronize(st));
+        for (int64_t i = 0; i < nrec; ++i) {
+            if (id[i] < 0 || id[i] >= C) return fail(ARA_E_RANGE, "ara_build_elt_sigma: an event ID outside [0, catalog)");
+            if (!(sg[i] >= 0.0f) || !(sg[i] <= 3.402823466e38f))
+                return fail(ARA_E_INVAL, "ara_build_elt_sigma: a negative or non-finite standard deviation");
+        }
+    }
+    ARA_HIP(hipMemsetAsync(sigma, 0, static_cast<size_t>(K) * C * sizeof(float), st));
+    if (nrec > 0) {
+        const unsigned gx = static_cast<unsigned>(std::min<int64_t>((most + 255) / 256, 1024));
+        k_sigma_scatter<<<dim3(gx, static_cast<unsigned>(K)), 256, 0, st>>>(rec_off, rec_ids, rec_sigma, C, sigma);
+        ARA_HIP(hipGetLastError());
+    }
+    ARA_HIP(hipStreamSynchronize(st));
+    return ARA_OK;
+}
+
+extern "C" int32_t ara_su_workspace_bytes(const ara_tables *tables, const ara_layers *layers,
+                                          const int64_t *elt_records, size_t *bytes) {
+    if (!tables || !bytes || !elt_records) return fail(ARA_E_INVAL, "null argument");
+    int32_t rc = check_layers(layers, tables->n_elts);
+    if (rc) return rc;
+    SuLayout S;
+    if ((rc = su_layout(tables, layers, elt_records, S))) return rc;
+    *bytes = su_workspace(tables, layers, S);
+    return ARA_OK;
+}
+
+extern "C" int32_t ara_ylt_forward_su(const ara_tables *tables, const float *sigma, const int64_t *offsets,
+                                      const int32_t *ids, int64_t n_trials, const ara_layers *layers,
+                                      const int64_t *elt_records, const double *elt_terms,
+                                      const double *layer_terms, uint64_t seed, int64_t trial_begin,
+                                      int64_t trial_end, int64_t occ_begin, int64_t occ_count, double *ylt,
+                                      double *s_pre, void *ws, size_t ws_bytes, void *stream) {
+    if (!tables || !elt_records) return fail(ARA_E_INVAL, "null tables or record counts");
+    int32_t rc = check_layers(layers, tables->n_elts);
+    if (rc) return rc;
+    if (trial_begin < 0 || trial_end < trial_begin || trial_end > n_trials)
+        return fail(ARA_E_RANGE, "trial range outside the YET");
+    if (occ_begin < 0 || occ_count < 0) return fail(ARA_E_RANGE, "negative occurrence range");
+    if (!ws) return fail(ARA_E_INVAL, "null workspace");
+    const int L = layers->n_layers;
+    const int64_t n = trial_end - trial_begin;
+    if (L > 0 && n > 0 && (!offsets || !sigma || !elt_terms || !layer_terms || !ylt || (occ_count > 0 && !ids)))
+        return fail(ARA_E_INVAL, "null input or output");
+    SuLayout S;
+    if ((rc = su_layout(tables, layers, elt_records, S))) return rc;
+    if (ws_bytes < su_workspace(tables, layers, S)) return fail(ARA_E_NOSPACE, "workspace too small");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (L == 0 || n == 0) {
+        ARA_HIP(hipMemsetAsync(ws, 0, kWsHeaderBytes, st));
+        return ARA_OK;
+    }
+    const int nJ = layers->elt_off[L];
+    const int n_sr = S.z.n_sr;
+    Carver c(ws);
+    int32_t *d_err = c.take<int32_t>(kWsHeaderBytes / sizeof(int32_t));
+    int32_t *d_off = c.take<int32_t>(static_cast<size_t>(L + 1));
+    int32_t *d_ids = c.take<int32_t>(static_cast<size_t>(std::max(nJ, 1)));
+    OccTables *d_tabs = c.take<OccTables>(static_cast<size_t>(L));
+    uint64_t *d_cap = c.take<uint64_t>(static_cast<size_t>(L));
+    uint64_t *d_region = c.take<uint64_t>(static_cast<size_t>(L));
+    std::vector<OccTables> tabs(static_cast<size_t>(L));
+    for (int j = 0; j < L; ++j) tabs[j] = occ_carve(c, S.z, true);
+    uint32_t *eoff = c.take<uint32_t>(static_cast<size_t>(L) * n_sr * kSr);
+    uint32_t *etot = c.take<uint32_t>(static_cast<size_t>(L) * n_sr);
+    uint64_t *ebase = c.take<uint64_t>(static_cast<size_t>(L) * (n_sr + 1));
+    uint32_t *filter = c.take<uint32_t>(static_cast<size_t>(L) * kFilterWords);
+    SuEntry *ent = c.take<SuEntry>(static_cast<size_t>(std::max<uint64_t>(S.n_ent, 1)));
+    HeadImage img(ws);
+    img.cover(d_err + kWsHeaderBytes / sizeof(int32_t));
+    img.put(d_off, layers->elt_off, static_cast<size_t>(L + 1));
+    img.put(d_ids, layers->elt_ids, static_cast<size_t>(nJ));
+    img.put(d_tabs, tabs.data(), tabs.size());
+    img.put(d_cap, S.cap.data(), S.cap.size());
+    img.put(d_region, S.region.data(), S.region.size());
+    if ((rc = img.send(st))) return rc;
+
+    {
+        ProfScope prof(ARA_PROF_OCC, st);
+        if ((rc = launch_occ(tables, d_off, d_ids, elt_terms, layer_terms, L, true, d_tabs, n_sr, d_err, st)))
+            return rc;
+        k_su_scan<<<dim3(static_cast<unsigned>(n_sr), static_cast<unsigned>(L)), kSuThreads, 0, st>>>(d_tabs, n_sr,
+                                                                                                    eoff, etot);
+        k_su_base<<<static_cast<unsigned>(L), kSuThreads, 0, st>>>(etot, n_sr, d_cap, ebase, d_err);
+        k_su_fill<<<dim3(static_cast<unsigned>(n_sr * kSuFillChunks), static_cast<unsigned>(L)), kSuThreads, 0, st>>>(
+            tables->loss, sigma, tables->present, tables->catalog, tables->words, d_off, d_ids, d_tabs, n_sr, eoff,
+            ebase, d_cap, d_region, ent);
+        ARA_HIP(hipGetLastError());
+        if ((rc = launch_set_filter(d_tabs, n_sr * kSrWords, filter, L, st))) return rc;
+    }
+    SuParams P{};
+    P.off = offsets;
+    P.ids = ids;
+    P.catalog = tables->catalog;
+    P.n_sr = n_sr;
+    P.t0 = trial_begin;
+    P.t1 = trial_end;
+    P.occ_begin = occ_begin;
+    P.occ_count = occ_count;
+    P.tabs = d_tabs;
+    P.filter = filter;
+    P.eoff = eoff;
+    P.ebase = ebase;
+    P.eregion = d_region;
+    P.ent = ent;
+    P.elt_off = d_off;
+    P.elt_ids = d_ids;
+    P.elt_terms = elt_terms;
+    P.layer_terms = layer_terms;
+    P.seed = seed;
+    P.ylt = ylt;
+    P.s_pre = s_pre;
+    P.err = d_err;
+    const int waves_per_wg = kSuThreads / kWave;
+    const int64_t want = (n + waves_per_wg - 1) / waves_per_wg;
+    const unsigned gx = static_cast<unsigned>(std::max<int64_t>(1, std::min<int64_t>(want, device_cu_count())));
+    ProfScope prof(ARA_PROF_SU, st);
+    k_su_fwd<<<dim3(gx, static_cast<unsigned>(L)), kSuThreads, 0, st>>>(P);
+    ARA_HIP(hipGetLastError());
+    return ARA_OK;
+}

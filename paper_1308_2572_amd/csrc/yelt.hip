@@ -29,7 +29,6 @@ namespace ara {
 constexpr int kYeltThreads = 1024;
 constexpr int kYeltSteps = 8;           // 64-occurrence slices per step
 constexpr int kYeltGroup = 4;           // slices per transposed scan
-constexpr int kFilterWords = 1 << 15;   // 2^20 bits = 128 KB of LDS (+ 32 KB of staging)
 
 struct YeltParams {
     const int64_t *off;
@@ -251,6 +250,13 @@ __global__ __launch_bounds__(kYeltThreads) void k_yelt(YeltParams P) {
     }
 }
 
+int32_t launch_set_filter(const OccTables *d_tabs, int n_words, uint32_t *filter, int n_layers, hipStream_t st) {
+    if (n_layers <= 0) return ARA_OK;
+    k_yelt_filter<<<dim3(kFilterWords / 256, n_layers), 256, 0, st>>>(d_tabs, n_words, filter);
+    ARA_HIP(hipGetLastError());
+    return ARA_OK;
+}
+
 static size_t yelt_workspace(const ara_tables *tables, const ara_layers *layers) {
     const OccLayoutSizes z = occ_sizes(tables->catalog, false);
     const int L = layers->n_layers;
@@ -320,8 +326,7 @@ extern "C" int32_t ara_yelt_forward(const ara_tables *tables, const int64_t *off
         if ((rc = launch_occ(tables, d_off, d_ids, elt_terms, layer_terms, L, false, d_tabs, z.n_sr, d_err, st)))
             return rc;
     }
-    k_yelt_filter<<<dim3(kFilterWords / 256, L), 256, 0, st>>>(d_tabs, z.n_sr * kSrWords, d_filter);
-    ARA_HIP(hipGetLastError());
+    if ((rc = launch_set_filter(d_tabs, z.n_sr * kSrWords, d_filter, L, st))) return rc;
     YeltParams P{};
     P.off = offsets;
     P.ids = ids;

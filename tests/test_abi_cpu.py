@@ -96,6 +96,41 @@ def test_argument_validation_before_device_work(ara):
     assert b"ARA_PREP_TRANSPOSED" in lib.ara_last_error()
 
 
+def test_secondary_uncertainty_queries_and_validation(ara):
+    lib = ara.library()
+    tables = ara.ara_tables(n_elts=3, catalog=200_000, words=6250)
+    lay = ara.Layers([0, 2, 3], [0, 2, 1])
+    rec = np.array([1000, 50, 20_000], np.int64)
+    nb = ctypes.c_size_t()
+    assert lib.ara_su_workspace_bytes(ctypes.byref(tables), ctypes.byref(lay.handle), rec.ctypes.data_as(ctypes.c_void_p),
+                                      ctypes.byref(nb)) == 0
+    small = nb.value
+    assert small >= (1000 + 20_000 + 50) * 32                       # one 32-byte entry per (event, ELT) pair
+    rec2 = np.array([1000, 50, 90_000], np.int64)
+    assert lib.ara_su_workspace_bytes(ctypes.byref(tables), ctypes.byref(lay.handle),
+                                      rec2.ctypes.data_as(ctypes.c_void_p), ctypes.byref(nb)) == 0
+    assert nb.value >= small + 70_000 * 32
+    bad = np.array([1000, -1, 5], np.int64)
+    assert lib.ara_su_workspace_bytes(ctypes.byref(tables), ctypes.byref(lay.handle),
+                                      bad.ctypes.data_as(ctypes.c_void_p), ctypes.byref(nb)) == 1
+    assert lib.ara_su_workspace_bytes(ctypes.byref(tables), ctypes.byref(lay.handle), None, ctypes.byref(nb)) == 1
+    # trial range outside the YET, null workspace, null records: all before any device work
+    assert lib.ara_ylt_forward_su(ctypes.byref(tables), None, None, None, 10, ctypes.byref(lay.handle),
+                                  rec.ctypes.data_as(ctypes.c_void_p), None, None, 7, 0, 11, 0, 0, None, None,
+                                  ctypes.c_void_p(256), 1 << 30, None) == 2
+    assert lib.ara_ylt_forward_su(ctypes.byref(tables), None, None, None, 10, ctypes.byref(lay.handle),
+                                  rec.ctypes.data_as(ctypes.c_void_p), None, None, 7, 0, 10, 0, 0, None, None,
+                                  None, 1 << 30, None) == 1
+    assert lib.ara_ylt_forward_su(ctypes.byref(tables), None, None, None, 10, ctypes.byref(lay.handle), None, None,
+                                  None, 7, 0, 10, 0, 0, None, None, ctypes.c_void_p(256), 1 << 30, None) == 1
+    # a workspace smaller than the query
+    assert lib.ara_ylt_forward_su(ctypes.byref(tables), ctypes.c_void_p(256), ctypes.c_void_p(256), ctypes.c_void_p(256),
+                                  10, ctypes.byref(lay.handle), rec.ctypes.data_as(ctypes.c_void_p),
+                                  ctypes.c_void_p(256), ctypes.c_void_p(256), 7, 0, 10, 0, 100,
+                                  ctypes.c_void_p(256), None, ctypes.c_void_p(256), 4096, None) == 4
+    assert lib.ara_build_elt_sigma(ctypes.byref(tables), None, None, None, None, None) == 1
+
+
 def test_product_refuses_to_run_without_library(tmp_path, monkeypatch):
     import paper_1308_2572_amd as ara
     monkeypatch.setattr(ara, "LIB_PATH", str(tmp_path / "missing.so"))
