@@ -298,9 +298,11 @@ int32_t ara_ylt_backward(const ara_tables *tables, const ara_yet *yet, const ara
  *   x = mu                      if sigma = 0,
  *   x = exp(m + s z)            otherwise, s^2 = ln(1 + sigma^2/mu^2),
  *                               m = ln mu - s^2/2 (lognormal, mean mu, sd sigma),
- *   z = sqrt(-2 ln u1) cos(2 pi u2),  u_j = ((w_j >> 12) + 1/2) 2^-52,
- *   (w_0, w_1, ...) = Philox4x64-10 block of counter (i, k, 0, 0) under key
- *   (seed, 0), k the ELT's index (Salmon, Moraes, Dror, Shaw, SC'11),
+ *   z = sqrt(-2 ln u1) cos(2 pi u2),  u1 = (((w1 2^32 + w0) >> 12) + 1/2) 2^-52,
+ *   u2 likewise from (w3, w2), (w0, w1, w2, w3) = Philox4x32-10 block
+ *   (Salmon, Moraes, Dror, Shaw, SC'11) of counter words (i mod 2^32,
+ *   i div 2^32, k, 0) under key words (seed mod 2^32, seed div 2^32), k the
+ *   ELT's index,
  * and x replaces the table lookup of step one of Algorithm 1; steps two to
  * four are unchanged.  The same occurrence and ELT draw the same loss in
  * every layer and every call with the same seed.

@@ -52,7 +52,7 @@ def _load():
         lib.oracle_backward.argtypes = [_I32, _I32, _P, _I64, _P, _P, _I32, _P, _P, _P, _P,
                                         _I64, _I64, _I32, _P, _I32, _P, _P]
         lib.oracle_num_threads_available.restype = _I32
-        lib.oracle_philox4x64_10.argtypes = [_P, _P, _P]
+        lib.oracle_philox4x32_10.argtypes = [_P, _P, _P]
         lib.oracle_su_draw.argtypes = [_F64, _F64, ctypes.c_uint64, _I64, _I32]
         lib.oracle_su_draw.restype = _F64
         lib.oracle_forward_su.argtypes = [_I32, _I32, _P, _P, _I64, _P, _P, _I32, _P, _P, _P, _P,
@@ -170,12 +170,12 @@ def backward(tables: np.ndarray, yet, layers, elt_terms, layer_terms, cot: np.nd
     return ge, gl
 
 
-def philox4x64_10(ctr, key) -> np.ndarray:
-    """One Philox4x64-10 block (uint64 [4]) of counter ctr[4] under key[2]."""
-    c = _c(ctr, np.uint64)
-    k = _c(key, np.uint64)
-    out = np.empty(4, np.uint64)
-    _load().oracle_philox4x64_10(_ptr(c), _ptr(k), _ptr(out))
+def philox4x32_10(ctr, key) -> np.ndarray:
+    """One Philox4x32-10 block (uint32 [4]) of counter ctr[4] under key[2]."""
+    c = _c(ctr, np.uint32)
+    k = _c(key, np.uint32)
+    out = np.empty(4, np.uint32)
+    _load().oracle_philox4x32_10(_ptr(c), _ptr(k), _ptr(out))
     return out
 
 

@@ -53,17 +53,18 @@
  *       deviation; sigma = 0 draws mu itself.  The draw replaces the table
  *       lookup of step one; steps two to four are unchanged.
  *   R11 the draw of occurrence i (its index in the YET) in ELT k: the
- *       Philox4x64-10 block (Salmon, Moraes, Dror and Shaw, SC'11) of
- *       counter (i, k, 0, 0) under key (seed, 0); its first two words give
- *       u_j = ((w_j >> 12) + 1/2) 2^-52, z = sqrt(-2 ln u_1) cos(2 pi u_2)
- *       (Box-Muller), x = exp(m + s z) with s^2 = ln(1 + sigma^2/mu^2) and
- *       m = ln mu - s^2/2.  The same occurrence and ELT draw the same loss in
- *       every layer.
+ *       Philox4x32-10 block (Salmon, Moraes, Dror and Shaw, SC'11) of the
+ *       32-bit counter words (i mod 2^32, i div 2^32, k, 0) under key words
+ *       (seed mod 2^32, seed div 2^32); output words w0..w3 give
+ *       u_1 = (((w1 2^32 + w0) >> 12) + 1/2) 2^-52 and u_2 likewise from
+ *       (w3, w2); z = sqrt(-2 ln u_1) cos(2 pi u_2) (Box-Muller),
+ *       x = exp(m + s z) with s^2 = ln(1 + sigma^2/mu^2), m = ln mu - s^2/2.
+ *       The same occurrence and ELT draw the same loss in every layer.
  *
- * Secondary-uncertainty pins: the generator against numpy's Philox
- * (a library implementation of the same published generator), sigma = 0
- * against the deterministic path bit for bit, and the moments of the draws
- * (mean mu, standard deviation sigma, log-mean m, log-variance s^2).
+ * Secondary-uncertainty pins: the generator against the published
+ * known-answer vectors of Philox4x32-10, sigma = 0 against the deterministic
+ * path bit for bit, and the moments of the draws (mean mu, standard
+ * deviation sigma, log-mean m, log-variance s^2).
  */
 #include <math.h>
 #include <stdint.h>
@@ -488,23 +489,23 @@ int oracle_num_threads_available(void)
 /* Secondary uncertainty (readings R10, R11).                                */
 /* ------------------------------------------------------------------------ */
 
-/* Philox4x64-10: ten rounds of two 64x64->128-bit multiplies (constants
- * 0xD2E7470EE14C6C93 and 0xCA5A826395121157) with the key bumped by the
- * Weyl constants 0x9E3779B97F4A7C15 and 0xBB67AE8584CAA73B between rounds. */
-static void philox4x64_10(const uint64_t ctr_in[4], const uint64_t key_in[2], uint64_t out[4])
+/* Philox4x32-10: ten rounds of two 32x32->64-bit multiplies (constants
+ * 0xD2511F53 and 0xCD9E8D57) with the key bumped by the Weyl constants
+ * 0x9E3779B9 and 0xBB67AE85 between rounds. */
+static void philox4x32_10(const uint32_t ctr_in[4], const uint32_t key_in[2], uint32_t out[4])
 {
-    uint64_t c[4] = {ctr_in[0], ctr_in[1], ctr_in[2], ctr_in[3]};
-    uint64_t k0 = key_in[0], k1 = key_in[1];
+    uint32_t c[4] = {ctr_in[0], ctr_in[1], ctr_in[2], ctr_in[3]};
+    uint32_t k0 = key_in[0], k1 = key_in[1];
     for (int r = 0; r < 10; ++r) {
         if (r > 0) {
-            k0 += 0x9E3779B97F4A7C15ull;
-            k1 += 0xBB67AE8584CAA73Bull;
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
         }
-        const unsigned __int128 p0 = (unsigned __int128)0xD2E7470EE14C6C93ull * c[0];
-        const unsigned __int128 p1 = (unsigned __int128)0xCA5A826395121157ull * c[2];
-        const uint64_t hi0 = (uint64_t)(p0 >> 64), lo0 = (uint64_t)p0;
-        const uint64_t hi1 = (uint64_t)(p1 >> 64), lo1 = (uint64_t)p1;
-        const uint64_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c[0];
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c[2];
+        const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        const uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
         c[0] = n0;
         c[1] = lo1;
         c[2] = n2;
@@ -516,9 +517,9 @@ static void philox4x64_10(const uint64_t ctr_in[4], const uint64_t key_in[2], ui
     out[3] = c[3];
 }
 
-int oracle_philox4x64_10(const uint64_t *ctr, const uint64_t *key, uint64_t *out)
+int oracle_philox4x32_10(const uint32_t *ctr, const uint32_t *key, uint32_t *out)
 {
-    philox4x64_10(ctr, key, out);
+    philox4x32_10(ctr, key, out);
     return OR_OK;
 }
 
@@ -526,12 +527,13 @@ int oracle_philox4x64_10(const uint64_t *ctr, const uint64_t *key, uint64_t *out
 double oracle_su_draw(double mu, double sigma, uint64_t seed, int64_t occ, int32_t elt)
 {
     if (sigma == 0.0) return mu;
-    const uint64_t ctr[4] = {(uint64_t)occ, (uint64_t)(uint32_t)elt, 0, 0};
-    const uint64_t key[2] = {seed, 0};
-    uint64_t w[4];
-    philox4x64_10(ctr, key, w);
-    const double u1 = ((double)(w[0] >> 12) + 0.5) * 0x1p-52;
-    const double u2 = ((double)(w[1] >> 12) + 0.5) * 0x1p-52;
+    const uint32_t ctr[4] = {(uint32_t)(uint64_t)occ, (uint32_t)((uint64_t)occ >> 32), (uint32_t)elt, 0};
+    const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    uint32_t w[4];
+    philox4x32_10(ctr, key, w);
+    const uint64_t b1 = ((uint64_t)w[1] << 32) | w[0], b2 = ((uint64_t)w[3] << 32) | w[2];
+    const double u1 = ((double)(b1 >> 12) + 0.5) * 0x1p-52;
+    const double u2 = ((double)(b2 >> 12) + 0.5) * 0x1p-52;
     const double two_pi = 6.283185307179586476925286766559; /* the binary64 nearest 2 pi */
     const double z = sqrt(-2.0 * log(u1)) * cos(two_pi * u2);
     const double r = sigma / mu;

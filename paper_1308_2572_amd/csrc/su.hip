@@ -11,14 +11,15 @@
 //     lognormal's parameters (m, s), the mean, the ELT's position and index;
 //   * the streaming kernel walks the trial-major YET (the occurrence index
 //     keys the draws, so storage order matters): one wavefront per trial, a
-//     1-Mbit LDS filter of the union, then for each union occurrence the
-//     draws of its entries, the ELT terms (step two) summed in listed order,
-//     the occurrence terms (step three); the trial's occurrence losses meet
-//     in a DPP wavefront sum and the aggregate terms give the year loss (step
-//     four, telescoped).
-// The draw: Philox4x64-10 (Salmon, Moraes, Dror and Shaw, SC'11) block of
-// counter (occurrence, ELT index, 0, 0) under key (seed, 0); uniforms from
-// the top 52 bits of the first two words, Box-Muller, x = exp(m + s z).
+//     1-Mbit LDS filter of the union, a queue of union occurrences drawn 64
+//     at a time: the draws of each one's entries, the ELT terms (step two)
+//     summed in listed order, the occurrence terms (step three); the trial's
+//     occurrence losses meet in a DPP wavefront sum and the aggregate terms
+//     give the year loss (step four, telescoped).
+// The draw: Philox4x32-10 (Salmon, Moraes, Dror and Shaw, SC'11) block of
+// counter words (occurrence low, high, ELT index, 0) under key words (seed
+// low, high); two uniforms from the top 52 bits of the word pairs (w1 w0)
+// and (w3 w2), Box-Muller, x = exp(m + s z).
 #include "occ.h"
 #include "wave.h"
 
@@ -181,18 +182,18 @@ __global__ __launch_bounds__(kSuThreads) void k_su_fill(const float *__restrict_
 // ---------------------------------------------------------------------------
 // The draw.
 
-__device__ __forceinline__ void philox4x64_10(uint64_t c[4], uint64_t k0, uint64_t k1) {
-    constexpr uint64_t kM0 = 0xD2E7470EE14C6C93ull, kM1 = 0xCA5A826395121157ull;
-    constexpr uint64_t kW0 = 0x9E3779B97F4A7C15ull, kW1 = 0xBB67AE8584CAA73Bull;
+__device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
+    constexpr uint32_t kM0 = 0xD2511F53u, kM1 = 0xCD9E8D57u;
+    constexpr uint32_t kW0 = 0x9E3779B9u, kW1 = 0xBB67AE85u;
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
         if (r > 0) {
             k0 += kW0;
             k1 += kW1;
         }
-        const uint64_t hi0 = __umul64hi(kM0, c[0]), lo0 = kM0 * c[0];
-        const uint64_t hi1 = __umul64hi(kM1, c[2]), lo1 = kM1 * c[2];
-        const uint64_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+        const uint32_t hi0 = __umulhi(kM0, c[0]), lo0 = kM0 * c[0];
+        const uint32_t hi1 = __umulhi(kM1, c[2]), lo1 = kM1 * c[2];
+        const uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
         c[0] = n0;
         c[1] = lo1;
         c[2] = n2;
@@ -202,10 +203,12 @@ __device__ __forceinline__ void philox4x64_10(uint64_t c[4], uint64_t k0, uint64
 
 __device__ __forceinline__ double su_draw(const SuEntry &e, uint64_t seed, int64_t occ) {
     if (e.exact) return static_cast<double>(e.mu);
-    uint64_t c[4] = {static_cast<uint64_t>(occ), static_cast<uint64_t>(static_cast<uint32_t>(e.k)), 0ull, 0ull};
-    philox4x64_10(c, seed, 0ull);
-    const double u1 = (static_cast<double>(c[0] >> 12) + 0.5) * 0x1p-52;
-    const double u2 = (static_cast<double>(c[1] >> 12) + 0.5) * 0x1p-52;
+    const uint64_t o = static_cast<uint64_t>(occ);
+    uint32_t c[4] = {static_cast<uint32_t>(o), static_cast<uint32_t>(o >> 32), static_cast<uint32_t>(e.k), 0u};
+    philox4x32_10(c, static_cast<uint32_t>(seed), static_cast<uint32_t>(seed >> 32));
+    const uint64_t b1 = (static_cast<uint64_t>(c[1]) << 32) | c[0], b2 = (static_cast<uint64_t>(c[3]) << 32) | c[2];
+    const double u1 = (static_cast<double>(b1 >> 12) + 0.5) * 0x1p-52;
+    const double u2 = (static_cast<double>(b2 >> 12) + 0.5) * 0x1p-52;
     const double two_pi = 6.283185307179586476925286766559;   // the binary64 nearest 2 pi
     const double z = sqrt(-2.0 * log(u1)) * cos(two_pi * u2);
     return exp(e.m + e.s * z);
@@ -213,8 +216,17 @@ __device__ __forceinline__ double su_draw(const SuEntry &e, uint64_t seed, int64
 
 // ---------------------------------------------------------------------------
 // Streaming kernel: one wavefront per trial.
+//
+// Only ~15% of occurrences belong to the union, so drawing where they fall
+// would leave most lanes idle.  Each wavefront appends its union occurrences
+// (offset in the trial, first entry, entry count) to a queue in LDS as it
+// streams, and whenever 64 are queued they are drawn together, one
+// occurrence per lane; the rest are drawn at the end of the trial.  Each
+// lane sums the losses of the occurrences it drew, in queue order; the
+// trial's total is the wavefront sum of those.
 
-constexpr int kSuSlices = 4;   // 64-occurrence slices per step
+constexpr int kSuSlices = 4;        // 64-occurrence slices per step
+constexpr int kSuQueue = 2 * kWave; // queue capacity: < 64 waiting + one slice
 
 struct SuParams {
     const int64_t *off;
@@ -238,6 +250,9 @@ struct SuParams {
 __global__ __launch_bounds__(kSuThreads) void k_su_fwd(SuParams P) {
     __shared__ uint32_t filt[kFilterWords];
     __shared__ double ls[kSuMaxJ], lr[kSuMaxJ], ll[kSuMaxJ];
+    __shared__ int32_t q_d[kSuThreads / kWave][kSuQueue];     // occurrence's offset in the trial
+    __shared__ uint64_t q_e[kSuThreads / kWave][kSuQueue];    // its first entry
+    __shared__ uint8_t q_n[kSuThreads / kWave][kSuQueue];     // its number of entries
     const int j = blockIdx.y, tid = threadIdx.x, lane = tid & 63;
     const int a0 = P.elt_off[j], J = P.elt_off[j + 1] - a0;
     for (int q = tid; q < J; q += blockDim.x) {
@@ -249,6 +264,9 @@ __global__ __launch_bounds__(kSuThreads) void k_su_fwd(SuParams P) {
     for (int i = tid; i < kFilterWords; i += blockDim.x) filt[i] = P.filter[static_cast<size_t>(j) * kFilterWords + i];
     __syncthreads();
     const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+    int32_t *qd = q_d[wv];
+    uint64_t *qe = q_e[wv];
+    uint8_t *qn = q_n[wv];
     const int64_t nw = static_cast<int64_t>(gridDim.x) * (kSuThreads / kWave);
     const OccTables T = P.tabs[j];
     const uint32_t *eo = P.eoff + static_cast<size_t>(j) * P.n_sr * kSr;
@@ -264,42 +282,100 @@ __global__ __launch_bounds__(kSuThreads) void k_su_fwd(SuParams P) {
             if (lane == 0) atomicCAS(P.err, 0, ARA_E_RANGE);
             b = a;
         }
-        double acc = 0.0;   // this lane's occurrence losses, in its order
-        for (int64_t base = a; base < b; base += kSuSlices * kWave) {
-            int32_t ev[kSuSlices];
-#pragma unroll
-            for (int k = 0; k < kSuSlices; ++k) {
-                const int64_t i = base + k * kWave + lane;
-                ev[k] = (i < b) ? P.ids[i] : -1;
-            }
-#pragma unroll
-            for (int k = 0; k < kSuSlices; ++k) {
-                const int64_t i = base + k * kWave + lane;
-                const int32_t e = ev[k];
-                if (i >= b) continue;
-                if (e < 0 || e >= P.catalog) {
-                    atomicCAS(P.err, 0, ARA_E_RANGE);
-                    continue;
-                }
-                if (!((filt[(static_cast<uint32_t>(e) >> 5) & (kFilterWords - 1)] >> (e & 31)) & 1u)) continue;
-                const uint2 w = T.br[static_cast<uint32_t>(e) >> 5];
-                const uint32_t bit = e & 31;
-                if (!((w.x >> bit) & 1u)) continue;
-                const uint32_t sr = static_cast<uint32_t>(e) >> kSrBits;
-                const uint32_t r = w.y + __popc(w.x & ((1u << bit) - 1u));
-                const int nb = T.cnt[static_cast<size_t>(sr) * kSr + r];
-                const SuEntry *pe = E + eb[sr] + eo[static_cast<size_t>(sr) * kSr + r];
-                // steps one and two for each ELT holding the event, summed in
-                // listed order; step three
+        double acc = 0.0;   // losses of the occurrences this lane drew, in queue order
+        int qlen = 0;       // uniform
+        // draws for queue entries [0, cnt), one per lane: steps one to three
+        auto drain = [&](int cnt) {
+            if (lane < cnt) {
+                const int64_t i = a + qd[lane];
+                const SuEntry *pe = E + qe[lane];
+                const int nb = qn[lane];
                 double x = 0.0;
                 for (int h = 0; h < nb; ++h) {
                     const SuEntry en = pe[h];
                     const double v = su_draw(en, P.seed, i);
-                    x = x + xl(ls[en.q] * v, lr[en.q], ll[en.q]);
+                    x = x + xl(ls[en.q] * v, lr[en.q], ll[en.q]);   // the ELTs in listed order
                 }
                 acc += xl(x, occR, occL);
             }
+        };
+        for (int64_t base = a; base < b; base += kSuSlices * kWave) {
+            // the step's IDs, then the bitmap words of its maybe-set events
+            // and then the counts and first entries of its set events, each
+            // round trip shared by all the step's slices
+            int32_t ev[kSuSlices];
+            bool in[kSuSlices];
+#pragma unroll
+            for (int k = 0; k < kSuSlices; ++k) {
+                const int64_t i = base + k * kWave + lane;
+                in[k] = i < b;
+                ev[k] = in[k] ? P.ids[i] : 0;
+            }
+            uint2 w[kSuSlices];
+#pragma unroll
+            for (int k = 0; k < kSuSlices; ++k) {
+                const int32_t e = ev[k];
+                if (in[k] && (e < 0 || e >= P.catalog)) {
+                    atomicCAS(P.err, 0, ARA_E_RANGE);
+                    in[k] = false;
+                }
+                const bool maybe = in[k] && ((filt[(static_cast<uint32_t>(e) >> 5) & (kFilterWords - 1)] >> (e & 31)) & 1u);
+                w[k] = make_uint2(0u, 0u);
+                if (maybe) w[k] = T.br[static_cast<uint32_t>(e) >> 5];
+            }
+            int nbk[kSuSlices];
+            uint64_t fk[kSuSlices];
+#pragma unroll
+            for (int k = 0; k < kSuSlices; ++k) {
+                const uint32_t e = static_cast<uint32_t>(ev[k]), bit = e & 31;
+                nbk[k] = 0;
+                fk[k] = 0;
+                if ((w[k].x >> bit) & 1u) {
+                    const uint32_t sr = e >> kSrBits;
+                    const uint32_t r = w[k].y + __popc(w[k].x & ((1u << bit) - 1u));
+                    nbk[k] = T.cnt[static_cast<size_t>(sr) * kSr + r];
+                    fk[k] = eb[sr] + eo[static_cast<size_t>(sr) * kSr + r];
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < kSuSlices; ++k) {
+                // append this slice's union occurrences, in slice order
+                const bool u = nbk[k] > 0;
+                const uint64_t m = __ballot(u);
+                if (u) {
+                    const int pos = qlen + static_cast<int>(__builtin_amdgcn_mbcnt_hi(
+                                               static_cast<uint32_t>(m >> 32),
+                                               __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(m), 0u)));
+                    qd[pos] = static_cast<int32_t>(base - a) + k * kWave + lane;
+                    qe[pos] = fk[k];
+                    qn[pos] = static_cast<uint8_t>(nbk[k]);
+                }
+                qlen += __popcll(m);
+                __builtin_amdgcn_wave_barrier();
+                if (qlen >= kWave) {
+                    drain(kWave);
+                    // move the rest (< 64) to the front
+                    const int rest = qlen - kWave;
+                    int32_t d2 = 0;
+                    uint64_t e2 = 0;
+                    uint8_t n2 = 0;
+                    if (lane < rest) {
+                        d2 = qd[kWave + lane];
+                        e2 = qe[kWave + lane];
+                        n2 = qn[kWave + lane];
+                    }
+                    __builtin_amdgcn_wave_barrier();
+                    if (lane < rest) {
+                        qd[lane] = d2;
+                        qe[lane] = e2;
+                        qn[lane] = n2;
+                    }
+                    __builtin_amdgcn_wave_barrier();
+                    qlen = rest;
+                }
+            }
         }
+        drain(qlen);
         // step four, telescoped: the aggregate terms on the trial's total
         const double S = lane63(wave_inclusive_sum(acc));
         if (lane == 0) {
@@ -307,6 +383,7 @@ __global__ __launch_bounds__(kSuThreads) void k_su_fwd(SuParams P) {
             P.ylt[o] = xl(S, aggR, aggL);
             if (P.s_pre) P.s_pre[o] = S;
         }
+        __builtin_amdgcn_wave_barrier();
     }
 }
 

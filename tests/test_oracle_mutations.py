@@ -110,28 +110,29 @@ def _battery():
 
 
 SU_MUTATIONS = {
-    "su-philox-multiplier": ("(unsigned __int128)0xD2E7470EE14C6C93ull * c[0]",
-                             "(unsigned __int128)0xD2E7470EE14C6C95ull * c[0]"),
-    "su-philox-key-bump": ("k1 += 0xBB67AE8584CAA73Bull;", "k1 += 0xBB67AE8584CAA73Aull;"),
+    "su-philox-multiplier": ("(uint64_t)0xD2511F53u * c[0]", "(uint64_t)0xD2511F55u * c[0]"),
+    "su-philox-key-bump": ("k1 += 0xBB67AE85u;", "k1 += 0xBB67AE84u;"),
     "su-philox-word-order": ("c[1] = lo1;\n        c[2] = n2;", "c[1] = n2;\n        c[2] = lo1;"),
     "su-no-half-variance": ("const double m = log(mu) - 0.5 * s2;", "const double m = log(mu);"),
     "su-sigma-not-relative": ("const double r = sigma / mu;", "const double r = sigma;"),
-    "su-draw-ignores-elt": ("(uint64_t)(uint32_t)elt, 0, 0};", "0, 0, 0};"),
+    "su-draw-ignores-elt": ("(uint32_t)((uint64_t)occ >> 32), (uint32_t)elt, 0};",
+                            "(uint32_t)((uint64_t)occ >> 32), 0, 0};"),
     "su-sigma-zero-not-special": ("if (sigma == 0.0) return mu;", "if (sigma < 0.0) return mu;"),
     "su-lookup-not-drawn": ("? oracle_su_draw(mu, (double)sig[ev[d]], seed, offsets[b] + d, k) : 0.0;",
                             "? mu : 0.0;"),
-    "su-same-uniform-twice": ("const double u2 = ((double)(w[1] >> 12) + 0.5) * 0x1p-52;",
-                              "const double u2 = ((double)(w[0] >> 12) + 0.5) * 0x1p-52;"),
+    "su-same-uniform-twice": ("const double u2 = ((double)(b2 >> 12) + 0.5) * 0x1p-52;",
+                              "const double u2 = ((double)(b1 >> 12) + 0.5) * 0x1p-52;"),
+    "su-high-word-dropped": ("const uint64_t b1 = ((uint64_t)w[1] << 32) | w[0]", "const uint64_t b1 = (uint64_t)w[0]"),
 }
 
 
 def _battery_su():
     """True iff every pin of the secondary-uncertainty path holds (small
     versions of tests/test_oracle_su.py)."""
-    for key, ctr in [((12345, 0), (8, 0, 0, 0)), ((0x0123456789ABCDEF, 0xFEDCBA9876543210), (6, 3, 0, 0))]:
-        start = np.array([ctr[0] - 1, ctr[1], ctr[2], ctr[3]], dtype=np.uint64)
-        ref = np.random.Philox(key=np.array(key, dtype=np.uint64), counter=start).random_raw(4)
-        if oracle.philox4x64_10(np.array(ctr, np.uint64), np.array(key, np.uint64)).tolist() != [int(v) for v in ref]:
+    for ctr, key, want in [((0, 0, 0, 0), (0, 0), (0x6627E8D5, 0xE169C58D, 0xBC57AC4C, 0x9B00DBD8)),
+                           ((0x243F6A88, 0x85A308D3, 0x13198A2E, 0x03707344), (0xA4093822, 0x299F31D0),
+                            (0xD16CFE09, 0x94FDCCEB, 0x5001E420, 0x24126EA1))]:
+        if oracle.philox4x32_10(np.array(ctr, np.uint32), np.array(key, np.uint32)).tolist() != list(want):
             return False
     w = synth.tiny_random(1, n_trials=30, max_events=12, n_layers=2)
     tb = oracle.build_tables(w.elts)
