@@ -31,14 +31,19 @@ namespace ara {
 constexpr int kSuThreads = 1024;
 constexpr int kSuMaxJ = ARA_MAX_ELTS_PER_LAYER;
 constexpr int kSuScanPer = kSr / kSuThreads;   // 64 ranks per thread in the count scan
+constexpr int kSuMaxSr = (ARA_MAX_CATALOG + kSr - 1) / kSr;   // super-ranges of the largest catalogue
 
-// One (union event, ELT of the layer) pair; 32 bytes.
+// One (union event, ELT of the layer) pair; 32 bytes.  The first ELT (in
+// listed order) holding a union event has its entry at the event's union
+// rank; the others follow at `next`, contiguous.
 struct SuEntry {
     double m, s;       // lognormal parameters of the draw
     float mu;          // the record's mean loss
-    int32_t q;         // the ELT's position in the layer's list
     int32_t k;         // the ELT's index (keys the draw)
-    int32_t exact;     // sigma = 0: the draw is mu itself
+    uint32_t next;     // first of the event's further entries (first entry only)
+    uint16_t q;        // the ELT's position in the layer's list
+    uint8_t exact;     // sigma = 0: the draw is mu itself
+    uint8_t more;      // number of further entries (first entry only)
 };
 static_assert(sizeof(SuEntry) == 32, "entry layout");
 
@@ -58,19 +63,20 @@ __global__ void k_sigma_scatter(const int64_t *__restrict__ rec_off, const int32
 // ---------------------------------------------------------------------------
 // Entry layout.
 
-// Per (super-range, layer): exclusive scan of the union events' ELT counts
-// in rank order -> eoff (relative to the super-range), total -> etot.
+// Per (super-range, layer): exclusive scan, in rank order, of the number of
+// further entries of each union event (its ELT count less one) -> ooff
+// (relative to the super-range), total -> otot.
 __global__ __launch_bounds__(kSuThreads) void k_su_scan(const OccTables *__restrict__ tabs, int n_sr,
-                                                        uint32_t *__restrict__ eoff, uint32_t *__restrict__ etot) {
+                                                        uint32_t *__restrict__ ooff, uint32_t *__restrict__ otot) {
     __shared__ uint32_t wsum[kSuThreads / kWave];
     const int s = blockIdx.x, j = blockIdx.y, tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const OccTables T = tabs[j];
     const int cnt_s = T.count[s];
     const uint8_t *c = T.cnt + static_cast<size_t>(s) * kSr;
-    uint32_t *eo = eoff + (static_cast<size_t>(j) * n_sr + s) * kSr;
+    uint32_t *oo = ooff + (static_cast<size_t>(j) * n_sr + s) * kSr;
     const int r0 = tid * kSuScanPer;
     uint32_t mine = 0;
-    for (int r = r0; r < min(r0 + kSuScanPer, cnt_s); ++r) mine += c[r];
+    for (int r = r0; r < min(r0 + kSuScanPer, cnt_s); ++r) mine += c[r] - 1u;
     uint32_t incl = mine;
     for (int o = 1; o < kWave; o <<= 1) {
         const uint32_t v = __shfl_up(incl, o);
@@ -81,41 +87,58 @@ __global__ __launch_bounds__(kSuThreads) void k_su_scan(const OccTables *__restr
     uint32_t before = incl - mine;
     for (int i = 0; i < w; ++i) before += wsum[i];
     for (int r = r0; r < min(r0 + kSuScanPer, cnt_s); ++r) {
-        eo[r] = before;
-        before += c[r];
+        oo[r] = before;
+        before += c[r] - 1u;
     }
-    if (tid == kSuThreads - 1) etot[static_cast<size_t>(j) * n_sr + s] = before;
+    if (tid == kSuThreads - 1) otot[static_cast<size_t>(j) * n_sr + s] = before;
 }
 
-// Per layer: super-range bases (exclusive scan of etot); the layer's total
-// must fit its entry capacity.
-__global__ __launch_bounds__(kSuThreads) void k_su_base(const uint32_t *__restrict__ etot, int n_sr,
-                                                        const uint64_t *__restrict__ ecap,
-                                                        uint64_t *__restrict__ ebase, int32_t *__restrict__ err) {
-    __shared__ uint64_t wsum[kSuThreads / kWave];
-    const int j = blockIdx.x, tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const uint32_t *et = etot + static_cast<size_t>(j) * n_sr;
-    uint64_t *eb = ebase + static_cast<size_t>(j) * (n_sr + 1);
-    const int per = (n_sr + kSuThreads - 1) / kSuThreads;
+// Exclusive scan of n values of one workgroup (n up to a few thousand).
+template <class T>
+__device__ T block_exclusive_scan(const T *in, T *out, int n, T *wsum) {
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int per = (n + kSuThreads - 1) / kSuThreads;
     const int s0 = tid * per;
-    uint64_t mine = 0;
-    for (int s = s0; s < min(s0 + per, n_sr); ++s) mine += et[s];
-    uint64_t incl = mine;
+    T mine = 0;
+    for (int s = s0; s < min(s0 + per, n); ++s) mine += in[s];
+    T incl = mine;
     for (int o = 1; o < kWave; o <<= 1) {
-        const uint64_t v = __shfl_up(incl, o);
+        const T v = __shfl_up(incl, o);
         if (lane >= o) incl += v;
     }
     if (lane == kWave - 1) wsum[w] = incl;
     __syncthreads();
-    uint64_t before = incl - mine;
+    T before = incl - mine;
     for (int i = 0; i < w; ++i) before += wsum[i];
-    for (int s = s0; s < min(s0 + per, n_sr); ++s) {
-        eb[s] = before;
-        before += et[s];
+    for (int s = s0; s < min(s0 + per, n); ++s) {
+        out[s] = before;
+        before += in[s];
     }
-    if (tid == kSuThreads - 1) {
-        eb[n_sr] = before;
-        if (before > ecap[j]) atomicCAS(err, 0, ARA_E_LIMIT);
+    __syncthreads();
+    T total = 0;
+    for (int i = 0; i < kSuThreads / kWave; ++i) total += wsum[i];
+    __syncthreads();
+    return total;
+}
+
+// Per layer: union-rank bases of the super-ranges (ubase, from the
+// occurrence table's counts) and bases of their further entries (obase,
+// after all first entries); every entry must fit the layer's capacity.
+__global__ __launch_bounds__(kSuThreads) void k_su_base(const OccTables *__restrict__ tabs, const uint32_t *__restrict__ otot,
+                                                        int n_sr, const uint64_t *__restrict__ ecap,
+                                                        uint32_t *__restrict__ ubase, uint32_t *__restrict__ obase,
+                                                        int32_t *__restrict__ err) {
+    __shared__ uint32_t wsum[kSuThreads / kWave];
+    const int j = blockIdx.x;
+    const OccTables T = tabs[j];
+    uint32_t *ub = ubase + static_cast<size_t>(j) * (n_sr + 1);
+    uint32_t *ob = obase + static_cast<size_t>(j) * n_sr;
+    const uint32_t n_union = block_exclusive_scan<uint32_t>(reinterpret_cast<const uint32_t *>(T.count), ub, n_sr, wsum);
+    const uint32_t n_more = block_exclusive_scan<uint32_t>(otot + static_cast<size_t>(j) * n_sr, ob, n_sr, wsum);
+    for (int s = threadIdx.x; s < n_sr; s += blockDim.x) ob[s] += n_union;
+    if (threadIdx.x == 0) {
+        ub[n_sr] = n_union;
+        if (static_cast<uint64_t>(n_union) + n_more > ecap[j]) atomicCAS(err, 0, ARA_E_LIMIT);
     }
 }
 
@@ -129,8 +152,9 @@ __global__ __launch_bounds__(kSuThreads) void k_su_fill(const float *__restrict_
                                                         int32_t words, const int32_t *__restrict__ elt_off,
                                                         const int32_t *__restrict__ elt_ids,
                                                         const OccTables *__restrict__ tabs, int n_sr,
-                                                        const uint32_t *__restrict__ eoff,
-                                                        const uint64_t *__restrict__ ebase,
+                                                        const uint32_t *__restrict__ ooff,
+                                                        const uint32_t *__restrict__ ubase,
+                                                        const uint32_t *__restrict__ obase,
                                                         const uint64_t *__restrict__ ecap,
                                                         const uint64_t *__restrict__ eregion,
                                                         SuEntry *__restrict__ ent) {
@@ -141,10 +165,13 @@ __global__ __launch_bounds__(kSuThreads) void k_su_fill(const float *__restrict_
     for (int q = tid; q < J; q += blockDim.x) lk[q] = elt_ids[a + q];
     __syncthreads();
     const OccTables T = tabs[j];
-    const uint64_t base_s = ebase[static_cast<size_t>(j) * (n_sr + 1) + s];
     const uint64_t cap = ecap[j];
+    const uint32_t ub = ubase[static_cast<size_t>(j) * (n_sr + 1) + s];
+    const uint32_t n_union = ubase[static_cast<size_t>(j) * (n_sr + 1) + n_sr];
+    const uint32_t ob = obase[static_cast<size_t>(j) * n_sr + s];
+    if (n_union > cap) return;   // flagged by k_su_base
     SuEntry *E = ent + eregion[j];
-    const uint32_t *eo = eoff + (static_cast<size_t>(j) * n_sr + s) * kSr;
+    const uint32_t *oo = ooff + (static_cast<size_t>(j) * n_sr + s) * kSr;
     for (int it = 0; it < 4; ++it) {
         const int local = p * (kSuFillWords * 32) + it * kSuThreads + tid;   // event within the super-range
         const int64_t ev = static_cast<int64_t>(s) * kSr + local;
@@ -153,7 +180,11 @@ __global__ __launch_bounds__(kSuThreads) void k_su_fill(const float *__restrict_
         const int bit = local & 31;
         if (!((q2.x >> bit) & 1u)) continue;
         const uint32_t r = q2.y + __popc(q2.x & ((1u << bit) - 1u));
-        uint64_t o = base_s + eo[r];
+        const uint32_t nb = T.cnt[static_cast<size_t>(s) * kSr + r];
+        const uint64_t first = static_cast<uint64_t>(ub) + r;
+        const uint64_t next = static_cast<uint64_t>(ob) + oo[r];
+        uint64_t o = first;
+        int h = 0;
         for (int q = 0; q < J; ++q) {
             const int k = lk[q];
             if (!((present[static_cast<size_t>(k) * words + (ev >> 5)] >> (ev & 31)) & 1u)) continue;
@@ -162,9 +193,11 @@ __global__ __launch_bounds__(kSuThreads) void k_su_fill(const float *__restrict_
             const float sg = sigma[static_cast<size_t>(k) * catalog + ev];
             SuEntry e;
             e.mu = mu;
-            e.q = q;
             e.k = k;
+            e.q = static_cast<uint16_t>(q);
             e.exact = (sg == 0.0f) ? 1 : 0;
+            e.next = h == 0 ? static_cast<uint32_t>(next) : 0u;
+            e.more = h == 0 ? static_cast<uint8_t>(nb - 1) : 0;
             if (e.exact) {
                 e.m = 0.0;
                 e.s = 0.0;
@@ -174,7 +207,9 @@ __global__ __launch_bounds__(kSuThreads) void k_su_fill(const float *__restrict_
                 e.m = log(static_cast<double>(mu)) - 0.5 * s2;
                 e.s = sqrt(s2);
             }
-            E[o++] = e;
+            E[o] = e;
+            o = (h == 0) ? next : o + 1;
+            ++h;
         }
     }
 }
@@ -236,8 +271,7 @@ struct SuParams {
     int64_t occ_begin, occ_count;
     const OccTables *tabs;
     const uint32_t *filter;      // [n_layers][kFilterWords]
-    const uint32_t *eoff;        // [n_layers][n_sr][kSr]
-    const uint64_t *ebase;       // [n_layers][n_sr + 1]
+    const uint32_t *ubase;       // [n_layers][n_sr + 1] union-rank bases of the super-ranges
     const uint64_t *eregion;     // [n_layers]
     const SuEntry *ent;
     const int32_t *elt_off, *elt_ids;
@@ -251,8 +285,8 @@ __global__ __launch_bounds__(kSuThreads) void k_su_fwd(SuParams P) {
     __shared__ uint32_t filt[kFilterWords];
     __shared__ double ls[kSuMaxJ], lr[kSuMaxJ], ll[kSuMaxJ];
     __shared__ int32_t q_d[kSuThreads / kWave][kSuQueue];     // occurrence's offset in the trial
-    __shared__ uint64_t q_e[kSuThreads / kWave][kSuQueue];    // its first entry
-    __shared__ uint8_t q_n[kSuThreads / kWave][kSuQueue];     // its number of entries
+    __shared__ uint32_t q_e[kSuThreads / kWave][kSuQueue];    // its event's union rank = its first entry
+    __shared__ uint32_t ub_s[kSuMaxSr + 1];                   // the layer's union-rank bases
     const int j = blockIdx.y, tid = threadIdx.x, lane = tid & 63;
     const int a0 = P.elt_off[j], J = P.elt_off[j + 1] - a0;
     for (int q = tid; q < J; q += blockDim.x) {
@@ -262,15 +296,13 @@ __global__ __launch_bounds__(kSuThreads) void k_su_fwd(SuParams P) {
         ll[q] = P.elt_terms[3 * k + 2];
     }
     for (int i = tid; i < kFilterWords; i += blockDim.x) filt[i] = P.filter[static_cast<size_t>(j) * kFilterWords + i];
+    for (int i = tid; i <= P.n_sr; i += blockDim.x) ub_s[i] = P.ubase[static_cast<size_t>(j) * (P.n_sr + 1) + i];
     __syncthreads();
     const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
     int32_t *qd = q_d[wv];
-    uint64_t *qe = q_e[wv];
-    uint8_t *qn = q_n[wv];
+    uint32_t *qe = q_e[wv];
     const int64_t nw = static_cast<int64_t>(gridDim.x) * (kSuThreads / kWave);
     const OccTables T = P.tabs[j];
-    const uint32_t *eo = P.eoff + static_cast<size_t>(j) * P.n_sr * kSr;
-    const uint64_t *eb = P.ebase + static_cast<size_t>(j) * (P.n_sr + 1);
     const SuEntry *E = P.ent + P.eregion[j];
     const double occR = P.layer_terms[4 * j + 0], occL = P.layer_terms[4 * j + 1];
     const double aggR = P.layer_terms[4 * j + 2], aggL = P.layer_terms[4 * j + 3];
@@ -288,13 +320,16 @@ __global__ __launch_bounds__(kSuThreads) void k_su_fwd(SuParams P) {
         auto drain = [&](int cnt) {
             if (lane < cnt) {
                 const int64_t i = a + qd[lane];
-                const SuEntry *pe = E + qe[lane];
-                const int nb = qn[lane];
+                const SuEntry first = E[qe[lane]];
                 double x = 0.0;
-                for (int h = 0; h < nb; ++h) {
-                    const SuEntry en = pe[h];
+                {
+                    const double v = su_draw(first, P.seed, i);
+                    x = x + xl(ls[first.q] * v, lr[first.q], ll[first.q]);
+                }
+                for (int h = 0; h < first.more; ++h) {   // the further ELTs, in listed order
+                    const SuEntry en = E[first.next + h];
                     const double v = su_draw(en, P.seed, i);
-                    x = x + xl(ls[en.q] * v, lr[en.q], ll[en.q]);   // the ELTs in listed order
+                    x = x + xl(ls[en.q] * v, lr[en.q], ll[en.q]);
                 }
                 acc += xl(x, occR, occL);
             }
@@ -323,32 +358,24 @@ __global__ __launch_bounds__(kSuThreads) void k_su_fwd(SuParams P) {
                 w[k] = make_uint2(0u, 0u);
                 if (maybe) w[k] = T.br[static_cast<uint32_t>(e) >> 5];
             }
-            int nbk[kSuSlices];
-            uint64_t fk[kSuSlices];
+            uint32_t gr[kSuSlices];   // union rank (first entry) of each set event
+            bool u[kSuSlices];
 #pragma unroll
             for (int k = 0; k < kSuSlices; ++k) {
                 const uint32_t e = static_cast<uint32_t>(ev[k]), bit = e & 31;
-                nbk[k] = 0;
-                fk[k] = 0;
-                if ((w[k].x >> bit) & 1u) {
-                    const uint32_t sr = e >> kSrBits;
-                    const uint32_t r = w[k].y + __popc(w[k].x & ((1u << bit) - 1u));
-                    nbk[k] = T.cnt[static_cast<size_t>(sr) * kSr + r];
-                    fk[k] = eb[sr] + eo[static_cast<size_t>(sr) * kSr + r];
-                }
+                u[k] = ((w[k].x >> bit) & 1u) != 0u;
+                gr[k] = ub_s[e >> kSrBits] + w[k].y + __popc(w[k].x & ((1u << bit) - 1u));
             }
 #pragma unroll
             for (int k = 0; k < kSuSlices; ++k) {
                 // append this slice's union occurrences, in slice order
-                const bool u = nbk[k] > 0;
-                const uint64_t m = __ballot(u);
-                if (u) {
+                const uint64_t m = __ballot(u[k]);
+                if (u[k]) {
                     const int pos = qlen + static_cast<int>(__builtin_amdgcn_mbcnt_hi(
                                                static_cast<uint32_t>(m >> 32),
                                                __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(m), 0u)));
                     qd[pos] = static_cast<int32_t>(base - a) + k * kWave + lane;
-                    qe[pos] = fk[k];
-                    qn[pos] = static_cast<uint8_t>(nbk[k]);
+                    qe[pos] = gr[k];
                 }
                 qlen += __popcll(m);
                 __builtin_amdgcn_wave_barrier();
@@ -357,18 +384,15 @@ __global__ __launch_bounds__(kSuThreads) void k_su_fwd(SuParams P) {
                     // move the rest (< 64) to the front
                     const int rest = qlen - kWave;
                     int32_t d2 = 0;
-                    uint64_t e2 = 0;
-                    uint8_t n2 = 0;
+                    uint32_t e2 = 0;
                     if (lane < rest) {
                         d2 = qd[kWave + lane];
                         e2 = qe[kWave + lane];
-                        n2 = qn[kWave + lane];
                     }
                     __builtin_amdgcn_wave_barrier();
                     if (lane < rest) {
                         qd[lane] = d2;
                         qe[lane] = e2;
-                        qn[lane] = n2;
                     }
                     __builtin_amdgcn_wave_barrier();
                     qlen = rest;
@@ -428,9 +452,10 @@ static size_t su_workspace(const ara_tables *tables, const ara_layers *layers, c
     c.take<uint64_t>(static_cast<size_t>(std::max(L, 1)));   // regions
     size_t b = c.bytes();
     b += static_cast<size_t>(L) * S.z.per_layer;
-    b += align256(static_cast<size_t>(L) * n_sr * kSr * sizeof(uint32_t));            // eoff
-    b += align256(static_cast<size_t>(std::max(L, 1)) * n_sr * sizeof(uint32_t));     // etot
-    b += align256(static_cast<size_t>(std::max(L, 1)) * (n_sr + 1) * sizeof(uint64_t));   // ebase
+    b += align256(static_cast<size_t>(L) * n_sr * kSr * sizeof(uint32_t));            // ooff
+    b += align256(static_cast<size_t>(std::max(L, 1)) * n_sr * sizeof(uint32_t));     // otot
+    b += align256(static_cast<size_t>(std::max(L, 1)) * (n_sr + 1) * sizeof(uint32_t));   // ubase
+    b += align256(static_cast<size_t>(std::max(L, 1)) * n_sr * sizeof(uint32_t));     // obase
     b += align256(static_cast<size_t>(std::max(L, 1)) * kFilterWords * sizeof(uint32_t));
     b += align256(static_cast<size_t>(std::max<uint64_t>(S.n_ent, 1)) * sizeof(SuEntry));
     return b;
@@ -525,9 +550,10 @@ extern "C" int32_t ara_ylt_forward_su(const ara_tables *tables, const float *sig
     uint64_t *d_region = c.take<uint64_t>(static_cast<size_t>(L));
     std::vector<OccTables> tabs(static_cast<size_t>(L));
     for (int j = 0; j < L; ++j) tabs[j] = occ_carve(c, S.z, true);
-    uint32_t *eoff = c.take<uint32_t>(static_cast<size_t>(L) * n_sr * kSr);
-    uint32_t *etot = c.take<uint32_t>(static_cast<size_t>(L) * n_sr);
-    uint64_t *ebase = c.take<uint64_t>(static_cast<size_t>(L) * (n_sr + 1));
+    uint32_t *ooff = c.take<uint32_t>(static_cast<size_t>(L) * n_sr * kSr);
+    uint32_t *otot = c.take<uint32_t>(static_cast<size_t>(L) * n_sr);
+    uint32_t *ubase = c.take<uint32_t>(static_cast<size_t>(L) * (n_sr + 1));
+    uint32_t *obase = c.take<uint32_t>(static_cast<size_t>(L) * n_sr);
     uint32_t *filter = c.take<uint32_t>(static_cast<size_t>(L) * kFilterWords);
     SuEntry *ent = c.take<SuEntry>(static_cast<size_t>(std::max<uint64_t>(S.n_ent, 1)));
     HeadImage img(ws);
@@ -544,11 +570,11 @@ extern "C" int32_t ara_ylt_forward_su(const ara_tables *tables, const float *sig
         if ((rc = launch_occ(tables, d_off, d_ids, elt_terms, layer_terms, L, true, d_tabs, n_sr, d_err, st)))
             return rc;
         k_su_scan<<<dim3(static_cast<unsigned>(n_sr), static_cast<unsigned>(L)), kSuThreads, 0, st>>>(d_tabs, n_sr,
-                                                                                                    eoff, etot);
-        k_su_base<<<static_cast<unsigned>(L), kSuThreads, 0, st>>>(etot, n_sr, d_cap, ebase, d_err);
+                                                                                                    ooff, otot);
+        k_su_base<<<static_cast<unsigned>(L), kSuThreads, 0, st>>>(d_tabs, otot, n_sr, d_cap, ubase, obase, d_err);
         k_su_fill<<<dim3(static_cast<unsigned>(n_sr * kSuFillChunks), static_cast<unsigned>(L)), kSuThreads, 0, st>>>(
-            tables->loss, sigma, tables->present, tables->catalog, tables->words, d_off, d_ids, d_tabs, n_sr, eoff,
-            ebase, d_cap, d_region, ent);
+            tables->loss, sigma, tables->present, tables->catalog, tables->words, d_off, d_ids, d_tabs, n_sr, ooff,
+            ubase, obase, d_cap, d_region, ent);
         ARA_HIP(hipGetLastError());
         if ((rc = launch_set_filter(d_tabs, n_sr * kSrWords, filter, L, st))) return rc;
     }
@@ -563,8 +589,7 @@ extern "C" int32_t ara_ylt_forward_su(const ara_tables *tables, const float *sig
     P.occ_count = occ_count;
     P.tabs = d_tabs;
     P.filter = filter;
-    P.eoff = eoff;
-    P.ebase = ebase;
+    P.ubase = ubase;
     P.eregion = d_region;
     P.ent = ent;
     P.elt_off = d_off;
