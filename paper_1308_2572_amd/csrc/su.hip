@@ -127,7 +127,7 @@ __device__ T block_exclusive_scan(const T *in, T *out, int n, T *wsum) {
 __global__ __launch_bounds__(kSuThreads) void k_su_base(const OccTables *__restrict__ tabs, const uint32_t *__restrict__ otot,
                                                         int n_sr, const uint64_t *__restrict__ ecap,
                                                         uint32_t *__restrict__ ubase, uint32_t *__restrict__ obase,
-                                                        int32_t *__restrict__ err) {
+                                                        uint64_t *__restrict__ eused, int32_t *__restrict__ err) {
     __shared__ uint32_t wsum[kSuThreads / kWave];
     const int j = blockIdx.x;
     const OccTables T = tabs[j];
@@ -138,7 +138,8 @@ __global__ __launch_bounds__(kSuThreads) void k_su_base(const OccTables *__restr
     for (int s = threadIdx.x; s < n_sr; s += blockDim.x) ob[s] += n_union;
     if (threadIdx.x == 0) {
         ub[n_sr] = n_union;
-        if (static_cast<uint64_t>(n_union) + n_more > ecap[j]) atomicCAS(err, 0, ARA_E_LIMIT);
+        eused[j] = static_cast<uint64_t>(n_union) + n_more;
+        if (eused[j] > ecap[j]) atomicCAS(err, 0, ARA_E_LIMIT);
     }
 }
 
@@ -273,6 +274,8 @@ struct SuParams {
     const uint32_t *filter;      // [n_layers][kFilterWords]
     const uint32_t *ubase;       // [n_layers][n_sr + 1] union-rank bases of the super-ranges
     const uint64_t *eregion;     // [n_layers]
+    const uint64_t *ecap;        // [n_layers] entries allocated
+    const uint64_t *eused;       // [n_layers] entries the layer needs
     const SuEntry *ent;
     const int32_t *elt_off, *elt_ids;
     const double *elt_terms, *layer_terms;
@@ -288,6 +291,10 @@ __global__ __launch_bounds__(kSuThreads) void k_su_fwd(SuParams P) {
     __shared__ uint32_t q_e[kSuThreads / kWave][kSuQueue];    // its event's union rank = its first entry
     __shared__ uint32_t ub_s[kSuMaxSr + 1];                   // the layer's union-rank bases
     const int j = blockIdx.y, tid = threadIdx.x, lane = tid & 63;
+    // a layer whose entries did not fit its capacity has none laid out (the
+    // call reports ARA_E_LIMIT): nothing of it is read or written
+    const uint64_t cap = P.ecap[j];
+    if (P.eused[j] > cap) return;
     const int a0 = P.elt_off[j], J = P.elt_off[j + 1] - a0;
     for (int q = tid; q < J; q += blockDim.x) {
         const int k = P.elt_ids[a0 + q];
@@ -318,7 +325,7 @@ __global__ __launch_bounds__(kSuThreads) void k_su_fwd(SuParams P) {
         int qlen = 0;       // uniform
         // draws for queue entries [0, cnt), one per lane: steps one to three
         auto drain = [&](int cnt) {
-            if (lane < cnt) {
+            if (lane < cnt && qe[lane] < cap) {
                 const int64_t i = a + qd[lane];
                 const SuEntry first = E[qe[lane]];
                 double x = 0.0;
@@ -326,7 +333,8 @@ __global__ __launch_bounds__(kSuThreads) void k_su_fwd(SuParams P) {
                     const double v = su_draw(first, P.seed, i);
                     x = x + xl(ls[first.q] * v, lr[first.q], ll[first.q]);
                 }
-                for (int h = 0; h < first.more; ++h) {   // the further ELTs, in listed order
+                const int more = static_cast<uint64_t>(first.next) + first.more <= cap ? first.more : 0;
+                for (int h = 0; h < more; ++h) {   // the further ELTs, in listed order
                     const SuEntry en = E[first.next + h];
                     const double v = su_draw(en, P.seed, i);
                     x = x + xl(ls[en.q] * v, lr[en.q], ll[en.q]);
@@ -363,8 +371,8 @@ __global__ __launch_bounds__(kSuThreads) void k_su_fwd(SuParams P) {
 #pragma unroll
             for (int k = 0; k < kSuSlices; ++k) {
                 const uint32_t e = static_cast<uint32_t>(ev[k]), bit = e & 31;
-                u[k] = ((w[k].x >> bit) & 1u) != 0u;
-                gr[k] = ub_s[e >> kSrBits] + w[k].y + __popc(w[k].x & ((1u << bit) - 1u));
+                u[k] = ((w[k].x >> bit) & 1u) != 0u;   // only for a valid ID (w is 0 otherwise)
+                gr[k] = u[k] ? ub_s[e >> kSrBits] + w[k].y + __popc(w[k].x & ((1u << bit) - 1u)) : 0u;
             }
 #pragma unroll
             for (int k = 0; k < kSuSlices; ++k) {
@@ -450,6 +458,7 @@ static size_t su_workspace(const ara_tables *tables, const ara_layers *layers, c
     c.take<OccTables>(static_cast<size_t>(std::max(L, 1)));
     c.take<uint64_t>(static_cast<size_t>(std::max(L, 1)));   // capacities
     c.take<uint64_t>(static_cast<size_t>(std::max(L, 1)));   // regions
+    c.take<uint64_t>(static_cast<size_t>(std::max(L, 1)));   // entries used
     size_t b = c.bytes();
     b += static_cast<size_t>(L) * S.z.per_layer;
     b += align256(static_cast<size_t>(L) * n_sr * kSr * sizeof(uint32_t));            // ooff
@@ -548,6 +557,7 @@ extern "C" int32_t ara_ylt_forward_su(const ara_tables *tables, const float *sig
     OccTables *d_tabs = c.take<OccTables>(static_cast<size_t>(L));
     uint64_t *d_cap = c.take<uint64_t>(static_cast<size_t>(L));
     uint64_t *d_region = c.take<uint64_t>(static_cast<size_t>(L));
+    uint64_t *d_used = c.take<uint64_t>(static_cast<size_t>(L));
     std::vector<OccTables> tabs(static_cast<size_t>(L));
     for (int j = 0; j < L; ++j) tabs[j] = occ_carve(c, S.z, true);
     uint32_t *ooff = c.take<uint32_t>(static_cast<size_t>(L) * n_sr * kSr);
@@ -571,7 +581,8 @@ extern "C" int32_t ara_ylt_forward_su(const ara_tables *tables, const float *sig
             return rc;
         k_su_scan<<<dim3(static_cast<unsigned>(n_sr), static_cast<unsigned>(L)), kSuThreads, 0, st>>>(d_tabs, n_sr,
                                                                                                     ooff, otot);
-        k_su_base<<<static_cast<unsigned>(L), kSuThreads, 0, st>>>(d_tabs, otot, n_sr, d_cap, ubase, obase, d_err);
+        k_su_base<<<static_cast<unsigned>(L), kSuThreads, 0, st>>>(d_tabs, otot, n_sr, d_cap, ubase, obase, d_used,
+                                                                  d_err);
         k_su_fill<<<dim3(static_cast<unsigned>(n_sr * kSuFillChunks), static_cast<unsigned>(L)), kSuThreads, 0, st>>>(
             tables->loss, sigma, tables->present, tables->catalog, tables->words, d_off, d_ids, d_tabs, n_sr, ooff,
             ubase, obase, d_cap, d_region, ent);
@@ -591,6 +602,8 @@ extern "C" int32_t ara_ylt_forward_su(const ara_tables *tables, const float *sig
     P.filter = filter;
     P.ubase = ubase;
     P.eregion = d_region;
+    P.ecap = d_cap;
+    P.eused = d_used;
     P.ent = ent;
     P.elt_off = d_off;
     P.elt_ids = d_ids;
