@@ -261,7 +261,7 @@ __device__ __forceinline__ double su_draw(const SuEntry &e, uint64_t seed, int64
 // lane sums the losses of the occurrences it drew, in queue order; the
 // trial's total is the wavefront sum of those.
 
-constexpr int kSuSlices = 4;        // 64-occurrence slices per step
+constexpr int kSuSlices = 8;        // 64-occurrence slices per step
 constexpr int kSuQueue = 2 * kWave; // queue capacity: < 64 waiting + one slice
 
 struct SuParams {
