@@ -3,13 +3,16 @@
 //
 // Selection is a radix select on the binary64 bit patterns (year losses are
 // >= 0, so the unsigned order of the bits is the numeric order), with digits
-// of 11 bits from the top.  Two grid passes fix the exponent and the leading
-// mantissa digit; if few values share that 23-bit prefix they are gathered
-// and one workgroup finishes in LDS, otherwise (heavy ties) four more grid
-// passes finish (they exit at once when the small path already finished).
-// Sums use a fixed partition of the trials and fixed-order trees, so every
-// result is deterministic.
+// of 11 bits from the top.  Two grid passes histogram the exponent and the
+// leading mantissa digit; a third gathers every value sharing that 23-bit
+// prefix, and the workgroup that finishes it last selects among them (in LDS
+// when they fit, from the gathered copy otherwise, at once when they are all
+// equal).  A fourth pass sums above the PML value.  Each pass ends in the
+// workgroup that finishes last (a counter per layer), so a call is four
+// kernels whatever the ties.  Sums use a fixed partition of the trials and
+// fixed-order trees, so every result is deterministic.
 #include "ara_internal.h"
+#include "wave.h"
 
 #include <algorithm>
 #include <cmath>
@@ -17,22 +20,26 @@
 namespace ara {
 
 constexpr int kMetThreads = 1024;
+constexpr int kMetUnroll = 8;                          // values per thread per sweep (loads in flight together)
+constexpr int kMetSweep = kMetThreads * kMetUnroll;
 constexpr int kBins = 2048;
-constexpr int kPassesMet = 6;
-constexpr int kCandCap = 16384;     // candidates finished inside one workgroup's LDS
+constexpr int kDigits = 6;
+constexpr int kCandCap = 16384;     // gathered values selected inside LDS
 // digit d covers bits [kShift[d], kShift[d] + kWidth[d]) of the key; bit 63
 // (the sign) is 0 for every year loss
-__constant__ int kShift[kPassesMet] = {52, 41, 30, 19, 8, 0};
-__constant__ int kWidth[kPassesMet] = {11, 11, 11, 11, 11, 8};
+__constant__ int kShift[kDigits] = {52, 41, 30, 19, 8, 0};
+__constant__ int kWidth[kDigits] = {11, 11, 11, 11, 11, 8};
 
 struct MetState {
-    uint64_t prefix[kPassesMet + 1];   // bits fixed before digit d (prefix[d] has 64 - kShift[d] - kWidth[d] bits)
-    int64_t need[kPassesMet + 1];      // rank (1-based from the top) to find among values with prefix[d]
-    int64_t cand_n;
-    int32_t small, done;
-    double thr;
+    uint64_t prefix[3];        // bits fixed before digit d = 0, 1, 2 (prefix[d] = key >> (kShift[d-1]))
+    int64_t need[3];           // rank (1-based from the top) to find among values with prefix[d]
+    unsigned long long cand_n; // values gathered
+    unsigned long long kmax;   // largest gathered key
+    unsigned long long kminc;  // complement of the smallest gathered key
+    double thr;                // the PML value
     int64_t cnt_gt, cnt_eq;
     int64_t r;
+    uint32_t tick[4];          // workgroups finished, per pass
 };
 
 struct MetPart {
@@ -50,33 +57,50 @@ __device__ __forceinline__ void chunk_of(int64_t n, int nwg, int wg, int64_t &lo
     hi = std::min<int64_t>(n, lo + c);
 }
 
-// Fixed-order block reductions (value valid in thread 0).
-__device__ double block_sum(double v, double *red) {
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o);
-    if (lane == 0) red[w] = v;
+// Workgroup sums of K binary64 values per thread (counts below 2^53 are
+// exact as binary64), each in a fixed order: a DPP prefix sum within every
+// wavefront, then one over the 16 wavefront totals, which every wavefront
+// forms for itself.  All threads return the sums.  red: [K][16].
+template <int K>
+__device__ void block_sums(double (&v)[K], double (*red)[16]) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] = wave_inclusive_sum(v[k]);
+    if (lane == 63)
+#pragma unroll
+        for (int k = 0; k < K; ++k) red[k][w] = v[k];
     __syncthreads();
-    double t = 0.0;
-    if (tid == 0)
-        for (int i = 0; i < static_cast<int>(blockDim.x >> 6); ++i) t += red[i];
-    __syncthreads();
-    return t;
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] = lane63(wave_inclusive_sum(lane < kMetThreads / 64 ? red[k][lane] : 0.0));
+    __syncthreads();   // red may be reused
 }
 
-__device__ int64_t block_count(int64_t v, int64_t *red) {
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o);
-    if (lane == 0) red[w] = v;
+// Values one workgroup hands to the one that finishes last go through
+// device-scope atomic stores and loads, which need no cache write-back or
+// invalidation.
+template <class T>
+__device__ __forceinline__ void put(T *p, T v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <class T>
+__device__ __forceinline__ T get(const T *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// True in the workgroup that finishes pass k of layer l last.  Every wave
+// waits for its own stores and atomics to complete before the workgroup
+// counts itself done, and the last one reads only after its count returned,
+// so it sees all the values handed over.
+__device__ bool finished_last(MetState &S, int k, int nwg, int *flag) {
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();
-    int64_t t = 0;
-    if (tid == 0)
-        for (int i = 0; i < static_cast<int>(blockDim.x >> 6); ++i) t += red[i];
+    if (threadIdx.x == 0) *flag = atomicAdd(&S.tick[k], 1u) == static_cast<uint32_t>(nwg - 1);
     __syncthreads();
-    return t;
+    return *flag != 0;
 }
 
 struct FindShared {
-    int64_t wtot[16];
+    double wtot[16];
     int digit;
     int64_t need;
 };
@@ -84,6 +108,7 @@ struct FindShared {
 // Locate the bin holding the need-th largest value (counting from the top) in
 // histogram h[0..bins); every thread of the block takes part (1024 threads,
 // two bins each).  Result in fs.digit / fs.need (the rank inside that bin).
+// Counts are summed as binary64, exact below 2^53.
 __device__ void find_digit(const uint32_t *h, int bins, int64_t need, FindShared &fs) {
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     if (t == 0) {   // defaults (never used when the histogram holds `need` values)
@@ -93,17 +118,15 @@ __device__ void find_digit(const uint32_t *h, int bins, int64_t need, FindShared
     const int64_t c_lo = (2 * t < bins) ? h[2 * t] : 0;
     const int64_t c_hi = (2 * t + 1 < bins) ? h[2 * t + 1] : 0;
     const int64_t v = c_lo + c_hi;
-    // inclusive suffix sum over threads t' >= t
-    int64_t suf = v;
-    for (int o = 1; o < 64; o <<= 1) {
-        const int64_t x = __shfl_down(suf, o);
-        if (lane + o < 64) suf += x;
-    }
-    if (lane == 0) fs.wtot[w] = suf;
+    const double incl = wave_inclusive_sum(static_cast<double>(v));   // lanes <= this one
+    const double wsum = lane63(incl);
+    if (lane == 63) fs.wtot[w] = incl;
     __syncthreads();
-    int64_t higher = 0;
-    for (int i = w + 1; i < static_cast<int>(blockDim.x >> 6); ++i) higher += fs.wtot[i];
-    const int64_t above = suf - v + higher;   // values in bins above 2t+1
+    // totals of the wavefronts after this one
+    const double wp = wave_inclusive_sum(lane < kMetThreads / 64 ? fs.wtot[lane] : 0.0);
+    const double all = lane63(wp);
+    const double upto = __shfl(wp, w);   // wavefronts 0..w
+    const int64_t above = static_cast<int64_t>((all - upto) + (wsum - incl));   // values in bins above 2t+1
     if (above < need && need <= above + c_hi) {
         fs.digit = 2 * t + 1;
         fs.need = need - above;
@@ -114,34 +137,21 @@ __device__ void find_digit(const uint32_t *h, int bins, int64_t need, FindShared
     __syncthreads();
 }
 
-// Digit pass d over the whole YLT row: histogram of digit d among the values
-// whose higher bits equal the prefix selected so far.  Pass 0 also forms the
-// fixed-partition partial sums for the mean.
-__global__ __launch_bounds__(kMetThreads) void k_met_pass(const double *__restrict__ ylt, int64_t n, int nwg, int d,
+// Digit pass d (0 or 1) over the whole YLT row: histogram of digit d among
+// the values whose higher bits equal the prefix selected so far.  Pass 0 also
+// forms the fixed-partition partial sums for the mean.  The last workgroup
+// selects the digit for the next pass.
+__global__ __launch_bounds__(kMetThreads) void k_met_hist(const double *__restrict__ ylt, int64_t n, int nwg, int d,
                                                          uint32_t *__restrict__ hist, MetState *__restrict__ st,
                                                          MetPart *__restrict__ part, int64_t r) {
     __shared__ uint32_t h[kBins];
     __shared__ FindShared fs;
-    __shared__ double red[16];
-    const int l = blockIdx.y, wg = blockIdx.x;
+    __shared__ double red[1][16];
+    __shared__ int flag;
+    const int l = blockIdx.y, wg = blockIdx.x, tid = threadIdx.x, lane = tid & 63;
     MetState &S = st[l];
-    uint64_t prefix = 0;
-    int64_t need = r;
-    if (d > 0) {
-        if (S.done) return;
-        const uint32_t *hp = hist + (static_cast<size_t>(d - 1) * gridDim.y + l) * kBins;
-        for (int i = threadIdx.x; i < kBins; i += blockDim.x) h[i] = hp[i];
-        __syncthreads();
-        find_digit(h, 1 << kWidth[d - 1], S.need[d - 1], fs);
-        prefix = (S.prefix[d - 1] << kWidth[d - 1]) | static_cast<uint64_t>(fs.digit);
-        need = fs.need;
-    }
-    if (wg == 0 && threadIdx.x == 0) {
-        S.prefix[d] = prefix;
-        S.need[d] = need;
-        if (d == 0) S.r = r;
-    }
-    for (int i = threadIdx.x; i < kBins; i += blockDim.x) h[i] = 0;
+    const uint64_t prefix = d ? S.prefix[1] : 0ull;
+    for (int i = tid; i < kBins; i += kMetThreads) h[i] = 0;
     __syncthreads();
     const int sh = kShift[d], hb = kShift[d] + kWidth[d];
     const uint32_t mask = (1u << kWidth[d]) - 1u;
@@ -149,201 +159,201 @@ __global__ __launch_bounds__(kMetThreads) void k_met_pass(const double *__restri
     chunk_of(n, nwg, wg, lo, hi);
     const double *y = ylt + static_cast<size_t>(l) * n;
     double s = 0.0;
-    const int lane = threadIdx.x & 63;
-    for (int64_t i0 = lo; i0 < hi; i0 += blockDim.x) {   // uniform trip count: every lane reaches the ballots
-        const int64_t i = i0 + threadIdx.x;
-        const double v = (i < hi) ? y[i] : 0.0;
-        const uint64_t u = key_of(v);
-        if (d == 0) s += v;
-        const bool want = i < hi && (hb >= 64 || (u >> hb) == prefix);
-        const uint32_t dg = static_cast<uint32_t>((u >> sh) & mask);
-        // year losses of one row crowd into few digits (the exponent above
-        // all): the first lane's digit is counted for all the lanes that
-        // share it with one LDS atomic, the rest count themselves
-        const uint64_t act = __ballot(want);
-        if (act) {
-            const int leader = __builtin_ctzll(act);
-            const uint32_t ld = __builtin_amdgcn_readlane(dg, leader);
-            const uint64_t same = __ballot(want && dg == ld);
-            if (lane == leader) atomicAdd(&h[ld], static_cast<uint32_t>(__popcll(same)));
-            if (want && dg != ld) atomicAdd(&h[dg], 1u);
+    for (int64_t i0 = lo; i0 < hi; i0 += kMetSweep) {   // uniform trip count: every lane reaches the ballots
+        double v[kMetUnroll];
+#pragma unroll
+        for (int u = 0; u < kMetUnroll; ++u) {
+            const int64_t i = i0 + u * kMetThreads + tid;
+            v[u] = (i < hi) ? y[i] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < kMetUnroll; ++u) {
+            const int64_t i = i0 + u * kMetThreads + tid;
+            const uint64_t k = key_of(v[u]);
+            if (d == 0) s += v[u];
+            const bool want = i < hi && (k >> hb) == prefix;
+            const uint32_t dg = static_cast<uint32_t>((k >> sh) & mask);
+            // year losses of one row crowd into few digits (the exponent above
+            // all): the first lane's digit is counted for all the lanes that
+            // share it with one LDS atomic, the rest count themselves
+            const uint64_t act = __ballot(want);
+            if (act) {
+                const int leader = __builtin_ctzll(act);
+                const uint32_t ld = __builtin_amdgcn_readlane(dg, leader);
+                const uint64_t same = __ballot(want && dg == ld);
+                if (lane == leader) atomicAdd(&h[ld], static_cast<uint32_t>(__popcll(same)));
+                if (want && dg != ld) atomicAdd(&h[dg], 1u);
+            }
         }
     }
     if (d == 0) {
-        const double tot = block_sum(s, red);
-        if (threadIdx.x == 0) part[static_cast<size_t>(l) * nwg + wg].sum = tot;
+        double t[1] = {s};
+        block_sums(t, red);
+        if (tid == 0) part[static_cast<size_t>(l) * nwg + wg].sum = t[0];
     }
     __syncthreads();
     uint32_t *hd = hist + (static_cast<size_t>(d) * gridDim.y + l) * kBins;
-    for (int i = threadIdx.x; i < kBins; i += blockDim.x)
+    for (int i = tid; i < kBins; i += kMetThreads)
         if (h[i]) atomicAdd(&hd[i], h[i]);
+    if (!finished_last(S, d, nwg, &flag)) return;
+    for (int i = tid; i < kBins; i += kMetThreads) h[i] = get(&hd[i]);
+    __syncthreads();
+    find_digit(h, 1 << kWidth[d], d ? S.need[1] : r, fs);
+    if (tid == 0) {
+        S.prefix[d + 1] = (prefix << kWidth[d]) | static_cast<uint64_t>(fs.digit);
+        S.need[d + 1] = fs.need;
+        if (d == 0) S.r = r;
+    }
 }
 
-// After pass 1: if at most kCandCap values share the 23-bit prefix, gather
-// them (one reservation per workgroup) so a single workgroup can finish.
+// Gathers every value whose 23-bit prefix is the selected one (a wavefront
+// reserves its slots with one atomic), with their smallest and largest key.
+// The last workgroup finishes digits 2..5 on them.
 __global__ __launch_bounds__(kMetThreads) void k_met_collect(const double *__restrict__ ylt, int64_t n, int nwg,
-                                                            const uint32_t *__restrict__ hist, MetState *__restrict__ st,
-                                                            uint64_t *__restrict__ cand) {
+                                                            MetState *__restrict__ st, uint64_t *__restrict__ cand) {
+    __shared__ uint64_t cs[kCandCap];
     __shared__ uint32_t h[kBins];
     __shared__ FindShared fs;
-    __shared__ int64_t wcnt[16], wbase[16];
-    const int l = blockIdx.y, wg = blockIdx.x;
+    __shared__ int flag;
+    const int l = blockIdx.y, wg = blockIdx.x, tid = threadIdx.x, lane = tid & 63;
     MetState &S = st[l];
-    const uint32_t *hp = hist + (static_cast<size_t>(1) * gridDim.y + l) * kBins;
-    for (int i = threadIdx.x; i < kBins; i += blockDim.x) h[i] = hp[i];
-    __syncthreads();
-    find_digit(h, 1 << kWidth[1], S.need[1], fs);
-    const uint64_t prefix = (S.prefix[1] << kWidth[1]) | static_cast<uint64_t>(fs.digit);
-    const int64_t in_bin = h[fs.digit];
-    const bool small = in_bin <= kCandCap;
-    if (wg == 0 && threadIdx.x == 0) S.small = small ? 1 : 0;
-    if (!small) return;
+    const uint64_t prefix = S.prefix[2];
     const int hb = kShift[1];
     int64_t lo, hi;
     chunk_of(n, nwg, wg, lo, hi);
     const double *y = ylt + static_cast<size_t>(l) * n;
-    uint64_t *c = cand + static_cast<size_t>(l) * kCandCap;
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    int64_t mine = 0;
-    for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) mine += ((key_of(y[i]) >> hb) == prefix);
-    for (int o = 32; o > 0; o >>= 1) mine += __shfl_down(mine, o);
-    if (lane == 0) wcnt[w] = mine;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int64_t tot = 0;
-        for (int i = 0; i < static_cast<int>(blockDim.x >> 6); ++i) tot += wcnt[i];
-        int64_t base = tot ? static_cast<int64_t>(atomicAdd(reinterpret_cast<unsigned long long *>(&S.cand_n),
-                                                           static_cast<unsigned long long>(tot)))
-                           : 0;
-        for (int i = 0; i < static_cast<int>(blockDim.x >> 6); ++i) {
-            wbase[i] = base;
-            base += wcnt[i];
+    uint64_t *c = cand + static_cast<size_t>(l) * n;
+    uint64_t kmin = ~0ull, kmax = 0ull;
+    for (int64_t i0 = lo; i0 < hi; i0 += kMetSweep) {
+        uint64_t k[kMetUnroll], m[kMetUnroll];
+        int64_t mine = 0;
+#pragma unroll
+        for (int u = 0; u < kMetUnroll; ++u) {
+            const int64_t i = i0 + u * kMetThreads + tid;
+            k[u] = (i < hi) ? key_of(y[i]) : 0ull;
+        }
+#pragma unroll
+        for (int u = 0; u < kMetUnroll; ++u) {
+            const int64_t i = i0 + u * kMetThreads + tid;
+            const bool is = i < hi && (k[u] >> hb) == prefix;
+            m[u] = __ballot(is);
+            mine += __popcll(m[u]);
+            if (is) {
+                kmin = std::min(kmin, k[u]);
+                kmax = std::max(kmax, k[u]);
+            }
+        }
+        if (mine) {   // uniform: the wavefront reserves its slots itself
+            unsigned long long base = 0;
+            if (lane == 0) base = atomicAdd(&S.cand_n, static_cast<unsigned long long>(mine));
+            int64_t off = static_cast<int64_t>(__shfl(base, 0));
+#pragma unroll
+            for (int u = 0; u < kMetUnroll; ++u) {
+                if ((m[u] >> lane) & 1ull) {
+                    const uint32_t pos = __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(m[u] >> 32),
+                                                                   __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(m[u]), 0u));
+                    put(&c[off + pos], k[u]);
+                }
+                off += __popcll(m[u]);
+            }
         }
     }
-    __syncthreads();
-    int64_t off = wbase[w];
-    for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
-        const uint64_t u = key_of(y[i]);
-        const bool is = (u >> hb) == prefix;
-        const uint64_t m = __ballot(is);
-        if (is) {
-            const uint32_t pos = __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(m >> 32),
-                                                           __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(m), 0u));
-            c[off + pos] = u;
+    if (__ballot(kmin <= kmax)) {   // uniform: this wavefront gathered something
+        for (int o = 32; o > 0; o >>= 1) {
+            kmin = std::min(kmin, static_cast<uint64_t>(__shfl_xor(static_cast<unsigned long long>(kmin), o)));
+            kmax = std::max(kmax, static_cast<uint64_t>(__shfl_xor(static_cast<unsigned long long>(kmax), o)));
         }
-        off += __popcll(m);
+        if (lane == 0) {
+            atomicMax(&S.kmax, static_cast<unsigned long long>(kmax));
+            atomicMax(&S.kminc, static_cast<unsigned long long>(~kmin));
+        }
     }
+    if (!finished_last(S, 2, nwg, &flag)) return;
+    const int64_t cn = static_cast<int64_t>(get(&S.cand_n));
+    const uint64_t lo_key = ~static_cast<uint64_t>(get(&S.kminc)), hi_key = static_cast<uint64_t>(get(&S.kmax));
+    uint64_t bits = hi_key;
+    if (lo_key != hi_key) {
+        // the values differ: radix select on the gathered copy
+        const bool in_lds = cn <= kCandCap;   // uniform
+        if (in_lds)
+            for (int64_t i = tid; i < cn; i += kMetThreads) cs[i] = get(&c[i]);
+        uint64_t pre = prefix;
+        int64_t need = S.need[2];
+        for (int d = 2; d < kDigits; ++d) {
+            for (int i = tid; i < kBins; i += kMetThreads) h[i] = 0;
+            __syncthreads();
+            const int sh = kShift[d], hbd = kShift[d] + kWidth[d];
+            const uint32_t mask = (1u << kWidth[d]) - 1u;
+            for (int64_t i = tid; i < cn; i += kMetThreads) {
+                const uint64_t u = in_lds ? cs[i] : get(&c[i]);
+                if ((u >> hbd) == pre) atomicAdd(&h[(u >> sh) & mask], 1u);
+            }
+            __syncthreads();
+            find_digit(h, 1 << kWidth[d], need, fs);
+            pre = (pre << kWidth[d]) | static_cast<uint64_t>(fs.digit);
+            need = fs.need;
+        }
+        bits = pre;
+    }
+    if (tid == 0) S.thr = __longlong_as_double(static_cast<long long>(bits));
 }
 
-// One workgroup per layer finishes digits 2..5 on the collected candidates.
-__global__ __launch_bounds__(kMetThreads) void k_met_small(const uint32_t *__restrict__ hist, MetState *__restrict__ st,
-                                                          const uint64_t *__restrict__ cand) {
-    __shared__ uint64_t cs[kCandCap];
-    __shared__ uint32_t h[kBins];
-    __shared__ FindShared fs;
-    const int l = blockIdx.x;
-    MetState &S = st[l];
-    if (!S.small) return;
-    const int64_t cn = S.cand_n;
-    for (int64_t i = threadIdx.x; i < cn; i += blockDim.x) cs[i] = cand[static_cast<size_t>(l) * kCandCap + i];
-    const uint32_t *hp = hist + (static_cast<size_t>(1) * gridDim.x + l) * kBins;
-    for (int i = threadIdx.x; i < kBins; i += blockDim.x) h[i] = hp[i];
-    __syncthreads();
-    find_digit(h, 1 << kWidth[1], S.need[1], fs);
-    uint64_t prefix = (S.prefix[1] << kWidth[1]) | static_cast<uint64_t>(fs.digit);
-    int64_t need = fs.need;
-    for (int d = 2; d < kPassesMet; ++d) {
-        for (int i = threadIdx.x; i < kBins; i += blockDim.x) h[i] = 0;
-        __syncthreads();
-        const int sh = kShift[d], hb = kShift[d] + kWidth[d];
-        const uint32_t mask = (1u << kWidth[d]) - 1u;
-        for (int64_t i = threadIdx.x; i < cn; i += blockDim.x) {
-            const uint64_t u = cs[i];
-            if ((u >> hb) == prefix) atomicAdd(&h[(u >> sh) & mask], 1u);
-        }
-        __syncthreads();
-        find_digit(h, 1 << kWidth[d], need, fs);
-        prefix = (prefix << kWidth[d]) | static_cast<uint64_t>(fs.digit);
-        need = fs.need;
-    }
-    if (threadIdx.x == 0) {
-        S.thr = __longlong_as_double(static_cast<long long>(prefix));
-        S.done = 1;
-    }
-}
-
-// Counts and sum above the PML value (fixed partition, fixed-order trees).
+// Counts and sum above the PML value (fixed partition); the last workgroup
+// adds the partial results in a fixed order and writes the metrics.
 __global__ __launch_bounds__(kMetThreads) void k_met_tail(const double *__restrict__ ylt, int64_t n, int nwg,
-                                                         const uint32_t *__restrict__ hist, MetState *__restrict__ st,
-                                                         MetPart *__restrict__ part) {
-    __shared__ uint32_t h[kBins];
-    __shared__ FindShared fs;
-    __shared__ double red[16];
-    __shared__ int64_t redi[16];
-    const int l = blockIdx.y, wg = blockIdx.x;
+                                                         MetState *__restrict__ st, MetPart *__restrict__ part,
+                                                         double *__restrict__ out) {
+    __shared__ double red[4][16];
+    __shared__ int flag;
+    const int l = blockIdx.y, wg = blockIdx.x, tid = threadIdx.x;
     MetState &S = st[l];
-    double thr;
-    if (S.done) {
-        thr = S.thr;
-    } else {
-        const int d = kPassesMet - 1;
-        const uint32_t *hp = hist + (static_cast<size_t>(d) * gridDim.y + l) * kBins;
-        for (int i = threadIdx.x; i < kBins; i += blockDim.x) h[i] = hp[i];
-        __syncthreads();
-        find_digit(h, 1 << kWidth[d], S.need[d], fs);
-        const uint64_t bits = (S.prefix[d] << kWidth[d]) | static_cast<uint64_t>(fs.digit);
-        thr = __longlong_as_double(static_cast<long long>(bits));
-        if (wg == 0 && threadIdx.x == 0) S.thr = thr;
-    }
+    const double thr = S.thr;
     int64_t lo, hi;
     chunk_of(n, nwg, wg, lo, hi);
     const double *y = ylt + static_cast<size_t>(l) * n;
     double s = 0.0;
     int64_t gt = 0, eq = 0;
-    for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
-        const double v = y[i];
-        if (v > thr) {
-            s += v;
-            ++gt;
-        } else if (v == thr) {
-            ++eq;
+    for (int64_t i0 = lo; i0 < hi; i0 += kMetSweep) {
+        double v[kMetUnroll];
+#pragma unroll
+        for (int u = 0; u < kMetUnroll; ++u) {
+            const int64_t i = i0 + u * kMetThreads + tid;
+            v[u] = (i < hi) ? y[i] : -1.0;   // below every year loss and the PML value
+        }
+#pragma unroll
+        for (int u = 0; u < kMetUnroll; ++u) {
+            if (v[u] > thr) {
+                s += v[u];
+                ++gt;
+            } else if (v[u] == thr) {
+                ++eq;
+            }
         }
     }
-    const double ts = block_sum(s, red);
-    const int64_t tg = block_count(gt, redi);
-    const int64_t te = block_count(eq, redi);
-    if (threadIdx.x == 0) {
-        MetPart &p = part[static_cast<size_t>(l) * nwg + wg];
-        p.sum_gt = ts;
-        p.cnt_gt = tg;
-        p.cnt_eq = te;
+    double t3[3] = {s, static_cast<double>(gt), static_cast<double>(eq)};
+    block_sums(t3, red);
+    MetPart *pl = part + static_cast<size_t>(l) * nwg;
+    if (tid == 0) {
+        put(&pl[wg].sum_gt, t3[0]);
+        put(&pl[wg].cnt_gt, static_cast<int64_t>(t3[1]));
+        put(&pl[wg].cnt_eq, static_cast<int64_t>(t3[2]));
     }
-}
-
-__global__ __launch_bounds__(kMetThreads) void k_met_final(int64_t n, int nwg, const MetPart *__restrict__ part,
-                                                          MetState *__restrict__ st, double *__restrict__ out) {
-    __shared__ double red[16];
-    __shared__ int64_t redi[16];
-    const int l = blockIdx.x;
-    double s = 0.0, sg = 0.0;
-    int64_t gt = 0, eq = 0;
-    for (int i = threadIdx.x; i < nwg; i += blockDim.x) {
-        const MetPart &p = part[static_cast<size_t>(l) * nwg + i];
-        s += p.sum;
-        sg += p.sum_gt;
-        gt += p.cnt_gt;
-        eq += p.cnt_eq;
+    if (!finished_last(S, 3, nwg, &flag)) return;
+    double t4[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int i = tid; i < nwg; i += kMetThreads) {
+        t4[0] += pl[i].sum;   // written by an earlier kernel
+        t4[1] += get(&pl[i].sum_gt);
+        t4[2] += static_cast<double>(get(&pl[i].cnt_gt));
+        t4[3] += static_cast<double>(get(&pl[i].cnt_eq));
     }
-    const double ts = block_sum(s, red);
-    const double tsg = block_sum(sg, red);
-    const int64_t tgt = block_count(gt, redi);
-    const int64_t teq = block_count(eq, redi);
-    if (threadIdx.x == 0) {
-        const int64_t r = st[l].r;
-        const double thr = st[l].thr;
-        st[l].cnt_gt = tgt;
-        st[l].cnt_eq = teq;
-        out[3 * l + 0] = ts / static_cast<double>(n);
+    block_sums(t4, red);
+    const double tsa = t4[0], tsg = t4[1];
+    const int64_t tgt = static_cast<int64_t>(t4[2]), teq = static_cast<int64_t>(t4[3]);
+    if (tid == 0) {
+        const int64_t r = S.r;
+        S.cnt_gt = tgt;
+        S.cnt_eq = teq;
+        out[3 * l + 0] = tsa / static_cast<double>(n);
         out[3 * l + 1] = thr;
         out[3 * l + 2] = (tsg + static_cast<double>(r - tgt) * thr) / static_cast<double>(r);
     }
@@ -385,17 +395,17 @@ __global__ void k_met_vjp(const double *__restrict__ w, int64_t n, int n_layers,
 }
 
 static int met_nwg(int64_t n) {
-    return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>((n + 8191) / 8192, 1024)));
+    return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>((n + kMetSweep - 1) / kMetSweep, 1024)));
 }
 
 static size_t met_bytes(int32_t L, int64_t n) {
     const int nwg = met_nwg(n);
     Carver c(nullptr);
     c.take<int32_t>(kWsHeaderBytes / 4);
-    c.take<uint32_t>(static_cast<size_t>(kPassesMet) * L * kBins);
+    c.take<uint32_t>(static_cast<size_t>(2) * L * kBins);
     c.take<MetState>(static_cast<size_t>(L));
     c.take<MetPart>(static_cast<size_t>(L) * nwg);
-    c.take<uint64_t>(static_cast<size_t>(L) * kCandCap);
+    c.take<uint64_t>(static_cast<size_t>(L) * n);   // gathered keys: up to the whole row
     return c.bytes();
 }
 
@@ -419,10 +429,10 @@ extern "C" int32_t ara_metrics(const double *ylt, int32_t n_layers, int64_t n, d
     const int nwg = met_nwg(n);
     Carver c(ws);
     int32_t *hdr = c.take<int32_t>(kWsHeaderBytes / 4);
-    uint32_t *hist = c.take<uint32_t>(static_cast<size_t>(kPassesMet) * n_layers * kBins);
+    uint32_t *hist = c.take<uint32_t>(static_cast<size_t>(2) * n_layers * kBins);
     MetState *state = c.take<MetState>(static_cast<size_t>(n_layers));
     MetPart *part = c.take<MetPart>(static_cast<size_t>(n_layers) * nwg);
-    uint64_t *cand = c.take<uint64_t>(static_cast<size_t>(n_layers) * kCandCap);
+    uint64_t *cand = c.take<uint64_t>(static_cast<size_t>(n_layers) * n);
     // header, histograms and states are contiguous: clear them at once
     const size_t clear = reinterpret_cast<char *>(part) - reinterpret_cast<char *>(hdr);
     ARA_HIP(hipMemsetAsync(hdr, 0, clear, st));
@@ -431,13 +441,10 @@ extern "C" int32_t ara_metrics(const double *ylt, int32_t n_layers, int64_t n, d
     r = std::max<int64_t>(1, std::min<int64_t>(n, r));
     dim3 grid(static_cast<unsigned>(nwg), static_cast<unsigned>(n_layers));
     ProfScope prof(ARA_PROF_METRICS, st);
-    k_met_pass<<<grid, kMetThreads, 0, st>>>(ylt, n, nwg, 0, hist, state, part, r);
-    k_met_pass<<<grid, kMetThreads, 0, st>>>(ylt, n, nwg, 1, hist, state, part, r);
-    k_met_collect<<<grid, kMetThreads, 0, st>>>(ylt, n, nwg, hist, state, cand);
-    k_met_small<<<n_layers, kMetThreads, 0, st>>>(hist, state, cand);
-    for (int d = 2; d < kPassesMet; ++d) k_met_pass<<<grid, kMetThreads, 0, st>>>(ylt, n, nwg, d, hist, state, part, r);
-    k_met_tail<<<grid, kMetThreads, 0, st>>>(ylt, n, nwg, hist, state, part);
-    k_met_final<<<n_layers, kMetThreads, 0, st>>>(n, nwg, part, state, out);
+    k_met_hist<<<grid, kMetThreads, 0, st>>>(ylt, n, nwg, 0, hist, state, part, r);
+    k_met_hist<<<grid, kMetThreads, 0, st>>>(ylt, n, nwg, 1, hist, state, part, r);
+    k_met_collect<<<grid, kMetThreads, 0, st>>>(ylt, n, nwg, state, cand);
+    k_met_tail<<<grid, kMetThreads, 0, st>>>(ylt, n, nwg, state, part, out);
     if (weights) {
         const unsigned gx = static_cast<unsigned>(std::min<int64_t>((n + 255) / 256, 4096));
         k_met_weights<<<dim3(gx, static_cast<unsigned>(n_layers)), 256, 0, st>>>(ylt, n, n_layers, state, weights);

@@ -195,6 +195,44 @@ def test_metrics_vs_oracle(ara, seed):
         np.testing.assert_array_equal(wts, oracle.metric_weights(y, p))
 
 
+@pytest.mark.parametrize("n_crowd,ties", [(16_000, 0), (16_385, 0), (60_000, 0), (60_000, 25_000), (200_000, 199_000)])
+def test_metrics_crowded_prefix_bin(ara, n_crowd, ties):
+    """Values crowded into one 23-bit prefix bin (the window [999936, 1000192)
+    shares exponent and 11 leading mantissa bits): distinct values spaced
+    1e-5 apart, some of them repeated, the rest of the row below the window.
+    Below and above the 16384 values selected inside LDS."""
+    import torch
+    g = np.random.default_rng(n_crowd + ties)
+    n = 250_000
+    y = g.uniform(0.0, 9.9e5, size=(1, n))
+    crowd = 1e6 + np.arange(n_crowd, dtype=np.float64) * 1e-5
+    crowd[:ties] = crowd[ties]                       # the first `ties` values equal one value
+    y[0, g.permutation(n)[:n_crowd]] = crowd
+    for p in [0.5, 0.8, 0.95, 0.9999]:
+        out, wts = ara.metrics(torch.tensor(y, device="cuda"), p, want_weights=True)
+        out, wts = out.cpu().numpy(), wts.cpu().numpy()
+        ref = oracle.metrics(y, p)
+        assert np.array_equal(out[:, 1], ref[:, 1]), (p, out[:, 1], ref[:, 1])
+        np.testing.assert_allclose(out[:, [0, 2]], ref[:, [0, 2]], rtol=TOL, atol=0)
+        np.testing.assert_array_equal(wts, oracle.metric_weights(y, p))
+
+
+def test_metrics_repeatable_and_layers_independent(ara):
+    """Same answer twice (order-free gathering) and each layer as if alone."""
+    import torch
+    g = np.random.default_rng(11)
+    y = g.lognormal(14, 1.5, size=(3, 70_000))
+    y[1] = np.round(y[1] / 1e6) * 1e6
+    y[2, :40_000] = 5e7
+    t = torch.tensor(y, device="cuda")
+    a, _ = ara.metrics(t, 0.99)
+    b, _ = ara.metrics(t, 0.99)
+    assert torch.equal(a, b)
+    for l in range(3):
+        one, _ = ara.metrics(t[l:l + 1].contiguous(), 0.99)
+        assert torch.equal(one[0], a[l])
+
+
 def test_metrics_constant_and_vjp(ara):
     import torch
     y = torch.full((2, 50_000), 1e8, dtype=torch.float64, device="cuda")
