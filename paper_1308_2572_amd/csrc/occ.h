@@ -9,6 +9,10 @@
 //                 number of set bits in words 0..w-1}
 //   vals[s][i] = O of the i-th set event of super-range s (binary64)
 //   cnt[s][i]  = number of the layer's ELTs holding that event (hits mode)
+// built in two steps: each chunk of 4096 events finds its set events, their
+// bitmap words and count, and O in event order at the start of the chunk's
+// slice of `dense`; then every chunk's ranks start after the earlier chunks'
+// counts and its values move into `vals`.
 // The set events are those with O != 0 ("hot"), or, when hit counts are
 // requested, every event present in at least one of the layer's ELTs.
 #pragma once
@@ -18,15 +22,18 @@
 namespace ara {
 
 constexpr int kMaxJ = ARA_MAX_ELTS_PER_LAYER;
+constexpr int kOccChunkWords = 128;                    // 4096 events per chunk
+constexpr int kOccChunks = kSrWords / kOccChunkWords;   // 16 chunks per super-range
 
 struct OccTables {
     uint2 *br;          // [n_sr][kSrWords]
     double *vals;       // [n_sr][kSr]
     uint8_t *cnt;       // [n_sr][kSr] or null
     int32_t *count;     // [n_sr]
+    int32_t *pcount;    // [n_sr][kOccChunks]  set events per chunk (phase one)
     uint32_t *bits;     // [n_sr][kSrWords]  set-event bitmap (phase one)
-    double *dense;      // [n_sr][kSr]       O by event (phase one; set events only)
-    uint8_t *dense_nb;  // [n_sr][kSr]       ELT count by event (hits mode)
+    double *dense;      // [n_sr][kSr]       O of each chunk's set events, from the chunk's start (phase one)
+    uint8_t *dense_nb;  // [n_sr][kSr]       their ELT counts (hits mode)
 };
 
 // min(max(v - R, 0), L), evaluated exactly as the oracle does: a separately
@@ -41,7 +48,7 @@ __device__ __forceinline__ double xl(double v, double r, double lim) {
 struct OccLayoutSizes {
     int n_sr;
     size_t per_layer;
-    size_t br, vals, cnt, count, bits, dense, dense_nb;
+    size_t br, vals, cnt, count, pcount, bits, dense, dense_nb;
 };
 
 inline OccLayoutSizes occ_sizes(int32_t catalog, bool with_cnt) {
@@ -51,10 +58,11 @@ inline OccLayoutSizes occ_sizes(int32_t catalog, bool with_cnt) {
     z.vals = align256(static_cast<size_t>(z.n_sr) * kSr * sizeof(double));
     z.cnt = with_cnt ? align256(static_cast<size_t>(z.n_sr) * kSr) : 0;
     z.count = align256(static_cast<size_t>(z.n_sr) * sizeof(int32_t));
+    z.pcount = align256(static_cast<size_t>(z.n_sr) * kOccChunks * sizeof(int32_t));
     z.bits = align256(static_cast<size_t>(z.n_sr) * kSrWords * sizeof(uint32_t));
     z.dense = align256(static_cast<size_t>(z.n_sr) * kSr * sizeof(double));
     z.dense_nb = with_cnt ? align256(static_cast<size_t>(z.n_sr) * kSr) : 0;
-    z.per_layer = z.br + z.vals + z.cnt + z.count + z.bits + z.dense + z.dense_nb;
+    z.per_layer = z.br + z.vals + z.cnt + z.count + z.pcount + z.bits + z.dense + z.dense_nb;
     return z;
 }
 
@@ -64,6 +72,7 @@ inline OccTables occ_carve(Carver &c, const OccLayoutSizes &z, bool with_cnt) {
     t.vals = c.take<double>(static_cast<size_t>(z.n_sr) * kSr);
     t.cnt = with_cnt ? c.take<uint8_t>(static_cast<size_t>(z.n_sr) * kSr) : nullptr;
     t.count = c.take<int32_t>(static_cast<size_t>(z.n_sr));
+    t.pcount = c.take<int32_t>(static_cast<size_t>(z.n_sr) * kOccChunks);
     t.bits = c.take<uint32_t>(static_cast<size_t>(z.n_sr) * kSrWords);
     t.dense = c.take<double>(static_cast<size_t>(z.n_sr) * kSr);
     t.dense_nb = with_cnt ? c.take<uint8_t>(static_cast<size_t>(z.n_sr) * kSr) : nullptr;

@@ -8,17 +8,39 @@
 
 namespace ara {
 
-constexpr int kPassWords = 128;                 // 4096 events per pass
-constexpr int kPasses = kSrWords / kPassWords;  // 16
+constexpr int kPassWords = kOccChunkWords;      // 4096 events per chunk
+constexpr int kPasses = kOccChunks;             // 16 chunks per super-range
 
 __device__ __forceinline__ bool bad_scale(double s) { return !(s > 0.0) || !(s < INFINITY); }
 __device__ __forceinline__ bool bad_retention(double r) { return !(r >= 0.0) || !(r < INFINITY); }
 __device__ __forceinline__ bool bad_limit(double l) { return !(l > 0.0); }
 
-// Phase one: one workgroup per (4096-event chunk, layer).  For every event,
-// sum g_k over the layer's ELTs in listed order (losses of 8 ELTs are loaded
-// together so their latencies overlap), apply the occurrence terms, mark the
-// set events in a bitmap and keep O (and the ELT count) densely.
+// Exclusive prefix sum of v over the first 128 threads (two wavefronts);
+// *total receives the sum.  Every thread of the block must call it.
+__device__ __forceinline__ uint32_t scan128(uint32_t v, uint32_t *wtot, uint32_t *total) {
+    const int tid = threadIdx.x, lane = tid & 63;
+    uint32_t incl = v;
+    if (tid < 128) {
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t x = __shfl_up(incl, o);
+            if (lane >= o) incl += x;
+        }
+        if (lane == 63) wtot[tid >> 6] = incl;
+    }
+    __syncthreads();
+    const uint32_t before = (tid >= 64 && tid < 128) ? wtot[0] : 0u;
+    if (tid == 0) *total = wtot[0] + wtot[1];
+    __syncthreads();
+    return before + incl - v;
+}
+
+// Phase one: one workgroup per (4096-event chunk, layer).  The events held
+// by at least one of the layer's ELTs are listed in event order; each is
+// evaluated once: g_k summed over the layer's ELTs in listed order (losses of
+// 8 ELTs are loaded together so their latencies overlap), then the occurrence
+// terms.  The set events are compacted in event order: the chunk's bitmap
+// words, its count, and O (and the ELT count) at the start of the chunk's
+// slice of the staging arrays.
 template <bool UNION>
 __global__ __launch_bounds__(1024) void k_occ_eval(const float *__restrict__ loss, const uint32_t *__restrict__ present,
                                                    int32_t catalog, int32_t words, const int32_t *__restrict__ elt_off,
@@ -30,6 +52,9 @@ __global__ __launch_bounds__(1024) void k_occ_eval(const float *__restrict__ los
     __shared__ int32_t lk[kMaxJ];
     __shared__ double ls[kMaxJ], lr[kMaxJ], ll[kMaxJ];
     __shared__ double lterm[4];
+    __shared__ uint32_t anyw[kPassWords], cbase[kPassWords], fbits[kPassWords];
+    __shared__ uint16_t cand[kPassWords * 32];
+    __shared__ uint32_t wtot[16], wtot2[2], n_cand;
 
     const int s = blockIdx.x / kPasses, p = blockIdx.x % kPasses, j = blockIdx.y;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -49,25 +74,46 @@ __global__ __launch_bounds__(1024) void k_occ_eval(const float *__restrict__ los
         const bool bad = (tid & 1) ? bad_limit(lterm[tid]) : bad_retention(lterm[tid]);
         if (checker && bad) atomicCAS(err, 0, ARA_E_INVAL);
     }
-    __syncthreads();
     for (int idx = tid; idx < J * kPassWords; idx += blockDim.x) {
         const int q = idx / kPassWords, ww = idx % kPassWords;
         const int64_t gw = static_cast<int64_t>(s) * kSrWords + p * kPassWords + ww;
-        stage[idx] = (gw < words) ? present[static_cast<size_t>(lk[q]) * words + gw] : 0u;
+        stage[idx] = (gw < words) ? present[static_cast<size_t>(elt_ids[a + q]) * words + gw] : 0u;
     }
     __syncthreads();
+    // events held by any of the layer's ELTs, word by word, and where each
+    // word's events start in the candidate list
+    uint32_t any = 0;
+    if (tid < kPassWords) {
+        for (int q = 0; q < J; ++q) any |= stage[q * kPassWords + tid];
+        anyw[tid] = any;
+        fbits[tid] = 0u;
+    }
+    const uint32_t cb = scan128(__popc(any), wtot2, &n_cand);
+    if (tid < kPassWords) cbase[tid] = cb;
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < 4; ++it) {
+        const int local = it * 1024 + tid;
+        const uint32_t m = anyw[local >> 5];
+        const uint32_t bit = static_cast<uint32_t>(local & 31);
+        if ((m >> bit) & 1u) cand[cbase[local >> 5] + __popc(m & ((1u << bit) - 1u))] = static_cast<uint16_t>(local);
+    }
+    __syncthreads();
+    const int nc = static_cast<int>(n_cand);
     const double occR = lterm[0], occL = lterm[1];
     const OccTables T = tabs[j];
     const int64_t ev0 = static_cast<int64_t>(s) * kSr + p * (kPassWords * 32);
-    for (int it = 0; it < 4; ++it) {
-        const int local = it * 1024 + tid;
+    double *ov = T.dense + ev0;                           // the chunk's compacted O
+    uint8_t *onb = UNION ? T.dense_nb + ev0 : nullptr;    // and ELT counts
+    uint32_t run = 0;                                     // set events before this pass
+    for (int i0 = 0; i0 < nc; i0 += 1024) {   // uniform trip count: every thread reaches the barriers
+        const int i = i0 + tid;
+        const int local = i < nc ? cand[i] : 0;
         const int wip = local >> 5, bit = local & 31;
         const int64_t ev = ev0 + local;
-        uint32_t any = 0;
-        for (int q = 0; q < J; ++q) any |= stage[q * kPassWords + wip];
         double x = 0.0;
         int nb = 0;
-        if ((any >> bit) & 1u) {
+        if (i < nc) {
             for (int q0 = 0; q0 < J; q0 += 8) {
                 float v[8];
                 bool on[8];
@@ -92,58 +138,55 @@ __global__ __launch_bounds__(1024) void k_occ_eval(const float *__restrict__ los
             }
         }
         const double O = xl(x, occR, occL);
-        const bool flag = UNION ? (nb > 0) : (O != 0.0);
+        const bool flag = i < nc && (UNION ? (nb > 0) : (O != 0.0));
+        // rank among this pass's set events: lanes below, then wavefronts below
         const uint64_t m = __ballot(flag);
-        if (lane == 0) {
-            const size_t wi = static_cast<size_t>(s) * kSrWords + p * kPassWords + (it * 1024 + w * 64) / 32;
-            T.bits[wi] = static_cast<uint32_t>(m);
-            T.bits[wi + 1] = static_cast<uint32_t>(m >> 32);
+        const uint32_t below = __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(m >> 32),
+                                                         __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(m), 0u));
+        if (lane == 0) wtot[w] = static_cast<uint32_t>(__popcll(m));
+        __syncthreads();
+        uint32_t wb = 0, tot = 0;
+        for (int k = 0; k < 16; ++k) {
+            const uint32_t c = wtot[k];
+            wb += (k < w) ? c : 0u;
+            tot += c;
         }
         if (flag) {
-            T.dense[ev] = O;
-            if (UNION) T.dense_nb[ev] = static_cast<uint8_t>(nb > 255 ? 255 : nb);
+            const uint32_t r = run + wb + below;
+            ov[r] = O;
+            if (UNION) onb[r] = static_cast<uint8_t>(nb > 255 ? 255 : nb);
+            atomicOr(&fbits[wip], 1u << bit);
         }
+        run += tot;
+        __syncthreads();   // wtot is rewritten by the next pass
     }
+    if (tid < kPassWords) T.bits[static_cast<size_t>(s) * kSrWords + p * kPassWords + tid] = fbits[tid];
+    if (tid == 0) T.pcount[static_cast<size_t>(s) * kPasses + p] = static_cast<int32_t>(run);
 }
 
-// Phase two: one workgroup per (super-range, layer): rank of every set event
-// (prefix count of the bitmap) and compaction of O into rank order.
+// Phase two: one workgroup per (chunk, layer): the chunk's rank base (set
+// events of the super-range's earlier chunks), the rank of every bitmap word,
+// and the chunk's compacted values moved to their place in rank order.
 template <bool UNION>
 __global__ __launch_bounds__(1024) void k_occ_rank(const OccTables *__restrict__ tabs) {
-    __shared__ uint32_t wsum[16];
-    const int s = blockIdx.x, j = blockIdx.y;
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    __shared__ uint32_t wtot2[2], tot;
+    const int s = blockIdx.x / kPasses, p = blockIdx.x % kPasses, j = blockIdx.y;
+    const int tid = threadIdx.x;
     const OccTables T = tabs[j];
-    const uint32_t b0 = T.bits[static_cast<size_t>(s) * kSrWords + 2 * tid];
-    const uint32_t b1 = T.bits[static_cast<size_t>(s) * kSrWords + 2 * tid + 1];
-    const uint32_t c0 = __popc(b0), c1 = __popc(b1);
-    uint32_t incl = c0 + c1;
-    for (int o = 1; o < 64; o <<= 1) {
-        const uint32_t v = __shfl_up(incl, o);
-        if (lane >= o) incl += v;
-    }
-    if (lane == 63) wsum[w] = incl;
-    __syncthreads();
-    uint32_t before = 0;
-    for (int i = 0; i < w; ++i) before += wsum[i];
-    const uint32_t r0 = before + incl - (c0 + c1), r1 = r0 + c0;
-    T.br[static_cast<size_t>(s) * kSrWords + 2 * tid] = make_uint2(b0, r0);
-    T.br[static_cast<size_t>(s) * kSrWords + 2 * tid + 1] = make_uint2(b1, r1);
-    if (tid == 1023) T.count[s] = static_cast<int32_t>(r1 + c1);
-    double *vals = T.vals + static_cast<size_t>(s) * kSr;
-    uint8_t *cnt = UNION ? T.cnt + static_cast<size_t>(s) * kSr : nullptr;
-    const int64_t ev0 = static_cast<int64_t>(s) * kSr + 64 * tid;
-    uint32_t rank = r0;
-    for (int h = 0; h < 2; ++h) {
-        uint32_t b = h ? b1 : b0;
-        while (b) {
-            const int bit = __ffs(b) - 1;
-            b &= b - 1;
-            const int64_t ev = ev0 + 32 * h + bit;
-            vals[rank] = T.dense[ev];
-            if (UNION) cnt[rank] = T.dense_nb[ev];
-            ++rank;
-        }
+    const int32_t *pc = T.pcount + static_cast<size_t>(s) * kPasses;
+    uint32_t base = 0;
+    for (int k = 0; k < p; ++k) base += static_cast<uint32_t>(pc[k]);
+    const uint32_t cnt = static_cast<uint32_t>(pc[p]);
+    const size_t w0 = static_cast<size_t>(s) * kSrWords + p * kPassWords;
+    const uint32_t b = tid < kPassWords ? T.bits[w0 + tid] : 0u;
+    const uint32_t r = scan128(__popc(b), wtot2, &tot);
+    if (tid < kPassWords) T.br[w0 + tid] = make_uint2(b, base + r);
+    if (p == kPasses - 1 && tid == 0) T.count[s] = static_cast<int32_t>(base + cnt);
+    const size_t src = static_cast<size_t>(s) * kSr + static_cast<size_t>(p) * (kPassWords * 32);
+    const size_t dst = static_cast<size_t>(s) * kSr + base;
+    for (uint32_t i = tid; i < cnt; i += blockDim.x) {
+        T.vals[dst + i] = T.dense[src + i];
+        if (UNION) T.cnt[dst + i] = T.dense_nb[src + i];
     }
 }
 
@@ -169,7 +212,7 @@ int32_t launch_occ(const ara_tables *tables, const int32_t *d_elt_off, const int
                    OccTables *d_tabs, int n_sr, int32_t *d_err, hipStream_t st) {
     if (n_layers == 0 || n_sr == 0) return ARA_OK;
     dim3 grid_a(static_cast<unsigned>(n_sr * kPasses), static_cast<unsigned>(n_layers));
-    dim3 grid_b(static_cast<unsigned>(n_sr), static_cast<unsigned>(n_layers));
+    dim3 grid_b(static_cast<unsigned>(n_sr * kPasses), static_cast<unsigned>(n_layers));
     if (union_mode) {
         k_occ_eval<true><<<grid_a, 1024, 0, st>>>(tables->loss, tables->present, tables->catalog, tables->words,
                                                   d_elt_off, d_elt_ids, elt_terms, layer_terms, d_tabs, d_err);
