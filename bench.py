@@ -99,6 +99,7 @@ def main() -> int:
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-yelt", action="store_true")
     ap.add_argument("--no-su", action="store_true", help="skip the secondary-uncertainty forward")
+    ap.add_argument("--no-fp32", action="store_true", help="skip the binary32-accumulation forward")
     ap.add_argument("--serving-requests", type=int, default=200)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy three times (scales the HBM byte counters)")
@@ -198,6 +199,8 @@ def main() -> int:
         "metrics": {"aal": float(m[0]), "pml": float(m[1]), "tvar": float(m[2])},
     }
 
+    if not args.no_fp32:
+        result["fp32_accum"] = bench_fp32(ara, tables, yet, layers, et, lt, w, args.steps, args.warmup, ylt)
     if not args.no_backward:
         try:
             result["fwd_bwd"] = bench_backward(ara, tables, yet, layers, et, lt, w, args.steps, args.warmup, ms_step)
@@ -231,6 +234,41 @@ def main() -> int:
         result["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(result), flush=True)
     return 0
+
+
+def bench_fp32(ara, tables, yet, layers, et, lt, w, steps, warmup, ylt64):
+    """The same step with binary32 occurrence values and trial totals
+    (ARA_F_FP32_ACCUM), and its largest deviation from the binary64 year
+    losses relative to max(Y, S)."""
+    import torch
+    N, nnz = w.yet.n_trials, w.yet.nnz
+    J = int(w.layers.elt_off[-1])
+
+    def step():
+        y, _, _ = ara.ylt_forward(tables, yet, layers, et, lt, 0, N, want_s_pre=False, fp32_accum=True)
+        out, _ = ara.metrics(y, w.p)
+        return y, out
+
+    for _ in range(max(1, warmup)):
+        step()
+    torch.cuda.synchronize()
+    ara.profile_reset()
+    ara.profile_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        y32, out32 = step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ara.profile_enable(False)
+    k_ms, k_n = ara.profile_read(ara.PROF_FWD)
+    ms = (t1 - t0) * 1e3 / steps
+    _, s64, _ = ara.ylt_forward(tables, yet, layers, et, lt, 0, N, want_s_pre=True)
+    dev = ((y32 - ylt64).abs() / torch.maximum(ylt64, s64).clamp_min(1e-300)).max().item()
+    k = k_ms / max(k_n, 1)
+    log(f"binary32 accumulation: step {ms:.4f} ms, forward kernel {k:.4f} ms, largest deviation {dev:.2e}")
+    return {"ms_per_step": ms, "lookups_per_s": nnz * J / (ms * 1e-3), "kernel_ms": k,
+            "max_rel_dev_vs_f64": dev, "dtype": "f32 values and totals, f64 aggregate terms",
+            "metrics": [float(v) for v in out32.cpu().numpy()[0]]}
 
 
 def bench_yelt(ara, tables, layers, et, lt, w, steps, warmup):

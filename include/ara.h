@@ -59,6 +59,9 @@ extern "C" {
 
 /* forward flags */
 #define ARA_F_EMIT_HITS   1u  /* also produce per-(layer, trial) hit counts */
+#define ARA_F_FP32_ACCUM  2u  /* binary32 occurrence values and trial totals (the precision reduction of the
+                                 optimised kernel, Sections III-IV); hits unchanged; YLT within 1e-5 of
+                                 the binary64 result relative to max(YLT, total) */
 
 /* implementation limits */
 #define ARA_MAX_CATALOG       (1 << 26)   /* events in the catalogue */
@@ -193,7 +196,9 @@ int32_t ara_ylt_workspace_bytes(const ara_tables *tables, const ara_yet *yet,
  * layer_terms: device binary64 [n_layers][4] = (OccR, OccL, AggR, AggL)
  * ylt:         device binary64 [n_layers][n], n = trial_end - trial_begin
  * s_pre:       device binary64 [n_layers][n] or NULL: the trial's total of
- *              occurrence losses before aggregate terms (kept for the backward)
+ *              occurrence losses before aggregate terms (kept for the backward;
+ *              with ARA_F_FP32_ACCUM the binary32 total, widened exactly)
+ * flags:       ARA_F_EMIT_HITS, ARA_F_FP32_ACCUM (ARA_E_INVAL for other bits)
  * hits:        device int32 [n_layers][n] or NULL; requires ARA_F_EMIT_HITS
  * ws:          device workspace of at least ara_ylt_workspace_bytes
  * Invalid term values are detected on the device: ara_check_device_error.

@@ -23,6 +23,7 @@ LIB_PATH = os.path.join(HERE, "libara.so")
 
 ARA_OK, ARA_E_INVAL, ARA_E_RANGE, ARA_E_DUP, ARA_E_NOSPACE, ARA_E_HIP, ARA_E_LIMIT, ARA_E_BUSY = range(8)
 ARA_F_EMIT_HITS = 1
+ARA_F_FP32_ACCUM = 2
 PREP_TRANSPOSED = 1          # ARA_PREP_TRANSPOSED
 ARA_MAX_COTANGENTS = 4
 
@@ -319,14 +320,15 @@ def ylt_forward_su(tables: EltTables, sigma: SigmaTables, offsets: torch.Tensor,
 
 def ylt_forward(tables: EltTables, yet: PreparedYet, layers: Layers, elt_terms: torch.Tensor,
                 layer_terms: torch.Tensor, trial_begin: int = 0, trial_end: Optional[int] = None,
-                want_s_pre: bool = True, want_hits: bool = False, check: bool = False):
-    """Returns (ylt, s_pre or None, hits or None), each [n_layers, n]."""
+                want_s_pre: bool = True, want_hits: bool = False, check: bool = False, fp32_accum: bool = False):
+    """Returns (ylt, s_pre or None, hits or None), each [n_layers, n].
+    fp32_accum: binary32 occurrence values and trial totals (ARA_F_FP32_ACCUM)."""
     lib = library()
     trial_end = yet.n_trials if trial_end is None else trial_end
     n = trial_end - trial_begin
     L = layers.n_layers
     dev = yet.device
-    flags = ARA_F_EMIT_HITS if want_hits else 0
+    flags = (ARA_F_EMIT_HITS if want_hits else 0) | (ARA_F_FP32_ACCUM if fp32_accum else 0)
     nb = _c_sz()
     _check(lib.ara_ylt_workspace_bytes(ctypes.byref(tables.handle), ctypes.byref(yet.handle),
                                        ctypes.byref(layers.handle), flags, ctypes.byref(nb)), "ara_ylt_workspace_bytes")
@@ -541,5 +543,5 @@ class Metrics(torch.autograd.Function):
 __all__ = [
     "AraError", "PreparedYet", "EltTables", "SigmaTables", "Layers", "ylt_forward", "ylt_forward_su", "yelt_forward",
     "metrics", "metrics_vjp", "ylt_backward",
-    "YLT", "Metrics", "QuoteServer", "library", "ara_yet", "ara_tables", "ara_layers", "ARA_F_EMIT_HITS",
+    "YLT", "Metrics", "QuoteServer", "library", "ara_yet", "ara_tables", "ara_layers", "ARA_F_EMIT_HITS", "ARA_F_FP32_ACCUM",
 ]

@@ -597,7 +597,7 @@ extern "C" int32_t ara_ylt_backward(const ara_tables *tables, const ara_yet *yet
 
     {
         ProfScope prof(ARA_PROF_OCC, st);
-        if ((rc = launch_occ(tables, d_off, d_ids, elt_terms, layer_terms, L, false, d_tabs, B.z.n_sr, d_err, st)))
+        if ((rc = launch_occ(tables, d_off, d_ids, elt_terms, layer_terms, L, false, false, d_tabs, B.z.n_sr, d_err, st)))
             return rc;
     }
     const int nwg_v = bwd_nwg_v(n);

@@ -57,24 +57,25 @@ __device__ __forceinline__ void lds_dma16(const void *src, uint32_t lds_base) {
 
 __device__ __forceinline__ void wait_dma() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
 
-// a + 8 * (bit POS of x): two instructions.  Written out because the
+// a + (bit POS of x << SH): two instructions.  Written out because the
 // optimiser otherwise turns it into shift, mask and add, or re-derives every
 // address of a chain from a running count (three instructions either way).
-template <int POS>
-__device__ __forceinline__ uint32_t add_bit8(uint32_t a, uint32_t x) {
+template <int POS, int SH>
+__device__ __forceinline__ uint32_t add_bit(uint32_t a, uint32_t x) {
     uint32_t b, r;
     asm("v_bfe_u32 %0, %1, %2, 1" : "=v"(b) : "v"(x), "n"(POS));
-    asm("v_lshl_add_u32 %0, %1, 3, %2" : "=v"(r) : "v"(b), "v"(a));
+    asm("v_lshl_add_u32 %0, %1, %2, %3" : "=v"(r) : "v"(b), "n"(SH), "v"(a));
     return r;
 }
 
-// LDS bytes of the per-trial totals (and hit counts), including the padding
-// slot; the table counts of every range; each wavefront's window of 64
-// segment descriptors (run length, base) -- descriptors come from LDS so that
-// moving to the next range never waits on the vector memory counter, which
-// also counts the prefetched stream.
-__host__ __device__ inline size_t fwd_acc_lds(int tb, bool hits) {
-    return align256(static_cast<size_t>(tb + 1) * 8 + (hits ? static_cast<size_t>(tb + 1) * 4 : 0));
+// LDS bytes of the per-trial totals (binary64, or binary32 when
+// accumulating in binary32) and hit counts, including the padding slot; the
+// table counts of every range; each wavefront's window of 64 segment
+// descriptors (run length, base) -- descriptors come from LDS so that moving
+// to the next range never waits on the vector memory counter, which also
+// counts the prefetched stream.
+__host__ __device__ inline size_t fwd_acc_lds(int tb, bool hits, size_t vbytes) {
+    return align256(static_cast<size_t>(tb + 1) * vbytes + (hits ? static_cast<size_t>(tb + 1) * 4 : 0));
 }
 __host__ __device__ inline size_t fwd_meta_lds(int n_ranges) {
     return align256(static_cast<size_t>(n_ranges) * 8) + align256(static_cast<size_t>(kGroups) * kWave * 12);
@@ -86,19 +87,26 @@ struct RangeInfo {
     uint32_t base, cnt;
 };
 
-template <bool HITS>
+// F32: occurrence values are binary32 in the table and trial totals are
+// accumulated in binary32 (the aggregate terms are still applied in
+// binary64); otherwise both are binary64.
+template <bool HITS, bool F32>
 __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_fwd(FwdParams P) {
+    using V = typename std::conditional<F32, float, double>::type;
+    constexpr uint32_t kV = sizeof(V);             // bytes per value and per trial total
+    constexpr int kVSh = F32 ? 2 : 3;              // log2(kV)
+    constexpr uint32_t kVPer16 = 16 / kV;          // values per 16-byte copy
     // LDS: [range buffer][trial totals][hit counts][range table][segment windows].
     // A static array: its addresses are compile-time constants, which the LDS
     // instructions take as immediate offsets.
     __shared__ __align__(16) unsigned char smem[kLdsBytes];
     const int tb = P.tb;
     const uint32_t acc_off = static_cast<uint32_t>(P.buf_bytes);
-    const uint32_t hacc_off = acc_off + static_cast<uint32_t>(tb + 1) * 8;
-    double *acc = reinterpret_cast<double *>(smem + acc_off);     // [tb + 1]
+    const uint32_t hacc_off = acc_off + static_cast<uint32_t>(tb + 1) * kV;
+    V *acc = reinterpret_cast<V *>(smem + acc_off);                // [tb + 1]
     int32_t *hacc = reinterpret_cast<int32_t *>(smem + hacc_off);  // [tb + 1]
     const int G = P.n_ranges;
-    unsigned char *meta = smem + acc_off + fwd_acc_lds(tb, HITS);
+    unsigned char *meta = smem + acc_off + fwd_acc_lds(tb, HITS, kV);
     uint2 *rinfo = reinterpret_cast<uint2 *>(meta);                                             // [G] (base, cnt)
     unsigned char *meta2 = meta + align256(static_cast<size_t>(G) * 8);
     int64_t *wbase_all = reinterpret_cast<int64_t *>(meta2);                                    // [16][64]
@@ -116,7 +124,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8))) vo
     const size_t seg0 = static_cast<size_t>(b) * G * kGroups + w;
 
     for (int i = tid; i <= tb; i += blockDim.x) {   // slot tb collects the padding
-        acc[i] = 0.0;
+        acc[i] = V(0);
         if (HITS) hacc[i] = 0;
     }
     const OccTables T = *I.tab;
@@ -128,16 +136,17 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8))) vo
         const unsigned char *gbr = reinterpret_cast<const unsigned char *>(T.br + s * kSrWords + (r & 1) * 1024);
         for (int c0 = w * kWave; c0 < kBrBytes / 16; c0 += kGroups * kWave)
             lds_dma16(gbr + static_cast<size_t>(c0 + lane) * 16, dst + c0 * 16);
-        const uint32_t nv = min(ri.cnt + (ri.base & 1u), static_cast<uint32_t>(P.capv));
-        const int nvc = static_cast<int>((nv + 1) / 2);
-        const unsigned char *gv = reinterpret_cast<const unsigned char *>(T.vals + s * kSr + (ri.base & ~1u));
+        const uint32_t nv = min(ri.cnt + (ri.base & (kVPer16 - 1u)), static_cast<uint32_t>(P.capv));
+        const int nvc = static_cast<int>((nv + kVPer16 - 1u) / kVPer16);
+        const unsigned char *gv =
+            reinterpret_cast<const unsigned char *>(reinterpret_cast<const V *>(T.vals) + s * kSr + (ri.base & ~(kVPer16 - 1u)));
         for (int c0 = w * kWave; c0 < nvc; c0 += kGroups * kWave)
             if (c0 + lane < nvc) lds_dma16(gv + static_cast<size_t>(c0 + lane) * 16, dst + kBrBytes + c0 * 16);
         if (HITS) {
             const uint32_t nb = min(ri.cnt + (ri.base & 15u), static_cast<uint32_t>(P.capv));
             const int nbc = static_cast<int>((nb + 15) / 16);
             const unsigned char *gc = T.cnt + s * kSr + (ri.base & ~15u);
-            const uint32_t cdst = dst + kBrBytes + static_cast<uint32_t>(P.capv) * 8;
+            const uint32_t cdst = dst + kBrBytes + static_cast<uint32_t>(P.capv) * kV;
             for (int c0 = w * kWave; c0 < nbc; c0 += kGroups * kWave)
                 if (c0 + lane < nbc) lds_dma16(gc + static_cast<size_t>(c0 + lane) * 16, cdst + c0 * 16);
         }
@@ -227,7 +236,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8))) vo
 
     // byte offset (from smem) of the lane's current trial total; a trial
     // advance moves it by one slot
-    const uint32_t accw_off = acc_off + static_cast<uint32_t>(w * P.tg) * 8;
+    const uint32_t accw_off = acc_off + static_cast<uint32_t>(w * P.tg) * kV;
     uint32_t tofs = accw_off;
     __syncthreads();   // range table counts published
     RangeInfo cur = range_info(0);
@@ -239,12 +248,12 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8))) vo
 
     for (int r = 0; r < G; ++r) {
         const uint2 *tbr = reinterpret_cast<const uint2 *>(smem);
-        const double *tvals = reinterpret_cast<const double *>(smem + kBrBytes);
-        const uint8_t *tcnt = smem + kBrBytes + static_cast<size_t>(P.capv) * 8;
+        const V *tvals = reinterpret_cast<const V *>(smem + kBrBytes);
+        const uint8_t *tcnt = smem + kBrBytes + static_cast<size_t>(P.capv) * kV;
         const size_t s = static_cast<size_t>(r >> 1);
-        const double *gvals = T.vals + s * kSr;
+        const V *gvals = reinterpret_cast<const V *>(T.vals) + s * kSr;
         const uint8_t *gcnt = HITS ? T.cnt + s * kSr : nullptr;
-        const uint32_t vsh = cur.base & ~1u, csh = cur.base & ~15u;
+        const uint32_t vsh = cur.base & ~(kVPer16 - 1u), csh = cur.base & ~15u;
         // values with buffer index below vlim (and counts below clim) are in LDS
         const uint32_t vlim = static_cast<uint32_t>(P.capv), clim = static_cast<uint32_t>(P.capv);
         const bool all_lds = cur.cnt + (cur.base & 15u) <= static_cast<uint32_t>(P.capv);   // uniform
@@ -256,11 +265,11 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8))) vo
         // LDS byte offsets of value and count 0 of the super-range: unsigned
         // arithmetic, so the offsets wrap, while every address formed from
         // them lies in the buffer
-        const uint32_t vbase = static_cast<uint32_t>(kBrBytes) - vsh * 8u;
-        const uint32_t cbase = static_cast<uint32_t>(kBrBytes) + static_cast<uint32_t>(P.capv) * 8u - csh;
+        const uint32_t vbase = static_cast<uint32_t>(kBrBytes) - vsh * kV;
+        const uint32_t cbase = static_cast<uint32_t>(kBrBytes) + static_cast<uint32_t>(P.capv) * kV - csh;
         auto chunk = [&](auto skip_tag) {
             constexpr bool kTellSkip = decltype(skip_tag)::value;
-            if (X_first) tofs = accw_off + 8u * static_cast<uint32_t>(X_start);
+            if (X_first) tofs = accw_off + kV * static_cast<uint32_t>(X_start);
             // codes of this chunk, two per 32-bit word, low half first
             uint32_t wd[kUnroll / 2];
 #pragma unroll
@@ -278,7 +287,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8))) vo
             uint32_t ta[kUnroll];
 #pragma unroll
             for (int u = 0; u < kUnroll; ++u) {
-                tofs = (u & 1) ? add_bit8<31>(tofs, wd[u >> 1]) : add_bit8<15>(tofs, wd[u >> 1]);
+                tofs = (u & 1) ? add_bit<31, kVSh>(tofs, wd[u >> 1]) : add_bit<15, kVSh>(tofs, wd[u >> 1]);
                 ta[u] = tofs;
             }
             // bit and rank: the bit field instructions read only the low five
@@ -292,16 +301,16 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8))) vo
                 rank[u] = __popc(__builtin_amdgcn_ubfe(q[u].x, 0, cw[u])) + q[u].y;
             }
             if (all_lds) {
-                double v[kUnroll];
+                V v[kUnroll];
 #pragma unroll
                 for (int u = 0; u < kUnroll; ++u)
-                    v[u] = *reinterpret_cast<const double *>(smem + ((on[u] ? rank[u] : vsh) * 8u + vbase));
+                    v[u] = *reinterpret_cast<const V *>(smem + ((on[u] ? rank[u] : vsh) * kV + vbase));
 #pragma unroll
                 for (int u = 0; u < kUnroll; ++u)
                     if (on[u]) {
-                        atomicAdd(reinterpret_cast<double *>(smem + ta[u]), v[u]);
+                        atomicAdd(reinterpret_cast<V *>(smem + ta[u]), v[u]);
                         if (HITS)
-                            atomicAdd(reinterpret_cast<int32_t *>(smem + hacc_off + ((ta[u] - acc_off) >> 1)),
+                            atomicAdd(reinterpret_cast<int32_t *>(smem + hacc_off + ((ta[u] - acc_off) >> (kVSh - 2))),
                                       static_cast<int>(smem[rank[u] + cbase]));
                     }
             } else {
@@ -310,7 +319,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8))) vo
                     if (on[u]) {
                         // indexes relative to the buffer start, so that every
                         // address stays inside its array
-                        double v;
+                        V v;
                         int c = 0;
                         const uint32_t iv = rank[u] - vsh;
                         if (iv < vlim) v = tvals[iv];
@@ -320,8 +329,8 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8))) vo
                             if (ic < clim) c = tcnt[ic];
                             else c = gcnt[rank[u]];
                         }
-                        atomicAdd(reinterpret_cast<double *>(smem + ta[u]), v);
-                        if (HITS) atomicAdd(reinterpret_cast<int32_t *>(smem + hacc_off + ((ta[u] - acc_off) >> 1)), c);
+                        atomicAdd(reinterpret_cast<V *>(smem + ta[u]), v);
+                        if (HITS) atomicAdd(reinterpret_cast<int32_t *>(smem + hacc_off + ((ta[u] - acc_off) >> (kVSh - 2))), c);
                     }
             }
         };
@@ -341,7 +350,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8))) vo
         const int64_t lo = max(gt0, I.t0), hi = min(gt1, I.t1);
         for (int64_t t = lo + lane; t < hi; t += kWave) {
             const int i = static_cast<int>(t - b * tb);
-            const double S = acc[i];
+            const double S = static_cast<double>(acc[i]);
             const size_t o = static_cast<size_t>(t - I.t0);
             I.ylt[o] = xl(S, aggR, aggL);
             if (I.s_pre) I.s_pre[o] = S;
@@ -350,7 +359,8 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8))) vo
     }
 }
 
-int32_t launch_forward(const ara_yet *yet, int n_sr, bool hits, const FwdItem *d_items, int n_items, hipStream_t st) {
+int32_t launch_forward(const ara_yet *yet, int n_sr, bool hits, bool f32, const FwdItem *d_items, int n_items,
+                       hipStream_t st) {
     (void)n_sr;
     if (n_items <= 0) return ARA_OK;
     FwdParams P{};
@@ -364,15 +374,21 @@ int32_t launch_forward(const ara_yet *yet, int n_sr, bool hits, const FwdItem *d
     P.tb = yet->trials_per_block;
     P.n_ranges = yet->n_ranges;
     // the range's table slice: [bitmap words with ranks][values][counts (hits mode)]
-    const size_t per_buf = (kLdsBytes - fwd_acc_lds(P.tb, hits) - fwd_meta_lds(P.n_ranges)) & ~size_t(255);
-    size_t capv = hits ? (per_buf - kBrBytes - 16) / 9 : (per_buf - kBrBytes) / 8;
+    const size_t vb = f32 ? sizeof(float) : sizeof(double);
+    const size_t per_buf = (kLdsBytes - fwd_acc_lds(P.tb, hits, vb) - fwd_meta_lds(P.n_ranges)) & ~size_t(255);
+    size_t capv = hits ? (per_buf - kBrBytes - 16) / (vb + 1) : (per_buf - kBrBytes) / vb;
     capv &= ~size_t(15);
     P.capv = static_cast<int32_t>(capv);
     P.buf_bytes = static_cast<int32_t>(per_buf);
     P.items = d_items;
     ProfScope prof(ARA_PROF_FWD, st);
-    if (hits) k_fwd<true><<<n_items, 1024, 0, st>>>(P);
-    else k_fwd<false><<<n_items, 1024, 0, st>>>(P);
+    if (f32) {
+        if (hits) k_fwd<true, true><<<n_items, 1024, 0, st>>>(P);
+        else k_fwd<false, true><<<n_items, 1024, 0, st>>>(P);
+    } else {
+        if (hits) k_fwd<true, false><<<n_items, 1024, 0, st>>>(P);
+        else k_fwd<false, false><<<n_items, 1024, 0, st>>>(P);
+    }
     ARA_HIP(hipGetLastError());
     return ARA_OK;
 }
@@ -407,7 +423,7 @@ extern "C" int32_t ara_ylt_workspace_bytes(const ara_tables *tables, const ara_y
     int32_t rc = check_pair(tables, yet);
     if (rc) return rc;
     if ((rc = check_layers(layers, tables->n_elts))) return rc;
-    if (flags & ~ARA_F_EMIT_HITS) return fail(ARA_E_INVAL, "unknown flag");
+    if (flags & ~(ARA_F_EMIT_HITS | ARA_F_FP32_ACCUM)) return fail(ARA_E_INVAL, "unknown flag");
     *bytes = fwd_workspace(tables, yet, layers, (flags & ARA_F_EMIT_HITS) != 0);
     return ARA_OK;
 }
@@ -419,8 +435,9 @@ extern "C" int32_t ara_ylt_forward(const ara_tables *tables, const ara_yet *yet,
     int32_t rc = check_pair(tables, yet);
     if (rc) return rc;
     if ((rc = check_layers(layers, tables->n_elts))) return rc;
-    if (flags & ~ARA_F_EMIT_HITS) return fail(ARA_E_INVAL, "unknown flag");
+    if (flags & ~(ARA_F_EMIT_HITS | ARA_F_FP32_ACCUM)) return fail(ARA_E_INVAL, "unknown flag");
     const bool want_hits = (flags & ARA_F_EMIT_HITS) != 0;
+    const bool f32 = (flags & ARA_F_FP32_ACCUM) != 0;
     if (hits && !want_hits) return fail(ARA_E_INVAL, "hits output requires ARA_F_EMIT_HITS");
     if (trial_begin < 0 || trial_end < trial_begin || trial_end > yet->n_trials)
         return fail(ARA_E_RANGE, "trial range outside the YET");
@@ -471,8 +488,9 @@ extern "C" int32_t ara_ylt_forward(const ara_tables *tables, const ara_yet *yet,
 
     {
         ProfScope prof(ARA_PROF_OCC, st);
-        if ((rc = launch_occ(tables, d_off, d_ids, elt_terms, layer_terms, L, want_hits, d_tabs, z.n_sr, d_err, st)))
+        if ((rc = launch_occ(tables, d_off, d_ids, elt_terms, layer_terms, L, want_hits, f32, d_tabs, z.n_sr, d_err,
+                             st)))
             return rc;
     }
-    return launch_forward(yet, z.n_sr, want_hits, d_items, L * nb, st);
+    return launch_forward(yet, z.n_sr, want_hits, f32, d_items, L * nb, st);
 }

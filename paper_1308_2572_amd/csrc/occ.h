@@ -93,7 +93,9 @@ struct FwdItem {
 };
 
 // Enqueue the forward streaming kernel over a device array of items.
-int32_t launch_forward(const ara_yet *yet, int n_sr, bool hits, const FwdItem *d_items, int n_items, hipStream_t st);
+// f32: binary32 occurrence values (tables built with f32_vals) and totals.
+int32_t launch_forward(const ara_yet *yet, int n_sr, bool hits, bool f32, const FwdItem *d_items, int n_items,
+                       hipStream_t st);
 
 // A layer's set-event bitmap folded onto 2^20 bits by OR (128 KB, staged in
 // LDS by the kernels that stream the trial-major YET): one filter per layer.
@@ -104,9 +106,10 @@ int32_t launch_set_filter(const OccTables *d_tabs, int n_words, uint32_t *filter
 int32_t check_layers(const ara_layers *layers, int32_t n_elts);
 
 // Enqueue the occurrence-table kernel for every layer.  `tabs` has one entry
-// per layer; the layer CSR must already be on the device.
+// per layer; the layer CSR must already be on the device.  f32_vals stores
+// each O rounded to binary32 (vals then holds floats at the same indices).
 int32_t launch_occ(const ara_tables *tables, const int32_t *d_elt_off, const int32_t *d_elt_ids,
                    const double *elt_terms, const double *layer_terms, int32_t n_layers, bool union_mode,
-                   OccTables *d_tabs, int n_sr, int32_t *d_err, hipStream_t st);
+                   bool f32_vals, OccTables *d_tabs, int n_sr, int32_t *d_err, hipStream_t st);
 
 }  // namespace ara

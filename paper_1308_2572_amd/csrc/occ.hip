@@ -167,7 +167,7 @@ __global__ __launch_bounds__(1024) void k_occ_eval(const float *__restrict__ los
 // Phase two: one workgroup per (chunk, layer): the chunk's rank base (set
 // events of the super-range's earlier chunks), the rank of every bitmap word,
 // and the chunk's compacted values moved to their place in rank order.
-template <bool UNION>
+template <bool UNION, bool F32>
 __global__ __launch_bounds__(1024) void k_occ_rank(const OccTables *__restrict__ tabs) {
     __shared__ uint32_t wtot2[2], tot;
     const int s = blockIdx.x / kPasses, p = blockIdx.x % kPasses, j = blockIdx.y;
@@ -185,7 +185,8 @@ __global__ __launch_bounds__(1024) void k_occ_rank(const OccTables *__restrict__
     const size_t src = static_cast<size_t>(s) * kSr + static_cast<size_t>(p) * (kPassWords * 32);
     const size_t dst = static_cast<size_t>(s) * kSr + base;
     for (uint32_t i = tid; i < cnt; i += blockDim.x) {
-        T.vals[dst + i] = T.dense[src + i];
+        if (F32) reinterpret_cast<float *>(T.vals)[dst + i] = static_cast<float>(T.dense[src + i]);
+        else T.vals[dst + i] = T.dense[src + i];
         if (UNION) T.cnt[dst + i] = T.dense_nb[src + i];
     }
 }
@@ -209,18 +210,20 @@ int32_t check_layers(const ara_layers *layers, int32_t n_elts) {
 
 int32_t launch_occ(const ara_tables *tables, const int32_t *d_elt_off, const int32_t *d_elt_ids,
                    const double *elt_terms, const double *layer_terms, int32_t n_layers, bool union_mode,
-                   OccTables *d_tabs, int n_sr, int32_t *d_err, hipStream_t st) {
+                   bool f32_vals, OccTables *d_tabs, int n_sr, int32_t *d_err, hipStream_t st) {
     if (n_layers == 0 || n_sr == 0) return ARA_OK;
     dim3 grid_a(static_cast<unsigned>(n_sr * kPasses), static_cast<unsigned>(n_layers));
     dim3 grid_b(static_cast<unsigned>(n_sr * kPasses), static_cast<unsigned>(n_layers));
     if (union_mode) {
         k_occ_eval<true><<<grid_a, 1024, 0, st>>>(tables->loss, tables->present, tables->catalog, tables->words,
                                                   d_elt_off, d_elt_ids, elt_terms, layer_terms, d_tabs, d_err);
-        k_occ_rank<true><<<grid_b, 1024, 0, st>>>(d_tabs);
+        if (f32_vals) k_occ_rank<true, true><<<grid_b, 1024, 0, st>>>(d_tabs);
+        else k_occ_rank<true, false><<<grid_b, 1024, 0, st>>>(d_tabs);
     } else {
         k_occ_eval<false><<<grid_a, 1024, 0, st>>>(tables->loss, tables->present, tables->catalog, tables->words,
                                                    d_elt_off, d_elt_ids, elt_terms, layer_terms, d_tabs, d_err);
-        k_occ_rank<false><<<grid_b, 1024, 0, st>>>(d_tabs);
+        if (f32_vals) k_occ_rank<false, true><<<grid_b, 1024, 0, st>>>(d_tabs);
+        else k_occ_rank<false, false><<<grid_b, 1024, 0, st>>>(d_tabs);
     }
     ARA_HIP(hipGetLastError());
     return ARA_OK;

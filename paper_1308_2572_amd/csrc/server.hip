@@ -164,7 +164,7 @@ int32_t ServerImpl::setup(Job &j) {
     ARA_HIP(hipMemcpyAsync(j.d_tab, &j.tab, sizeof(OccTables), hipMemcpyHostToDevice, st));
     // the quote's occurrence table; device-side term errors land in the metric workspace header
     int32_t *d_err = static_cast<int32_t *>(j.met_ws);
-    int32_t rc = launch_occ(&tables, j.d_off, j.d_ids, elt_terms, j.d_lterm, 1, false, j.d_tab, z.n_sr, d_err, st);
+    int32_t rc = launch_occ(&tables, j.d_off, j.d_ids, elt_terms, j.d_lterm, 1, false, false, j.d_tab, z.n_sr, d_err, st);
     if (rc) return rc;
     j.b_lo = static_cast<int>(j.q.trial_begin / yet.trials_per_block);
     j.b_hi = static_cast<int>((j.q.trial_end + yet.trials_per_block - 1) / yet.trials_per_block);
@@ -251,7 +251,7 @@ void ServerImpl::loop() {
             }
             if (n_items > 0) {
                 hipMemcpyAsync(d_items[ring], hi, n_items * sizeof(FwdItem), hipMemcpyHostToDevice, st);
-                rc = launch_forward(&yet, z.n_sr, false, d_items[ring], n_items, st);
+                rc = launch_forward(&yet, z.n_sr, false, false, d_items[ring], n_items, st);
                 hipEventRecord(item_ev[ring], st);
                 item_used[ring] = true;
                 ring = (ring + 1) % kRing;

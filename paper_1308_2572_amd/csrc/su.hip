@@ -577,7 +577,7 @@ extern "C" int32_t ara_ylt_forward_su(const ara_tables *tables, const float *sig
 
     {
         ProfScope prof(ARA_PROF_OCC, st);
-        if ((rc = launch_occ(tables, d_off, d_ids, elt_terms, layer_terms, L, true, d_tabs, n_sr, d_err, st)))
+        if ((rc = launch_occ(tables, d_off, d_ids, elt_terms, layer_terms, L, true, false, d_tabs, n_sr, d_err, st)))
             return rc;
         k_su_scan<<<dim3(static_cast<unsigned>(n_sr), static_cast<unsigned>(L)), kSuThreads, 0, st>>>(d_tabs, n_sr,
                                                                                                     ooff, otot);

@@ -323,7 +323,7 @@ extern "C" int32_t ara_yelt_forward(const ara_tables *tables, const int64_t *off
     if ((rc = img.send(st))) return rc;
     {
         ProfScope prof(ARA_PROF_OCC, st);
-        if ((rc = launch_occ(tables, d_off, d_ids, elt_terms, layer_terms, L, false, d_tabs, z.n_sr, d_err, st)))
+        if ((rc = launch_occ(tables, d_off, d_ids, elt_terms, layer_terms, L, false, false, d_tabs, z.n_sr, d_err, st)))
             return rc;
     }
     if ((rc = launch_set_filter(d_tabs, z.n_sr * kSrWords, d_filter, L, st))) return rc;

@@ -82,9 +82,14 @@ def test_argument_validation_before_device_work(ara):
     lay = ara.Layers([0, 1], [0])
     assert lib.ara_ylt_workspace_bytes(ctypes.byref(tables), ctypes.byref(yet2), ctypes.byref(lay.handle), 0,
                                        ctypes.byref(nb)) == 1
+    # the two known flags are accepted alone and together; any other bit is not
+    for fl in (ara.ARA_F_EMIT_HITS, ara.ARA_F_FP32_ACCUM, ara.ARA_F_EMIT_HITS | ara.ARA_F_FP32_ACCUM):
+        assert lib.ara_ylt_workspace_bytes(ctypes.byref(tables), ctypes.byref(yet), ctypes.byref(lay.handle), fl,
+                                           ctypes.byref(nb)) == 0
     # unknown flag, and hits without the flag
-    assert lib.ara_ylt_workspace_bytes(ctypes.byref(tables), ctypes.byref(yet), ctypes.byref(lay.handle), 8,
-                                       ctypes.byref(nb)) == 1
+    for fl in (4, 8, 1 << 31):
+        assert lib.ara_ylt_workspace_bytes(ctypes.byref(tables), ctypes.byref(yet), ctypes.byref(lay.handle), fl,
+                                           ctypes.byref(nb)) == 1
     assert lib.ara_ylt_forward(ctypes.byref(tables), ctypes.byref(yet), ctypes.byref(lay.handle), None, None, 0, 5,
                                0, None, None, ctypes.c_void_p(16), None, 0, None) == 1
     # trial range outside the YET
