@@ -205,6 +205,8 @@ def main() -> int:
         "one_time_s": {"generate": t_gen, "elt_tables": t_tables, "yet_layout": t_prepare},
         "step_hbm_frac": (algo_bytes + 8.0 * int(w.elts.rec_off[-1])) / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS,
         "metrics": {"aal": float(m[0]), "pml": float(m[1]), "tvar": float(m[2])},
+        # one table read per (occurrence, layer) once the per-event steps are folded into the occurrence table
+        "physical_gathers_per_s": nnz * L / (ms_step * 1e-3),
     }
 
     if not args.no_fp32:
