@@ -125,10 +125,17 @@ typedef struct ara_yet {
     int64_t   slice_trials;      /* a multiple of trials_per_block */
     int64_t  *tr_off;            /* device [n_slices * catalog + 1] */
     uint32_t *tr_ent;            /* device [nnz] */
+    /* trial-major copy of the input (ARA_PREP_TRIAL_MAJOR; NULL otherwise) */
+    int64_t  *t_off;             /* device [n_trials + 1] */
+    int32_t  *t_ids;             /* device [nnz] */
+    int32_t  *t_cnt;             /* device [catalog]: occurrences of each event */
 } ara_yet;
 
 /* prepare flags */
 #define ARA_PREP_TRANSPOSED 1u   /* also build the event-major copy (needed by ara_ylt_backward) */
+#define ARA_PREP_TRIAL_MAJOR 2u  /* also keep a trial-major copy of offsets and ids: lets ara_ylt_backward
+                                    handle cotangents that are constant over most trials (the metrics')
+                                    from the deviating trials' own events */
 
 /* Upper bound of the device buffer ara_yet_prepare needs for these flags. */
 int32_t ara_yet_prepare_bytes(int64_t n_trials, int64_t nnz, int32_t catalog, uint32_t flags, size_t *bytes);
@@ -137,7 +144,7 @@ int32_t ara_yet_prepare_bytes(int64_t n_trials, int64_t nnz, int32_t catalog, ui
  * offsets: device int64 [n_trials+1], offsets[0] = 0, non-decreasing; trial t
  *          holds ids[offsets[t] .. offsets[t+1]).
  * ids:     device int32 [offsets[n_trials]].
- * flags:   0 or ARA_PREP_TRANSPOSED.
+ * flags:   ARA_PREP_TRANSPOSED, ARA_PREP_TRIAL_MAJOR (ARA_E_INVAL for other bits).
  * buf:     device buffer of at least ara_yet_prepare_bytes (same flags); it
  *          holds the prepared YET afterwards and must outlive every use of *out.
  * Validates every ID (ARA_E_RANGE) and every offset.  SYNCHRONISES `stream`

@@ -25,6 +25,7 @@ ARA_OK, ARA_E_INVAL, ARA_E_RANGE, ARA_E_DUP, ARA_E_NOSPACE, ARA_E_HIP, ARA_E_LIM
 ARA_F_EMIT_HITS = 1
 ARA_F_FP32_ACCUM = 2
 PREP_TRANSPOSED = 1          # ARA_PREP_TRANSPOSED
+PREP_TRIAL_MAJOR = 2         # ARA_PREP_TRIAL_MAJOR
 ARA_MAX_COTANGENTS = 4
 
 _c_i32, _c_i64, _c_u32, _c_f64, _c_p, _c_sz = (ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_double,
@@ -43,7 +44,7 @@ class ara_yet(ctypes.Structure):
                 ("trials_per_block", _c_i32), ("n_blocks", _c_i32), ("max_occ", _c_i32),
                 ("n_codes", _c_i64), ("code", _c_p), ("seg_base", _c_p), ("seg_run", _c_p), ("lane_start", _c_p),
                 ("n_slices", _c_i32), ("reserved", _c_i32), ("slice_trials", _c_i64), ("tr_off", _c_p),
-                ("tr_ent", _c_p)]
+                ("tr_ent", _c_p), ("t_off", _c_p), ("t_ids", _c_p), ("t_cnt", _c_p)]
 
 
 class ara_tables(ctypes.Structure):
@@ -154,15 +155,20 @@ def _workspace(nbytes: int, device) -> torch.Tensor:
 class PreparedYet:
     """A YET laid out on the device by ara_yet_prepare (keeps its buffer alive)."""
 
-    def __init__(self, offsets: torch.Tensor, ids: torch.Tensor, catalog: int, transposed: bool = True):
+    def __init__(self, offsets: torch.Tensor, ids: torch.Tensor, catalog: int, transposed: bool = True,
+                 trial_major: Optional[bool] = None):
         """transposed: also build the event-major copy that the backward
-        needs (ARA_PREP_TRANSPOSED); leave it off for forward-only use."""
+        needs (ARA_PREP_TRANSPOSED); leave it off for forward-only use.
+        trial_major: also keep a trial-major copy (ARA_PREP_TRIAL_MAJOR), with
+        which the backward of the metrics reads only the trials whose weight
+        differs from the common one; on by default with `transposed`."""
         lib = library()
         if offsets.dtype != torch.int64 or ids.dtype != torch.int32:
             raise ValueError("offsets must be int64 and ids int32")
         n_trials = offsets.numel() - 1
         nnz = ids.numel()
-        flags = PREP_TRANSPOSED if transposed else 0
+        trial_major = transposed if trial_major is None else trial_major
+        flags = (PREP_TRANSPOSED if transposed else 0) | (PREP_TRIAL_MAJOR if trial_major else 0)
         nb = _c_sz()
         _check(lib.ara_yet_prepare_bytes(n_trials, nnz, catalog, flags, ctypes.byref(nb)), "ara_yet_prepare_bytes")
         self.device = offsets.device
@@ -175,10 +181,10 @@ class PreparedYet:
         self.transposed = transposed
 
     @classmethod
-    def from_numpy(cls, yet, device="cuda", transposed: bool = True):
+    def from_numpy(cls, yet, device="cuda", transposed: bool = True, trial_major: Optional[bool] = None):
         off = torch.from_numpy(np.ascontiguousarray(yet.offsets, np.int64)).to(device)
         ids = torch.from_numpy(np.ascontiguousarray(yet.ids, np.int32)).to(device)
-        out = cls(off, ids, int(yet.catalog), transposed=transposed)
+        out = cls(off, ids, int(yet.catalog), transposed=transposed, trial_major=trial_major)
         return out
 
 

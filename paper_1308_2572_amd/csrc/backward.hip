@@ -29,6 +29,18 @@
 // result does not depend on the order; (6) per 4096-event chunk, W times
 // the per-event derivatives, reduced in a fixed order; (7) a fixed-order sum
 // of the chunk partials into the outputs.
+//
+// Step (5) has a second form for cotangents that take one value on most
+// trials, as the metrics' do (AAL: the same weight wherever the aggregate
+// clamp is linear; PML, TVaR: zero outside the tied or top trials).  With c
+// that common fixed-point value and D the trials whose value differs,
+//   W(e) = c * (occurrences of e) + sum over t in D of (v_t - c) * (occurrences of e in t),
+// integer arithmetic that gives the gather's result bit for bit.  The
+// occurrence counts come from the event-major offsets, the second term from
+// the trial-major copy of the deviating trials' events.  It is used when D
+// holds at most an eighth of the trials (and either the call covers every
+// trial or c = 0); the decision is taken on the device from the counts, so
+// both forms are enqueued and the one not chosen returns at once.
 #include "occ.h"
 #include "wave.h"
 
@@ -199,6 +211,42 @@ __global__ __launch_bounds__(256) void k_bwd_hot(const OccTables *__restrict__ t
     }
 }
 
+constexpr int kCand = 8;   // candidates for the common value of a row: 0 and seven sampled trials
+constexpr int kDevChunk = 4096;   // trials per workgroup when counting and listing them
+
+struct BwdSparse {
+    const int64_t *vq;                 // [n_layers][n][cs]
+    int64_t n, t0, n_trials;
+    int32_t cs, n_cot, catalog, n_sr;
+    int32_t full;                      // the call covers every trial
+    int32_t pad;
+    unsigned long long *ndev;          // [n_layers] deviating trials
+    int64_t *common;                   // [n_layers][kMaxCot] the chosen common value
+    int32_t *dev;                      // [n_layers][n] deviating trials (call-relative)
+    const int32_t *t_cnt;              // occurrences of each event
+    const int64_t *t_off;              // trial-major copy
+    const int32_t *t_ids;
+    const OccTables *tabs;
+    const int32_t *hot_ev, *hot_base;
+    int64_t *W;                        // [n_layers][n_cot][catalog], by hot index
+};
+
+__device__ __forceinline__ int64_t cand_value(const BwdSparse &P, int j, int c, int k) {
+    if (k == 0 || P.n == 0) return 0;
+    const int64_t t = (static_cast<int64_t>(k) * P.n) / kCand;
+    return P.vq[(static_cast<size_t>(j) * P.n + t) * P.cs + c];
+}
+
+// The second form's condition, the same in every kernel that reads it.
+__device__ __forceinline__ bool sparse_chosen(const BwdSparse &P, int j) {
+    const unsigned long long nd = P.ndev[j];
+    if (nd * kCand > static_cast<unsigned long long>(P.n)) return false;
+    if (P.full) return true;
+    for (int c = 0; c < P.n_cot; ++c)
+        if (P.common[static_cast<size_t>(j) * kMaxCot + c] != 0) return false;
+    return true;
+}
+
 struct BwdGather {
     const int64_t *tr_off;        // event-major YET
     const uint32_t *tr_ent;
@@ -209,6 +257,9 @@ struct BwdGather {
     const int32_t *hot_base;      // [n_layers][n_sr + 1]
     const int64_t *vq;            // [n_layers][n][CS]
     int64_t *W;                   // [n_layers][n_cot][catalog], by hot index
+    BwdSparse sp;                 // the second form's state
+    int32_t use_sp;               // 0 when the second form is not available (no trial-major copy)
+    int32_t pad2;
 };
 
 // (5) W(e) = sum of v_t over the occurrences (t, e), per hot event, as a
@@ -223,6 +274,7 @@ template <int CS, int G>
 __global__ __launch_bounds__(256) void k_bwd_w(BwdGather P) {
     constexpr int kU = 2;
     const int x = blockIdx.x % kSlices, wi = blockIdx.x / kSlices, nw = gridDim.x / kSlices, j = blockIdx.y;
+    if (P.use_sp && sparse_chosen(P.sp, j)) return;   // W comes from the deviating trials instead
     const int64_t tx0 = static_cast<int64_t>(x) * P.slice_trials;
     const int64_t ulo = max<int64_t>(P.t0 - tx0, 0), uhi = min<int64_t>(P.t1 - tx0, P.slice_trials);
     if (uhi <= ulo) return;   // the slice lies outside the call's trials
@@ -280,6 +332,154 @@ static void launch_bwd_w(int cs, dim3 grid, hipStream_t st, const BwdGather &S) 
     if (cs == 1) k_bwd_w<1, G><<<grid, 256, 0, st>>>(S);
     else if (cs == 2) k_bwd_w<2, G><<<grid, 256, 0, st>>>(S);
     else k_bwd_w<4, G><<<grid, 256, 0, st>>>(S);
+}
+
+// (5a) the common value of every row: of 0 and the values at seven sampled
+// trials, the one held by most of 1024 evenly spaced trials (the first on
+// ties).  Any choice gives the same W; a good one keeps the list of
+// deviating trials short.  One workgroup per layer.
+constexpr int kPickSamples = 1024;
+
+__global__ __launch_bounds__(kPickSamples) void k_bwd_pick(BwdSparse P) {
+    __shared__ uint32_t cnt[kMaxCot * kCand];
+    const int j = blockIdx.x, tid = threadIdx.x, lane = tid & 63;
+    if (tid < kMaxCot * kCand) cnt[tid] = 0;
+    __syncthreads();
+    const int64_t t = (static_cast<int64_t>(tid) * P.n) / kPickSamples;
+    const int64_t *q = P.vq + (static_cast<size_t>(j) * P.n + t) * P.cs;
+    for (int c = 0; c < P.n_cot; ++c) {
+        const int64_t v = q[c];
+        for (int k = 0; k < kCand; ++k) {
+            const uint64_t m = __ballot(v == cand_value(P, j, c, k));
+            if (lane == 0 && m) atomicAdd(&cnt[c * kCand + k], static_cast<uint32_t>(__popcll(m)));
+        }
+    }
+    __syncthreads();
+    if (tid < kMaxCot) {
+        int64_t cm = 0;
+        if (tid < P.n_cot) {
+            int best = 0;
+            for (int k = 1; k < kCand; ++k)
+                if (cnt[tid * kCand + k] > cnt[tid * kCand + best]) best = k;
+            cm = cand_value(P, j, tid, best);
+        }
+        P.common[static_cast<size_t>(j) * kMaxCot + tid] = cm;
+    }
+}
+
+// (5b) the list of trials where some row differs from its common value.
+// A workgroup gathers the deviating trials of its chunk of kDevChunk trials
+// in LDS and reserves their place in the list with one atomic.
+__global__ __launch_bounds__(1024) void k_bwd_dev(BwdSparse P) {
+    __shared__ int32_t buf[kDevChunk];
+    __shared__ uint32_t nbuf;
+    __shared__ unsigned long long base;
+    const int j = blockIdx.y, lane = threadIdx.x & 63;
+    int64_t cm[kMaxCot];
+#pragma unroll
+    for (int c = 0; c < kMaxCot; ++c) cm[c] = P.common[static_cast<size_t>(j) * kMaxCot + c];
+    if (threadIdx.x == 0) nbuf = 0;
+    __syncthreads();
+    const int64_t *q = P.vq + static_cast<size_t>(j) * P.n * P.cs;
+    const int64_t c0 = static_cast<int64_t>(blockIdx.x) * kDevChunk;
+    const int64_t c1 = min<int64_t>(c0 + kDevChunk, P.n);
+    for (int64_t t0 = c0; t0 < c1; t0 += blockDim.x) {   // uniform
+        const int64_t t = t0 + threadIdx.x;
+        bool d = false;
+        if (t < c1)
+#pragma unroll
+            for (int c = 0; c < kMaxCot; ++c)
+                if (c < P.n_cot) d = d || (q[static_cast<size_t>(t) * P.cs + c] != cm[c]);
+        const uint64_t m = __ballot(d);
+        if (m) {
+            uint32_t wb = 0;
+            if (lane == 0) wb = atomicAdd(&nbuf, static_cast<uint32_t>(__popcll(m)));
+            wb = __shfl(wb, 0);
+            if (d) {
+                const uint32_t pos = __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(m >> 32),
+                                                               __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(m), 0u));
+                buf[wb + pos] = static_cast<int32_t>(t);
+            }
+        }
+    }
+    __syncthreads();
+    const uint32_t nb = nbuf;
+    if (nb == 0) return;   // uniform
+    if (threadIdx.x == 0) base = atomicAdd(&P.ndev[j], static_cast<unsigned long long>(nb));
+    __syncthreads();
+    int32_t *dv = P.dev + static_cast<size_t>(j) * P.n + base;
+    for (uint32_t i = threadIdx.x; i < nb; i += blockDim.x) dv[i] = buf[i];
+}
+
+// (5c) W(e) = c * (occurrences of e) for every hot event (when the second
+// form is chosen; the accumulators are zero from step 4 otherwise)
+__global__ __launch_bounds__(256) void k_bwd_winit(BwdSparse P) {
+    const int j = blockIdx.y;
+    if (!sparse_chosen(P, j) || !P.full) return;
+    const int H = P.hot_base[static_cast<size_t>(j) * (P.n_sr + 1) + P.n_sr];
+    const int32_t *hev = P.hot_ev + static_cast<size_t>(j) * P.catalog;
+    int64_t *Wj = P.W + static_cast<size_t>(j) * P.n_cot * P.catalog;
+    for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < H; g += gridDim.x * blockDim.x) {
+        const int64_t cnt = P.t_cnt[hev[g]];
+#pragma unroll
+        for (int c = 0; c < kMaxCot; ++c)
+            if (c < P.n_cot)
+                Wj[static_cast<size_t>(c) * P.catalog + g] = static_cast<int64_t>(
+                    static_cast<unsigned long long>(P.common[static_cast<size_t>(j) * kMaxCot + c]) *
+                    static_cast<unsigned long long>(cnt));   // exact modulo 2^64, like every sum below
+    }
+}
+
+// (5d) the deviating trials: a wavefront per trial adds v_t - c to W of each
+// hot event of the trial, one integer atomic per (occurrence, row)
+__global__ __launch_bounds__(256) void k_bwd_wsparse(BwdSparse P) {
+    const int j = blockIdx.y, lane = threadIdx.x & 63;
+    if (!sparse_chosen(P, j)) return;
+    const int64_t nd = static_cast<int64_t>(P.ndev[j]);
+    const OccTables T = P.tabs[j];
+    const int32_t *hb = P.hot_base + static_cast<size_t>(j) * (P.n_sr + 1);
+    const int64_t *q = P.vq + static_cast<size_t>(j) * P.n * P.cs;
+    int64_t *Wj = P.W + static_cast<size_t>(j) * P.n_cot * P.catalog;
+    const int waves = gridDim.x * (blockDim.x >> 6);
+    for (int64_t i = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); i < nd; i += waves) {
+        const int32_t u = P.dev[static_cast<size_t>(j) * P.n + i];
+        unsigned long long dl[kMaxCot];
+#pragma unroll
+        for (int c = 0; c < kMaxCot; ++c)
+            dl[c] = c < P.n_cot ? static_cast<unsigned long long>(q[static_cast<size_t>(u) * P.cs + c]) -
+                                      static_cast<unsigned long long>(P.common[static_cast<size_t>(j) * kMaxCot + c])
+                                : 0ull;
+        const int64_t t = P.t0 + u;
+        const int64_t a = P.t_off[t], b = P.t_off[t + 1];
+        constexpr int kU = 16;   // events per lane in flight: a 1000-event trial in one round
+        for (int64_t k0 = a; k0 < b; k0 += 64 * kU) {
+            int e[kU];
+#pragma unroll
+            for (int v = 0; v < kU; ++v) {
+                const int64_t k = k0 + v * 64 + lane;
+                e[v] = k < b ? P.t_ids[k] : -1;
+            }
+            uint2 w[kU];
+#pragma unroll
+            for (int v = 0; v < kU; ++v) {
+                const int ev = e[v] < 0 ? 0 : e[v];
+                w[v] = T.br[static_cast<size_t>(ev >> kSrBits) * kSrWords + ((ev & (kSr - 1)) >> 5)];
+            }
+#pragma unroll
+            for (int v = 0; v < kU; ++v) {
+                if (e[v] < 0) continue;
+                const int s = e[v] >> kSrBits;
+                const uint32_t bit = static_cast<uint32_t>(e[v] & 31);
+                if ((w[v].x >> bit) & 1u) {
+                    const int g = hb[s] + static_cast<int>(w[v].y + __popc(w[v].x & ((1u << bit) - 1u)));
+#pragma unroll
+                    for (int c = 0; c < kMaxCot; ++c)
+                        if (dl[c])
+                            atomicAdd(reinterpret_cast<unsigned long long *>(&Wj[static_cast<size_t>(c) * P.catalog + g]), dl[c]);
+                }
+            }
+        }
+    }
 }
 
 struct BwdGrad {
@@ -491,6 +691,8 @@ static int bwd_nwg_v(int64_t n) {   // about two trials per thread, at most 512 
     return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>((n + 2047) / 2048, 512)));
 }
 
+static int64_t dev_blocks(int64_t n) { return std::max<int64_t>(1, (n + kDevChunk - 1) / kDevChunk); }
+
 static int bwd_cs(int n_cot) { return n_cot <= 1 ? 1 : (n_cot <= 2 ? 2 : 4); }
 
 static BwdLayout bwd_layout(const ara_tables *tables, const ara_layers *layers, int n_cot, int64_t n) {
@@ -510,6 +712,9 @@ static BwdLayout bwd_layout(const ara_tables *tables, const ara_layers *layers, 
     size_t b = c.bytes() + static_cast<size_t>(L) * B.z.per_layer;
     Carver d(nullptr);
     d.take<VScale>(static_cast<size_t>(std::max(L * n_cot, 1)));
+    d.take<unsigned long long>(static_cast<size_t>(std::max(L, 1)));
+    d.take<int64_t>(static_cast<size_t>(std::max(L, 1)) * kMaxCot);
+    d.take<int32_t>(static_cast<size_t>(L) * std::max<int64_t>(n, 1));
     d.take<double>(static_cast<size_t>(L) * n_cot * B.nwg_v * 2);
     d.take<int64_t>(static_cast<size_t>(L) * std::max<int64_t>(n, 1) * B.cs);
     d.take<int32_t>(static_cast<size_t>(L) * cat);
@@ -579,6 +784,8 @@ extern "C" int32_t ara_ylt_backward(const ara_tables *tables, const ara_yet *yet
     int32_t *d_ids = c.take<int32_t>(static_cast<size_t>(std::max(nJ, 1)));
     OccTables *d_tabs = c.take<OccTables>(static_cast<size_t>(L));
     VScale *vs = c.take<VScale>(static_cast<size_t>(L * n_cot));
+    unsigned long long *ndev = c.take<unsigned long long>(static_cast<size_t>(L));
+    int64_t *common = c.take<int64_t>(static_cast<size_t>(L) * kMaxCot);
     std::vector<OccTables> tabs(static_cast<size_t>(L));
     for (int j = 0; j < L; ++j) tabs[j] = occ_carve(c, B.z, false);
     double *aggpart = c.take<double>(static_cast<size_t>(L) * n_cot * bwd_nwg_v(n) * 2);
@@ -588,11 +795,12 @@ extern "C" int32_t ara_ylt_backward(const ara_tables *tables, const ara_yet *yet
     int64_t *W = c.take<int64_t>(static_cast<size_t>(L) * n_cot * tables->catalog);
     double *part_elt = c.take<double>(static_cast<size_t>(B.n_chunks) * kGradWaves * std::max(nJ, 1) * n_cot * 3);
     double *part_occ = c.take<double>(static_cast<size_t>(L) * B.n_chunks * kGradWaves * n_cot * 2);
-    HeadImage img(ws);   // clears the error header and the weight scales
+    int32_t *dev = c.take<int32_t>(static_cast<size_t>(L) * std::max<int64_t>(n, 1));
+    HeadImage img(ws);   // clears the error header, the weight scales and the deviating-trial counts
     img.put(d_off, layers->elt_off, static_cast<size_t>(L + 1));
     img.put(d_ids, layers->elt_ids, static_cast<size_t>(nJ));
     img.put(d_tabs, tabs.data(), tabs.size());
-    img.cover(vs + L * n_cot);
+    img.cover(ndev + L);
     if ((rc = img.send(st))) return rc;
 
     {
@@ -623,8 +831,38 @@ extern "C" int32_t ara_ylt_backward(const ara_tables *tables, const ara_yet *yet
     S.hot_base = hot_base;
     S.vq = vq;
     S.W = W;
+    // the second form of step (5) needs the trial-major copy
+    BwdSparse &Q = S.sp;
+    S.use_sp = yet->t_off != nullptr && yet->t_ids != nullptr && yet->t_cnt != nullptr;
+    Q.vq = vq;
+    Q.n = n;
+    Q.t0 = trial_begin;
+    Q.n_trials = yet->n_trials;
+    Q.cs = B.cs;
+    Q.n_cot = n_cot;
+    Q.catalog = tables->catalog;
+    Q.n_sr = B.z.n_sr;
+    Q.full = trial_begin == 0 && trial_end == yet->n_trials;
+    Q.ndev = ndev;
+    Q.common = common;
+    Q.dev = dev;
+    Q.t_cnt = yet->t_cnt;
+    Q.t_off = yet->t_off;
+    Q.t_ids = yet->t_ids;
+    Q.tabs = d_tabs;
+    Q.hot_ev = hot_ev;
+    Q.hot_base = hot_base;
+    Q.W = W;
     {
         ProfScope prof(ARA_PROF_BWD, st);
+        if (S.use_sp) {
+            const unsigned gt = static_cast<unsigned>(dev_blocks(n));
+            k_bwd_pick<<<L, kPickSamples, 0, st>>>(Q);
+            k_bwd_dev<<<dim3(gt, L), 1024, 0, st>>>(Q);
+            const unsigned gh = static_cast<unsigned>(std::min<int64_t>((tables->catalog + 255) / 256, 1024));
+            k_bwd_winit<<<dim3(gh, L), 256, 0, st>>>(Q);
+            k_bwd_wsparse<<<dim3(2048, L), 256, 0, st>>>(Q);
+        }
         // four 256-thread workgroups per CU, a multiple of the slice count
         const int cu = device_cu_count();
         const unsigned gx = static_cast<unsigned>(kSlices * std::max(1, (4 * cu) / kSlices));

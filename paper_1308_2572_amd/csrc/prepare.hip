@@ -57,7 +57,7 @@ static int64_t max_codes(const Geometry &g, int64_t nnz) {
     return nnz + static_cast<int64_t>(g.nseg) * (2 * g.tg + 4 * kWave);
 }
 
-static size_t prepare_bytes(const Geometry &g, int64_t nnz, int32_t catalog, uint32_t flags) {
+static size_t prepare_bytes(const Geometry &g, int64_t n_trials, int64_t nnz, int32_t catalog, uint32_t flags) {
     Carver c(nullptr);
     c.take<uint16_t>(static_cast<size_t>(max_codes(g, nnz)) + kPadCodes);
     c.take<int64_t>(g.nseg);
@@ -68,6 +68,11 @@ static size_t prepare_bytes(const Geometry &g, int64_t nnz, int32_t catalog, uin
         c.take<int64_t>(static_cast<size_t>(kSlices) * catalog + 1);
         c.take<uint32_t>(static_cast<size_t>(std::max<int64_t>(nnz, 1)));
         c.take<int64_t>(static_cast<size_t>(kSlices) * g.n_ranges);
+    }
+    if (flags & ARA_PREP_TRIAL_MAJOR) {
+        c.take<int64_t>(static_cast<size_t>(n_trials) + 1);
+        c.take<int32_t>(static_cast<size_t>(std::max<int64_t>(nnz, 1)));
+        c.take<int32_t>(static_cast<size_t>(catalog));
     }
     return c.bytes();
 }
@@ -188,11 +193,13 @@ __global__ __launch_bounds__(1024) void k_prep_codes(const int64_t *__restrict__
 }
 
 // Largest number of occurrences of any single event (bounds the backward's
-// fixed-point accumulators).
+// fixed-point accumulators), and on request every event's count (ev_count,
+// [catalog]).  0xFFFF never encodes an occurrence, so the counts are exact.
 __global__ __launch_bounds__(1024) void k_prep_max_occ(const uint16_t *__restrict__ code,
                                                        const int64_t *__restrict__ seg_base,
                                                        const int32_t *__restrict__ seg_run, int n_blocks,
-                                                       int n_ranges, int32_t *__restrict__ max_occ) {
+                                                       int n_ranges, int32_t *__restrict__ max_occ,
+                                                       int32_t catalog, int32_t *__restrict__ ev_count) {
     __shared__ uint32_t hist[kRange];
     __shared__ uint32_t red[16];
     for (int i = threadIdx.x; i < kRange; i += blockDim.x) hist[i] = 0;
@@ -210,6 +217,11 @@ __global__ __launch_bounds__(1024) void k_prep_max_occ(const uint16_t *__restric
         }
     }
     __syncthreads();
+    if (ev_count)
+        for (int i = threadIdx.x; i < kRange; i += blockDim.x) {
+            const int64_t e = static_cast<int64_t>(r) * kRange + i;
+            if (e < catalog) ev_count[e] = static_cast<int32_t>(hist[i]);
+        }
     uint32_t m = 0;
     for (int i = threadIdx.x; i < kRange; i += blockDim.x) m = std::max(m, hist[i]);
     for (int o = 32; o > 0; o >>= 1) m = std::max(m, static_cast<uint32_t>(__shfl_xor(static_cast<int>(m), o)));
@@ -342,8 +354,8 @@ extern "C" int32_t ara_yet_prepare_bytes(int64_t n_trials, int64_t nnz, int32_t 
     if (!bytes) return fail(ARA_E_INVAL, "ara_yet_prepare_bytes: null output");
     if (n_trials < 0 || nnz < 0 || catalog <= 0) return fail(ARA_E_INVAL, "ara_yet_prepare_bytes: negative size");
     if (catalog > ARA_MAX_CATALOG) return fail(ARA_E_LIMIT, "catalog exceeds ARA_MAX_CATALOG");
-    if (flags & ~ARA_PREP_TRANSPOSED) return fail(ARA_E_INVAL, "ara_yet_prepare_bytes: unknown flag");
-    *bytes = prepare_bytes(geometry(n_trials, catalog), nnz, catalog, flags);
+    if (flags & ~(ARA_PREP_TRANSPOSED | ARA_PREP_TRIAL_MAJOR)) return fail(ARA_E_INVAL, "ara_yet_prepare_bytes: unknown flag");
+    *bytes = prepare_bytes(geometry(n_trials, catalog), n_trials, nnz, catalog, flags);
     return ARA_OK;
 }
 
@@ -352,7 +364,7 @@ extern "C" int32_t ara_yet_prepare(const int64_t *offsets, const int32_t *ids, i
     if (!offsets || !buf || !out) return fail(ARA_E_INVAL, "ara_yet_prepare: null pointer");
     if (n_trials < 0 || catalog <= 0) return fail(ARA_E_INVAL, "ara_yet_prepare: bad size");
     if (catalog > ARA_MAX_CATALOG) return fail(ARA_E_LIMIT, "catalog exceeds ARA_MAX_CATALOG");
-    if (flags & ~ARA_PREP_TRANSPOSED) return fail(ARA_E_INVAL, "ara_yet_prepare: unknown flag");
+    if (flags & ~(ARA_PREP_TRANSPOSED | ARA_PREP_TRIAL_MAJOR)) return fail(ARA_E_INVAL, "ara_yet_prepare: unknown flag");
     hipStream_t st = static_cast<hipStream_t>(stream);
     const Geometry g = geometry(n_trials, catalog);
     int64_t ends[2] = {0, 0};
@@ -362,7 +374,7 @@ extern "C" int32_t ara_yet_prepare(const int64_t *offsets, const int32_t *ids, i
     if (ends[0] != 0 || ends[1] < 0) return fail(ARA_E_RANGE, "offsets[0] must be 0 and offsets[n] >= 0");
     const int64_t nnz = ends[1];
     if (nnz > 0 && !ids) return fail(ARA_E_INVAL, "ara_yet_prepare: null ids");
-    if (buf_bytes < prepare_bytes(g, nnz, catalog, flags)) return fail(ARA_E_NOSPACE, "ara_yet_prepare: buffer too small");
+    if (buf_bytes < prepare_bytes(g, n_trials, nnz, catalog, flags)) return fail(ARA_E_NOSPACE, "ara_yet_prepare: buffer too small");
 
     Carver c(buf);
     uint16_t *code = c.take<uint16_t>(static_cast<size_t>(max_codes(g, nnz)) + kPadCodes);
@@ -381,6 +393,18 @@ extern "C" int32_t ara_yet_prepare(const int64_t *offsets, const int32_t *ids, i
         tr_ent = c.take<uint32_t>(static_cast<size_t>(std::max<int64_t>(nnz, 1)));
         rtot = c.take<int64_t>(static_cast<size_t>(kSlices) * g.n_ranges);
     }
+    int64_t *t_off = nullptr;
+    int32_t *t_ids = nullptr, *t_cnt = nullptr;
+    if (flags & ARA_PREP_TRIAL_MAJOR) {
+        t_off = c.take<int64_t>(static_cast<size_t>(n_trials) + 1);
+        t_ids = c.take<int32_t>(static_cast<size_t>(std::max<int64_t>(nnz, 1)));
+        t_cnt = c.take<int32_t>(static_cast<size_t>(catalog));
+        ARA_HIP(hipMemsetAsync(t_cnt, 0, static_cast<size_t>(catalog) * sizeof(int32_t), st));
+        ARA_HIP(hipMemcpyAsync(t_off, offsets, (static_cast<size_t>(n_trials) + 1) * sizeof(int64_t),
+                               hipMemcpyDeviceToDevice, st));
+        if (nnz > 0)
+            ARA_HIP(hipMemcpyAsync(t_ids, ids, static_cast<size_t>(nnz) * sizeof(int32_t), hipMemcpyDeviceToDevice, st));
+    }
     ARA_HIP(hipMemsetAsync(misc, 0, 32 * sizeof(int64_t), st));
 
     ara_yet y{};
@@ -397,6 +421,9 @@ extern "C" int32_t ara_yet_prepare(const int64_t *offsets, const int32_t *ids, i
     y.seg_base = seg_base;
     y.seg_run = seg_run;
     y.lane_start = lane_start;
+    y.t_off = t_off;
+    y.t_ids = t_ids;
+    y.t_cnt = t_cnt;
     if (transposed) {
         y.n_slices = kSlices;
         y.slice_trials = static_cast<int64_t>(g.slice_blocks) * g.tb;
@@ -444,7 +471,8 @@ extern "C" int32_t ara_yet_prepare(const int64_t *offsets, const int32_t *ids, i
                                                     nullptr);
     ARA_HIP(hipGetLastError());
     ARA_HIP(hipStreamSynchronize(st));   // the host copies of base and run live in this scope
-    k_prep_max_occ<<<g.n_ranges, 1024, 0, st>>>(code, seg_base, seg_run, g.n_blocks, g.n_ranges, max_occ);
+    k_prep_max_occ<<<g.n_ranges, 1024, 0, st>>>(code, seg_base, seg_run, g.n_blocks, g.n_ranges, max_occ, catalog,
+                                                t_cnt);
     ARA_HIP(hipGetLastError());
     if (transposed) {
         const dim3 grid(static_cast<unsigned>(g.n_ranges), kSlices);

@@ -52,7 +52,12 @@ def test_size_queries(ara):
     plain = nb.value
     assert lib.ara_yet_prepare_bytes(1000, 1_000_000, 200_000, ara.PREP_TRANSPOSED, ctypes.byref(nb)) == 0
     assert nb.value >= plain + 4 * 1_000_000 + 8 * (8 * 200_000 + 1)     # event-major entries and list offsets
-    assert lib.ara_yet_prepare_bytes(1000, 1_000_000, 200_000, 2, ctypes.byref(nb)) == 1   # unknown flag
+    tr = nb.value
+    # the trial-major copy adds the offsets and the IDs once more
+    assert lib.ara_yet_prepare_bytes(1000, 1_000_000, 200_000, ara.PREP_TRANSPOSED | ara.PREP_TRIAL_MAJOR,
+                                     ctypes.byref(nb)) == 0
+    assert nb.value >= tr + 4 * 1_000_000 + 8 * 1001
+    assert lib.ara_yet_prepare_bytes(1000, 1_000_000, 200_000, 4, ctypes.byref(nb)) == 1   # unknown flag
     assert lib.ara_build_elt_tables_bytes(15, 2_000_000, ctypes.byref(nb)) == 0
     assert nb.value >= 15 * 2_000_000 * 4
     assert lib.ara_metrics_workspace_bytes(2, 1000, ctypes.byref(nb)) == 0

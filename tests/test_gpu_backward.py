@@ -224,3 +224,69 @@ def test_cotangent_row_limit(ara):
     with pytest.raises(ara.AraError) as ex:
         e.backward(s_pre, torch.zeros((5, w.layers.n_layers, w.yet.n_trials), dtype=torch.float64, device="cuda"))
     assert ex.value.status == 6
+
+
+# ---------------------------------------------------------- the two forms of W
+def _both_forms(ara, w):
+    import torch
+    tables = ara.EltTables.from_numpy(w.elts)
+    layers = ara.Layers(w.layers.elt_off, w.layers.elt_ids)
+    et = torch.tensor(w.elts.terms, dtype=torch.float64, device="cuda")
+    lt = torch.tensor(w.layers.terms, dtype=torch.float64, device="cuda")
+    with_tm = ara.PreparedYet.from_numpy(w.yet, trial_major=True)
+    without = ara.PreparedYet.from_numpy(w.yet, trial_major=False)
+
+    def run(yet, s_pre, cot, t0=0, t1=None):
+        ge, gl = ara.ylt_backward(tables, yet, layers, et, lt, s_pre, cot, t0, t1)
+        return ge.cpu().numpy(), gl.cpu().numpy()
+
+    ylt, s_pre, _ = ara.ylt_forward(tables, with_tm, layers, et, lt, want_s_pre=True)
+    return ylt, s_pre, (lambda *a, **k: run(with_tm, *a, **k)), (lambda *a, **k: run(without, *a, **k))
+
+
+def test_deviating_trial_form_is_bitwise_the_gather(ara):
+    """Cotangents constant over most trials take W from the deviating trials'
+    events; the same call on a YET without the trial-major copy takes the
+    gather.  The fixed-point sums are exact, so the results are identical
+    bit for bit: metric weights (AAL nearly constant, PML and TVaR nearly
+    zero), deviating-trial counts at the eighth of the trials and one above,
+    a sub-range with a non-zero common value (gather) and one with zero."""
+    import torch
+    _say("workload 2 prefix (24k trials, 4 layers): both forms of W")
+    w = synth.config(2, n_trials=24_000)
+    ylt, s_pre, sparse, dense = _both_forms(ara, w)
+    n = w.yet.n_trials
+    _, wts = ara.metrics(ylt, 0.99, want_weights=True)
+    cases = [("metric weights", wts, 0, None), ("PML and TVaR rows", wts[1:].contiguous(), 0, None)]
+    g = np.random.default_rng(8)
+    for nd in (n // 8, n // 8 + 1, 1, 0):
+        c = np.full((2, w.layers.n_layers, n), 1.0 / n)
+        c[1] = 0.0
+        idx = g.choice(n, size=nd, replace=False)
+        c[0, :, idx] = g.uniform(-2.0, 2.0, size=(nd, w.layers.n_layers)) / n
+        c[1, :, idx[: nd // 2]] = 3.0
+        cases.append((f"{nd} deviating trials", torch.tensor(c, device="cuda"), 0, None))
+    _, wts_sub = ara.metrics(ylt[:, 5000:17000].contiguous(), 0.95, want_weights=True)
+    cases.append(("sub-range, AAL row (gather)", wts_sub, 5000, 17000))
+    cases.append(("sub-range, PML and TVaR rows", wts_sub[1:].contiguous(), 5000, 17000))
+    for label, cot, t0, t1 in cases:
+        _say(label)
+        sp = s_pre if t1 is None else s_pre[:, t0:t1].contiguous()
+        a = sparse(sp, cot, t0, t1)
+        b = dense(sp, cot, t0, t1)
+        assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]), label
+
+
+def test_deviating_trial_form_full_size_vs_oracle(ara):
+    """1M x 1000 x 15 (the differentiated workload), where every trial's
+    aggregate clamp is linear: the metric weights go through the
+    deviating-trial form (AAL constant, PML and TVaR zero outside about
+    10,000 trials) and give the gather's gradients bit for bit."""
+    _say("workload 3: generating 1M x 1000")
+    w = synth.config(3)
+    ylt, s_pre, sparse, dense = _both_forms(ara, w)
+    _, wts = ara.metrics(ylt, w.p, want_weights=True)
+    _say("workload 3: both forms")
+    a = sparse(s_pre, wts)
+    b = dense(s_pre, wts)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])

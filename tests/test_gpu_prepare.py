@@ -100,8 +100,14 @@ def check(ara, yet_np):
     off_ref, key_ref, loc_ref = expected(yet_np, h.slice_trials, h.n_slices)
     off = read_dev(py, h.tr_off, h.n_slices * yet_np.catalog + 1, torch.int64)
     assert np.array_equal(off, off_ref)
+    # the trial-major copy and every event's occurrence count
+    assert np.array_equal(read_dev(py, h.t_off, yet_np.n_trials + 1, torch.int64), yet_np.offsets)
+    cnt = read_dev(py, h.t_cnt, yet_np.catalog, torch.int32)
+    assert np.array_equal(cnt, np.bincount(yet_np.ids, minlength=yet_np.catalog))
+    assert h.max_occ == (cnt.max() if yet_np.nnz else 0)
     if yet_np.nnz == 0:
         return
+    assert np.array_equal(read_dev(py, h.t_ids, yet_np.nnz, torch.int32), yet_np.ids)
     ent = read_dev(py, h.tr_ent, yet_np.nnz, torch.int32).astype(np.int64)
     key = np.repeat(np.arange(h.n_slices * yet_np.catalog, dtype=np.int64), np.diff(off))
     order = np.lexsort((ent, key))
@@ -172,6 +178,7 @@ def test_forward_only_prepare_and_backward_refusal(ara):
     w = synth.tiny_random(1)
     yet = ara.PreparedYet.from_numpy(w.yet, "cuda", transposed=False)
     assert yet.handle.n_slices == 0 and not yet.handle.tr_off
+    assert not yet.handle.t_off and not yet.handle.t_ids and not yet.handle.t_cnt
     tables = ara.EltTables.from_numpy(w.elts, "cuda")
     layers = ara.Layers(w.layers.elt_off, w.layers.elt_ids)
     et = torch.tensor(w.elts.terms, dtype=torch.float64, device="cuda")
