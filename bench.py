@@ -52,7 +52,7 @@ def traffic_from_profiles(kernel_file: str):
     return float(m_b.group(1))
 
 
-def cpu_baseline(w, budget_s: float = 10.0):
+def cpu_baseline(w, budget_s: float = 20.0):
     """The oracle (as it stands) on a bounded prefix of the same workload,
     all host cores via its OpenMP trial split."""
     import oracle
