@@ -393,8 +393,32 @@ def bench_backward(ara, tables, yet, layers, et, lt, w, steps, warmup, ms_fwd_st
     bwd_ms, bwd_n = ara.profile_read(ara.PROF_BWD)
     red_ms, red_n = ara.profile_read(ara.PROF_BWD_RED)
     ms = (t1 - t0) * 1e3 / steps
-    return {"ms_per_step": ms, "ratio_to_forward": ms / ms_fwd_step, "cotangents": 3,
-            "backward_stream_ms": bwd_ms / max(bwd_n, 1), "backward_reduce_ms": red_ms / max(red_n, 1)}
+    out = {"ms_per_step": ms, "ratio_to_forward": ms / ms_fwd_step, "cotangents": 3,
+           "backward_stream_ms": bwd_ms / max(bwd_n, 1), "backward_reduce_ms": red_ms / max(red_n, 1)}
+    # the same backward on a YET without the trial-major copy takes the full gather for W: both forms,
+    # timed as backward calls alone, and their results compared bit for bit
+    ylt, s_pre, _ = ara.ylt_forward(tables, yet, layers, et, lt, 0, N, want_s_pre=True)
+    _, wts = ara.metrics(ylt, w.p, want_weights=True)
+    yet_g = ara.PreparedYet.from_numpy(w.yet, trial_major=False)
+
+    def time_bwd(y):
+        for _ in range(max(1, warmup)):
+            ara.ylt_backward(tables, y, layers, et, lt, s_pre, wts)
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        for _ in range(steps):
+            g = ara.ylt_backward(tables, y, layers, et, lt, s_pre, wts)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - a) * 1e3 / steps, g
+
+    ms_dev, g_dev = time_bwd(yet)
+    ms_gat, g_gat = time_bwd(yet_g)
+    del yet_g
+    out["backward_call_ms"] = {"deviating_trials": ms_dev, "full_gather": ms_gat,
+                               "identical": bool(torch.equal(g_dev[0], g_gat[0]) and torch.equal(g_dev[1], g_gat[1]))}
+    log(f"backward call: {ms_dev:.3f} ms (deviating trials), {ms_gat:.3f} ms (full gather), "
+        f"identical {out['backward_call_ms']['identical']}")
+    return out
 
 
 if __name__ == "__main__":
