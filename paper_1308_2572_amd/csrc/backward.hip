@@ -833,7 +833,8 @@ extern "C" int32_t ara_ylt_backward(const ara_tables *tables, const ara_yet *yet
     S.W = W;
     // the second form of step (5) needs the trial-major copy
     BwdSparse &Q = S.sp;
-    S.use_sp = yet->t_off != nullptr && yet->t_ids != nullptr && yet->t_cnt != nullptr;
+    // (the list of deviating trials holds call-relative int32 indices)
+    S.use_sp = yet->t_off != nullptr && yet->t_ids != nullptr && yet->t_cnt != nullptr && n < (int64_t(1) << 31);
     Q.vq = vq;
     Q.n = n;
     Q.t0 = trial_begin;
