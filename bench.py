@@ -155,8 +155,10 @@ def main() -> int:
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
+    # inside the timed steps only the forward kernel's events are recorded (each recorded launch adds
+    # two event records, which the device runs as barriers); the other parts are timed afterwards
     ara.profile_reset()
-    ara.profile_enable(True)
+    ara.profile_enable(True, kinds=[ara.PROF_FWD])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -165,9 +167,15 @@ def main() -> int:
     t1 = time.perf_counter()
     ara.profile_enable(False)
     fwd_ms, fwd_n = ara.profile_read(ara.PROF_FWD)
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    ara.profile_reset()
+    ara.profile_enable(True, kinds=[ara.PROF_OCC, ara.PROF_METRICS])
+    for _ in range(max(3, min(args.steps, 10))):
+        step()
+    torch.cuda.synchronize()
+    ara.profile_enable(False)
     occ_ms, occ_n = ara.profile_read(ara.PROF_OCC)
     met_ms, met_n = ara.profile_read(ara.PROF_METRICS)
-    ms_step = (t1 - t0) * 1e3 / args.steps
     lookups = nnz * J
     value = lookups / (ms_step * 1e-3)
     k_fwd = fwd_ms / max(fwd_n, 1)

@@ -422,8 +422,13 @@ int32_t ara_server_destroy(void *server);
 #define ARA_PROF_SU       6   /* secondary-uncertainty streaming kernel      */
 #define ARA_PROF_KINDS    8
 
-/* on != 0 starts recording (process-wide); 0 stops. */
+/* on != 0 starts recording every kind (process-wide); 0 stops.  Each
+ * recorded launch group adds two event records to its stream, which the
+ * device executes as barriers between kernels. */
 int32_t ara_profile_enable(int32_t on);
+/* Records only the kinds whose bit (1 << kind) is set; 0 stops.  ARA_E_INVAL
+ * for bits beyond ARA_PROF_KINDS. */
+int32_t ara_profile_enable_kinds(uint32_t mask);
 /* Synchronises outstanding events of `kind` and returns their total elapsed
  * milliseconds and launch count since the last reset. */
 int32_t ara_profile_read(int32_t kind, double *total_ms, int64_t *launches);

@@ -98,6 +98,7 @@ _SIGNATURES = {
     "ara_server_stats": (_c_i32, [_c_p, _P(_c_i64)]),
     "ara_server_destroy": (_c_i32, [_c_p]),
     "ara_profile_enable": (_c_i32, [_c_i32]),
+    "ara_profile_enable_kinds": (_c_i32, [ctypes.c_uint32]),
     "ara_profile_read": (_c_i32, [_c_i32, _P(_c_f64), _P(_c_i64)]),
     "ara_profile_reset": (_c_i32, []),
     "ara_ylt_backward_workspace_bytes": (_c_i32, [_P(ara_tables), _P(ara_yet), _P(ara_layers), _c_i32, _P(_c_sz)]),
@@ -407,8 +408,16 @@ def ylt_backward(tables: EltTables, yet: PreparedYet, layers: Layers, elt_terms:
 PROF_OCC, PROF_FWD, PROF_METRICS, PROF_BWD, PROF_BWD_RED, PROF_YELT, PROF_SU = range(7)
 
 
-def profile_enable(on: bool = True) -> None:
-    _check(library().ara_profile_enable(1 if on else 0), "ara_profile_enable")
+def profile_enable(on: bool = True, kinds=None) -> None:
+    """Record HIP-event timings of every kind (or only of `kinds`, a list of
+    PROF_* values); on=False stops."""
+    if kinds is None or not on:
+        _check(library().ara_profile_enable(1 if on else 0), "ara_profile_enable")
+    else:
+        mask = 0
+        for k in kinds:
+            mask |= 1 << int(k)
+        _check(library().ara_profile_enable_kinds(mask), "ara_profile_enable_kinds")
 
 
 def profile_reset() -> None:

@@ -35,14 +35,14 @@ struct ProfPending {
 };
 
 static std::mutex g_prof_mu;
-static bool g_prof_on = false;
+static uint32_t g_prof_mask = 0;   // bit k: record kind k
 static std::vector<ProfPending> g_prof_pending;
 static double g_prof_ms[ARA_PROF_KINDS];
 static int64_t g_prof_n[ARA_PROF_KINDS];
 
 ProfScope::ProfScope(int kind, hipStream_t st) : kind_(kind), st_(st) {
     std::lock_guard<std::mutex> lk(g_prof_mu);
-    if (!g_prof_on) return;
+    if (!((g_prof_mask >> kind) & 1u)) return;
     if (hipEventCreate(&start_) != hipSuccess) {
         start_ = nullptr;
         return;
@@ -81,7 +81,14 @@ extern "C" {
 
 int32_t ara_profile_enable(int32_t on) {
     std::lock_guard<std::mutex> lk(ara::g_prof_mu);
-    ara::g_prof_on = on != 0;
+    ara::g_prof_mask = on ? ((1u << ARA_PROF_KINDS) - 1u) : 0u;
+    return ARA_OK;
+}
+
+int32_t ara_profile_enable_kinds(uint32_t mask) {
+    if (mask >> ARA_PROF_KINDS) return ara::fail(ARA_E_INVAL, "ara_profile_enable_kinds: unknown kind");
+    std::lock_guard<std::mutex> lk(ara::g_prof_mu);
+    ara::g_prof_mask = mask;
     return ARA_OK;
 }
 
