@@ -33,8 +33,34 @@ struct FwdParams {
     int32_t tg, tb, n_ranges;
     int32_t capv;              // values per range buffer
     int32_t buf_bytes;         // bytes per range buffer
-    const FwdItem *items;      // one (layer, block of trials) per workgroup
+    const FwdItem *items;      // one (layer, block of trials) per workgroup, or null: then workgroup i
+                               // takes layer i / reg_nb, block reg_b0 + i % reg_nb of the regular set below
+    const OccTables *reg_tabs;
+    const double *reg_lterm;
+    double *reg_ylt, *reg_s_pre;
+    int32_t *reg_hits;
+    int64_t reg_t0, reg_t1;
+    int32_t reg_b0, reg_nb;
 };
+
+// Workgroup i's item: from the list, or formed from the regular set (one
+// layer after another, each over the blocks of one trial range).
+__device__ __forceinline__ FwdItem fwd_item(const FwdParams &P, int i) {
+    if (P.items) return P.items[i];
+    FwdItem it;
+    const int j = i / P.reg_nb;
+    const size_t n = static_cast<size_t>(P.reg_t1 - P.reg_t0);
+    it.tab = P.reg_tabs + j;
+    it.lterm = P.reg_lterm + 4 * j;
+    it.block = P.reg_b0 + i % P.reg_nb;
+    it.pad = 0;
+    it.t0 = P.reg_t0;
+    it.t1 = P.reg_t1;
+    it.ylt = P.reg_ylt + static_cast<size_t>(j) * n;
+    it.s_pre = P.reg_s_pre ? P.reg_s_pre + static_cast<size_t>(j) * n : nullptr;
+    it.hits = P.reg_hits ? P.reg_hits + static_cast<size_t>(j) * n : nullptr;
+    return it;
+}
 
 // Four consecutive codes of one lane, streamed past the cache.
 __device__ __forceinline__ unsigned long long ld_codes(const uint16_t *p) {
@@ -114,7 +140,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8))) vo
     unsigned char *bufs = smem;
     const uint32_t bufs_lds = static_cast<uint32_t>(reinterpret_cast<uintptr_t>(bufs));
 
-    const FwdItem I = P.items[blockIdx.x];
+    const FwdItem I = fwd_item(P, blockIdx.x);
     const int tid = threadIdx.x, lane = tid & 63;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int64_t b = I.block;
@@ -360,7 +386,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8))) vo
 }
 
 int32_t launch_forward(const ara_yet *yet, int n_sr, bool hits, bool f32, const FwdItem *d_items, int n_items,
-                       hipStream_t st) {
+                       hipStream_t st, const FwdRegular *reg) {
     (void)n_sr;
     if (n_items <= 0) return ARA_OK;
     FwdParams P{};
@@ -381,6 +407,17 @@ int32_t launch_forward(const ara_yet *yet, int n_sr, bool hits, bool f32, const 
     P.capv = static_cast<int32_t>(capv);
     P.buf_bytes = static_cast<int32_t>(per_buf);
     P.items = d_items;
+    if (reg) {
+        P.reg_tabs = reg->tabs;
+        P.reg_lterm = reg->lterm;
+        P.reg_ylt = reg->ylt;
+        P.reg_s_pre = reg->s_pre;
+        P.reg_hits = reg->hits;
+        P.reg_t0 = reg->t0;
+        P.reg_t1 = reg->t1;
+        P.reg_b0 = reg->b0;
+        P.reg_nb = reg->nb;
+    }
     ProfScope prof(ARA_PROF_FWD, st);
     if (f32) {
         if (hits) k_fwd<true, true><<<n_items, 1024, 0, st>>>(P);
@@ -401,7 +438,6 @@ static size_t fwd_workspace(const ara_tables *tables, const ara_yet *yet, const 
     b += align256(static_cast<size_t>(L + 1) * sizeof(int32_t));
     b += align256(static_cast<size_t>(std::max(nJ, 1)) * sizeof(int32_t));
     b += align256(static_cast<size_t>(std::max(L, 1)) * sizeof(OccTables));
-    b += align256(static_cast<size_t>(std::max(L, 1)) * std::max(yet->n_blocks, 1) * sizeof(FwdItem));
     b += static_cast<size_t>(L) * z.per_layer;
     return b;
 }
@@ -462,28 +498,23 @@ extern "C" int32_t ara_ylt_forward(const ara_tables *tables, const ara_yet *yet,
     const int64_t b_lo = trial_begin / yet->trials_per_block;
     const int64_t b_hi = (trial_end + yet->trials_per_block - 1) / yet->trials_per_block;
     const int nb = static_cast<int>(b_hi - b_lo);
-    FwdItem *d_items = c.take<FwdItem>(static_cast<size_t>(L) * std::max(yet->n_blocks, 1));
     std::vector<OccTables> tabs(static_cast<size_t>(L));
     for (int j = 0; j < L; ++j) tabs[j] = occ_carve(c, z, want_hits);
-    std::vector<FwdItem> items(static_cast<size_t>(L) * nb);
-    for (int j = 0; j < L; ++j)
-        for (int i = 0; i < nb; ++i) {
-            FwdItem &it = items[static_cast<size_t>(j) * nb + i];
-            it.tab = d_tabs + j;
-            it.lterm = layer_terms + 4 * j;
-            it.block = static_cast<int32_t>(b_lo + i);
-            it.t0 = trial_begin;
-            it.t1 = trial_end;
-            it.ylt = ylt + static_cast<size_t>(j) * n;
-            it.s_pre = s_pre ? s_pre + static_cast<size_t>(j) * n : nullptr;
-            it.hits = hits ? hits + static_cast<size_t>(j) * n : nullptr;
-        }
+    FwdRegular reg{};
+    reg.tabs = d_tabs;
+    reg.lterm = layer_terms;
+    reg.ylt = ylt;
+    reg.s_pre = s_pre;
+    reg.hits = hits;
+    reg.t0 = trial_begin;
+    reg.t1 = trial_end;
+    reg.b0 = static_cast<int32_t>(b_lo);
+    reg.nb = nb;
     HeadImage img(ws);
     img.cover(d_err + kWsHeaderBytes / sizeof(int32_t));
     img.put(d_off, layers->elt_off, static_cast<size_t>(L + 1));
     img.put(d_ids, layers->elt_ids, static_cast<size_t>(nJ));
     img.put(d_tabs, tabs.data(), tabs.size());
-    img.put(d_items, items.data(), items.size());
     if ((rc = img.send(st))) return rc;
 
     {
@@ -492,5 +523,5 @@ extern "C" int32_t ara_ylt_forward(const ara_tables *tables, const ara_yet *yet,
                              st)))
             return rc;
     }
-    return launch_forward(yet, z.n_sr, want_hits, f32, d_items, L * nb, st);
+    return launch_forward(yet, z.n_sr, want_hits, f32, nullptr, L * nb, st, &reg);
 }

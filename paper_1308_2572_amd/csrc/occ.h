@@ -93,9 +93,22 @@ struct FwdItem {
 };
 
 // Enqueue the forward streaming kernel over a device array of items.
+// The regular set of forward items: every layer over the blocks b0 ..
+// b0 + nb - 1 of one trial range [t0, t1), rows of ylt / s_pre / hits
+// indexed t - t0 (formed on the device, so nothing is copied per call).
+struct FwdRegular {
+    const OccTables *tabs;     // device, [n_layers]
+    const double *lterm;       // device, [n_layers][4]
+    double *ylt, *s_pre;
+    int32_t *hits;
+    int64_t t0, t1;
+    int32_t b0, nb;
+};
+
 // f32: binary32 occurrence values (tables built with f32_vals) and totals.
+// Items come from d_items, or (d_items null) from `reg`.
 int32_t launch_forward(const ara_yet *yet, int n_sr, bool hits, bool f32, const FwdItem *d_items, int n_items,
-                       hipStream_t st);
+                       hipStream_t st, const FwdRegular *reg = nullptr);
 
 // A layer's set-event bitmap folded onto 2^20 bits by OR (128 KB, staged in
 // LDS by the kernels that stream the trial-major YET): one filter per layer.
