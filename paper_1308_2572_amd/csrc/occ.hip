@@ -10,6 +10,7 @@ namespace ara {
 
 constexpr int kPassWords = kOccChunkWords;      // 4096 events per chunk
 constexpr int kPasses = kOccChunks;             // 16 chunks per super-range
+constexpr int kLossBatch = 16;                  // ELT losses of one event loaded together
 
 __device__ __forceinline__ bool bad_scale(double s) { return !(s > 0.0) || !(s < INFINITY); }
 __device__ __forceinline__ bool bad_retention(double r) { return !(r >= 0.0) || !(r < INFINITY); }
@@ -37,7 +38,7 @@ __device__ __forceinline__ uint32_t scan128(uint32_t v, uint32_t *wtot, uint32_t
 // Phase one: one workgroup per (4096-event chunk, layer).  The events held
 // by at least one of the layer's ELTs are listed in event order; each is
 // evaluated once: g_k summed over the layer's ELTs in listed order (losses of
-// 8 ELTs are loaded together so their latencies overlap), then the occurrence
+// up to 16 ELTs are loaded together so their latencies overlap), then the occurrence
 // terms.  The set events are compacted in event order: the chunk's bitmap
 // words, its count, and O (and the ELT count) at the start of the chunk's
 // slice of the staging arrays.
@@ -114,11 +115,11 @@ __global__ __launch_bounds__(1024) void k_occ_eval(const float *__restrict__ los
         double x = 0.0;
         int nb = 0;
         if (i < nc) {
-            for (int q0 = 0; q0 < J; q0 += 8) {
-                float v[8];
-                bool on[8];
+            for (int q0 = 0; q0 < J; q0 += kLossBatch) {
+                float v[kLossBatch];
+                bool on[kLossBatch];
 #pragma unroll
-                for (int u = 0; u < 8; ++u) {
+                for (int u = 0; u < kLossBatch; ++u) {
                     const int q = q0 + u;
                     on[u] = q < J && ((stage[q * kPassWords + wip] >> bit) & 1u);
                     // lanes without the event read element 0 (always valid) and ignore it,
@@ -127,7 +128,7 @@ __global__ __launch_bounds__(1024) void k_occ_eval(const float *__restrict__ los
                     v[u] = loss[idx];
                 }
 #pragma unroll
-                for (int u = 0; u < 8; ++u) {
+                for (int u = 0; u < kLossBatch; ++u) {
                     if (on[u]) {
                         const int q = q0 + u;
                         const double scaled = ls[q] * static_cast<double>(v[u]);
