@@ -44,6 +44,23 @@ def test_status_strings(ara):
     assert lib.ara_abi_version() == 1
 
 
+def test_profile_controls(ara):
+    """Recording by kind: known kinds are accepted (nothing is recorded
+    without device work), unknown bits are refused, and reads of a kind
+    with no launches give zero."""
+    lib = ara.library()
+    assert lib.ara_profile_enable_kinds(1 << ara.PROF_FWD) == 0
+    assert lib.ara_profile_enable_kinds(0xFF) == 0
+    assert lib.ara_profile_enable_kinds(1 << 8) == 1
+    assert b"unknown kind" in lib.ara_last_error()
+    assert lib.ara_profile_enable(0) == 0
+    assert lib.ara_profile_reset() == 0
+    ms, n = ctypes.c_double(), ctypes.c_int64()
+    assert lib.ara_profile_read(ara.PROF_METRICS, ctypes.byref(ms), ctypes.byref(n)) == 0
+    assert ms.value == 0.0 and n.value == 0
+    assert lib.ara_profile_read(8, ctypes.byref(ms), ctypes.byref(n)) == 1
+
+
 def test_size_queries(ara):
     lib = ara.library()
     nb = ctypes.c_size_t()
