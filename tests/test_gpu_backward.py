@@ -266,6 +266,11 @@ def test_deviating_trial_form_is_bitwise_the_gather(ara):
         c[0, :, idx] = g.uniform(-2.0, 2.0, size=(nd, w.layers.n_layers)) / n
         c[1, :, idx[: nd // 2]] = 3.0
         cases.append((f"{nd} deviating trials", torch.tensor(c, device="cuda"), 0, None))
+    # one row (packed one wide) and four rows (the most: packed four wide)
+    cases.append(("AAL row alone", wts[:1].contiguous(), 0, None))
+    four = torch.cat([wts, wts[2:3] * 0.5], dim=0).contiguous()
+    four[3, :, :7] = 1.0
+    cases.append(("four rows", four, 0, None))
     _, wts_sub = ara.metrics(ylt[:, 5000:17000].contiguous(), 0.95, want_weights=True)
     cases.append(("sub-range, AAL row (gather)", wts_sub, 5000, 17000))
     cases.append(("sub-range, PML and TVaR rows", wts_sub[1:].contiguous(), 5000, 17000))
