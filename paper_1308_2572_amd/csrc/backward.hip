@@ -52,8 +52,6 @@ namespace ara {
 
 constexpr int kBwdThreads = 1024;
 constexpr int kMaxCot = ARA_MAX_COTANGENTS;
-constexpr int kChunkWords = 128;                  // 4096 events per reduction workgroup
-constexpr int kChunks = kSrWords / kChunkWords;   // 16 per super-range
 
 struct VScale {
     unsigned long long maxabs_bits;   // max |v| as binary64 bits (non-negative: order-preserving)
@@ -491,27 +489,35 @@ struct BwdGrad {
     const OccTables *tabs;
     const int64_t *W;              // [n_layers][n_cot][catalog] by hot index
     const int32_t *hot_base;       // [n_layers][n_sr + 1]
-    int32_t n_sr, n_cot, n_chunks, n_elt_slots;   // chunks = n_sr * kChunks; slots = ELT positions of all layers
+    const int32_t *hot_ev;         // [n_layers][catalog]
+    int32_t n_sr, n_cot, n_cw, n_elt_slots;   // cw = (workgroup, wavefront) slots; slots = ELT positions of all layers
     const VScale *vs;
-    double *part_elt;    // [n_chunks * 16 waves][n_elt_slots][n_cot][3]
-    double *part_occ;    // [n_layers][n_chunks * 16 waves][n_cot][2]
+    double *part_elt;    // [n_cw][n_elt_slots][n_cot][3]
+    double *part_occ;    // [n_layers][n_cw][n_cot][2]
 };
 
-constexpr int kGradWaves = kBwdThreads / kWave;   // 16
-constexpr int kGradBatch = 4;                      // ELTs whose losses are loaded together
+constexpr int kGradThreads = 256;
+constexpr int kGradWaves = kGradThreads / kWave;   // 4
+constexpr int kGradHot = 4 * kGradThreads;         // hot events per workgroup
+constexpr int kGradBatch = 4;                      // ELTs whose presence words and losses are loaded together
 
-// (6) per 4096-event chunk: W(e) times the derivatives of O(e).  Each
-// thread owns four events; each wavefront reduces its lanes in a fixed tree
-// and writes its own partials, so no workgroup barrier sits in the ELT loop
-// and the final sums (a fixed order over chunks and wavefronts) are
-// deterministic.  Every per-row array is indexed by compile-time constants
-// (rows beyond n_cot are zero), so nothing leaves registers.
-__global__ __launch_bounds__(kBwdThreads) void k_bwd_grad(BwdGrad P) {
-    __shared__ uint32_t stage[kMaxJ * kChunkWords];
+// (6) W(e) times the derivatives of O(e), over the layer's hot events
+// (the only ones with W): workgroup i takes hot indices 1024 i .. 1024 i +
+// 1023, each thread four of them.  Each wavefront reduces its lanes in a
+// fixed tree and writes its own partials, so no workgroup barrier sits in
+// the ELT loop and the final sums (a fixed order over workgroups and
+// wavefronts) are deterministic.  Every per-row array is indexed by
+// compile-time constants (rows beyond n_cot are zero), so nothing leaves
+// registers.
+__global__ __launch_bounds__(kGradThreads) void k_bwd_grad(BwdGrad P) {
     __shared__ int32_t lk[kMaxJ];
     __shared__ double ls[kMaxJ], lr[kMaxJ], ll[kMaxJ];
-    const int s = blockIdx.x / kChunks, p = blockIdx.x % kChunks, j = blockIdx.y;
+    const int hb = blockIdx.x, j = blockIdx.y;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int32_t *hbase = P.hot_base + static_cast<size_t>(j) * (P.n_sr + 1);
+    const int H = hbase[P.n_sr];
+    const int g0 = hb * kGradHot;
+    if (g0 >= H) return;   // uniform; the final sums read only the slots of workgroups with hot events
     const int a = P.elt_off[j];
     const int J = P.elt_off[j + 1] - a;
     for (int q = tid; q < J; q += blockDim.x) {
@@ -522,51 +528,43 @@ __global__ __launch_bounds__(kBwdThreads) void k_bwd_grad(BwdGrad P) {
         ll[q] = P.elt_terms[3 * k + 2];
     }
     __syncthreads();
-    for (int idx = tid; idx < J * kChunkWords; idx += blockDim.x) {
-        const int q = idx / kChunkWords, ww = idx % kChunkWords;
-        const int64_t gw = static_cast<int64_t>(s) * kSrWords + p * kChunkWords + ww;
-        stage[idx] = (gw < P.words) ? P.present[static_cast<size_t>(lk[q]) * P.words + gw] : 0u;
-    }
-    const double occR = P.layer_terms[4 * j + 0], occL = P.layer_terms[4 * j + 1];
-    (void)occR;
+    const double occL = P.layer_terms[4 * j + 1];
     const OccTables T = P.tabs[j];
-    const int64_t ev0 = static_cast<int64_t>(s) * kSr + p * (kChunkWords * 32);
-    const int32_t hb = P.hot_base[static_cast<size_t>(j) * (P.n_sr + 1) + s];
-    __syncthreads();
+    const int32_t *hev = P.hot_ev + static_cast<size_t>(j) * P.catalog;
 
-    // the thread's four events: weight per row and occurrence-clamp branch.
-    // O = min(max(x - OccR, 0), OccL) is non-zero for these events, and it is
-    // below OccL exactly when the occurrence clamp is in its linear branch.
+    // the thread's four hot events: weight per row and occurrence-clamp
+    // branch.  O = min(max(x - OccR, 0), OccL) is non-zero for these events,
+    // and it is below OccL exactly when the occurrence clamp is linear.
     double W[4][kMaxCot];
     bool lin_occ[4];
-    int local[4];
+    int ev[4];
     double po[kMaxCot][2];
 #pragma unroll
     for (int c = 0; c < kMaxCot; ++c) po[c][0] = po[c][1] = 0.0;
 #pragma unroll
     for (int it = 0; it < 4; ++it) {
-        local[it] = it * 1024 + tid;
-        const int wip = local[it] >> 5, bit = local[it] & 31;
-        const uint2 q = T.br[static_cast<size_t>(s) * kSrWords + p * kChunkWords + wip];
-        const bool hot = (q.x >> bit) & 1u;
-        const uint32_t rk = q.y + __popc(q.x & ((1u << bit) - 1u));
-        const double O = hot ? T.vals[static_cast<size_t>(s) * kSr + rk] : 0.0;
-        lin_occ[it] = hot && (O < occL);
+        const int g = g0 + it * kGradThreads + tid;
+        const bool valid = g < H;
+        const int e = valid ? hev[g] : 0;
+        ev[it] = e;
+        const int sr = e >> kSrBits;
+        const double O = valid ? T.vals[static_cast<size_t>(sr) * kSr + (g - hbase[sr])] : 0.0;
+        lin_occ[it] = valid && (O < occL);
 #pragma unroll
         for (int c = 0; c < kMaxCot; ++c) {
             double wv = 0.0;
-            if (hot && c < P.n_cot) {
-                const int64_t acc = P.W[(static_cast<size_t>(j) * P.n_cot + c) * P.catalog + hb + rk];
+            if (valid && c < P.n_cot) {
+                const int64_t acc = P.W[(static_cast<size_t>(j) * P.n_cot + c) * P.catalog + g];
                 wv = ldexp(static_cast<double>(acc), -P.vs[j * P.n_cot + c].sigma);
             }
             W[it][c] = wv;
-            if (hot) {
+            if (valid) {
                 if (lin_occ[it]) po[c][0] -= wv;
                 else po[c][1] += wv;
             }
         }
     }
-    const size_t cw = static_cast<size_t>(blockIdx.x) * kGradWaves + w;   // (chunk, wave) partial slot
+    const size_t cw = static_cast<size_t>(hb) * kGradWaves + w;   // (workgroup, wave) partial slot
     // occurrence-term partials of this wavefront
     // (wavefront sums by DPP: lane 63 holds the total, in a fixed order)
 #pragma unroll
@@ -576,11 +574,19 @@ __global__ __launch_bounds__(kBwdThreads) void k_bwd_grad(BwdGrad P) {
             for (int m = 0; m < 2; ++m) {
                 const double v = wave_inclusive_sum(po[c][m]);
                 if (lane == 63)
-                    P.part_occ[((static_cast<size_t>(j) * P.n_chunks * kGradWaves + cw) * P.n_cot + c) * 2 + m] = v;
+                    P.part_occ[((static_cast<size_t>(j) * P.n_cw + cw) * P.n_cot + c) * 2 + m] = v;
             }
         }
-    // ELT-term partials, kGradBatch ELTs' losses in flight at a time
+    // ELT-term partials, kGradBatch ELTs' presence words and losses in flight at a time
     for (int q0 = 0; q0 < J; q0 += kGradBatch) {
+        uint32_t pw[kGradBatch][4];
+#pragma unroll
+        for (int b = 0; b < kGradBatch; ++b) {
+            const int qq = q0 + b;
+#pragma unroll
+            for (int it = 0; it < 4; ++it)
+                pw[b][it] = (qq < J && lin_occ[it]) ? P.present[static_cast<size_t>(lk[qq]) * P.words + (ev[it] >> 5)] : 0u;
+        }
         float lv[kGradBatch][4];
         bool on[kGradBatch][4];
 #pragma unroll
@@ -588,9 +594,8 @@ __global__ __launch_bounds__(kBwdThreads) void k_bwd_grad(BwdGrad P) {
             const int qq = q0 + b;
 #pragma unroll
             for (int it = 0; it < 4; ++it) {
-                const int wip = local[it] >> 5, bit = local[it] & 31;
-                on[b][it] = qq < J && lin_occ[it] && ((stage[qq * kChunkWords + wip] >> bit) & 1u);
-                const size_t idx = on[b][it] ? static_cast<size_t>(lk[qq]) * P.catalog + ev0 + local[it] : 0;
+                on[b][it] = (pw[b][it] >> (ev[it] & 31)) & 1u;
+                const size_t idx = on[b][it] ? static_cast<size_t>(lk[qq]) * P.catalog + ev[it] : 0;
                 lv[b][it] = P.loss[idx];   // element 0 (always valid) for events without the ELT
             }
         }
@@ -633,11 +638,18 @@ __global__ __launch_bounds__(kBwdThreads) void k_bwd_grad(BwdGrad P) {
     }
 }
 
+// Partial slots written for layer j: those of the workgroups that had hot events.
+__device__ __forceinline__ int grad_slots_used(const int32_t *hot_base, int n_sr, int j, int n_cw) {
+    const int H = hot_base[static_cast<size_t>(j) * (n_sr + 1) + n_sr];
+    return min(n_cw, ((H + kGradHot - 1) / kGradHot) * kGradWaves);
+}
+
 // (7) fixed-order sums into the outputs: one workgroup per output value,
 // each thread a fixed stride of the (chunk, wavefront) partials, then a
 // fixed-order tree.
 __global__ __launch_bounds__(256) void k_bwd_final(const int32_t *__restrict__ elt_off, const int32_t *__restrict__ elt_ids,
-                                                  int n_layers, int n_elts, int n_cot, int n_cw, int n_elt_slots,
+                                                  int n_layers, int n_elts, int n_cot, int n_cw,
+                                                  const int32_t *__restrict__ hot_base, int n_sr, int n_elt_slots,
                                                   int nwg_v, const double *__restrict__ part_elt,
                                                   const double *__restrict__ part_occ,
                                                   const double *__restrict__ aggpart, double *__restrict__ grad_elt,
@@ -651,14 +663,16 @@ __global__ __launch_bounds__(256) void k_bwd_final(const int32_t *__restrict__ e
         for (int j = 0; j < n_layers; ++j)
             for (int q = elt_off[j]; q < elt_off[j + 1]; ++q) {
                 if (elt_ids[q] != k) continue;
-                for (int cw = tid; cw < n_cw; cw += blockDim.x)
+                const int used = grad_slots_used(hot_base, n_sr, j, n_cw);
+                for (int cw = tid; cw < used; cw += blockDim.x)
                     v += part_elt[((static_cast<size_t>(cw) * n_elt_slots + q) * n_cot + c) * 3 + m];
             }
     } else {
         const int i = o - n_e;
         const int c = i / (n_layers * 4), j = (i / 4) % n_layers, m = i % 4;
         if (m < 2) {
-            for (int cw = tid; cw < n_cw; cw += blockDim.x)
+            const int used = grad_slots_used(hot_base, n_sr, j, n_cw);
+            for (int cw = tid; cw < used; cw += blockDim.x)
                 v += part_occ[((static_cast<size_t>(j) * n_cw + cw) * n_cot + c) * 2 + m];
         } else {
             for (int wg = tid; wg < nwg_v; wg += blockDim.x)
@@ -683,7 +697,7 @@ __global__ __launch_bounds__(256) void k_bwd_final(const int32_t *__restrict__ e
 
 struct BwdLayout {
     OccLayoutSizes z;
-    int nwg_v, n_chunks, cs;
+    int nwg_v, n_cw, cs;
     size_t bytes;
 };
 
@@ -701,7 +715,7 @@ static BwdLayout bwd_layout(const ara_tables *tables, const ara_layers *layers, 
     const int L = layers->n_layers;
     const int nJ = L > 0 ? layers->elt_off[L] : 0;
     B.nwg_v = bwd_nwg_v(n);
-    B.n_chunks = B.z.n_sr * kChunks;
+    B.n_cw = static_cast<int>((static_cast<int64_t>(tables->catalog) + kGradHot - 1) / kGradHot) * kGradWaves;
     B.cs = bwd_cs(n_cot);
     const size_t cat = static_cast<size_t>(tables->catalog);
     Carver c(nullptr);
@@ -720,8 +734,8 @@ static BwdLayout bwd_layout(const ara_tables *tables, const ara_layers *layers, 
     d.take<int32_t>(static_cast<size_t>(L) * cat);
     d.take<int32_t>(static_cast<size_t>(L) * (B.z.n_sr + 1));
     d.take<int64_t>(static_cast<size_t>(L) * n_cot * cat);
-    d.take<double>(static_cast<size_t>(B.n_chunks) * kGradWaves * std::max(nJ, 1) * n_cot * 3);
-    d.take<double>(static_cast<size_t>(L) * B.n_chunks * kGradWaves * n_cot * 2);
+    d.take<double>(static_cast<size_t>(B.n_cw) * std::max(nJ, 1) * n_cot * 3);
+    d.take<double>(static_cast<size_t>(L) * B.n_cw * n_cot * 2);
     B.bytes = b + d.bytes();
     return B;
 }
@@ -793,8 +807,8 @@ extern "C" int32_t ara_ylt_backward(const ara_tables *tables, const ara_yet *yet
     int32_t *hot_ev = c.take<int32_t>(static_cast<size_t>(L) * tables->catalog);
     int32_t *hot_base = c.take<int32_t>(static_cast<size_t>(L) * (B.z.n_sr + 1));
     int64_t *W = c.take<int64_t>(static_cast<size_t>(L) * n_cot * tables->catalog);
-    double *part_elt = c.take<double>(static_cast<size_t>(B.n_chunks) * kGradWaves * std::max(nJ, 1) * n_cot * 3);
-    double *part_occ = c.take<double>(static_cast<size_t>(L) * B.n_chunks * kGradWaves * n_cot * 2);
+    double *part_elt = c.take<double>(static_cast<size_t>(B.n_cw) * std::max(nJ, 1) * n_cot * 3);
+    double *part_occ = c.take<double>(static_cast<size_t>(L) * B.n_cw * n_cot * 2);
     int32_t *dev = c.take<int32_t>(static_cast<size_t>(L) * std::max<int64_t>(n, 1));
     HeadImage img(ws);   // clears the error header, the weight scales and the deviating-trial counts
     img.put(d_off, layers->elt_off, static_cast<size_t>(L + 1));
@@ -888,16 +902,17 @@ extern "C" int32_t ara_ylt_backward(const ara_tables *tables, const ara_yet *yet
     Gp.hot_base = hot_base;
     Gp.n_sr = B.z.n_sr;
     Gp.n_cot = n_cot;
-    Gp.n_chunks = B.n_chunks;
+    Gp.n_cw = B.n_cw;
+    Gp.hot_ev = hot_ev;
     Gp.n_elt_slots = std::max(nJ, 1);
     Gp.vs = vs;
     Gp.part_elt = part_elt;
     Gp.part_occ = part_occ;
     {
         ProfScope prof(ARA_PROF_BWD_RED, st);
-        k_bwd_grad<<<dim3(B.n_chunks, L), kBwdThreads, 0, st>>>(Gp);
+        k_bwd_grad<<<dim3(B.n_cw / kGradWaves, L), kGradThreads, 0, st>>>(Gp);
         const int outs = n_cot * tables->n_elts * 3 + n_cot * L * 4;
-        k_bwd_final<<<outs, 256, 0, st>>>(d_off, d_ids, L, tables->n_elts, n_cot, B.n_chunks * kGradWaves,
+        k_bwd_final<<<outs, 256, 0, st>>>(d_off, d_ids, L, tables->n_elts, n_cot, B.n_cw, hot_base, B.z.n_sr,
                                           std::max(nJ, 1), nwg_v, part_elt, part_occ, aggpart, grad_elt, grad_layer);
         ARA_HIP(hipGetLastError());
     }
