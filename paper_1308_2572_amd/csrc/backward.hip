@@ -26,7 +26,7 @@
 // can overflow (|W| <= max|v| * largest occurrence count of one event);
 // (4) the list of hot events; (5) W(e) per hot event, gathered per trial
 // slice over the event-major YET and combined with integer atomics, so the
-// result does not depend on the order; (6) per 4096-event chunk, W times
+// result does not depend on the order; (6) over the hot events, W times
 // the per-event derivatives, reduced in a fixed order; (7) a fixed-order sum
 // of the chunk partials into the outputs.
 //
