@@ -7,10 +7,12 @@
 // leading mantissa digit; a third gathers every value sharing that 23-bit
 // prefix, and the workgroup that finishes it last selects among them (in LDS
 // when they fit, from the gathered copy otherwise, at once when they are all
-// equal).  A fourth pass sums above the PML value.  Each pass ends in the
-// workgroup that finishes last (a counter per layer), so a call is four
-// kernels whatever the ties.  Sums use a fixed partition of the trials and
-// fixed-order trees, so every result is deterministic.
+// equal).  The same pass sums and counts the values above that bin, and its
+// last workgroup adds the gathered values above the PML value exactly (as
+// integers: they share one exponent) and writes the metrics.  Each pass ends
+// in the workgroup that finishes last (a counter per layer), so a call is
+// three kernels whatever the ties.  Sums use a fixed partition of the trials,
+// fixed-order trees and exact integer sums, so every result is deterministic.
 #include "ara_internal.h"
 #include "wave.h"
 
@@ -39,7 +41,7 @@ struct MetState {
     double thr;                // the PML value
     int64_t cnt_gt, cnt_eq;
     int64_t r;
-    uint32_t tick[4];          // workgroups finished, per pass
+    uint32_t tick[3];          // workgroups finished, per pass
 };
 
 struct MetPart {
@@ -210,14 +212,19 @@ __global__ __launch_bounds__(kMetThreads) void k_met_hist(const double *__restri
 // reserves its slots with one atomic), with their smallest and largest key.
 // The last workgroup finishes digits 2..5 on them.
 __global__ __launch_bounds__(kMetThreads) void k_met_collect(const double *__restrict__ ylt, int64_t n, int nwg,
-                                                            MetState *__restrict__ st, uint64_t *__restrict__ cand) {
+                                                            MetState *__restrict__ st, uint64_t *__restrict__ cand,
+                                                            MetPart *__restrict__ part, double *__restrict__ out) {
     __shared__ uint64_t cs[kCandCap];
     __shared__ uint32_t h[kBins];
     __shared__ FindShared fs;
+    __shared__ double red[4][16];
+    __shared__ unsigned long long ired[4][16];
     __shared__ int flag;
     const int l = blockIdx.y, wg = blockIdx.x, tid = threadIdx.x, lane = tid & 63;
     MetState &S = st[l];
     const uint64_t prefix = S.prefix[2];
+    double s_above = 0.0;   // values above the bin (all above the PML value)
+    int64_t n_above = 0;
     const int hb = kShift[1];
     int64_t lo, hi;
     chunk_of(n, nwg, wg, lo, hi);
@@ -236,6 +243,10 @@ __global__ __launch_bounds__(kMetThreads) void k_met_collect(const double *__res
         for (int u = 0; u < kMetUnroll; ++u) {
             const int64_t i = i0 + u * kMetThreads + tid;
             const bool is = i < hi && (k[u] >> hb) == prefix;
+            if (i < hi && (k[u] >> hb) > prefix) {
+                s_above += __longlong_as_double(static_cast<long long>(k[u]));
+                ++n_above;
+            }
             m[u] = __ballot(is);
             mine += __popcll(m[u]);
             if (is) {
@@ -268,6 +279,14 @@ __global__ __launch_bounds__(kMetThreads) void k_met_collect(const double *__res
             atomicMax(&S.kminc, static_cast<unsigned long long>(~kmin));
         }
     }
+    {
+        double t2[2] = {s_above, static_cast<double>(n_above)};
+        block_sums(t2, red);
+        if (tid == 0) {
+            put(&part[static_cast<size_t>(l) * nwg + wg].sum_gt, t2[0]);
+            put(&part[static_cast<size_t>(l) * nwg + wg].cnt_gt, static_cast<int64_t>(t2[1]));
+        }
+    }
     if (!finished_last(S, 2, nwg, &flag)) return;
     const int64_t cn = static_cast<int64_t>(get(&S.cand_n));
     const uint64_t lo_key = ~static_cast<uint64_t>(get(&S.kminc)), hi_key = static_cast<uint64_t>(get(&S.kmax));
@@ -295,65 +314,68 @@ __global__ __launch_bounds__(kMetThreads) void k_met_collect(const double *__res
         }
         bits = pre;
     }
-    if (tid == 0) S.thr = __longlong_as_double(static_cast<long long>(bits));
-}
-
-// Counts and sum above the PML value (fixed partition); the last workgroup
-// adds the partial results in a fixed order and writes the metrics.
-__global__ __launch_bounds__(kMetThreads) void k_met_tail(const double *__restrict__ ylt, int64_t n, int nwg,
-                                                         MetState *__restrict__ st, MetPart *__restrict__ part,
-                                                         double *__restrict__ out) {
-    __shared__ double red[4][16];
-    __shared__ int flag;
-    const int l = blockIdx.y, wg = blockIdx.x, tid = threadIdx.x;
-    MetState &S = st[l];
-    const double thr = S.thr;
-    int64_t lo, hi;
-    chunk_of(n, nwg, wg, lo, hi);
-    const double *y = ylt + static_cast<size_t>(l) * n;
-    double s = 0.0;
-    int64_t gt = 0, eq = 0;
-    for (int64_t i0 = lo; i0 < hi; i0 += kMetSweep) {
-        double v[kMetUnroll];
-#pragma unroll
-        for (int u = 0; u < kMetUnroll; ++u) {
-            const int64_t i = i0 + u * kMetThreads + tid;
-            v[u] = (i < hi) ? y[i] : -1.0;   // below every year loss and the PML value
-        }
-#pragma unroll
-        for (int u = 0; u < kMetUnroll; ++u) {
-            if (v[u] > thr) {
-                s += v[u];
-                ++gt;
-            } else if (v[u] == thr) {
-                ++eq;
+    const double thr = __longlong_as_double(static_cast<long long>(bits));
+    // the gathered values above the PML value, summed exactly: they share one
+    // exponent, so their 53-bit significands add as integers (in halves of 27
+    // and 26 bits, any order), and those equal to it, counted
+    unsigned long long sig_hi = 0, sig_lo = 0, c_gt = 0, c_eq = 0;
+    if (lo_key == hi_key) {
+        if (tid == 0) c_eq = static_cast<unsigned long long>(cn);
+    } else {
+        const bool in_lds = cn <= kCandCap;   // uniform; the copy in LDS is still there
+        for (int64_t i = tid; i < cn; i += kMetThreads) {
+            const uint64_t u = in_lds ? cs[i] : get(&c[i]);
+            if (u > bits) {
+                const uint64_t e = (u >> 52) & 0x7FFull;
+                const uint64_t sig = (u & ((1ull << 52) - 1ull)) | (e ? (1ull << 52) : 0ull);
+                sig_hi += sig >> 26;
+                sig_lo += sig & ((1ull << 26) - 1ull);
+                ++c_gt;
+            } else if (u == bits) {
+                ++c_eq;
             }
         }
     }
-    double t3[3] = {s, static_cast<double>(gt), static_cast<double>(eq)};
-    block_sums(t3, red);
-    MetPart *pl = part + static_cast<size_t>(l) * nwg;
-    if (tid == 0) {
-        put(&pl[wg].sum_gt, t3[0]);
-        put(&pl[wg].cnt_gt, static_cast<int64_t>(t3[1]));
-        put(&pl[wg].cnt_eq, static_cast<int64_t>(t3[2]));
+    {   // integer sums: any order gives the same totals
+        unsigned long long v[4] = {sig_hi, sig_lo, c_gt, c_eq};
+        const int w = tid >> 6;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            for (int o = 32; o > 0; o >>= 1) v[q] += __shfl_xor(v[q], o);
+            if (lane == 0) ired[q][w] = v[q];
+        }
+        __syncthreads();
+        if (tid == 0) {
+            sig_hi = sig_lo = c_gt = c_eq = 0;
+            for (int i = 0; i < kMetThreads / 64; ++i) {
+                sig_hi += ired[0][i];
+                sig_lo += ired[1][i];
+                c_gt += ired[2][i];
+                c_eq += ired[3][i];
+            }
+        }
+        __syncthreads();
     }
-    if (!finished_last(S, 3, nwg, &flag)) return;
-    double t4[4] = {0.0, 0.0, 0.0, 0.0};
+    // the sums over the workgroups, in a fixed order
+    MetPart *pl = part + static_cast<size_t>(l) * nwg;
+    double t4[3] = {0.0, 0.0, 0.0};
     for (int i = tid; i < nwg; i += kMetThreads) {
         t4[0] += pl[i].sum;   // written by an earlier kernel
         t4[1] += get(&pl[i].sum_gt);
         t4[2] += static_cast<double>(get(&pl[i].cnt_gt));
-        t4[3] += static_cast<double>(get(&pl[i].cnt_eq));
     }
     block_sums(t4, red);
-    const double tsa = t4[0], tsg = t4[1];
-    const int64_t tgt = static_cast<int64_t>(t4[2]), teq = static_cast<int64_t>(t4[3]);
     if (tid == 0) {
+        const int e = static_cast<int>((prefix >> 11) & 0x7FFu);   // the bin's exponent field
+        const double scale = ldexp(1.0, (e ? e : 1) - 1075);        // value of one significand unit
+        const double cand_sum = (ldexp(static_cast<double>(sig_hi), 26) + static_cast<double>(sig_lo)) * scale;
         const int64_t r = S.r;
+        const int64_t tgt = static_cast<int64_t>(t4[2]) + static_cast<int64_t>(c_gt);
+        const double tsg = t4[1] + cand_sum;
+        S.thr = thr;
         S.cnt_gt = tgt;
-        S.cnt_eq = teq;
-        out[3 * l + 0] = tsa / static_cast<double>(n);
+        S.cnt_eq = static_cast<int64_t>(c_eq);
+        out[3 * l + 0] = t4[0] / static_cast<double>(n);
         out[3 * l + 1] = thr;
         out[3 * l + 2] = (tsg + static_cast<double>(r - tgt) * thr) / static_cast<double>(r);
     }
@@ -443,8 +465,7 @@ extern "C" int32_t ara_metrics(const double *ylt, int32_t n_layers, int64_t n, d
     ProfScope prof(ARA_PROF_METRICS, st);
     k_met_hist<<<grid, kMetThreads, 0, st>>>(ylt, n, nwg, 0, hist, state, part, r);
     k_met_hist<<<grid, kMetThreads, 0, st>>>(ylt, n, nwg, 1, hist, state, part, r);
-    k_met_collect<<<grid, kMetThreads, 0, st>>>(ylt, n, nwg, state, cand);
-    k_met_tail<<<grid, kMetThreads, 0, st>>>(ylt, n, nwg, state, part, out);
+    k_met_collect<<<grid, kMetThreads, 0, st>>>(ylt, n, nwg, state, cand, part, out);
     if (weights) {
         const unsigned gx = static_cast<unsigned>(std::min<int64_t>((n + 255) / 256, 4096));
         k_met_weights<<<dim3(gx, static_cast<unsigned>(n_layers)), 256, 0, st>>>(ylt, n, n_layers, state, weights);
