@@ -217,6 +217,29 @@ def test_metrics_crowded_prefix_bin(ara, n_crowd, ties):
         np.testing.assert_array_equal(wts, oracle.metric_weights(y, p))
 
 
+def test_metrics_subnormal_and_zero_bins(ara):
+    """PML and TVaR among subnormal year losses (exponent field 0: the
+    gathered values' significands carry no implicit bit), among zeros, and
+    just above them, against the oracle."""
+    import torch
+    g = np.random.default_rng(17)
+    n = 50_000
+    y = np.zeros((3, n))
+    tiny = np.ldexp(g.integers(1, 1 << 40, size=n).astype(np.float64), -1074)   # subnormals
+    y[0] = np.where(g.random(n) < 0.7, tiny, 0.0)
+    y[1, : n // 3] = tiny[: n // 3]
+    y[1, n // 3: n // 2] = g.lognormal(0.0, 1.0, size=n // 2 - n // 3)          # a few normal values above
+    y[2] = 0.0
+    y[2, :5] = [1e-300, 2e-310, 5e-320, 1.0, 0.0]
+    for p in [0.01, 0.3, 0.5, 0.9, 0.99, 0.9999]:
+        out, wts = ara.metrics(torch.tensor(y, device="cuda"), p, want_weights=True)
+        out, wts = out.cpu().numpy(), wts.cpu().numpy()
+        ref = oracle.metrics(y, p)
+        assert np.array_equal(out[:, 1], ref[:, 1]), (p, out[:, 1], ref[:, 1])
+        np.testing.assert_allclose(out[:, [0, 2]], ref[:, [0, 2]], rtol=TOL, atol=0)
+        np.testing.assert_array_equal(wts, oracle.metric_weights(y, p))
+
+
 def test_metrics_repeatable_and_layers_independent(ara):
     """Same answer twice (order-free gathering) and each layer as if alone."""
     import torch
