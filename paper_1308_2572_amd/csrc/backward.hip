@@ -37,10 +37,11 @@
 //   W(e) = c * (occurrences of e) + sum over t in D of (v_t - c) * (occurrences of e in t),
 // integer arithmetic that gives the gather's result bit for bit.  The
 // occurrence counts come from the event-major offsets, the second term from
-// the trial-major copy of the deviating trials' events.  It is used when D
-// holds at most an eighth of the trials (and either the call covers every
-// trial or c = 0); the decision is taken on the device from the counts, so
-// both forms are enqueued and the one not chosen returns at once.
+// the trial-major copy of the deviating trials' events; for a call over part
+// of the trials, those outside it count as deviating (weight 0) when c is
+// not zero.  It is used when the trials to walk are at most an eighth of
+// all; the decision is taken on the device from the counts, so both forms
+// are enqueued and the one not chosen returns at once.
 #include "occ.h"
 #include "wave.h"
 
@@ -216,8 +217,8 @@ struct BwdSparse {
     const int64_t *vq;                 // [n_layers][n][cs]
     int64_t n, t0, n_trials;
     int32_t cs, n_cot, catalog, n_sr;
-    int32_t full;                      // the call covers every trial
     int32_t pad;
+    int64_t n_out;                     // trials outside the call's range (weight 0 there)
     unsigned long long *ndev;          // [n_layers] deviating trials
     int64_t *common;                   // [n_layers][kMaxCot] the chosen common value
     int32_t *dev;                      // [n_layers][n] deviating trials (call-relative)
@@ -235,14 +236,24 @@ __device__ __forceinline__ int64_t cand_value(const BwdSparse &P, int j, int c, 
     return P.vq[(static_cast<size_t>(j) * P.n + t) * P.cs + c];
 }
 
-// The second form's condition, the same in every kernel that reads it.
-__device__ __forceinline__ bool sparse_chosen(const BwdSparse &P, int j) {
-    const unsigned long long nd = P.ndev[j];
-    if (nd * kCand > static_cast<unsigned long long>(P.n)) return false;
-    if (P.full) return true;
+// Whether some row's common value is non-zero: then the trials outside the
+// call's range (weight 0) deviate from it too.
+__device__ __forceinline__ bool common_nonzero(const BwdSparse &P, int j) {
     for (int c = 0; c < P.n_cot; ++c)
-        if (P.common[static_cast<size_t>(j) * kMaxCot + c] != 0) return false;
-    return true;
+        if (P.common[static_cast<size_t>(j) * kMaxCot + c] != 0) return true;
+    return false;
+}
+
+// Deviating trials the second form walks: those of the range, and the ones
+// outside it when the common value is not zero.
+__device__ __forceinline__ int64_t sparse_walk(const BwdSparse &P, int j) {
+    return static_cast<int64_t>(P.ndev[j]) + (common_nonzero(P, j) ? P.n_out : 0);
+}
+
+// The second form's condition, the same in every kernel that reads it: at
+// most an eighth of all the trials to walk.
+__device__ __forceinline__ bool sparse_chosen(const BwdSparse &P, int j) {
+    return sparse_walk(P, j) * kCand <= P.n_trials;
 }
 
 struct BwdGather {
@@ -409,11 +420,12 @@ __global__ __launch_bounds__(1024) void k_bwd_dev(BwdSparse P) {
     for (uint32_t i = threadIdx.x; i < nb; i += blockDim.x) dv[i] = buf[i];
 }
 
-// (5c) W(e) = c * (occurrences of e) for every hot event (when the second
-// form is chosen; the accumulators are zero from step 4 otherwise)
+// (5c) W(e) = c * (occurrences of e in all trials) for every hot event (when
+// the second form is chosen and c is not zero; the accumulators are zero
+// from step 4 otherwise)
 __global__ __launch_bounds__(256) void k_bwd_winit(BwdSparse P) {
     const int j = blockIdx.y;
-    if (!sparse_chosen(P, j) || !P.full) return;
+    if (!sparse_chosen(P, j) || !common_nonzero(P, j)) return;   // c = 0: W starts at zero
     const int H = P.hot_base[static_cast<size_t>(j) * (P.n_sr + 1) + P.n_sr];
     const int32_t *hev = P.hot_ev + static_cast<size_t>(j) * P.catalog;
     int64_t *Wj = P.W + static_cast<size_t>(j) * P.n_cot * P.catalog;
@@ -429,25 +441,38 @@ __global__ __launch_bounds__(256) void k_bwd_winit(BwdSparse P) {
 }
 
 // (5d) the deviating trials: a wavefront per trial adds v_t - c to W of each
-// hot event of the trial, one integer atomic per (occurrence, row)
+// hot event of the trial, one integer atomic per (occurrence, row); the
+// trials outside the call's range (v_t = 0) follow the listed ones
 __global__ __launch_bounds__(256) void k_bwd_wsparse(BwdSparse P) {
     const int j = blockIdx.y, lane = threadIdx.x & 63;
     if (!sparse_chosen(P, j)) return;
     const int64_t nd = static_cast<int64_t>(P.ndev[j]);
+    const int64_t nwalk = sparse_walk(P, j);
+    const int64_t call_end = P.t0 + P.n;
     const OccTables T = P.tabs[j];
     const int32_t *hb = P.hot_base + static_cast<size_t>(j) * (P.n_sr + 1);
     const int64_t *q = P.vq + static_cast<size_t>(j) * P.n * P.cs;
     int64_t *Wj = P.W + static_cast<size_t>(j) * P.n_cot * P.catalog;
     const int waves = gridDim.x * (blockDim.x >> 6);
-    for (int64_t i = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); i < nd; i += waves) {
-        const int32_t u = P.dev[static_cast<size_t>(j) * P.n + i];
+    for (int64_t i = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); i < nwalk; i += waves) {
         unsigned long long dl[kMaxCot];
+        int64_t t;
+        if (i < nd) {   // a deviating trial of the range
+            const int32_t u = P.dev[static_cast<size_t>(j) * P.n + i];
 #pragma unroll
-        for (int c = 0; c < kMaxCot; ++c)
-            dl[c] = c < P.n_cot ? static_cast<unsigned long long>(q[static_cast<size_t>(u) * P.cs + c]) -
-                                      static_cast<unsigned long long>(P.common[static_cast<size_t>(j) * kMaxCot + c])
-                                : 0ull;
-        const int64_t t = P.t0 + u;
+            for (int c = 0; c < kMaxCot; ++c)
+                dl[c] = c < P.n_cot ? static_cast<unsigned long long>(q[static_cast<size_t>(u) * P.cs + c]) -
+                                          static_cast<unsigned long long>(P.common[static_cast<size_t>(j) * kMaxCot + c])
+                                    : 0ull;
+            t = P.t0 + u;
+        } else {        // a trial outside the range: weight 0
+            const int64_t o = i - nd;
+            t = o < P.t0 ? o : call_end + (o - P.t0);
+#pragma unroll
+            for (int c = 0; c < kMaxCot; ++c)
+                dl[c] = c < P.n_cot ? 0ull - static_cast<unsigned long long>(P.common[static_cast<size_t>(j) * kMaxCot + c])
+                                    : 0ull;
+        }
         const int64_t a = P.t_off[t], b = P.t_off[t + 1];
         constexpr int kU = 16;   // events per lane in flight: a 1000-event trial in one round
         for (int64_t k0 = a; k0 < b; k0 += 64 * kU) {
@@ -857,7 +882,7 @@ extern "C" int32_t ara_ylt_backward(const ara_tables *tables, const ara_yet *yet
     Q.n_cot = n_cot;
     Q.catalog = tables->catalog;
     Q.n_sr = B.z.n_sr;
-    Q.full = trial_begin == 0 && trial_end == yet->n_trials;
+    Q.n_out = yet->n_trials - n;
     Q.ndev = ndev;
     Q.common = common;
     Q.dev = dev;

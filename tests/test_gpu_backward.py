@@ -273,6 +273,10 @@ def test_deviating_trial_form_is_bitwise_the_gather(ara):
     cases.append(("four rows", four, 0, None))
     _, wts_sub = ara.metrics(ylt[:, 5000:17000].contiguous(), 0.95, want_weights=True)
     cases.append(("sub-range, AAL row (gather)", wts_sub, 5000, 17000))
+    # most of the trials: those outside the range count as deviating (weight 0)
+    _, wts_near = ara.metrics(ylt[:, 1000:23000].contiguous(), 0.95, want_weights=True)
+    cases.append(("near-full sub-range, every row", wts_near, 1000, 23000))
+    cases.append(("near-full sub-range, AAL row", wts_near[:1].contiguous(), 1000, 23000))
     cases.append(("sub-range, PML and TVaR rows", wts_sub[1:].contiguous(), 5000, 17000))
     for label, cot, t0, t1 in cases:
         _say(label)
@@ -294,4 +298,12 @@ def test_deviating_trial_form_full_size_vs_oracle(ara):
     _say("workload 3: both forms")
     a = sparse(s_pre, wts)
     b = dense(s_pre, wts)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+    # a range over 90% of the trials: the 100,000 outside it join the deviating ones (weight 0)
+    t0, t1 = 40_000, w.yet.n_trials - 60_000
+    _say("workload 3: both forms over trials [40000, 940000)")
+    _, wsub = ara.metrics(ylt[:, t0:t1].contiguous(), w.p, want_weights=True)
+    sp = s_pre[:, t0:t1].contiguous()
+    a = sparse(sp, wsub, t0, t1)
+    b = dense(sp, wsub, t0, t1)
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
