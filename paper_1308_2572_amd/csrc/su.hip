@@ -227,8 +227,10 @@ __device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32
             k0 += kW0;
             k1 += kW1;
         }
-        const uint32_t hi0 = __umulhi(kM0, c[0]), lo0 = kM0 * c[0];
-        const uint32_t hi1 = __umulhi(kM1, c[2]), lo1 = kM1 * c[2];
+        // each full 64-bit product in one multiply (high and low words)
+        const uint64_t p0 = static_cast<uint64_t>(kM0) * c[0], p1 = static_cast<uint64_t>(kM1) * c[2];
+        const uint32_t hi0 = static_cast<uint32_t>(p0 >> 32), lo0 = static_cast<uint32_t>(p0);
+        const uint32_t hi1 = static_cast<uint32_t>(p1 >> 32), lo1 = static_cast<uint32_t>(p1);
         const uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
         c[0] = n0;
         c[1] = lo1;
