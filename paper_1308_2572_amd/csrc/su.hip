@@ -257,11 +257,13 @@ __device__ __forceinline__ double su_draw(const SuEntry &e, uint64_t seed, int64
 //
 // Only ~15% of occurrences belong to the union, so drawing where they fall
 // would leave most lanes idle.  Each wavefront appends its union occurrences
-// (offset in the trial, first entry, entry count) to a queue in LDS as it
-// streams, and whenever 64 are queued they are drawn together, one
-// occurrence per lane; the rest are drawn at the end of the trial.  Each
-// lane sums the losses of the occurrences it drew, in queue order; the
-// trial's total is the wavefront sum of those.
+// (offset in the trial, first entry) to a queue in LDS as it streams, and
+// whenever 64 are queued they are drawn in rounds of one draw per lane: a
+// lane takes the next queued occurrence, draws its first ELT and, when
+// further ELTs hold the event, keeps the occurrence and draws one of them
+// per round while the other lanes take new ones; what is left is drawn at
+// the end of the trial.  Each lane sums the losses of the occurrences it
+// finished, in that order; the trial's total is the wavefront sum of those.
 
 constexpr int kSuSlices = 8;        // 64-occurrence slices per step
 constexpr int kSuQueue = 2 * kWave; // queue capacity: < 64 waiting + one slice
@@ -323,26 +325,75 @@ __global__ __launch_bounds__(kSuThreads) void k_su_fwd(SuParams P) {
             if (lane == 0) atomicCAS(P.err, 0, ARA_E_RANGE);
             b = a;
         }
-        double acc = 0.0;   // losses of the occurrences this lane drew, in queue order
+        double acc = 0.0;   // losses of the occurrences this lane finished
         int qlen = 0;       // uniform
-        // draws for queue entries [0, cnt), one per lane: steps one to three
-        auto drain = [&](int cnt) {
-            if (lane < cnt && qe[lane] < cap) {
-                const int64_t i = a + qd[lane];
-                const SuEntry first = E[qe[lane]];
-                double x = 0.0;
-                {
-                    const double v = su_draw(first, P.seed, i);
-                    x = x + xl(ls[first.q] * v, lr[first.q], ll[first.q]);
-                }
-                const int more = static_cast<uint64_t>(first.next) + first.more <= cap ? first.more : 0;
-                for (int h = 0; h < more; ++h) {   // the further ELTs, in listed order
-                    const SuEntry en = E[first.next + h];
-                    const double v = su_draw(en, P.seed, i);
-                    x = x + xl(ls[en.q] * v, lr[en.q], ll[en.q]);
-                }
-                acc += xl(x, occR, occL);
+        // A lane whose occurrence is held by further ELTs keeps it and draws
+        // one further ELT per round, so that no round waits on a few lanes.
+        bool pend = false;
+        uint32_t pe = 0;    // its next entry
+        int pleft = 0;      // entries still to draw, pe included
+        int64_t pi = 0;     // its index in the YET
+        double px = 0.0;    // its ELTs' losses so far, summed in listed order
+        // one draw per lane: the held occurrences' next ELTs, and the queue's
+        // first entries for the other lanes in lane order (at most `avail`);
+        // steps one to three.  Returns the number of queue entries taken.
+        auto draw_round = [&](int avail) {
+            const uint64_t freem = __ballot(!pend);
+            const int rank = static_cast<int>(__builtin_amdgcn_mbcnt_hi(
+                static_cast<uint32_t>(freem >> 32), __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(freem), 0u)));
+            const int taken = min(avail, static_cast<int>(__popcll(freem)));   // uniform
+            const bool first = !pend;
+            bool act = pend;
+            uint32_t ei = pe;
+            int64_t i = pi;
+            if (first && rank < taken && qe[rank] < cap) {
+                act = true;
+                ei = qe[rank];
+                i = a + qd[rank];
             }
+            if (act) {
+                const SuEntry en = E[ei];
+                const double v = su_draw(en, P.seed, i);
+                const double g = xl(ls[en.q] * v, lr[en.q], ll[en.q]);
+                if (first) {
+                    px = g;
+                    pi = i;
+                    pe = en.next;
+                    pleft = static_cast<uint64_t>(en.next) + en.more <= cap ? en.more : 0;
+                } else {
+                    px = px + g;
+                    ++pe;
+                    --pleft;
+                }
+                pend = pleft > 0;
+                if (!pend) acc += xl(px, occR, occL);
+            }
+            return taken;
+        };
+        // drop the first `taken` queue entries (the queue holds at most 127)
+        auto shift = [&](int taken) {
+            const int rest = qlen - taken;   // uniform
+            int32_t d0 = 0, d1 = 0;
+            uint32_t e0 = 0, e1 = 0;
+            if (lane < rest) {
+                d0 = qd[taken + lane];
+                e0 = qe[taken + lane];
+            }
+            if (lane + kWave < rest) {
+                d1 = qd[taken + kWave + lane];
+                e1 = qe[taken + kWave + lane];
+            }
+            __builtin_amdgcn_wave_barrier();
+            if (lane < rest) {
+                qd[lane] = d0;
+                qe[lane] = e0;
+            }
+            if (lane + kWave < rest) {
+                qd[kWave + lane] = d1;
+                qe[kWave + lane] = e1;
+            }
+            __builtin_amdgcn_wave_barrier();
+            qlen = rest;
         };
         for (int64_t base = a; base < b; base += kSuSlices * kWave) {
             // the step's IDs, then the bitmap words of its maybe-set events
@@ -389,27 +440,12 @@ __global__ __launch_bounds__(kSuThreads) void k_su_fwd(SuParams P) {
                 }
                 qlen += __popcll(m);
                 __builtin_amdgcn_wave_barrier();
-                if (qlen >= kWave) {
-                    drain(kWave);
-                    // move the rest (< 64) to the front
-                    const int rest = qlen - kWave;
-                    int32_t d2 = 0;
-                    uint32_t e2 = 0;
-                    if (lane < rest) {
-                        d2 = qd[kWave + lane];
-                        e2 = qe[kWave + lane];
-                    }
-                    __builtin_amdgcn_wave_barrier();
-                    if (lane < rest) {
-                        qd[lane] = d2;
-                        qe[lane] = e2;
-                    }
-                    __builtin_amdgcn_wave_barrier();
-                    qlen = rest;
-                }
+                // every round draws on every lane that has work; a round that
+                // takes no entry still moves the held occurrences on
+                while (qlen >= kWave) shift(draw_round(qlen));
             }
         }
-        drain(qlen);
+        while (qlen > 0 || __ballot(pend) != 0ull) shift(draw_round(qlen));
         // step four, telescoped: the aggregate terms on the trial's total
         const double S = lane63(wave_inclusive_sum(acc));
         if (lane == 0) {
