@@ -119,6 +119,9 @@ struct RangeInfo {
 template <bool HITS, bool F32>
 __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_fwd(FwdParams P) {
     using V = typename std::conditional<F32, float, double>::type;
+    // codes per lane and chunk: half as many with hit counts, whose extra
+    // per-code state would not fit the registers of eight codes
+    constexpr int kUn = HITS ? kUnroll / 2 : kUnroll;
     constexpr uint32_t kV = sizeof(V);             // bytes per value and per trial total
     constexpr int kVSh = F32 ? 2 : 3;              // log2(kV)
     constexpr uint32_t kVPer16 = 16 / kV;          // values per 16-byte copy
@@ -230,13 +233,14 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8))) vo
             rr = seg_win + kWave;
         }
     };
-    // a chunk is kUnroll codes per lane (two 8-byte loads); the first chunk of
+    // a chunk is kUn codes per lane (8-byte loads of four); the first chunk of
     // a segment also brings the lane's starting trial.  Runs are multiples of
-    // 4 codes, so only a chunk's second load can lie past the segment's end:
-    // it then reads skip codes from the block after the last code.  Nothing
+    // 4 codes, so only the second load of an eight-code chunk can lie past the
+    // segment's end: it then reads skip codes from the block after the last
+    // code.  Nothing
     // is selected on the loaded words, so the loads stay in flight while the
     // previous chunk is processed.
-    unsigned long long X[kUnroll / 4];
+    unsigned long long X[kUn / 4];
     int X_start = 0;
     bool X_first = false;
     int chunk_rr = G;
@@ -246,12 +250,12 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8))) vo
             X_first = step == 0;
             if (X_first) X_start = P.lane_start[(seg0 + static_cast<size_t>(rr) * kGroups) * kWave + lane];
 #pragma unroll
-            for (int q = 0; q < kUnroll / 4; ++q) {
+            for (int q = 0; q < kUn / 4; ++q) {
                 const uint16_t *src = step + 4 * q < R ? P.code + sb + static_cast<int64_t>((step >> 2) + q) * (4 * kWave)
                                                        : P.pad;   // uniform
                 X[q] = ld_codes(src + 4 * lane);
             }
-            step += kUnroll;
+            step += kUn;
             if (step >= R) {
                 ++rr;
                 step = 0;
@@ -297,42 +301,42 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8))) vo
             constexpr bool kTellSkip = decltype(skip_tag)::value;
             if (X_first) tofs = accw_off + kV * static_cast<uint32_t>(X_start);
             // codes of this chunk, two per 32-bit word, low half first
-            uint32_t wd[kUnroll / 2];
+            uint32_t wd[kUn / 2];
 #pragma unroll
-            for (int h = 0; h < kUnroll / 2; ++h) wd[h] = static_cast<uint32_t>(X[h >> 1] >> (32 * (h & 1)));
+            for (int h = 0; h < kUn / 2; ++h) wd[h] = static_cast<uint32_t>(X[h >> 1] >> (32 * (h & 1)));
             load();   // prefetch the next chunk (possibly of a later range)
             // bitmap words of all codes first, without branches, so the LDS
             // reads are in flight together (offset bits 5..14 pick the word)
-            uint32_t cw[kUnroll];
+            uint32_t cw[kUn];
 #pragma unroll
-            for (int u = 0; u < kUnroll; ++u) cw[u] = (u & 1) ? (wd[u >> 1] >> 16) : wd[u >> 1];
-            uint2 q[kUnroll];
+            for (int u = 0; u < kUn; ++u) cw[u] = (u & 1) ? (wd[u >> 1] >> 16) : wd[u >> 1];
+            uint2 q[kUn];
 #pragma unroll
-            for (int u = 0; u < kUnroll; ++u) q[u] = tbr[__builtin_amdgcn_ubfe(cw[u], 5, 10)];
+            for (int u = 0; u < kUn; ++u) q[u] = tbr[__builtin_amdgcn_ubfe(cw[u], 5, 10)];
             // each code advances the lane's trial by its top bit
-            uint32_t ta[kUnroll];
+            uint32_t ta[kUn];
 #pragma unroll
-            for (int u = 0; u < kUnroll; ++u) {
+            for (int u = 0; u < kUn; ++u) {
                 tofs = (u & 1) ? add_bit<31, kVSh>(tofs, wd[u >> 1]) : add_bit<15, kVSh>(tofs, wd[u >> 1]);
                 ta[u] = tofs;
             }
             // bit and rank: the bit field instructions read only the low five
             // bits of their offset and width operands, which hold the bit
-            bool on[kUnroll];
-            uint32_t rank[kUnroll];
+            bool on[kUn];
+            uint32_t rank[kUn];
 #pragma unroll
-            for (int u = 0; u < kUnroll; ++u) {
+            for (int u = 0; u < kUn; ++u) {
                 on[u] = __builtin_amdgcn_ubfe(q[u].x, cw[u], 1) != 0u;
                 if (kTellSkip) on[u] = on[u] && (cw[u] & 0xFFFFu) != 0xFFFFu;
                 rank[u] = __popc(__builtin_amdgcn_ubfe(q[u].x, 0, cw[u])) + q[u].y;
             }
             if (all_lds) {
-                V v[kUnroll];
+                V v[kUn];
 #pragma unroll
-                for (int u = 0; u < kUnroll; ++u)
+                for (int u = 0; u < kUn; ++u)
                     v[u] = *reinterpret_cast<const V *>(smem + ((on[u] ? rank[u] : vsh) * kV + vbase));
 #pragma unroll
-                for (int u = 0; u < kUnroll; ++u)
+                for (int u = 0; u < kUn; ++u)
                     if (on[u]) {
                         atomicAdd(reinterpret_cast<V *>(smem + ta[u]), v[u]);
                         if (HITS)
@@ -341,7 +345,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8))) vo
                     }
             } else {
 #pragma unroll
-                for (int u = 0; u < kUnroll; ++u)
+                for (int u = 0; u < kUn; ++u)
                     if (on[u]) {
                         // indexes relative to the buffer start, so that every
                         // address stays inside its array
