@@ -326,7 +326,11 @@ def _full_parity(ara, w, label):
     """Every trial of a full-size workload against the oracle (all host
     threads): YLT and S to the tolerance, hit counts bit-exact, through both
     the plain path and the hit-count path (whose larger tables spill out of
-    LDS on the uneven workload)."""
+    LDS on the uneven workload); AAL, PML and TVaR of the device YLT against
+    those of the oracle's, each within the tolerance times the layer's
+    largest S (a metric moves by at most the largest change of one year
+    loss)."""
+    import torch
     _say(f"{label}: oracle over every trial")
     ref = oracle_ref(w, threads=oracle.num_threads_available())
     e = Engine(ara, w)
@@ -336,6 +340,11 @@ def _full_parity(ara, w, label):
     yh, sh, hh = e.forward(hits=True)
     assert np.array_equal(hh, ref["hits"])
     assert np.array_equal(yh, y) and np.array_equal(sh, s)
+    _say(f"{label}: metrics against the oracle's")
+    out, _ = ara.metrics(torch.tensor(y, device="cuda"), w.p)
+    want = oracle.metrics(ref["ylt"], w.p)
+    bound = TOL * ref["s_pre"].max(axis=1)[:, None]
+    assert np.all(np.abs(out.cpu().numpy() - want) <= bound), (out.cpu().numpy(), want)
 
 
 def test_config1_full_size_every_trial(ara):
