@@ -208,6 +208,24 @@ __global__ __launch_bounds__(kMetThreads) void k_met_hist(const double *__restri
     }
 }
 
+// Visits the gathered keys [0, cn) of one workgroup's walk, from LDS or from
+// the global copy, kMetUnroll per thread and sweep so that the global reads
+// are in flight together; f(valid, key) runs on every lane (uniform trip
+// count, so f may hold ballots).
+template <class F>
+__device__ __forceinline__ void each_cand(bool in_lds, const uint64_t *cs, const uint64_t *c, int64_t cn, F f) {
+    for (int64_t i0 = 0; i0 < cn; i0 += kMetSweep) {
+        uint64_t u[kMetUnroll];
+#pragma unroll
+        for (int q = 0; q < kMetUnroll; ++q) {
+            const int64_t i = i0 + q * kMetThreads + threadIdx.x;
+            u[q] = i < cn ? (in_lds ? cs[i] : get(&c[i])) : 0ull;
+        }
+#pragma unroll
+        for (int q = 0; q < kMetUnroll; ++q) f(i0 + q * kMetThreads + threadIdx.x < cn, u[q]);
+    }
+}
+
 // Gathers every value whose 23-bit prefix is the selected one (a wavefront
 // reserves its slots with one atomic), with their smallest and largest key.
 // The last workgroup finishes digits 2..5 on them.
@@ -303,10 +321,20 @@ __global__ __launch_bounds__(kMetThreads) void k_met_collect(const double *__res
             __syncthreads();
             const int sh = kShift[d], hbd = kShift[d] + kWidth[d];
             const uint32_t mask = (1u << kWidth[d]) - 1u;
-            for (int64_t i = tid; i < cn; i += kMetThreads) {
-                const uint64_t u = in_lds ? cs[i] : get(&c[i]);
-                if ((u >> hbd) == pre) atomicAdd(&h[(u >> sh) & mask], 1u);
-            }
+            each_cand(in_lds, cs, c, cn, [&](bool valid, uint64_t u) {
+                const bool want = valid && (u >> hbd) == pre;
+                const uint32_t dg = static_cast<uint32_t>((u >> sh) & mask);
+                // tied keys crowd one digit: the first lane's digit is counted
+                // for all the lanes that share it with one LDS atomic
+                const uint64_t act = __ballot(want);
+                if (act) {
+                    const int leader = __builtin_ctzll(act);
+                    const uint32_t ld = __builtin_amdgcn_readlane(dg, leader);
+                    const uint64_t same = __ballot(want && dg == ld);
+                    if (lane == leader) atomicAdd(&h[ld], static_cast<uint32_t>(__popcll(same)));
+                    if (want && dg != ld) atomicAdd(&h[dg], 1u);
+                }
+            });
             __syncthreads();
             find_digit(h, 1 << kWidth[d], need, fs);
             pre = (pre << kWidth[d]) | static_cast<uint64_t>(fs.digit);
@@ -323,8 +351,8 @@ __global__ __launch_bounds__(kMetThreads) void k_met_collect(const double *__res
         if (tid == 0) c_eq = static_cast<unsigned long long>(cn);
     } else {
         const bool in_lds = cn <= kCandCap;   // uniform; the copy in LDS is still there
-        for (int64_t i = tid; i < cn; i += kMetThreads) {
-            const uint64_t u = in_lds ? cs[i] : get(&c[i]);
+        each_cand(in_lds, cs, c, cn, [&](bool valid, uint64_t u) {
+            if (!valid) return;
             if (u > bits) {
                 const uint64_t e = (u >> 52) & 0x7FFull;
                 const uint64_t sig = (u & ((1ull << 52) - 1ull)) | (e ? (1ull << 52) : 0ull);
@@ -334,7 +362,7 @@ __global__ __launch_bounds__(kMetThreads) void k_met_collect(const double *__res
             } else if (u == bits) {
                 ++c_eq;
             }
-        }
+        });
     }
     {   // integer sums: any order gives the same totals
         unsigned long long v[4] = {sig_hi, sig_lo, c_gt, c_eq};
