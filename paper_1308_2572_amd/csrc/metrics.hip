@@ -46,7 +46,9 @@ struct MetState {
 
 struct MetPart {
     double sum, sum_gt;
-    int64_t cnt_gt, cnt_eq;
+    int64_t cnt_gt;
+    uint64_t kmax;     // the largest gathered key of the workgroup
+    int64_t n_kmax;    // how many of its gathered keys equal it
 };
 
 __device__ __forceinline__ uint64_t key_of(double y) {
@@ -237,6 +239,8 @@ __global__ __launch_bounds__(kMetThreads) void k_met_collect(const double *__res
     __shared__ FindShared fs;
     __shared__ double red[4][16];
     __shared__ unsigned long long ired[4][16];
+    __shared__ unsigned long long wkm[kMetThreads / 64];
+    __shared__ long long wkn[kMetThreads / 64];
     __shared__ int flag;
     const int l = blockIdx.y, wg = blockIdx.x, tid = threadIdx.x, lane = tid & 63;
     MetState &S = st[l];
@@ -249,6 +253,7 @@ __global__ __launch_bounds__(kMetThreads) void k_met_collect(const double *__res
     const double *y = ylt + static_cast<size_t>(l) * n;
     uint64_t *c = cand + static_cast<size_t>(l) * n;
     uint64_t kmin = ~0ull, kmax = 0ull;
+    int64_t nkmax = 0;   // this lane's gathered keys equal to its kmax
     for (int64_t i0 = lo; i0 < hi; i0 += kMetSweep) {
         uint64_t k[kMetUnroll], m[kMetUnroll];
         int64_t mine = 0;
@@ -269,7 +274,12 @@ __global__ __launch_bounds__(kMetThreads) void k_met_collect(const double *__res
             mine += __popcll(m[u]);
             if (is) {
                 kmin = std::min(kmin, k[u]);
-                kmax = std::max(kmax, k[u]);
+                if (nkmax == 0 || k[u] > kmax) {
+                    kmax = k[u];
+                    nkmax = 1;
+                } else if (k[u] == kmax) {
+                    ++nkmax;
+                }
             }
         }
         if (mine) {   // uniform: the wavefront reserves its slots itself
@@ -287,29 +297,62 @@ __global__ __launch_bounds__(kMetThreads) void k_met_collect(const double *__res
             }
         }
     }
-    if (__ballot(kmin <= kmax)) {   // uniform: this wavefront gathered something
+    unsigned long long wk = 0ull;   // the wavefront's largest gathered key and its count
+    long long wn = 0;
+    if (__ballot(nkmax > 0)) {   // uniform: this wavefront gathered something
+        const uint64_t my_kmax = kmax;
         for (int o = 32; o > 0; o >>= 1) {
             kmin = std::min(kmin, static_cast<uint64_t>(__shfl_xor(static_cast<unsigned long long>(kmin), o)));
             kmax = std::max(kmax, static_cast<uint64_t>(__shfl_xor(static_cast<unsigned long long>(kmax), o)));
         }
+        wk = kmax;
+        wn = (nkmax > 0 && my_kmax == kmax) ? nkmax : 0;
+        for (int o = 32; o > 0; o >>= 1) wn += __shfl_xor(wn, o);
         if (lane == 0) {
             atomicMax(&S.kmax, static_cast<unsigned long long>(kmax));
             atomicMax(&S.kminc, static_cast<unsigned long long>(~kmin));
         }
     }
+    if (lane == 0) {
+        wkm[tid >> 6] = wk;
+        wkn[tid >> 6] = wn;
+    }
     {
         double t2[2] = {s_above, static_cast<double>(n_above)};
-        block_sums(t2, red);
+        block_sums(t2, red);   // also publishes wkm and wkn
         if (tid == 0) {
-            put(&part[static_cast<size_t>(l) * nwg + wg].sum_gt, t2[0]);
-            put(&part[static_cast<size_t>(l) * nwg + wg].cnt_gt, static_cast<int64_t>(t2[1]));
+            MetPart *pw = part + static_cast<size_t>(l) * nwg + wg;
+            put(&pw->sum_gt, t2[0]);
+            put(&pw->cnt_gt, static_cast<int64_t>(t2[1]));
+            unsigned long long km = 0ull;
+            long long kn = 0;
+            for (int i = 0; i < kMetThreads / 64; ++i) km = wkm[i] > km ? wkm[i] : km;
+            for (int i = 0; i < kMetThreads / 64; ++i) kn += wkm[i] == km ? wkn[i] : 0;
+            put(&pw->kmax, static_cast<uint64_t>(km));
+            put(&pw->n_kmax, static_cast<int64_t>(kn));
         }
     }
     if (!finished_last(S, 2, nwg, &flag)) return;
     const int64_t cn = static_cast<int64_t>(get(&S.cand_n));
     const uint64_t lo_key = ~static_cast<uint64_t>(get(&S.kminc)), hi_key = static_cast<uint64_t>(get(&S.kmax));
     uint64_t bits = hi_key;
-    if (lo_key != hi_key) {
+    // how many gathered keys equal the largest: when they reach the rank
+    // sought inside the bin (values capped at one limit crowd the top), that
+    // key is the PML and no pass over the gathered keys is needed
+    int64_t n_top = 0;
+    {
+        long long v = 0;
+        const MetPart *pl = part + static_cast<size_t>(l) * nwg;
+        for (int i = tid; i < nwg; i += kMetThreads)
+            if (get(&pl[i].kmax) == hi_key) v += get(&pl[i].n_kmax);
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+        if (lane == 0) wkn[tid >> 6] = v;
+        __syncthreads();
+        for (int i = 0; i < kMetThreads / 64; ++i) n_top += wkn[i];
+        __syncthreads();
+    }
+    const bool top_tied = lo_key != hi_key && n_top >= S.need[2];   // uniform
+    if (lo_key != hi_key && !top_tied) {
         // the values differ: radix select on the gathered copy
         const bool in_lds = cn <= kCandCap;   // uniform
         if (in_lds)
@@ -349,6 +392,8 @@ __global__ __launch_bounds__(kMetThreads) void k_met_collect(const double *__res
     unsigned long long sig_hi = 0, sig_lo = 0, c_gt = 0, c_eq = 0;
     if (lo_key == hi_key) {
         if (tid == 0) c_eq = static_cast<unsigned long long>(cn);
+    } else if (top_tied) {
+        if (tid == 0) c_eq = static_cast<unsigned long long>(n_top);   // none above it in the bin
     } else {
         const bool in_lds = cn <= kCandCap;   // uniform; the copy in LDS is still there
         each_cand(in_lds, cs, c, cn, [&](bool valid, uint64_t u) {

@@ -217,6 +217,30 @@ def test_metrics_crowded_prefix_bin(ara, n_crowd, ties):
         np.testing.assert_array_equal(wts, oracle.metric_weights(y, p))
 
 
+@pytest.mark.parametrize("n_crowd,n_top", [(5_000, 4_000), (20_000, 12_000), (60_000, 40_000), (200_000, 150_000)])
+def test_metrics_tied_at_the_top_of_the_bin(ara, n_crowd, n_top):
+    """Year losses capped at one limit: the largest value of the crowded
+    prefix bin repeated n_top times, the rest of the crowd distinct below it.
+    Ranks inside the tied block (the PML is that value, found from the tie
+    count alone), at its edge, just past it and past the whole crowd, below
+    and above the 16384 values selected inside LDS."""
+    import torch
+    g = np.random.default_rng(n_crowd + n_top)
+    n = 250_000
+    y = g.uniform(0.0, 9.9e5, size=(1, n))
+    crowd = 1e6 + np.arange(n_crowd, dtype=np.float64) * 1e-5
+    crowd[n_crowd - n_top:] = crowd[-1]
+    y[0, g.permutation(n)[:n_crowd]] = crowd
+    for r in [1, n_top // 2, n_top, n_top + 1, n_crowd, n_crowd + 3]:
+        p = (n - r) / n
+        out, wts = ara.metrics(torch.tensor(y, device="cuda"), p, want_weights=True)
+        out, wts = out.cpu().numpy(), wts.cpu().numpy()
+        ref = oracle.metrics(y, p)
+        assert np.array_equal(out[:, 1], ref[:, 1]), (r, out[:, 1], ref[:, 1])
+        np.testing.assert_allclose(out[:, [0, 2]], ref[:, [0, 2]], rtol=TOL, atol=0)
+        np.testing.assert_array_equal(wts, oracle.metric_weights(y, p))
+
+
 def test_metrics_subnormal_and_zero_bins(ara):
     """PML and TVaR among subnormal year losses (exponent field 0: the
     gathered values' significands carry no implicit bit), among zeros, and
