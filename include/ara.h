@@ -291,7 +291,7 @@ int32_t ara_ylt_backward_workspace_bytes(const ara_tables *tables, const ara_yet
  * accumulation of the per-event weights, fixed-order reductions).
  * The YET must have been prepared with ARA_PREP_TRANSPOSED (ARA_E_INVAL
  * otherwise).  With ARA_PREP_TRIAL_MAJOR too, cotangents that take one value
- * on all but an eighth of the trials (the metrics' weights) are served from
+ * on all but a sixteenth of the trials (the metrics' weights) are served from
  * the deviating trials' own events; the result is the same bit for bit.
  */
 int32_t ara_ylt_backward(const ara_tables *tables, const ara_yet *yet, const ara_layers *layers,

@@ -39,9 +39,10 @@
 // occurrence counts come from the event-major offsets, the second term from
 // the trial-major copy of the deviating trials' events; for a call over part
 // of the trials, those outside it count as deviating (weight 0) when c is
-// not zero.  It is used when the trials to walk are at most an eighth of
-// all; the decision is taken on the device from the counts, so both forms
-// are enqueued and the one not chosen returns at once.
+// not zero.  It is used when the trials to walk are at most a sixteenth of
+// all (each walked trial costs about sixteen times its share of the
+// gather's time); the decision is taken on the device from the counts, so
+// both forms are enqueued and the one not chosen returns at once.
 #include "occ.h"
 #include "wave.h"
 
@@ -251,9 +252,10 @@ __device__ __forceinline__ int64_t sparse_walk(const BwdSparse &P, int j) {
 }
 
 // The second form's condition, the same in every kernel that reads it: at
-// most an eighth of all the trials to walk.
+// most a sixteenth of all the trials to walk.
+constexpr int kWalkShare = 16;
 __device__ __forceinline__ bool sparse_chosen(const BwdSparse &P, int j) {
-    return sparse_walk(P, j) * kCand <= P.n_trials;
+    return sparse_walk(P, j) * kWalkShare <= P.n_trials;
 }
 
 struct BwdGather {
