@@ -338,9 +338,10 @@ __global__ __launch_bounds__(kMetThreads) void k_met_collect(const double *__res
     uint64_t bits = hi_key;
     // how many gathered keys equal the largest: when they reach the rank
     // sought inside the bin (values capped at one limit crowd the top), that
-    // key is the PML and no pass over the gathered keys is needed
+    // key is the PML and no pass over the gathered copy is needed (asked only
+    // when the keys do not fit in LDS, where the passes are cheap)
     int64_t n_top = 0;
-    {
+    if (lo_key != hi_key && cn > kCandCap) {   // uniform
         long long v = 0;
         const MetPart *pl = part + static_cast<size_t>(l) * nwg;
         for (int i = tid; i < nwg; i += kMetThreads)
@@ -364,7 +365,12 @@ __global__ __launch_bounds__(kMetThreads) void k_met_collect(const double *__res
             __syncthreads();
             const int sh = kShift[d], hbd = kShift[d] + kWidth[d];
             const uint32_t mask = (1u << kWidth[d]) - 1u;
-            each_cand(in_lds, cs, c, cn, [&](bool valid, uint64_t u) {
+            if (in_lds) {
+                for (int64_t i = tid; i < cn; i += kMetThreads) {
+                    const uint64_t u = cs[i];
+                    if ((u >> hbd) == pre) atomicAdd(&h[(u >> sh) & mask], 1u);
+                }
+            } else each_cand(false, cs, c, cn, [&](bool valid, uint64_t u) {
                 const bool want = valid && (u >> hbd) == pre;
                 const uint32_t dg = static_cast<uint32_t>((u >> sh) & mask);
                 // tied keys crowd one digit: the first lane's digit is counted
@@ -396,7 +402,7 @@ __global__ __launch_bounds__(kMetThreads) void k_met_collect(const double *__res
         if (tid == 0) c_eq = static_cast<unsigned long long>(n_top);   // none above it in the bin
     } else {
         const bool in_lds = cn <= kCandCap;   // uniform; the copy in LDS is still there
-        each_cand(in_lds, cs, c, cn, [&](bool valid, uint64_t u) {
+        auto add = [&](bool valid, uint64_t u) {
             if (!valid) return;
             if (u > bits) {
                 const uint64_t e = (u >> 52) & 0x7FFull;
@@ -407,7 +413,12 @@ __global__ __launch_bounds__(kMetThreads) void k_met_collect(const double *__res
             } else if (u == bits) {
                 ++c_eq;
             }
-        });
+        };
+        if (in_lds) {
+            for (int64_t i = tid; i < cn; i += kMetThreads) add(true, cs[i]);
+        } else {
+            each_cand(false, cs, c, cn, add);
+        }
     }
     {   // integer sums: any order gives the same totals
         unsigned long long v[4] = {sig_hi, sig_lo, c_gt, c_eq};
