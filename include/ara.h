@@ -1,8 +1,8 @@
 /*
  * ara.h -- C ABI of the MI355X (gfx950) aggregate-risk-analysis library.
  *
- * The operation is the aggregate analysis of Anderson, Rau-Chaplin,
- * Varbanescu et al. (arXiv 1308.2572), Section II and Algorithm 1: for every
+ * The operation is the aggregate analysis of Bahl, Baltzer, Rau-Chaplin,
+ * Varghese and Whiteway (arXiv 1308.2572), Section II and Algorithm 1: for every
  * layer and every trial of a Year Event Table (YET), look up each event
  * occurrence's loss in the layer's Event Loss Tables (ELTs), apply each ELT's
  * financial terms, sum across the layer's ELTs, apply the layer's occurrence
@@ -302,7 +302,7 @@ int32_t ara_ylt_backward(const ara_tables *tables, const ara_yet *yet, const ara
                          void *ws, size_t ws_bytes, void *stream);
 
 /* ------------------------------------------------------------------------ */
-/* Secondary uncertainty (named as future work in Section V): every          */
+/* Secondary uncertainty (named as future work in Section VI): every         */
 /* (occurrence, ELT) pair draws its loss instead of looking up the mean.     */
 /* ------------------------------------------------------------------------ */
 /*

@@ -1,6 +1,6 @@
 /*
  * ara_oracle.c -- plain, slow, obviously-correct CPU reference for aggregate
- * risk analysis (Anderson, Rau-Chaplin, Varbanescu et al., "Achieving Speedup
+ * risk analysis (Bahl, Baltzer, Rau-Chaplin, Varghese and Whiteway, "Achieving Speedup
  * in Aggregate Risk Analysis using Multiple GPUs", arXiv 1308.2572).
  *
  * TEST INFRASTRUCTURE ONLY.  Nothing in the product library links, loads or
@@ -46,7 +46,7 @@
  *       differencing pass; it sums to the year loss.  The per-year maximum
  *       of these increments is the occurrence loss used for occurrence
  *       exceedance metrics.
- *   R10 secondary uncertainty (named as future work in Section V, not
+ *   R10 secondary uncertainty (named as future work in Section VI, not
  *       defined there): an ELT record carries a standard deviation sigma
  *       beside its mean loss mu, and every (occurrence, ELT) pair draws its
  *       loss from the lognormal distribution with that mean and standard

@@ -1,4 +1,4 @@
-// Secondary uncertainty (named as future work in Section V): Algorithm 1 with
+// Secondary uncertainty (named as future work in Section VI): Algorithm 1 with
 // the table lookup of step one replaced by a draw per (occurrence, ELT) from
 // the lognormal distribution with the record's mean and standard deviation.
 //
