@@ -8,7 +8,12 @@ per-trial summation differs between the two sides):
                   before aggregate terms; near the aggregate retention a
                   plain relative error is ill-conditioned)
   S               1e-9 relative
-  AAL, PML, TVaR  1e-9 relative (PML exact when computed from the same YLT)
+  AAL             1e-9 relative
+  PML             1e-9 * max(PML, S) over the trials whose oracle year loss
+                  is the PML (the same rule as Y, at the selected trials)
+  TVaR            1e-9 * mean of max(Y, S) over the oracle's r largest
+                  year losses
+  (PML exact, AAL and TVaR 1e-9 relative when computed from the same YLT)
 """
 import sys
 
@@ -61,6 +66,24 @@ def assert_ylt(y, s, ref):
     assert not bad.any(), f"{bad.sum()} year losses off; worst {np.abs(y - ref['ylt'])[bad].max()}"
     sb = np.abs(s - ref["s_pre"]) > TOL * ref["s_pre"]
     assert not sb.any(), f"{sb.sum()} totals off"
+
+
+def metric_bounds(ref, p):
+    """Tolerance of (AAL, PML, TVaR) per layer of a forward: AAL plain
+    relative; PML and TVaR by the year-loss rule at the trials the metric
+    selects (the PML's trials, the r largest)."""
+    y, s = ref["ylt"], ref["s_pre"]
+    n = y.shape[1]
+    r = oracle.tail_count(n, p)
+    out = np.zeros((y.shape[0], 3))
+    for j in range(y.shape[0]):
+        order = np.argsort(-y[j], kind="stable")
+        top = order[:r]
+        pml = y[j, order[r - 1]]
+        out[j, 0] = TOL * abs(y[j].mean())
+        out[j, 1] = TOL * max(pml, s[j, y[j] == pml].max())
+        out[j, 2] = TOL * np.maximum(y[j, top], s[j, top]).mean()
+    return out
 
 
 def oracle_ref(w, t0=0, t1=None, threads=1):
@@ -128,6 +151,45 @@ def test_trial_subsets_match_full_run(ara):
     for t0, t1 in [(0, 1), (17, 4099), (4096, 4097), (8000, 9000), (123, 123)]:
         ys, ss, hs = e.forward(t0, t1)
         assert np.array_equal(ys, y[:, t0:t1]) and np.array_equal(ss, s[:, t0:t1]) and np.array_equal(hs, h[:, t0:t1])
+
+
+@pytest.mark.parametrize("hits", [True, False])
+def test_one_occurrence_trials_bit_exact(ara, hits):
+    """Binary64: when every trial holds one occurrence, its total S is that
+    event's occurrence loss O(e) (steps one to three of Algorithm 1: the
+    lookups, each ELT's terms, the sum over the layer's ELTs in listed order,
+    the occurrence terms), and the year loss is the aggregate terms of it.
+    Both sides evaluate these in the same operations and order, so S, Y and
+    the hit counts must be equal (==) for every event of a 200,000-event
+    catalogue (each once, in shuffled order, then 20,000 repeats, with empty
+    trials between), in three layers: scaled ELTs with mixed terms, three
+    ELTs in a scrambled order, two without terms."""
+    w0 = synth.config(0, n_trials=1)
+    C = w0.elts.catalog
+    g = np.random.default_rng(20)
+    ev = np.concatenate([g.permutation(C), g.integers(0, C, 20_000)]).astype(np.int32)
+    lens = np.ones(ev.shape[0] + 3000, np.int64)
+    lens[g.choice(lens.shape[0], 3000, replace=False)] = 0          # empty trials
+    off = np.zeros(lens.shape[0] + 1, np.int64)
+    np.cumsum(lens, out=off[1:])
+    et = w0.elts.terms.copy()
+    et[:, 0] = g.uniform(0.3, 3.0, 15)                              # products s*l round
+    et[:, 1] = g.uniform(0.0, 2e5, 15)
+    et[:, 2] = g.uniform(1e5, 5e6, 15)
+    et[4] = [1.0, 0.0, np.inf]
+    elts = synth.Elts(C, w0.elts.rec_off, w0.elts.rec_ids, w0.elts.rec_loss, et)
+    layers = synth.Layers(np.array([0, 15, 18, 20], np.int32),
+                          np.array(list(range(15)) + [9, 2, 13] + [4, 0], np.int32),
+                          np.array([[1e5, 2e7, 1e5, 1e7], [3.3e4, 9e5, 0.0, np.inf], [0.0, np.inf, 0.0, np.inf]]))
+    w = synth.Workload("one-occurrence", synth.Yet(C, off, ev), elts, layers, 0.9)
+    e = Engine(ara, w)
+    ref = oracle_ref(w, threads=8)
+    y, s, h = e.forward(hits=hits)
+    assert np.array_equal(s, ref["s_pre"]), f"{np.count_nonzero(s != ref['s_pre'])} totals differ"
+    assert np.array_equal(y, ref["ylt"]), f"{np.count_nonzero(y != ref['ylt'])} year losses differ"
+    if hits:
+        assert np.array_equal(h, ref["hits"])
+    assert np.count_nonzero(s[0]) > 10_000 and np.count_nonzero(s[1]) > 1000
 
 
 def test_run_twice_bitwise_identical(ara):
@@ -351,9 +413,7 @@ def _full_parity(ara, w, label):
     threads): YLT and S to the tolerance, hit counts bit-exact, through both
     the plain path and the hit-count path (whose larger tables spill out of
     LDS on the uneven workload); AAL, PML and TVaR of the device YLT against
-    those of the oracle's, each within the tolerance times the layer's
-    largest S (a metric moves by at most the largest change of one year
-    loss)."""
+    those of the oracle's YLT (metric_bounds)."""
     import torch
     _say(f"{label}: oracle over every trial")
     ref = oracle_ref(w, threads=oracle.num_threads_available())
@@ -366,9 +426,10 @@ def _full_parity(ara, w, label):
     assert np.array_equal(yh, y) and np.array_equal(sh, s)
     _say(f"{label}: metrics against the oracle's")
     out, _ = ara.metrics(torch.tensor(y, device="cuda"), w.p)
+    out = out.cpu().numpy()
     want = oracle.metrics(ref["ylt"], w.p)
-    bound = TOL * ref["s_pre"].max(axis=1)[:, None]
-    assert np.all(np.abs(out.cpu().numpy() - want) <= bound), (out.cpu().numpy(), want)
+    bound = metric_bounds(ref, w.p)
+    assert np.all(np.abs(out - want) <= bound), (out, want, bound)
 
 
 def test_config1_full_size_every_trial(ara):
