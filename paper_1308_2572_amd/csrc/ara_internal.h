@@ -30,6 +30,10 @@ constexpr int kPadCodes = 4 * kWave;
 // that a backward workgroup's gathers of per-trial weights stay in the L2 of
 // the XCD it runs on (workgroups are dealt to the XCDs round-robin).
 constexpr int kSlices = 8;
+// XCDs of the MI355X: consecutive workgroup indexes go to the XCDs in turn.
+constexpr int kXcds = 8;
+// Devices the library keeps per-device state for.
+constexpr int kMaxDevices = 64;
 
 // Error word kept at the head of every workspace.
 struct WsHeader {

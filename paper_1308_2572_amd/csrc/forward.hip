@@ -33,26 +33,37 @@ struct FwdParams {
     int32_t tg, tb, n_ranges;
     int32_t capv;              // values per range buffer
     int32_t buf_bytes;         // bytes per range buffer
-    const FwdItem *items;      // one (layer, block of trials) per workgroup, or null: then workgroup i
-                               // takes layer i / reg_nb, block reg_b0 + i % reg_nb of the regular set below
+    const FwdItem *items;      // one (layer, block of trials) per workgroup, or null: then the
+                               // workgroups take the regular set below (fwd_item)
     const OccTables *reg_tabs;
     const double *reg_lterm;
     double *reg_ylt, *reg_s_pre;
     int32_t *reg_hits;
     int64_t reg_t0, reg_t1;
     int32_t reg_b0, reg_nb;
+    int32_t reg_nl;            // layers of the regular set
 };
 
-// Workgroup i's item: from the list, or formed from the regular set (one
-// layer after another, each over the blocks of one trial range).
+// Workgroup i's item: from the list, or formed from the regular set.  With
+// one layer, workgroup i takes block reg_b0 + i.  With several, the layers
+// of one block go to the same XCD one after another (workgroups are dealt to
+// the eight XCDs round-robin by index): workgroup i = 8k + x is the k-th on
+// XCD x and takes layer k % L of block 8 (k / L) + x, so the L workgroups
+// that stream the same codes run together under one L2 and the codes come
+// from HBM once.  Indexes past the last block give an empty item (block -1).
 __device__ __forceinline__ FwdItem fwd_item(const FwdParams &P, int i) {
     if (P.items) return P.items[i];
     FwdItem it;
-    const int j = i / P.reg_nb;
+    int j = 0, bi = i;
+    if (P.reg_nl > 1) {
+        const int x = i & (kXcds - 1), k = i / kXcds;
+        j = k % P.reg_nl;
+        bi = (k / P.reg_nl) * kXcds + x;
+    }
     const size_t n = static_cast<size_t>(P.reg_t1 - P.reg_t0);
     it.tab = P.reg_tabs + j;
     it.lterm = P.reg_lterm + 4 * j;
-    it.block = P.reg_b0 + i % P.reg_nb;
+    it.block = bi < P.reg_nb ? P.reg_b0 + bi : -1;
     it.pad = 0;
     it.t0 = P.reg_t0;
     it.t1 = P.reg_t1;
@@ -62,8 +73,12 @@ __device__ __forceinline__ FwdItem fwd_item(const FwdParams &P, int i) {
     return it;
 }
 
-// Four consecutive codes of one lane, streamed past the cache.
+// Four consecutive codes of one lane: streamed past the cache when this
+// workgroup is the only reader of its block's codes; kept in L2 when the
+// workgroups of the block's other layers (or quotes) read them too.
+template <bool SHARED>
 __device__ __forceinline__ unsigned long long ld_codes(const uint16_t *p) {
+    if (SHARED) return *reinterpret_cast<const unsigned long long *>(p);
     return __builtin_nontemporal_load(reinterpret_cast<const unsigned long long *>(p));
 }
 
@@ -116,7 +131,8 @@ struct RangeInfo {
 // F32: occurrence values are binary32 in the table and trial totals are
 // accumulated in binary32 (the aggregate terms are still applied in
 // binary64); otherwise both are binary64.
-template <bool HITS, bool F32>
+// SHARED: several workgroups of the launch stream the same block's codes.
+template <bool HITS, bool F32, bool SHARED>
 __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_fwd(FwdParams P) {
     using V = typename std::conditional<F32, float, double>::type;
     // codes per lane and chunk: half as many with hit counts, whose extra
@@ -144,6 +160,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8))) vo
     const uint32_t bufs_lds = static_cast<uint32_t>(reinterpret_cast<uintptr_t>(bufs));
 
     const FwdItem I = fwd_item(P, blockIdx.x);
+    if (I.block < 0) return;   // uniform over the workgroup, before any barrier
     const int tid = threadIdx.x, lane = tid & 63;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int64_t b = I.block;
@@ -253,7 +270,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8))) vo
             for (int q = 0; q < kUn / 4; ++q) {
                 const uint16_t *src = step + 4 * q < R ? P.code + sb + static_cast<int64_t>((step >> 2) + q) * (4 * kWave)
                                                        : P.pad;   // uniform
-                X[q] = ld_codes(src + 4 * lane);
+                X[q] = ld_codes<SHARED>(src + 4 * lane);
             }
             step += kUn;
             if (step >= R) {
@@ -389,8 +406,32 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8))) vo
     }
 }
 
+// LDS of one forward workgroup: the per-trial totals (and hit counts), the
+// range table and segment windows, and what is left for one range's table
+// slice: its 8 KB of bitmap words with ranks, then capv values (and capv
+// ELT counts with hits; values and counts past capv are read from global
+// memory).  Signed arithmetic: with the largest blocks, hit counts and the
+// largest catalogue the fixed parts leave no room, which is a limit of this
+// layout (ARA_E_LIMIT), not a wrap-around.
+int32_t fwd_lds_plan(int tb, int n_ranges, bool hits, bool f32, int32_t *buf_bytes, int32_t *capv_out) {
+    const int64_t vb = f32 ? 4 : 8;
+    const int64_t fixed = static_cast<int64_t>(fwd_acc_lds(tb, hits, static_cast<size_t>(vb))) +
+                          static_cast<int64_t>(fwd_meta_lds(n_ranges));
+    const int64_t per_buf = (static_cast<int64_t>(kLdsBytes) - fixed) / 256 * 256;
+    const int64_t room = per_buf - kBrBytes - (hits ? 16 : 0);
+    int64_t capv = room > 0 ? (hits ? room / (vb + 1) : room / vb) : 0;
+    capv = capv / 16 * 16;
+    if (capv < 16)
+        return fail(ARA_E_LIMIT, "forward: " + std::to_string(tb) + " trials per block and " + std::to_string(n_ranges) +
+                                     " catalogue ranges leave no LDS for the table slice" +
+                                     (hits ? " with hit counts" : ""));
+    *buf_bytes = static_cast<int32_t>(per_buf);
+    *capv_out = static_cast<int32_t>(capv);
+    return ARA_OK;
+}
+
 int32_t launch_forward(const ara_yet *yet, int n_sr, bool hits, bool f32, const FwdItem *d_items, int n_items,
-                       hipStream_t st, const FwdRegular *reg) {
+                       hipStream_t st, const FwdRegular *reg, bool shared) {
     (void)n_sr;
     if (n_items <= 0) return ARA_OK;
     FwdParams P{};
@@ -404,12 +445,8 @@ int32_t launch_forward(const ara_yet *yet, int n_sr, bool hits, bool f32, const 
     P.tb = yet->trials_per_block;
     P.n_ranges = yet->n_ranges;
     // the range's table slice: [bitmap words with ranks][values][counts (hits mode)]
-    const size_t vb = f32 ? sizeof(float) : sizeof(double);
-    const size_t per_buf = (kLdsBytes - fwd_acc_lds(P.tb, hits, vb) - fwd_meta_lds(P.n_ranges)) & ~size_t(255);
-    size_t capv = hits ? (per_buf - kBrBytes - 16) / (vb + 1) : (per_buf - kBrBytes) / vb;
-    capv &= ~size_t(15);
-    P.capv = static_cast<int32_t>(capv);
-    P.buf_bytes = static_cast<int32_t>(per_buf);
+    int32_t rc = fwd_lds_plan(P.tb, P.n_ranges, hits, f32, &P.buf_bytes, &P.capv);
+    if (rc) return rc;
     P.items = d_items;
     if (reg) {
         P.reg_tabs = reg->tabs;
@@ -421,15 +458,23 @@ int32_t launch_forward(const ara_yet *yet, int n_sr, bool hits, bool f32, const 
         P.reg_t1 = reg->t1;
         P.reg_b0 = reg->b0;
         P.reg_nb = reg->nb;
+        P.reg_nl = reg->nl;
+        shared = reg->nl > 1;
     }
     ProfScope prof(ARA_PROF_FWD, st);
+#define ARA_FWD_LAUNCH(H, F)                                                   \
+    do {                                                                     \
+        if (shared) k_fwd<H, F, true><<<n_items, 1024, 0, st>>>(P);          \
+        else k_fwd<H, F, false><<<n_items, 1024, 0, st>>>(P);                \
+    } while (0)
     if (f32) {
-        if (hits) k_fwd<true, true><<<n_items, 1024, 0, st>>>(P);
-        else k_fwd<false, true><<<n_items, 1024, 0, st>>>(P);
+        if (hits) ARA_FWD_LAUNCH(true, true);
+        else ARA_FWD_LAUNCH(false, true);
     } else {
-        if (hits) k_fwd<true, false><<<n_items, 1024, 0, st>>>(P);
-        else k_fwd<false, false><<<n_items, 1024, 0, st>>>(P);
+        if (hits) ARA_FWD_LAUNCH(true, false);
+        else ARA_FWD_LAUNCH(false, false);
     }
+#undef ARA_FWD_LAUNCH
     ARA_HIP(hipGetLastError());
     return ARA_OK;
 }
@@ -464,34 +509,47 @@ extern "C" int32_t ara_ylt_workspace_bytes(const ara_tables *tables, const ara_y
     if (rc) return rc;
     if ((rc = check_layers(layers, tables->n_elts))) return rc;
     if (flags & ~(ARA_F_EMIT_HITS | ARA_F_FP32_ACCUM)) return fail(ARA_E_INVAL, "unknown flag");
+    int32_t bb = 0, cv = 0;
+    if ((rc = fwd_lds_plan(yet->trials_per_block, yet->n_ranges, (flags & ARA_F_EMIT_HITS) != 0,
+                           (flags & ARA_F_FP32_ACCUM) != 0, &bb, &cv)))
+        return rc;
     *bytes = fwd_workspace(tables, yet, layers, (flags & ARA_F_EMIT_HITS) != 0);
     return ARA_OK;
 }
 
-extern "C" int32_t ara_ylt_forward(const ara_tables *tables, const ara_yet *yet, const ara_layers *layers,
-                                   const double *elt_terms, const double *layer_terms, int64_t trial_begin,
-                                   int64_t trial_end, uint32_t flags, double *ylt, double *s_pre, int32_t *hits,
-                                   void *ws, size_t ws_bytes, void *stream) {
+namespace ara {
+
+// Checks the arguments of a forward call; on success *need holds the
+// workspace bytes it takes.
+int32_t forward_args(const ara_tables *tables, const ara_yet *yet, const ara_layers *layers, const double *elt_terms,
+                     const double *layer_terms, int64_t trial_begin, int64_t trial_end, uint32_t flags,
+                     const double *ylt, const int32_t *hits, size_t *need) {
     int32_t rc = check_pair(tables, yet);
     if (rc) return rc;
     if ((rc = check_layers(layers, tables->n_elts))) return rc;
     if (flags & ~(ARA_F_EMIT_HITS | ARA_F_FP32_ACCUM)) return fail(ARA_E_INVAL, "unknown flag");
     const bool want_hits = (flags & ARA_F_EMIT_HITS) != 0;
-    const bool f32 = (flags & ARA_F_FP32_ACCUM) != 0;
     if (hits && !want_hits) return fail(ARA_E_INVAL, "hits output requires ARA_F_EMIT_HITS");
     if (trial_begin < 0 || trial_end < trial_begin || trial_end > yet->n_trials)
         return fail(ARA_E_RANGE, "trial range outside the YET");
-    if (!ws) return fail(ARA_E_INVAL, "null workspace");
-    const int L = layers->n_layers;
-    const int64_t n = trial_end - trial_begin;
-    if (L > 0 && n > 0 && (!ylt || !elt_terms || !layer_terms)) return fail(ARA_E_INVAL, "null output or terms");
-    if (ws_bytes < fwd_workspace(tables, yet, layers, want_hits)) return fail(ARA_E_NOSPACE, "forward workspace too small");
-    hipStream_t st = static_cast<hipStream_t>(stream);
-    if (L == 0 || n == 0) {
-        ARA_HIP(hipMemsetAsync(ws, 0, kWsHeaderBytes, st));
-        return ARA_OK;
-    }
+    if (layers->n_layers > 0 && trial_end > trial_begin && (!ylt || !elt_terms || !layer_terms))
+        return fail(ARA_E_INVAL, "null output or terms");
+    int32_t bb = 0, cv = 0;
+    if ((rc = fwd_lds_plan(yet->trials_per_block, yet->n_ranges, want_hits, (flags & ARA_F_FP32_ACCUM) != 0, &bb, &cv)))
+        return rc;
+    *need = fwd_workspace(tables, yet, layers, want_hits);
+    return ARA_OK;
+}
 
+// The forward proper, once the arguments are checked, over a workspace of
+// at least the bytes forward_args gave.
+int32_t forward_run(const ara_tables *tables, const ara_yet *yet, const ara_layers *layers, const double *elt_terms,
+                    const double *layer_terms, int64_t trial_begin, int64_t trial_end, uint32_t flags, double *ylt,
+                    double *s_pre, int32_t *hits, void *ws, hipStream_t st) {
+    int32_t rc = ARA_OK;
+    const bool want_hits = (flags & ARA_F_EMIT_HITS) != 0;
+    const bool f32 = (flags & ARA_F_FP32_ACCUM) != 0;
+    const int L = layers->n_layers;
     const OccLayoutSizes z = occ_sizes(tables->catalog, want_hits);
     const int nJ = layers->elt_off[L];
     Carver c(ws);
@@ -514,6 +572,7 @@ extern "C" int32_t ara_ylt_forward(const ara_tables *tables, const ara_yet *yet,
     reg.t1 = trial_end;
     reg.b0 = static_cast<int32_t>(b_lo);
     reg.nb = nb;
+    reg.nl = L;
     HeadImage img(ws);
     img.cover(d_err + kWsHeaderBytes / sizeof(int32_t));
     img.put(d_off, layers->elt_off, static_cast<size_t>(L + 1));
@@ -527,5 +586,26 @@ extern "C" int32_t ara_ylt_forward(const ara_tables *tables, const ara_yet *yet,
                              st)))
             return rc;
     }
-    return launch_forward(yet, z.n_sr, want_hits, f32, nullptr, L * nb, st, &reg);
+    return launch_forward(yet, z.n_sr, want_hits, f32, nullptr, fwd_regular_items(L, nb), st, &reg);
+}
+
+}  // namespace ara
+
+extern "C" int32_t ara_ylt_forward(const ara_tables *tables, const ara_yet *yet, const ara_layers *layers,
+                                   const double *elt_terms, const double *layer_terms, int64_t trial_begin,
+                                   int64_t trial_end, uint32_t flags, double *ylt, double *s_pre, int32_t *hits,
+                                   void *ws, size_t ws_bytes, void *stream) {
+    size_t need = 0;
+    int32_t rc = forward_args(tables, yet, layers, elt_terms, layer_terms, trial_begin, trial_end, flags, ylt, hits,
+                              &need);
+    if (rc) return rc;
+    if (!ws) return fail(ARA_E_INVAL, "null workspace");
+    if (ws_bytes < need) return fail(ARA_E_NOSPACE, "forward workspace too small");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (layers->n_layers == 0 || trial_end == trial_begin) {
+        ARA_HIP(hipMemsetAsync(ws, 0, kWsHeaderBytes, st));
+        return ARA_OK;
+    }
+    return forward_run(tables, yet, layers, elt_terms, layer_terms, trial_begin, trial_end, flags, ylt, s_pre, hits,
+                       ws, st);
 }

@@ -103,12 +103,39 @@ struct FwdRegular {
     int32_t *hits;
     int64_t t0, t1;
     int32_t b0, nb;
+    int32_t nl;                // layers
 };
+
+// Workgroups of a regular launch: one per block with one layer; with L
+// layers, L per block over whole groups of kXcds blocks (the XCD-aware
+// mapping of the forward kernel; workgroups past the last block exit).
+inline int fwd_regular_items(int n_layers, int nb) {
+    if (n_layers <= 1) return nb;
+    return n_layers * kXcds * ((nb + kXcds - 1) / kXcds);
+}
+
+// LDS plan of a forward workgroup (bytes of the table-slice buffer, values
+// it holds); ARA_E_LIMIT when the layout leaves no room for a slice.
+int32_t fwd_lds_plan(int tb, int n_ranges, bool hits, bool f32, int32_t *buf_bytes, int32_t *capv);
 
 // f32: binary32 occurrence values (tables built with f32_vals) and totals.
 // Items come from d_items, or (d_items null) from `reg`.
+// shared: workgroups of the same block are adjacent on one XCD, so the codes
+// are loaded through L2 (a regular set decides this from its layer count).
 int32_t launch_forward(const ara_yet *yet, int n_sr, bool hits, bool f32, const FwdItem *d_items, int n_items,
-                       hipStream_t st, const FwdRegular *reg = nullptr);
+                       hipStream_t st, const FwdRegular *reg = nullptr, bool shared = false);
+
+// Checks the arguments of a forward call (those of ara_ylt_forward but the
+// workspace); *need receives the workspace bytes the call takes.
+int32_t forward_args(const ara_tables *tables, const ara_yet *yet, const ara_layers *layers, const double *elt_terms,
+                     const double *layer_terms, int64_t trial_begin, int64_t trial_end, uint32_t flags,
+                     const double *ylt, const int32_t *hits, size_t *need);
+// Enqueues a checked forward call with at least one layer and one trial on
+// `st`, over a workspace of at least the bytes forward_args gave (its first
+// int32 receives the device-side status).
+int32_t forward_run(const ara_tables *tables, const ara_yet *yet, const ara_layers *layers, const double *elt_terms,
+                    const double *layer_terms, int64_t trial_begin, int64_t trial_end, uint32_t flags, double *ylt,
+                    double *s_pre, int32_t *hits, void *ws, hipStream_t st);
 
 // A layer's set-event bitmap folded onto 2^20 bits by OR (128 KB, staged in
 // LDS by the kernels that stream the trial-major YET): one filter per layer.

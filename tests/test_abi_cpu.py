@@ -123,6 +123,39 @@ def test_argument_validation_before_device_work(ara):
     assert b"ARA_PREP_TRANSPOSED" in lib.ara_last_error()
 
 
+def test_forward_lds_plan_limits(ara):
+    """The forward workgroup's LDS holds the per-trial totals (and hit
+    counts), the range table and the segment windows, and the rest is one
+    range's table slice.  At the largest catalogue (2048 ranges) with blocks
+    of 4096 trials and hit counts nothing is left: the size query and the
+    forward refuse with ARA_E_LIMIT before any device work, instead of a
+    wrapped-around size.  Blocks of 3744 trials (234 per group) still do
+    not fit with hit counts; 3728 do, and so does every size without them."""
+    lib = ara.library()
+    cat = 1 << 26
+    tables = ara.ara_tables(n_elts=2, catalog=cat, words=cat // 32)
+    lay = ara.Layers([0, 2], [0, 1])
+    nb = ctypes.c_size_t()
+
+    def query(tb, flags):
+        yet = ara.ara_yet(n_trials=4 * tb, catalog=cat, range_bits=15, groups=16, trials_per_group=tb // 16,
+                          trials_per_block=tb, n_blocks=4, n_ranges=2048)
+        return lib.ara_ylt_workspace_bytes(ctypes.byref(tables), ctypes.byref(yet), ctypes.byref(lay.handle),
+                                           flags, ctypes.byref(nb)), yet
+
+    H, F = ara.ARA_F_EMIT_HITS, ara.ARA_F_FP32_ACCUM
+    rc, yet = query(4096, H)
+    assert rc == 6 and b"no LDS" in lib.ara_last_error()
+    assert lib.ara_ylt_forward(ctypes.byref(tables), ctypes.byref(yet), ctypes.byref(lay.handle), ctypes.c_void_p(256),
+                               ctypes.c_void_p(256), 0, 10, H, ctypes.c_void_p(256), None, ctypes.c_void_p(256),
+                               ctypes.c_void_p(256), 1 << 40, None) == 6
+    assert query(16 * 234, H)[0] == 6
+    assert query(16 * 233, H)[0] == 0
+    for fl in (0, F, H | F):
+        assert query(4096, fl)[0] == 0, fl
+    assert query(16 * 123, H)[0] == 0          # blocks of 1M trials on 256 CUs
+
+
 def test_secondary_uncertainty_queries_and_validation(ara):
     lib = ara.library()
     tables = ara.ara_tables(n_elts=3, catalog=200_000, words=6250)
