@@ -108,7 +108,10 @@ def main() -> int:
     ap.add_argument("--no-yelt", action="store_true")
     ap.add_argument("--no-su", action="store_true", help="skip the secondary-uncertainty forward")
     ap.add_argument("--no-fp32", action="store_true", help="skip the binary32-accumulation forward")
-    ap.add_argument("--serving-requests", type=int, default=200)
+    ap.add_argument("--no-uneven", action="store_true", help="skip the uneven four-layer forward")
+    ap.add_argument("--serving-requests", type=int, default=3000, help="quotes of the 50/s serving leg")
+    ap.add_argument("--saturating-requests", type=int, default=1500)
+    ap.add_argument("--saturating-rate", type=float, default=1000.0, help="arrivals per second of the second leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy three times (scales the HBM byte counters)")
     args = ap.parse_args()
@@ -186,6 +189,7 @@ def main() -> int:
         f"{occ_ms / max(occ_n, 1):.4f} ms; metrics {met_ms / max(met_n, 1):.4f} ms; AAL {m[0]:.6e} PML {m[1]:.6e} "
         f"TVaR {m[2]:.6e}")
 
+    traffic = traffic_from_profiles(os.path.join(HERE, "paper_1308_2572_amd", "csrc", "forward.hip"))
     result = {
         "metric": "event-ELT lookups/s & %HBM peak (1M×1000×15); fwd+bwd cost; p99 quote latency",
         "value": value,
@@ -205,8 +209,10 @@ def main() -> int:
                    "trials": N, "events": nnz, "elts_per_layer": J, "catalog": w.yet.catalog,
                    "parallelism": "single GPU", "step": "occurrence table + streaming forward + tail metrics"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": traffic_from_profiles(os.path.join(HERE, "paper_1308_2572_amd", "csrc", "forward.hip")),
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     # the bytes the kernel actually moves (16-bit codes, not the 4-byte IDs the
+                     # algorithmic figure counts) over its time, against the same peak
+                     "frac_moved": (traffic / (k_fwd * 1e-3) / 1e9 / HBM_PEAK_GBS) if traffic else None,
                      "kernel": "k_fwd", "kernel_ms": k_fwd, "algorithmic_bytes": algo_bytes},
         "step_breakdown_ms": {"occurrence_table": occ_ms / max(occ_n, 1), "forward_stream": k_fwd,
                               "metrics": met_ms / max(met_n, 1)},
@@ -219,9 +225,15 @@ def main() -> int:
 
     if not args.no_fp32:
         result["fp32_accum"] = bench_fp32(ara, tables, yet, layers, et, lt, w, args.steps, args.warmup, ylt)
+    if not args.no_uneven:
+        result["uneven_4_layers"] = bench_uneven(ara, dev, args.trials, args.steps, args.warmup, k_fwd)
     if not args.no_backward:
+        # the differentiated workload: the same YET and ELT records, terms perturbed off the kinks
+        w3 = synth.config(3, n_trials=args.trials)
+        et3 = torch.tensor(w3.elts.terms, dtype=torch.float64, device=dev)
+        lt3 = torch.tensor(w3.layers.terms, dtype=torch.float64, device=dev)
         try:
-            result["fwd_bwd"] = bench_backward(ara, tables, yet, layers, et, lt, w, args.steps, args.warmup, ms_step)
+            result["fwd_bwd"] = bench_backward(ara, tables, yet, layers, et3, lt3, w3, args.steps, args.warmup)
         except ara.AraError as ex:
             result["fwd_bwd"] = {"error": str(ex)}
     if not args.no_yelt:
@@ -235,17 +247,32 @@ def main() -> int:
         except ara.AraError as ex:
             result["secondary_uncertainty"] = {"error": str(ex)}
     if not args.no_serving:
-        log("serving: resident 1M x Poisson(1000) YET, 200 ELTs, Poisson arrivals at 50/s")
+        log(f"serving: resident 1M x Poisson(1000) YET, 200 ELTs, {args.serving_requests} quotes arriving at 50/s")
         from paper_1308_2572_amd import serve
         w4 = synth.config(4, n_trials=args.trials)
         tables4 = ara.EltTables.from_numpy(w4.elts, dev)
         yet4 = ara.PreparedYet.from_numpy(w4.yet, dev)
         et4 = torch.tensor(w4.elts.terms, dtype=torch.float64, device=dev)
         reqs = synth.serving_requests(args.serving_requests, w4.yet.n_trials, n_elts=w4.elts.n_elts)
-        result["serving"] = serve.run_benchmark(tables4, yet4, et4, reqs, p=0.99)
+        result["serving"] = serve.run_benchmark(tables4, yet4, et4, reqs, p=0.99, progress=log)
         result["serving"]["workload"] = ("resident 1,000,000 trials x Poisson(1000) events, 200 ELTs of "
                                          "10,000-30,000 events; quotes of 5-25 ELTs over 100k-1M trials, "
                                          "half with gradients, Poisson arrivals at 50/s")
+        # the same kind of quotes arriving faster than one at a time can be served: they overlap on the
+        # device and share launches; against the same quotes run one after another
+        rate = args.saturating_rate
+        log(f"serving: {args.saturating_requests} quotes arriving at {rate:.0f}/s")
+        sat = synth.serving_requests(args.saturating_requests, w4.yet.n_trials, n_elts=w4.elts.n_elts,
+                                     rate_per_s=rate, seed=synth.SEED_BASE + 40)
+        leg = serve.run_benchmark(tables4, yet4, et4, sat, p=0.99, progress=log)
+        leg["serial_req_per_s"] = serve.serial_throughput(tables4, yet4, et4, sat, 0.99)
+        leg["throughput_over_serial"] = leg["throughput_req_per_s"] / leg["serial_req_per_s"]
+        leg["workload"] = f"as above, Poisson arrivals at {rate:.0f}/s"
+        result["serving_saturated"] = leg
+        log(f"serving: 50/s p50 {result['serving']['p50_ms']:.2f} ms p99 {result['serving']['p99_ms']:.2f} ms; "
+            f"{rate:.0f}/s p50 {leg['p50_ms']:.2f} ms p99 {leg['p99_ms']:.2f} ms, {leg['throughput_req_per_s']:.0f} "
+            f"quotes/s ({leg['throughput_over_serial']:.2f}x serial), up to {leg['server']['max_quotes_per_launch']} "
+            f"quotes per launch")
         del yet4, tables4
     if not args.no_cpu_baseline:
         log("CPU baseline (oracle)")
@@ -375,11 +402,74 @@ def bench_su(ara, tables, yet, layers, et, lt, w, steps, warmup):
             "metrics": {"aal": float(mm[0]), "pml": float(mm[1]), "tvar": float(mm[2])}}
 
 
-def bench_backward(ara, tables, yet, layers, et, lt, w, steps, warmup, ms_fwd_step):
-    """Forward + metrics + backward of (AAL, PML, TVaR) w.r.t. every term, vs
-    the forward step alone."""
+def bench_uneven(ara, dev, n_trials, steps, warmup, k_fwd_one_layer):
+    """The uneven workload: 1M trials of Poisson(1000) events, four layers
+    over 8, 12, 15 and 20 of 55 ELTs, one forward launch for all layers
+    (the workgroups of a block's four layers share its codes through L2)."""
+    import torch
+    import synth
+    log("uneven workload: 1M x Poisson(1000), 4 layers over 55 ELTs")
+    w = synth.config(2, n_trials=n_trials)
+    tables = ara.EltTables.from_numpy(w.elts, dev)
+    yet = ara.PreparedYet.from_numpy(w.yet, dev, transposed=False, trial_major=False)
+    layers = ara.Layers(w.layers.elt_off, w.layers.elt_ids)
+    et = torch.tensor(w.elts.terms, dtype=torch.float64, device=dev)
+    lt = torch.tensor(w.layers.terms, dtype=torch.float64, device=dev)
+    N, nnz, L = w.yet.n_trials, w.yet.nnz, w.layers.n_layers
+    J = int(w.layers.elt_off[-1])
+
+    def step():
+        ylt, _, _ = ara.ylt_forward(tables, yet, layers, et, lt, 0, N, want_s_pre=False)
+        return ara.metrics(ylt, w.p)[0]
+
+    for _ in range(max(1, warmup)):
+        step()
+    torch.cuda.synchronize()
+    ara.profile_reset()
+    ara.profile_enable(True, kinds=[ara.PROF_FWD])
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        out = step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ara.profile_enable(False)
+    k_ms, k_n = ara.profile_read(ara.PROF_FWD)
+    k = k_ms / max(k_n, 1)
+    ms = (t1 - t0) * 1e3 / steps
+    algo = 4.0 * nnz + 8.0 * N + 8.0 * N * L
+    m = out.cpu().numpy()
+    del yet, tables
+    torch.cuda.empty_cache()
+    log(f"uneven: step {ms:.4f} ms, forward kernel {k:.4f} ms ({k / k_fwd_one_layer:.2f}x the one-layer kernel)")
+    return {"workload": "1000000 trials x Poisson(1000) events, 4 layers over 8/12/15/20 of 55 ELTs, catalogue 2000000",
+            "ms_per_step": ms, "lookups_per_s": nnz * J / (ms * 1e-3), "events": nnz, "elt_lookups": nnz * J,
+            "kernel": "k_fwd", "kernel_ms": k, "kernel_ratio_to_one_layer": k / k_fwd_one_layer,
+            "algorithmic_bytes": algo, "achieved_gbs": algo / (k * 1e-3) / 1e9,
+            "frac": algo / (k * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "metrics": [[float(v) for v in row] for row in m]}
+
+
+def bench_backward(ara, tables, yet, layers, et, lt, w, steps, warmup):
+    """On the differentiated workload (the paper-scale YET and ELTs, terms
+    perturbed off the kinks): forward + metrics + backward of (AAL, PML,
+    TVaR) w.r.t. every term, against the forward step (forward + metrics)
+    alone on the same terms."""
     import torch
     N = w.yet.n_trials
+    log("differentiated workload: forward step, then forward + backward")
+
+    def fwd():
+        ylt, _, _ = ara.ylt_forward(tables, yet, layers, et, lt, 0, N, want_s_pre=False)
+        return ara.metrics(ylt, w.p)[0]
+
+    for _ in range(max(1, warmup)):
+        fwd()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fwd()
+    torch.cuda.synchronize()
+    ms_fwd_step = (time.perf_counter() - t0) * 1e3 / steps
 
     def fb():
         ylt, s_pre, _ = ara.ylt_forward(tables, yet, layers, et, lt, 0, N, want_s_pre=True)
@@ -401,7 +491,9 @@ def bench_backward(ara, tables, yet, layers, et, lt, w, steps, warmup, ms_fwd_st
     bwd_ms, bwd_n = ara.profile_read(ara.PROF_BWD)
     red_ms, red_n = ara.profile_read(ara.PROF_BWD_RED)
     ms = (t1 - t0) * 1e3 / steps
-    out = {"ms_per_step": ms, "ratio_to_forward": ms / ms_fwd_step, "cotangents": 3,
+    out = {"workload": "1000000 trials x 1000 events, 1 layer x 15 ELTs, terms x U[0.97, 1.03]",
+           "ms_per_step": ms, "forward_ms_per_step": ms_fwd_step, "ratio_to_forward": ms / ms_fwd_step,
+           "cotangents": 3,
            "backward_stream_ms": bwd_ms / max(bwd_n, 1), "backward_reduce_ms": red_ms / max(red_n, 1)}
     # the same backward on a YET without the trial-major copy takes the full gather for W: both forms,
     # timed as backward calls alone, and their results compared bit for bit

@@ -220,6 +220,7 @@ int32_t ara_ylt_forward(const ara_tables *tables, const ara_yet *yet, const ara_
  * forward or backward left in `ws`; ARA_OK if none. */
 int32_t ara_check_device_error(const void *ws, void *stream);
 
+
 /* ------------------------------------------------------------------------ */
 /* Per-occurrence losses: step four of Algorithm 1 taken literally, per      */
 /* occurrence in storage order (the event-level YLT), and the per-year       */
@@ -365,10 +366,16 @@ int32_t ara_ylt_forward_su(const ara_tables *tables, const float *sigma, const i
 /*
  * A quote is a candidate layer over the resident ELTs with its own terms,
  * over a contiguous trial range.  A scheduler thread admits quotes in arrival
- * order as soon as a slot and enough arena memory are free, and every
- * iteration packs blocks of every active quote into one forward launch, so
- * quotes arriving while others run join at the next iteration.  Results do
- * not depend on the mix.  All device memory comes from the caller's arena.
+ * order as soon as a slot and enough arena memory are free.  The active
+ * quotes are served by a circular scan of the YET's trial blocks: every
+ * iteration is ONE forward launch over a window of consecutive blocks,
+ * holding each active quote's work on each block of the window in its range,
+ * the work items of one block on one XCD back to back so that the quotes
+ * sharing the block read its codes from HBM once.  A quote arriving while
+ * others run joins at the next iteration and is complete after one
+ * revolution over its range.  Results do not depend on the mix.  All device
+ * memory comes from the caller's arena; the resident ELT terms are checked
+ * once, at create (ARA_E_INVAL).
  */
 typedef struct ara_quote {
     int32_t        n_elts;
@@ -405,8 +412,9 @@ int32_t ara_server_poll(void *server, int64_t ticket, ara_quote_result *out);
 int32_t ara_server_wait(void *server, int64_t ticket, ara_quote_result *out);
 /* Cancels a quote still in the queue (ARA_E_BUSY once it is on the device). */
 int32_t ara_server_cancel(void *server, int64_t ticket);
-/* stats[6] = iterations, packed forward launches, most quotes in one launch,
- * queued, active, free arena bytes. */
+/* stats[8] = iterations, packed forward launches, most quotes in one launch,
+ * queued, active, free arena bytes, work items launched, items on a block
+ * that other items of the same launch share. */
 int32_t ara_server_stats(void *server, int64_t *stats);
 /* Stops admitting, drains the active quotes, frees host resources. */
 int32_t ara_server_destroy(void *server);

@@ -500,9 +500,10 @@ class QuoteServer:
         return True
 
     def stats(self):
-        st = (_c_i64 * 6)()
+        st = (_c_i64 * 8)()
         _check(library().ara_server_stats(self.handle, st), "ara_server_stats")
-        keys = ["iterations", "packed_launches", "max_quotes_per_launch", "queued", "active", "free_arena_bytes"]
+        keys = ["iterations", "packed_launches", "max_quotes_per_launch", "queued", "active", "free_arena_bytes",
+                "items", "shared_block_items"]
         return dict(zip(keys, list(st)))
 
     def close(self):

@@ -61,6 +61,7 @@ def test_alone_and_in_mix_equal_direct_calls(env):
         mix = [srv.wait(t) for t in tickets]
         st = srv.stats()
         assert st["max_quotes_per_launch"] >= 2, st       # quotes really shared forward launches
+        assert st["shared_block_items"] > 0, st           # and blocks: their codes read once per launch
         _say("alone: one quote at a time")
         alone = [srv.wait(srv.submit(r.elt_ids, r.layer_terms, r.trial_begin, r.trial_end, 0.99, r.want_grad))
                  for r in reqs]
@@ -121,6 +122,15 @@ def test_memory_pressure_queues_and_cancel(env):
             srv.wait(extra)
     finally:
         srv.close()
+
+
+def test_invalid_resident_terms_refused_at_create(env):
+    ara, w, tables, yet, et, reqs = env
+    bad = et.clone()
+    bad[3, 2] = 0.0                       # a limit of zero
+    with pytest.raises(ara.AraError) as ex:
+        ara.QuoteServer(tables, yet, bad, quotes_with_grad=1, max_slots=2)
+    assert ex.value.status == 1
 
 
 def test_submit_validation(env):

@@ -1,6 +1,8 @@
 """CPU checks of the quote server's host logic: the arena allocator that
 admits quotes by memory (first fit in address order, coalescing on release,
-never handing out overlapping ranges), driven against a Python model."""
+never handing out overlapping ranges), driven against a Python model; and the
+scheduler core with a stand-in executor backed by the oracle, under
+ThreadSanitizer."""
 import os
 import subprocess
 
@@ -86,3 +88,27 @@ def test_arena_coalesces_back_to_one_block(driver):
     ops = ["a 100", "a 200", "a 300", "f 100 200", "f 0 100", "f 300 300", "a 1000", "s"]
     got = run(driver, 1000, ops)
     assert got[:8] == ["ok 0", "ok 100", "ok 300", "freed", "freed", "freed", "ok 0", "free 0"]
+
+
+def test_scheduler_under_thread_sanitizer(tmp_path):
+    """The quote scheduler's host core (admission by slot and memory, the
+    circular scan packing every active quote's blocks into one launch, items
+    of one block dealt to one XCD, completion, cancellation, stop) driven by
+    a stand-in executor whose "device" thread computes each item with the
+    oracle: results alone == in the mix == the oracle over the whole range,
+    bit for bit; built with -fsanitize=thread, which fails the run on any
+    data race between the scheduler, submitting and device threads."""
+    csrc = os.path.join(ROOT, "paper_1308_2572_amd", "csrc")
+    obj = str(tmp_path / "oracle.o")
+    exe = str(tmp_path / "sched_driver")
+    subprocess.check_call(["gcc", "-std=c11", "-O1", "-g", "-fsanitize=thread", "-ffp-contract=off", "-c",
+                           os.path.join(ROOT, "oracle", "ara_oracle.c"), "-o", obj])
+    subprocess.check_call(["g++", "-std=c++17", "-O1", "-g", "-Wall", "-fsanitize=thread", "-pthread",
+                           "-I", os.path.join(ROOT, "include"), "-I", csrc,
+                           os.path.join(ROOT, "tests", "sched_driver.cpp"), os.path.join(csrc, "quote_sched.cpp"),
+                           obj, "-o", exe, "-lm"])
+    env = dict(os.environ, TSAN_OPTIONS="halt_on_error=1 exitcode=66")
+    r = subprocess.run([exe], capture_output=True, text=True, timeout=300, env=env)
+    assert r.returncode == 0, r.stdout + r.stderr
+    assert "all scheduler checks passed" in r.stdout
+    assert "WARNING: ThreadSanitizer" not in r.stderr
