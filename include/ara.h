@@ -220,6 +220,32 @@ int32_t ara_ylt_forward(const ara_tables *tables, const ara_yet *yet, const ara_
  * forward or backward left in `ws`; ARA_OK if none. */
 int32_t ara_check_device_error(const void *ws, void *stream);
 
+/*
+ * The forward for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same computation and results as ara_ylt_forward, with no workspace
+ * argument.  Its workspace is a scratch array of ARA_NOALLOC_SCRATCH_BYTES
+ * that the library holds on each device it runs on, from the first call on
+ * that device until the process ends; the call allocates and frees nothing.
+ * A call that needs more workspace than the scratch holds (the
+ * ara_ylt_workspace_bytes figure: about 32 MiB per layer at a 2,000,000-event
+ * catalogue) returns ARA_E_LIMIT before any device work.  Every call on one
+ * device shares that device's scratch and leaves its contents behind; each
+ * call rewrites what it reads, so no state carries over, but calls that
+ * overlap on one device (other streams, other host threads) race: serialise
+ * them.
+ * dev_status: device int32 or NULL; receives the device-side status of the
+ *             call (invalid term values: ARA_E_INVAL), 0 if none, at the end
+ *             of the call on `stream`.  ara_check_device_error(dev_status,
+ *             stream) reads it.
+ * The other arguments are those of ara_ylt_forward.
+ */
+#define ARA_NOALLOC_SCRATCH_BYTES (160u << 20)
+int32_t ara_ylt_forward_noalloc(const ara_tables *tables, const ara_yet *yet, const ara_layers *layers,
+                                const double *elt_terms, const double *layer_terms,
+                                int64_t trial_begin, int64_t trial_end, uint32_t flags,
+                                double *ylt, double *s_pre, int32_t *hits,
+                                int32_t *dev_status, void *stream);
 
 /* ------------------------------------------------------------------------ */
 /* Per-occurrence losses: step four of Algorithm 1 taken literally, per      */

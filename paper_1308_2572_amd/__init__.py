@@ -79,6 +79,8 @@ _SIGNATURES = {
     "ara_ylt_workspace_bytes": (_c_i32, [_P(ara_tables), _P(ara_yet), _P(ara_layers), _c_u32, _P(_c_sz)]),
     "ara_ylt_forward": (_c_i32, [_P(ara_tables), _P(ara_yet), _P(ara_layers), _c_p, _c_p, _c_i64, _c_i64, _c_u32,
                                  _c_p, _c_p, _c_p, _c_p, _c_sz, _c_p]),
+    "ara_ylt_forward_noalloc": (_c_i32, [_P(ara_tables), _P(ara_yet), _P(ara_layers), _c_p, _c_p, _c_i64, _c_i64,
+                                         _c_u32, _c_p, _c_p, _c_p, _c_p, _c_p]),
     "ara_yelt_workspace_bytes": (_c_i32, [_P(ara_tables), _P(ara_layers), _P(_c_sz)]),
     "ara_yelt_forward": (_c_i32, [_P(ara_tables), _c_p, _c_p, _c_i64, _P(ara_layers), _c_p, _c_p, _c_i64, _c_i64,
                                   _c_i64, _c_i64, _c_p, _c_p, _c_p, _c_sz, _c_p]),
@@ -351,6 +353,22 @@ def ylt_forward(tables: EltTables, yet: PreparedYet, layers: Layers, elt_terms: 
     if check:
         _check(lib.ara_check_device_error(_dptr(ws), _stream()), "ara_ylt_forward (device)")
     return ylt, s_pre, hits
+
+
+def ylt_forward_noalloc(tables: EltTables, yet: PreparedYet, layers: Layers, elt_terms: torch.Tensor,
+                        layer_terms: torch.Tensor, ylt: torch.Tensor, s_pre: Optional[torch.Tensor] = None,
+                        hits: Optional[torch.Tensor] = None, status: Optional[torch.Tensor] = None,
+                        trial_begin: int = 0, trial_end: Optional[int] = None, fp32_accum: bool = False) -> None:
+    """ara_ylt_forward_noalloc into caller tensors (ylt, s_pre, hits: [n_layers,
+    n]; status: one device int32 or None): the library's own scratch serves as
+    the workspace.  Terms must already be contiguous binary64 on the device."""
+    lib = library()
+    trial_end = yet.n_trials if trial_end is None else trial_end
+    flags = (ARA_F_EMIT_HITS if hits is not None else 0) | (ARA_F_FP32_ACCUM if fp32_accum else 0)
+    _check(lib.ara_ylt_forward_noalloc(ctypes.byref(tables.handle), ctypes.byref(yet.handle),
+                                       ctypes.byref(layers.handle), _dptr(elt_terms), _dptr(layer_terms), trial_begin,
+                                       trial_end, flags, _dptr(ylt), _dptr(s_pre), _dptr(hits), _dptr(status),
+                                       _stream()), "ara_ylt_forward_noalloc")
 
 
 def metrics(ylt: torch.Tensor, p: float, want_weights: bool = False):
