@@ -270,8 +270,9 @@ void Scheduler::loop() {
             if ((rc = ex_->setup(*j, &err))) break;
         std::vector<SchedItem> slots;
         std::vector<SchedJob *> completed;
-        bool shared = false;
+        bool shared = false, launched = false;
         if (!rc && next_launch(&slots, &shared, &completed)) {
+            launched = true;
             rc = ex_->launch(slots, shared, &err);
             int64_t n_items = 0, n_shared = 0, n_quotes = 0;
             std::vector<const SchedJob *> seen;
@@ -336,8 +337,12 @@ void Scheduler::loop() {
             }
             launchable = launchable || (!queue_.empty() && !free_slots_.empty());
         }
-        // results pending and nothing to launch: wait briefly instead of spinning
-        if (waiting && !launchable) std::this_thread::sleep_for(std::chrono::microseconds(20));
+        if (launched && rc == ARA_OK) {
+            ex_->settle();
+        } else if (waiting && !launchable) {
+            // results pending and nothing to launch: wait briefly instead of spinning
+            std::this_thread::sleep_for(std::chrono::microseconds(20));
+        }
     }
 }
 

@@ -87,6 +87,10 @@ class SchedExecutor {
     virtual int32_t collect(SchedJob &j) = 0;
     // releases the quote's per-quote state (completion marker and the like)
     virtual void release(SchedJob &j) = 0;
+    // after an iteration that launched: wait until that launch has run, so
+    // that the quotes arriving meanwhile are packed into the next launch
+    // instead of queueing behind it one launch each
+    virtual void settle() = 0;
 };
 
 // Deals items sorted by block to n_xcd XCDs: the items of one block go to

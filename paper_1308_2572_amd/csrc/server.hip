@@ -246,6 +246,11 @@ class HipExecutor final : public SchedExecutor {
         j.exec = nullptr;
     }
 
+    void settle() override {
+        const int last = (ring + kRing - 1) % kRing;
+        if (item_used[last]) hipEventSynchronize(item_ev[last]);
+    }
+
    private:
     static int32_t hip_step(hipError_t e, std::string *err) {
         if (e == hipSuccess) return ARA_OK;

@@ -259,6 +259,11 @@ class FakeExec final : public SchedExecutor {
         --live;
     }
 
+    void settle() override {
+        std::unique_lock<std::mutex> lk(m_);
+        cv_.wait(lk, [&] { return in_flight_ == 0; });
+    }
+
     std::vector<std::vector<Logged>> log() {
         std::lock_guard<std::mutex> lk(log_mu_);
         return log_;
