@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 OBJDIR = os.path.join(ROOT, "_build", "ara")
 LIB = os.path.join(HERE, "libara.so")
-SOURCES = ["common.hip", "prepare.hip", "tables.hip", "occ.hip", "forward.hip", "metrics.hip", "backward.hip", "server.hip", "quote_sched.cpp", "yelt.hip", "su.hip", "noalloc.hip"]
+SOURCES = ["common.hip", "prepare.hip", "tables.hip", "occ.hip", "forward.hip", "grpfwd.hip", "metrics.hip", "backward.hip", "server.hip", "quote_sched.cpp", "yelt.hip", "su.hip", "noalloc.hip"]
 ARCH = os.environ.get("ARA_OFFLOAD_ARCH", "gfx950")
 
 CFLAGS = [

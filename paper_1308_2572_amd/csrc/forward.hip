@@ -479,7 +479,48 @@ int32_t launch_forward(const ara_yet *yet, int n_sr, bool hits, bool f32, const 
     return ARA_OK;
 }
 
-static size_t fwd_workspace(const ara_tables *tables, const ara_yet *yet, const ara_layers *layers, bool hits) {
+// Layers are served in groups of four by the grouped forward (one
+// workgroup streams a block's codes once for the group) when the call asks
+// for neither hit counts nor binary32 accumulation and the workgroup holds
+// four layers' totals; the layers after the last full group (and every layer
+// otherwise) take the one-layer kernel.  Measured on the uneven workload's
+// YET: a group of four costs 0.85 of four one-layer passes, two or three
+// layers in one group no less than their one-layer passes.  Both kernels add
+// a trial's values in the same order, so the split does not change a bit.
+static int fwd_group_size(const ara_yet *yet, int n_layers, bool hits, bool f32) {
+    if (n_layers < kGrpMax || hits || f32) return 0;
+    return grp_max_members(yet->trials_per_block) >= kGrpMax ? kGrpMax : 0;
+}
+
+// Work items of a grouped launch: with one group, workgroup i takes block
+// b0 + i; with several, the groups of one block run back to back on one XCD
+// (workgroup 8k + x is the k-th on XCD x: group k % n_groups of block
+// 8 (k / n_groups) + x), padded with empty items.
+static int grp_items(int n_groups, int nb) {
+    return n_groups <= 1 ? nb : n_groups * kXcds * ((nb + kXcds - 1) / kXcds);
+}
+
+struct GrpLayout {
+    int gsize = 0, n_groups = 0, n_sr = 0;
+    size_t gts, ubr, ucount, sbr, items;
+};
+
+static GrpLayout grp_layout(const ara_yet *yet, int n_sr, int n_layers, bool hits, bool f32) {
+    GrpLayout g;
+    g.gsize = fwd_group_size(yet, n_layers, hits, f32);
+    if (!g.gsize) return g;
+    g.n_groups = n_layers / g.gsize;   // full groups only
+    g.n_sr = n_sr;
+    g.gts = align256(static_cast<size_t>(g.n_groups) * sizeof(GrpTables));
+    g.ubr = align256(static_cast<size_t>(g.n_groups) * n_sr * kSrWords * sizeof(uint2));
+    g.ucount = align256(static_cast<size_t>(g.n_groups) * n_sr * sizeof(int32_t));
+    g.sbr = align256(static_cast<size_t>(g.n_groups) * kGrpMax * n_sr * kSrWords * sizeof(uint2));
+    g.items = align256(static_cast<size_t>(grp_items(g.n_groups, yet->n_blocks)) * sizeof(GrpItem));
+    return g;
+}
+
+static size_t fwd_workspace(const ara_tables *tables, const ara_yet *yet, const ara_layers *layers, bool hits,
+                            bool f32) {
     const OccLayoutSizes z = occ_sizes(tables->catalog, hits);
     const int L = layers->n_layers;
     const int nJ = L > 0 ? layers->elt_off[L] : 0;
@@ -488,6 +529,8 @@ static size_t fwd_workspace(const ara_tables *tables, const ara_yet *yet, const 
     b += align256(static_cast<size_t>(std::max(nJ, 1)) * sizeof(int32_t));
     b += align256(static_cast<size_t>(std::max(L, 1)) * sizeof(OccTables));
     b += static_cast<size_t>(L) * z.per_layer;
+    const GrpLayout g = grp_layout(yet, z.n_sr, L, hits, f32);
+    if (g.gsize) b += g.gts + g.ubr + g.ucount + g.sbr + g.items;
     return b;
 }
 
@@ -513,7 +556,7 @@ extern "C" int32_t ara_ylt_workspace_bytes(const ara_tables *tables, const ara_y
     if ((rc = fwd_lds_plan(yet->trials_per_block, yet->n_ranges, (flags & ARA_F_EMIT_HITS) != 0,
                            (flags & ARA_F_FP32_ACCUM) != 0, &bb, &cv)))
         return rc;
-    *bytes = fwd_workspace(tables, yet, layers, (flags & ARA_F_EMIT_HITS) != 0);
+    *bytes = fwd_workspace(tables, yet, layers, (flags & ARA_F_EMIT_HITS) != 0, (flags & ARA_F_FP32_ACCUM) != 0);
     return ARA_OK;
 }
 
@@ -537,7 +580,7 @@ int32_t forward_args(const ara_tables *tables, const ara_yet *yet, const ara_lay
     int32_t bb = 0, cv = 0;
     if ((rc = fwd_lds_plan(yet->trials_per_block, yet->n_ranges, want_hits, (flags & ARA_F_FP32_ACCUM) != 0, &bb, &cv)))
         return rc;
-    *need = fwd_workspace(tables, yet, layers, want_hits);
+    *need = fwd_workspace(tables, yet, layers, want_hits, (flags & ARA_F_FP32_ACCUM) != 0);
     return ARA_OK;
 }
 
@@ -560,8 +603,62 @@ int32_t forward_run(const ara_tables *tables, const ara_yet *yet, const ara_laye
     const int64_t b_lo = trial_begin / yet->trials_per_block;
     const int64_t b_hi = (trial_end + yet->trials_per_block - 1) / yet->trials_per_block;
     const int nb = static_cast<int>(b_hi - b_lo);
+    const int64_t n = trial_end - trial_begin;
+    const GrpLayout gl = grp_layout(yet, z.n_sr, L, want_hits, f32);
+    GrpTables *d_gts = nullptr;
+    GrpItem *d_gitems = nullptr;
+    std::vector<GrpTables> gts;
+    std::vector<GrpItem> gitems;
+    // what the host sends (descriptors, layer lists, group descriptors and
+    // work items) comes first, so that the one copy per call stays small
+    if (gl.gsize) {
+        d_gts = c.take<GrpTables>(static_cast<size_t>(gl.n_groups));
+        d_gitems = c.take<GrpItem>(static_cast<size_t>(grp_items(gl.n_groups, nb)));
+    }
     std::vector<OccTables> tabs(static_cast<size_t>(L));
     for (int j = 0; j < L; ++j) tabs[j] = occ_carve(c, z, want_hits);
+    if (gl.gsize) {
+        uint2 *ubr = c.take<uint2>(static_cast<size_t>(gl.n_groups) * z.n_sr * kSrWords);
+        int32_t *ucount = c.take<int32_t>(static_cast<size_t>(gl.n_groups) * z.n_sr);
+        uint2 *sbr = c.take<uint2>(static_cast<size_t>(gl.n_groups) * kGrpMax * z.n_sr * kSrWords);
+        // layers [g G, (g + 1) G) form group g
+        gts.resize(static_cast<size_t>(gl.n_groups));
+        for (int g = 0; g < gl.n_groups; ++g) {
+            GrpTables &t = gts[g];
+            t = GrpTables{};
+            t.ubr = ubr + static_cast<size_t>(g) * z.n_sr * kSrWords;
+            t.ucount = ucount + static_cast<size_t>(g) * z.n_sr;
+            t.sbr = sbr + static_cast<size_t>(g) * kGrpMax * z.n_sr * kSrWords;
+            const int j0 = g * gl.gsize, j1 = j0 + gl.gsize;
+            t.n = j1 - j0;
+            for (int m = 0; m < t.n; ++m) t.mt[m] = d_tabs + j0 + m;
+        }
+        gitems.assign(static_cast<size_t>(grp_items(gl.n_groups, nb)), GrpItem{});
+        for (size_t i = 0; i < gitems.size(); ++i) {
+            GrpItem &it = gitems[i];
+            it.block = -1;
+            int g = 0, bi = static_cast<int>(i);
+            if (gl.n_groups > 1) {
+                const int x = static_cast<int>(i % kXcds), k = static_cast<int>(i / kXcds);
+                g = k % gl.n_groups;
+                bi = (k / gl.n_groups) * kXcds + x;
+            }
+            if (bi >= nb) continue;
+            const int j0 = g * gl.gsize, j1 = j0 + gl.gsize;
+            it.gt = d_gts + g;
+            it.block = static_cast<int32_t>(b_lo) + bi;
+            it.n = j1 - j0;
+            it.mask = (1u << it.n) - 1u;
+            for (int m = 0; m < it.n; ++m) {
+                const int j = j0 + m;
+                it.lterm[m] = layer_terms + 4 * j;
+                it.t0[m] = trial_begin;
+                it.t1[m] = trial_end;
+                it.ylt[m] = ylt + static_cast<size_t>(j) * n;
+                it.s_pre[m] = s_pre ? s_pre + static_cast<size_t>(j) * n : nullptr;
+            }
+        }
+    }
     FwdRegular reg{};
     reg.tabs = d_tabs;
     reg.lterm = layer_terms;
@@ -578,6 +675,10 @@ int32_t forward_run(const ara_tables *tables, const ara_yet *yet, const ara_laye
     img.put(d_off, layers->elt_off, static_cast<size_t>(L + 1));
     img.put(d_ids, layers->elt_ids, static_cast<size_t>(nJ));
     img.put(d_tabs, tabs.data(), tabs.size());
+    if (gl.gsize) {
+        img.put(d_gts, gts.data(), gts.size());
+        img.put(d_gitems, gitems.data(), gitems.size());
+    }
     if ((rc = img.send(st))) return rc;
 
     {
@@ -586,7 +687,21 @@ int32_t forward_run(const ara_tables *tables, const ara_yet *yet, const ara_laye
                              st)))
             return rc;
     }
-    return launch_forward(yet, z.n_sr, want_hits, f32, nullptr, fwd_regular_items(L, nb), st, &reg);
+    int jg = 0;   // layers served by the grouped forward
+    if (gl.gsize) {
+        if ((rc = launch_grp_union(d_gts, gl.n_groups, z.n_sr, st))) return rc;
+        if ((rc = launch_fwd_group(yet, d_gitems, static_cast<int>(gitems.size()), gl.gsize, st))) return rc;
+        jg = gl.n_groups * gl.gsize;
+    }
+    if (jg == L) return ARA_OK;
+    // the other layers [jg, L): the one-layer kernel
+    reg.tabs = d_tabs + jg;
+    reg.lterm = layer_terms + 4 * jg;
+    reg.ylt = ylt + static_cast<size_t>(jg) * n;
+    reg.s_pre = s_pre ? s_pre + static_cast<size_t>(jg) * n : nullptr;
+    reg.hits = hits ? hits + static_cast<size_t>(jg) * n : nullptr;
+    reg.nl = L - jg;
+    return launch_forward(yet, z.n_sr, want_hits, f32, nullptr, fwd_regular_items(L - jg, nb), st, &reg);
 }
 
 }  // namespace ara

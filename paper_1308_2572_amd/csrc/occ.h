@@ -79,6 +79,48 @@ inline OccTables occ_carve(Carver &c, const OccLayoutSizes &z, bool with_cnt) {
     return t;
 }
 
+// Members (layers, or quotes of the server) that one workgroup of the
+// grouped forward serves together.
+constexpr int kGrpMax = 4;
+
+// The union of a group's set events, per super-range: the union bitmap with
+// ranks (as an occurrence table's br), its count, and for every member its
+// set events as a bitmap over the union's ranks: word k of sbr[m] holds union
+// ranks 32k..32k+31 of the super-range, {bit set iff the member's O != 0 for
+// that event, the member's rank of the first of them} -- the member's rank of
+// an event is its index in the member's own occurrence-table values.
+struct GrpTables {
+    uint2 *ubr;                     // [n_sr][kSrWords]
+    int32_t *ucount;                // [n_sr]
+    uint2 *sbr;                     // [kGrpMax][n_sr][kSrWords]
+    const OccTables *mt[kGrpMax];   // the members' occurrence tables (device)
+    int32_t n;                      // members
+    int32_t pad;
+};
+
+// One unit of grouped forward work: the members of one group over one block
+// of trials; member m writes its trials in [t0[m], t1[m]) (rows indexed
+// t - t0[m]).  block -1 marks an empty slot (the workgroup exits at once).
+struct GrpItem {
+    const GrpTables *gt;            // device
+    int32_t block;
+    int32_t n;                      // members
+    uint32_t mask;                  // members to serve on this block (bit m); others are skipped
+    const double *lterm[kGrpMax];   // (OccR, OccL, AggR, AggL) of each member
+    int64_t t0[kGrpMax], t1[kGrpMax];
+    double *ylt[kGrpMax];
+    double *s_pre[kGrpMax];         // or null
+};
+
+// Members one grouped-forward workgroup holds with blocks of tb trials (0 if
+// not even one leaves room for the table slices).
+int grp_max_members(int tb);
+// Builds the union tables of n_groups groups (their mt and n set).
+int32_t launch_grp_union(const GrpTables *d_gts, int n_groups, int n_sr, hipStream_t st);
+// The grouped forward over a device array of items (one workgroup each, a
+// whole CU's LDS per workgroup).
+int32_t launch_fwd_group(const ara_yet *yet, const GrpItem *d_items, int n_items, int gmax, hipStream_t st);
+
 // One unit of forward work: one layer over one block of trials, with the
 // trial range [t0, t1) whose outputs are written (row bases indexed t - t0).
 struct FwdItem {
