@@ -139,7 +139,8 @@ def main() -> int:
     torch.cuda.synchronize()
     t_tables = time.perf_counter() - t
     t = time.perf_counter()
-    yet = ara.PreparedYet.from_numpy(w.yet, dev)
+    # positions (one 16-bit word per code) for the secondary-uncertainty leg
+    yet = ara.PreparedYet.from_numpy(w.yet, dev, positions=not args.no_su)
     torch.cuda.synchronize()
     t_prepare = time.perf_counter() - t
     log(f"tables {t_tables:.2f} s, YET layout {t_prepare:.2f} s (one-time, includes host->device copies)")
@@ -361,28 +362,25 @@ def bench_su(ara, tables, yet, layers, et, lt, w, steps, warmup):
     """Algorithm 1 with secondary uncertainty on the same workload: every
     record gets a standard deviation (cv ~ U[0.25, 1.5], 10% exact), and every
     (occurrence, ELT) pair the layer holds draws a lognormal loss."""
-    import numpy as np
     import torch
     import synth
     log("secondary uncertainty: draws per (occurrence, ELT)")
     sg = synth.record_sigmas(synth.SEED_BASE + 1, w.elts)
     sigma = ara.SigmaTables.from_numpy(tables, sg)
-    off = torch.from_numpy(np.ascontiguousarray(w.yet.offsets, np.int64)).cuda()
-    ids = torch.from_numpy(np.ascontiguousarray(w.yet.ids, np.int32)).cuda()
     N, nnz = w.yet.n_trials, w.yet.nnz
     J = int(w.layers.elt_off[-1])
     _, _, hits = ara.ylt_forward(tables, yet, layers, et, lt, 0, N, want_s_pre=False, want_hits=True)
     draws = int(hits.sum().item())          # (occurrence, ELT) pairs whose ELT holds the event
     del hits
     for _ in range(max(1, warmup)):
-        y, _ = ara.ylt_forward_su(tables, sigma, off, ids, layers, et, lt, 7, want_s_pre=False)
+        y, _ = ara.ylt_forward_su(tables, sigma, yet, layers, et, lt, 7, want_s_pre=False)
     torch.cuda.synchronize()
     n_steps = max(1, min(steps, 5))
     ara.profile_reset()
     ara.profile_enable(True)
     t0 = time.perf_counter()
     for _ in range(n_steps):
-        y, _ = ara.ylt_forward_su(tables, sigma, off, ids, layers, et, lt, 7, want_s_pre=False)
+        y, _ = ara.ylt_forward_su(tables, sigma, yet, layers, et, lt, 7, want_s_pre=False)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ara.profile_enable(False)
@@ -392,7 +390,7 @@ def bench_su(ara, tables, yet, layers, et, lt, w, steps, warmup):
     m, _ = ara.metrics(y, w.p)
     mm = m.cpu().numpy()[0]
     algo = 4.0 * nnz + 8.0 * N + 8.0 * N * w.layers.n_layers
-    del off, ids, y, sigma
+    del y, sigma
     torch.cuda.empty_cache()
     return {"ms_per_call": ms, "kernel": "k_su_fwd", "kernel_ms": k, "draws": draws,
             "draws_per_s": draws / (k * 1e-3), "lookups_per_s": nnz * J / (ms * 1e-3),

@@ -45,7 +45,7 @@
 extern "C" {
 #endif
 
-#define ARA_ABI_VERSION 1
+#define ARA_ABI_VERSION 2
 
 /* status codes */
 #define ARA_OK        0
@@ -126,9 +126,13 @@ typedef struct ara_yet {
     int64_t  *tr_off;            /* device [n_slices * catalog + 1] */
     uint32_t *tr_ent;            /* device [nnz] */
     /* trial-major copy of the input (ARA_PREP_TRIAL_MAJOR; NULL otherwise) */
-    int64_t  *t_off;             /* device [n_trials + 1] */
+    int64_t  *t_off;             /* device [n_trials + 1] (also with ARA_PREP_POSITIONS) */
     int32_t  *t_ids;             /* device [nnz] */
     int32_t  *t_cnt;             /* device [catalog]: occurrences of each event */
+    /* positions (ARA_PREP_POSITIONS; NULL otherwise) */
+    uint16_t *pos;               /* device [n_codes + 256]: at each occurrence code's index, the
+                                    occurrence's position in its trial (its index in ids less
+                                    offsets[trial]); 0xFFFF at gap codes and padding */
 } ara_yet;
 
 /* prepare flags */
@@ -136,6 +140,10 @@ typedef struct ara_yet {
 #define ARA_PREP_TRIAL_MAJOR 2u  /* also keep a trial-major copy of offsets and ids: lets ara_ylt_backward
                                     handle cotangents that are constant over most trials (the metrics')
                                     from the deviating trials' own events */
+#define ARA_PREP_POSITIONS 4u    /* also store each occurrence's position in its trial beside its code
+                                    (and a copy of offsets): needed by ara_ylt_forward_su, whose draws
+                                    are keyed by the trial-major occurrence index; every trial must then
+                                    hold at most 65536 occurrences (ARA_E_LIMIT otherwise) */
 
 /* Upper bound of the device buffer ara_yet_prepare needs for these flags. */
 int32_t ara_yet_prepare_bytes(int64_t n_trials, int64_t nnz, int32_t catalog, uint32_t flags, size_t *bytes);
@@ -144,13 +152,15 @@ int32_t ara_yet_prepare_bytes(int64_t n_trials, int64_t nnz, int32_t catalog, ui
  * offsets: device int64 [n_trials+1], offsets[0] = 0, non-decreasing; trial t
  *          holds ids[offsets[t] .. offsets[t+1]).
  * ids:     device int32 [offsets[n_trials]].
- * flags:   ARA_PREP_TRANSPOSED, ARA_PREP_TRIAL_MAJOR (ARA_E_INVAL for other bits).
+ * flags:   ARA_PREP_TRANSPOSED, ARA_PREP_TRIAL_MAJOR, ARA_PREP_POSITIONS (ARA_E_INVAL
+ *          for other bits).
  * buf:     device buffer of at least ara_yet_prepare_bytes (same flags); it
  *          holds the prepared YET afterwards and must outlive every use of *out.
  * Validates every ID (ARA_E_RANGE) and every offset.  SYNCHRONISES `stream`
  * (it sizes the layout from device-side counts); one-time cost.
  * ARA_E_LIMIT if one (slice, catalogue range) of the event-major copy would
- * hold 2^32 occurrences or more.
+ * hold 2^32 occurrences or more, or with ARA_PREP_POSITIONS if a trial holds
+ * more than 65536 occurrences.
  */
 int32_t ara_yet_prepare(const int64_t *offsets, const int32_t *ids, int64_t n_trials,
                         int32_t catalog, uint32_t flags, void *buf, size_t buf_bytes,
@@ -366,24 +376,24 @@ int32_t ara_su_workspace_bytes(const ara_tables *tables, const ara_layers *layer
                                size_t *bytes);
 
 /*
- * offsets, ids: the trial-major YET on the device, n_trials trials (the
- *              occurrence index keys the draws, so storage order matters).
- * occ_begin, occ_count: as for ara_yelt_forward.
+ * yet:         prepared with ARA_PREP_POSITIONS (ARA_E_INVAL otherwise): the
+ *              draws are keyed by each occurrence's index in the trial-major
+ *              YET given to ara_yet_prepare, which the positions recover.
  * ylt, s_pre:  device binary64 [n_layers][trial_end - trial_begin] (s_pre may
  *              be NULL): Algorithm 1 with the draws above.
  * ws:          device workspace of at least ara_su_workspace_bytes for the same
  *              elt_records (ARA_E_NOSPACE otherwise; an ELT holding more
  *              events than its elt_records is a device-side ARA_E_LIMIT).
- * Per trial the occurrence losses are summed in wavefront order, so S and
- * the YLT agree with a sequential sum to rounding; everything else follows
- * the definition step by step in binary64.
+ * A trial's occurrence losses are summed in an order fixed by the prepared
+ * layout (not the trial's storage order), so S and the YLT agree with a
+ * sequential sum to rounding, and do not depend on the trial range or on the
+ * other layers of the call; everything else follows the definition step by
+ * step in binary64.
  */
-int32_t ara_ylt_forward_su(const ara_tables *tables, const float *sigma, const int64_t *offsets,
-                           const int32_t *ids, int64_t n_trials, const ara_layers *layers,
-                           const int64_t *elt_records, const double *elt_terms, const double *layer_terms,
-                           uint64_t seed, int64_t trial_begin, int64_t trial_end, int64_t occ_begin,
-                           int64_t occ_count, double *ylt, double *s_pre, void *ws, size_t ws_bytes,
-                           void *stream);
+int32_t ara_ylt_forward_su(const ara_tables *tables, const float *sigma, const ara_yet *yet,
+                           const ara_layers *layers, const int64_t *elt_records, const double *elt_terms,
+                           const double *layer_terms, uint64_t seed, int64_t trial_begin, int64_t trial_end,
+                           double *ylt, double *s_pre, void *ws, size_t ws_bytes, void *stream);
 
 /* ------------------------------------------------------------------------ */
 /* Quote server: continuous batching of pricing requests over the resident   */

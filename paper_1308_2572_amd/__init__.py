@@ -26,6 +26,7 @@ ARA_F_EMIT_HITS = 1
 ARA_F_FP32_ACCUM = 2
 PREP_TRANSPOSED = 1          # ARA_PREP_TRANSPOSED
 PREP_TRIAL_MAJOR = 2         # ARA_PREP_TRIAL_MAJOR
+PREP_POSITIONS = 4           # ARA_PREP_POSITIONS
 ARA_MAX_COTANGENTS = 4
 
 _c_i32, _c_i64, _c_u32, _c_f64, _c_p, _c_sz = (ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_double,
@@ -44,7 +45,7 @@ class ara_yet(ctypes.Structure):
                 ("trials_per_block", _c_i32), ("n_blocks", _c_i32), ("max_occ", _c_i32),
                 ("n_codes", _c_i64), ("code", _c_p), ("seg_base", _c_p), ("seg_run", _c_p), ("lane_start", _c_p),
                 ("n_slices", _c_i32), ("reserved", _c_i32), ("slice_trials", _c_i64), ("tr_off", _c_p),
-                ("tr_ent", _c_p), ("t_off", _c_p), ("t_ids", _c_p), ("t_cnt", _c_p)]
+                ("tr_ent", _c_p), ("t_off", _c_p), ("t_ids", _c_p), ("t_cnt", _c_p), ("pos", _c_p)]
 
 
 class ara_tables(ctypes.Structure):
@@ -86,8 +87,8 @@ _SIGNATURES = {
                                   _c_i64, _c_i64, _c_p, _c_p, _c_p, _c_sz, _c_p]),
     "ara_build_elt_sigma": (_c_i32, [_P(ara_tables), _c_p, _c_p, _c_p, _c_p, _c_p]),
     "ara_su_workspace_bytes": (_c_i32, [_P(ara_tables), _P(ara_layers), _c_p, _P(_c_sz)]),
-    "ara_ylt_forward_su": (_c_i32, [_P(ara_tables), _c_p, _c_p, _c_p, _c_i64, _P(ara_layers), _c_p, _c_p, _c_p,
-                                    ctypes.c_uint64, _c_i64, _c_i64, _c_i64, _c_i64, _c_p, _c_p, _c_p, _c_sz, _c_p]),
+    "ara_ylt_forward_su": (_c_i32, [_P(ara_tables), _c_p, _P(ara_yet), _P(ara_layers), _c_p, _c_p, _c_p,
+                                    ctypes.c_uint64, _c_i64, _c_i64, _c_p, _c_p, _c_p, _c_sz, _c_p]),
     "ara_metrics_workspace_bytes": (_c_i32, [_c_i32, _c_i64, _P(_c_sz)]),
     "ara_metrics": (_c_i32, [_c_p, _c_i32, _c_i64, _c_f64, _c_p, _c_p, _c_p, _c_sz, _c_p]),
     "ara_metrics_vjp": (_c_i32, [_c_p, _c_i32, _c_i64, _c_p, _c_p, _c_p]),
@@ -159,19 +160,22 @@ class PreparedYet:
     """A YET laid out on the device by ara_yet_prepare (keeps its buffer alive)."""
 
     def __init__(self, offsets: torch.Tensor, ids: torch.Tensor, catalog: int, transposed: bool = True,
-                 trial_major: Optional[bool] = None):
+                 trial_major: Optional[bool] = None, positions: bool = False):
         """transposed: also build the event-major copy that the backward
         needs (ARA_PREP_TRANSPOSED); leave it off for forward-only use.
         trial_major: also keep a trial-major copy (ARA_PREP_TRIAL_MAJOR), with
         which the backward of the metrics reads only the trials whose weight
-        differs from the common one; on by default with `transposed`."""
+        differs from the common one; on by default with `transposed`.
+        positions: also store each occurrence's position in its trial
+        (ARA_PREP_POSITIONS), which the secondary-uncertainty forward needs."""
         lib = library()
         if offsets.dtype != torch.int64 or ids.dtype != torch.int32:
             raise ValueError("offsets must be int64 and ids int32")
         n_trials = offsets.numel() - 1
         nnz = ids.numel()
         trial_major = transposed if trial_major is None else trial_major
-        flags = (PREP_TRANSPOSED if transposed else 0) | (PREP_TRIAL_MAJOR if trial_major else 0)
+        flags = ((PREP_TRANSPOSED if transposed else 0) | (PREP_TRIAL_MAJOR if trial_major else 0)
+                 | (PREP_POSITIONS if positions else 0))
         nb = _c_sz()
         _check(lib.ara_yet_prepare_bytes(n_trials, nnz, catalog, flags, ctypes.byref(nb)), "ara_yet_prepare_bytes")
         self.device = offsets.device
@@ -182,12 +186,14 @@ class PreparedYet:
         self.n_trials = n_trials
         self.catalog = catalog
         self.transposed = transposed
+        self.positions = positions
 
     @classmethod
-    def from_numpy(cls, yet, device="cuda", transposed: bool = True, trial_major: Optional[bool] = None):
+    def from_numpy(cls, yet, device="cuda", transposed: bool = True, trial_major: Optional[bool] = None,
+                   positions: bool = False):
         off = torch.from_numpy(np.ascontiguousarray(yet.offsets, np.int64)).to(device)
         ids = torch.from_numpy(np.ascontiguousarray(yet.ids, np.int32)).to(device)
-        out = cls(off, ids, int(yet.catalog), transposed=transposed, trial_major=trial_major)
+        out = cls(off, ids, int(yet.catalog), transposed=transposed, trial_major=trial_major, positions=positions)
         return out
 
 
@@ -290,24 +296,19 @@ def yelt_forward(tables: EltTables, offsets: torch.Tensor, ids: torch.Tensor, la
     return yelt, occ_max
 
 
-def ylt_forward_su(tables: EltTables, sigma: SigmaTables, offsets: torch.Tensor, ids: torch.Tensor, layers: Layers,
+def ylt_forward_su(tables: EltTables, sigma: SigmaTables, yet: PreparedYet, layers: Layers,
                    elt_terms: torch.Tensor, layer_terms: torch.Tensor, seed: int, trial_begin: int = 0,
                    trial_end: Optional[int] = None, want_s_pre: bool = True, check: bool = False):
     """Algorithm 1 with secondary uncertainty (a lognormal draw per occurrence
-    and ELT) over the trial-major YET.  Returns (ylt, s_pre or None), each
-    [n_layers, n]."""
+    and ELT) over a YET prepared with positions.  Returns (ylt, s_pre or
+    None), each [n_layers, n]."""
     lib = library()
-    if offsets.dtype != torch.int64 or ids.dtype != torch.int32:
-        raise ValueError("offsets must be int64 and ids int32")
-    n_trials = offsets.numel() - 1
-    trial_end = n_trials if trial_end is None else trial_end
-    if not (0 <= trial_begin <= trial_end <= n_trials):
+    trial_end = yet.n_trials if trial_end is None else trial_end
+    if not (0 <= trial_begin <= trial_end <= yet.n_trials):
         raise AraError(ARA_E_RANGE, "trial range outside the YET")
     n = trial_end - trial_begin
     L = layers.n_layers
-    dev = offsets.device
-    occ_begin = int(offsets[trial_begin].item())
-    occ_count = int(offsets[trial_end].item()) - occ_begin
+    dev = yet.device
     rec = tables.records
     nb = _c_sz()
     _check(lib.ara_su_workspace_bytes(ctypes.byref(tables.handle), ctypes.byref(layers.handle),
@@ -317,11 +318,10 @@ def ylt_forward_su(tables: EltTables, sigma: SigmaTables, offsets: torch.Tensor,
     s_pre = torch.empty((L, n), dtype=torch.float64, device=dev) if want_s_pre else None
     et = elt_terms.to(device=dev, dtype=torch.float64).contiguous()
     lt = layer_terms.to(device=dev, dtype=torch.float64).contiguous()
-    _check(lib.ara_ylt_forward_su(ctypes.byref(tables.handle), _dptr(sigma.sigma), _dptr(offsets), _dptr(ids),
-                                  n_trials, ctypes.byref(layers.handle), rec.ctypes.data_as(_c_p), _dptr(et),
-                                  _dptr(lt), int(seed) & 0xFFFFFFFFFFFFFFFF, trial_begin, trial_end, occ_begin,
-                                  occ_count, _dptr(ylt), _dptr(s_pre), _dptr(ws), ws.numel(), _stream()),
-           "ara_ylt_forward_su")
+    _check(lib.ara_ylt_forward_su(ctypes.byref(tables.handle), _dptr(sigma.sigma), ctypes.byref(yet.handle),
+                                  ctypes.byref(layers.handle), rec.ctypes.data_as(_c_p), _dptr(et), _dptr(lt),
+                                  int(seed) & 0xFFFFFFFFFFFFFFFF, trial_begin, trial_end, _dptr(ylt), _dptr(s_pre),
+                                  _dptr(ws), ws.numel(), _stream()), "ara_ylt_forward_su")
     if check:
         _check(lib.ara_check_device_error(_dptr(ws), _stream()), "ara_ylt_forward_su (device)")
     return ylt, s_pre

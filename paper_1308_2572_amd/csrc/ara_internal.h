@@ -26,6 +26,9 @@ constexpr int kWave = 64;
 // 8-byte load per lane of a wavefront reads them in place of codes past a
 // segment's end.
 constexpr int kPadCodes = 4 * kWave;
+// Largest trial a YET prepared with positions holds: a position is 16 bits.
+constexpr int64_t kMaxPositions = 65536;
+constexpr uint32_t kPrepFlags = ARA_PREP_TRANSPOSED | ARA_PREP_TRIAL_MAJOR | ARA_PREP_POSITIONS;
 // Trial slices of the event-major YET copy: one per XCD of the MI355X, so
 // that a backward workgroup's gathers of per-trial weights stay in the L2 of
 // the XCD it runs on (workgroups are dealt to the XCDs round-robin).

@@ -16,6 +16,12 @@
 // trial lane_start[j] of the group; code s of lane j sits at
 //     base + (s / 4) * 256 + 4 * j + s % 4,
 // so a wavefront reads four steps of all its lanes as one 512-byte block.
+//
+// With positions, a second array of the same shape holds, at each code's
+// slot, the occurrence's position in its trial (its index less the trial's
+// first index; 0xFFFF for gap codes and padding), so that a walk of the code
+// stream can name each occurrence by its trial-major index.  Trials then hold
+// at most 65536 occurrences.
 #include "ara_internal.h"
 
 #include <algorithm>
@@ -74,6 +80,10 @@ static size_t prepare_bytes(const Geometry &g, int64_t n_trials, int64_t nnz, in
         c.take<int32_t>(static_cast<size_t>(std::max<int64_t>(nnz, 1)));
         c.take<int32_t>(static_cast<size_t>(catalog));
     }
+    if (flags & ARA_PREP_POSITIONS) {
+        c.take<uint16_t>(static_cast<size_t>(max_codes(g, nnz)) + kPadCodes);
+        if (!(flags & ARA_PREP_TRIAL_MAJOR)) c.take<int64_t>(static_cast<size_t>(n_trials) + 1);
+    }
     return c.bytes();
 }
 
@@ -87,7 +97,9 @@ __device__ __forceinline__ int64_t code_slot(int64_t base, int s, int lane) {
 // lanes' starting trials.  Within a 64-ID chunk of a trial, the lanes of one
 // range are its occurrences in storage order (a stable multi-split by
 // ballots); the first of them settles what precedes them in the segment: gap
-// codes for skipped trials and the advance flag.
+// codes for skipped trials and the advance flag.  With `pos`, pass two also
+// writes each occurrence's position in its trial beside its code, and with
+// `long_trial`, pass one flags a trial of more than kMaxPositions occurrences.
 template <bool SCATTER>
 __global__ __launch_bounds__(1024) void k_prep_codes(const int64_t *__restrict__ off,
                                                      const int32_t *__restrict__ ids, int64_t n_trials,
@@ -96,7 +108,8 @@ __global__ __launch_bounds__(1024) void k_prep_codes(const int64_t *__restrict__
                                                      const int64_t *__restrict__ seg_base,
                                                      const int32_t *__restrict__ seg_run,
                                                      uint16_t *__restrict__ code, uint8_t *__restrict__ lane_start,
-                                                     int32_t *__restrict__ err,
+                                                     uint16_t *__restrict__ pos, int32_t *__restrict__ err,
+                                                     int32_t *__restrict__ long_trial,
                                                      unsigned long long *__restrict__ events) {
     __shared__ int32_t cur_all[kGroups * kRangeWindow];   // codes so far per range
     __shared__ int16_t last_all[kGroups * kRangeWindow];  // last trial seen per range, -1 none
@@ -107,13 +120,16 @@ __global__ __launch_bounds__(1024) void k_prep_codes(const int64_t *__restrict__
     const int64_t t0 = b * tb + static_cast<int64_t>(w) * tg;
     const int64_t t1 = std::min<int64_t>(t0 + tg, n_trials);
     auto seg_of = [&](int r) { return (static_cast<size_t>(b) * n_ranges + r) * kGroups + w; };
-    // position p of range r's segment gets code c; the state before it is trial `start`
-    auto put = [&](int r, int64_t p, uint16_t c, int start) {
+    // position p of range r's segment gets code c (and, for an occurrence,
+    // its position `at` in the trial); the state before it is trial `start`
+    auto put = [&](int r, int64_t p, uint16_t c, int start, uint16_t at) {
         const size_t si = seg_of(r);
         const int run = seg_run[si];
         const int lj = static_cast<int>(p / run);
         const int s = static_cast<int>(p - static_cast<int64_t>(lj) * run);
-        code[code_slot(seg_base[si], s, lj)] = c;
+        const int64_t slot = code_slot(seg_base[si], s, lj);
+        code[slot] = c;
+        if (pos) pos[slot] = at;
         if (s == 0) lane_start[si * kWave + lj] = static_cast<uint8_t>(start);
     };
     unsigned long long ev = 0;
@@ -131,6 +147,7 @@ __global__ __launch_bounds__(1024) void k_prep_codes(const int64_t *__restrict__
                 if (!SCATTER && lane == 0 && w0 == 0) atomicCAS(err, 0, ARA_E_RANGE);
                 continue;
             }
+            if (!SCATTER && long_trial && lane == 0 && w0 == 0 && o1 - o0 > kMaxPositions) atomicOr(long_trial, 1);
             for (int64_t base = o0; base < o1; base += kWave) {
                 const int64_t k = base + lane;
                 const bool in = k < o1;
@@ -166,7 +183,7 @@ __global__ __launch_bounds__(1024) void k_prep_codes(const int64_t *__restrict__
                     }
                     const int p0 = cur[rl];
                     if (SCATTER)
-                        for (int q = 0; q < gap; ++q) put(r, p0 + q, kSkip, L + q);   // each advances one trial
+                        for (int q = 0; q < gap; ++q) put(r, p0 + q, kSkip, L + q, kSkip);   // each advances one trial
                     cur[rl] = p0 + gap + tot;
                     last[rl] = static_cast<int16_t>(i);
                     p_open = p0 + gap;
@@ -177,7 +194,8 @@ __global__ __launch_bounds__(1024) void k_prep_codes(const int64_t *__restrict__
                 adv_open = __shfl(adv_open, leader);
                 if (SCATTER && active) {
                     const int a = (rank == 0) ? adv_open : 0;
-                    put(r, p_open + static_cast<int>(rank), static_cast<uint16_t>((a ? kAdvance : 0) | local), i - a);
+                    put(r, p_open + static_cast<int>(rank), static_cast<uint16_t>((a ? kAdvance : 0) | local), i - a,
+                        static_cast<uint16_t>(k - o0));
                 }
                 __builtin_amdgcn_wave_barrier();
             }
@@ -354,7 +372,7 @@ extern "C" int32_t ara_yet_prepare_bytes(int64_t n_trials, int64_t nnz, int32_t 
     if (!bytes) return fail(ARA_E_INVAL, "ara_yet_prepare_bytes: null output");
     if (n_trials < 0 || nnz < 0 || catalog <= 0) return fail(ARA_E_INVAL, "ara_yet_prepare_bytes: negative size");
     if (catalog > ARA_MAX_CATALOG) return fail(ARA_E_LIMIT, "catalog exceeds ARA_MAX_CATALOG");
-    if (flags & ~(ARA_PREP_TRANSPOSED | ARA_PREP_TRIAL_MAJOR)) return fail(ARA_E_INVAL, "ara_yet_prepare_bytes: unknown flag");
+    if (flags & ~kPrepFlags) return fail(ARA_E_INVAL, "ara_yet_prepare_bytes: unknown flag");
     *bytes = prepare_bytes(geometry(n_trials, catalog), n_trials, nnz, catalog, flags);
     return ARA_OK;
 }
@@ -364,7 +382,7 @@ extern "C" int32_t ara_yet_prepare(const int64_t *offsets, const int32_t *ids, i
     if (!offsets || !buf || !out) return fail(ARA_E_INVAL, "ara_yet_prepare: null pointer");
     if (n_trials < 0 || catalog <= 0) return fail(ARA_E_INVAL, "ara_yet_prepare: bad size");
     if (catalog > ARA_MAX_CATALOG) return fail(ARA_E_LIMIT, "catalog exceeds ARA_MAX_CATALOG");
-    if (flags & ~(ARA_PREP_TRANSPOSED | ARA_PREP_TRIAL_MAJOR)) return fail(ARA_E_INVAL, "ara_yet_prepare: unknown flag");
+    if (flags & ~kPrepFlags) return fail(ARA_E_INVAL, "ara_yet_prepare: unknown flag");
     hipStream_t st = static_cast<hipStream_t>(stream);
     const Geometry g = geometry(n_trials, catalog);
     int64_t ends[2] = {0, 0};
@@ -400,12 +418,20 @@ extern "C" int32_t ara_yet_prepare(const int64_t *offsets, const int32_t *ids, i
         t_ids = c.take<int32_t>(static_cast<size_t>(std::max<int64_t>(nnz, 1)));
         t_cnt = c.take<int32_t>(static_cast<size_t>(catalog));
         ARA_HIP(hipMemsetAsync(t_cnt, 0, static_cast<size_t>(catalog) * sizeof(int32_t), st));
-        ARA_HIP(hipMemcpyAsync(t_off, offsets, (static_cast<size_t>(n_trials) + 1) * sizeof(int64_t),
-                               hipMemcpyDeviceToDevice, st));
         if (nnz > 0)
             ARA_HIP(hipMemcpyAsync(t_ids, ids, static_cast<size_t>(nnz) * sizeof(int32_t), hipMemcpyDeviceToDevice, st));
     }
+    const bool positions = (flags & ARA_PREP_POSITIONS) != 0;
+    uint16_t *pos = nullptr;
+    if (positions) {
+        pos = c.take<uint16_t>(static_cast<size_t>(max_codes(g, nnz)) + kPadCodes);
+        if (!t_off) t_off = c.take<int64_t>(static_cast<size_t>(n_trials) + 1);
+    }
+    if (t_off)
+        ARA_HIP(hipMemcpyAsync(t_off, offsets, (static_cast<size_t>(n_trials) + 1) * sizeof(int64_t),
+                               hipMemcpyDeviceToDevice, st));
     ARA_HIP(hipMemsetAsync(misc, 0, 32 * sizeof(int64_t), st));
+    int32_t *long_trial = positions ? reinterpret_cast<int32_t *>(misc + 3) : nullptr;
 
     ara_yet y{};
     y.n_trials = n_trials;
@@ -424,6 +450,7 @@ extern "C" int32_t ara_yet_prepare(const int64_t *offsets, const int32_t *ids, i
     y.t_off = t_off;
     y.t_ids = t_ids;
     y.t_cnt = t_cnt;
+    y.pos = pos;
     if (transposed) {
         y.n_slices = kSlices;
         y.slice_trials = static_cast<int64_t>(g.slice_blocks) * g.tb;
@@ -439,17 +466,18 @@ extern "C" int32_t ara_yet_prepare(const int64_t *offsets, const int32_t *ids, i
     }
     // pass 1: codes per segment (into seg_run for now)
     k_prep_codes<false><<<g.n_blocks, 1024, 0, st>>>(offsets, ids, n_trials, catalog, g.tg, g.tb, g.n_ranges,
-                                                     g.gbits, seg_run, nullptr, nullptr, nullptr, nullptr, err,
-                                                     events);
+                                                     g.gbits, seg_run, nullptr, nullptr, nullptr, nullptr, nullptr,
+                                                     err, long_trial, events);
     ARA_HIP(hipGetLastError());
     std::vector<int32_t> cnt(g.nseg);
-    int64_t head[3] = {0, 0, 0};
+    int64_t head[4] = {0, 0, 0, 0};
     ARA_HIP(hipMemcpyAsync(head, misc, sizeof(head), hipMemcpyDeviceToHost, st));
     ARA_HIP(hipMemcpyAsync(cnt.data(), seg_run, g.nseg * sizeof(int32_t), hipMemcpyDeviceToHost, st));
     ARA_HIP(hipStreamSynchronize(st));
     const int32_t err_h = static_cast<int32_t>(head[0] & 0xffffffff);
     if (err_h) return fail(err_h, "ara_yet_prepare: an event ID lies outside [0, catalog) or offsets decrease");
     if (head[2] != nnz) return fail(ARA_E_RANGE, "ara_yet_prepare: offsets do not cover the IDs consistently");
+    if (head[3] != 0) return fail(ARA_E_LIMIT, "ara_yet_prepare: a trial holds more than 65536 occurrences (positions)");
 
     std::vector<int64_t> base(g.nseg);
     std::vector<int32_t> run(g.nseg);
@@ -464,11 +492,12 @@ extern "C" int32_t ara_yet_prepare(const int64_t *offsets, const int32_t *ids, i
     ARA_HIP(hipMemcpyAsync(seg_run, run.data(), g.nseg * sizeof(int32_t), hipMemcpyHostToDevice, st));
     // padding, and the block of skip codes after the last code
     ARA_HIP(hipMemsetAsync(code, 0xFF, static_cast<size_t>(total + kPadCodes) * sizeof(uint16_t), st));
+    if (pos) ARA_HIP(hipMemsetAsync(pos, 0xFF, static_cast<size_t>(total + kPadCodes) * sizeof(uint16_t), st));
     ARA_HIP(hipMemsetAsync(lane_start, 0, g.nseg * kWave, st));
     // pass 2: the codes themselves
     k_prep_codes<true><<<g.n_blocks, 1024, 0, st>>>(offsets, ids, n_trials, catalog, g.tg, g.tb, g.n_ranges,
-                                                    g.gbits, nullptr, seg_base, seg_run, code, lane_start, err,
-                                                    nullptr);
+                                                    g.gbits, nullptr, seg_base, seg_run, code, lane_start, pos, err,
+                                                    nullptr, nullptr);
     ARA_HIP(hipGetLastError());
     ARA_HIP(hipStreamSynchronize(st));   // the host copies of base and run live in this scope
     k_prep_max_occ<<<g.n_ranges, 1024, 0, st>>>(code, seg_base, seg_run, g.n_blocks, g.n_ranges, max_occ, catalog,

@@ -31,7 +31,6 @@ namespace ara {
 constexpr int kSuThreads = 1024;
 constexpr int kSuMaxJ = ARA_MAX_ELTS_PER_LAYER;
 constexpr int kSuScanPer = kSr / kSuThreads;   // 64 ranks per thread in the count scan
-constexpr int kSuMaxSr = (ARA_MAX_CATALOG + kSr - 1) / kSr;   // super-ranges of the largest catalogue
 
 // One (union event, ELT of the layer) pair; 32 bytes.  The first ELT (in
 // listed order) holding a union event has its entry at the event's union
@@ -253,29 +252,45 @@ __device__ __forceinline__ double su_draw(const SuEntry &e, uint64_t seed, int64
 }
 
 // ---------------------------------------------------------------------------
-// Streaming kernel: one wavefront per trial.
+// Streaming kernel: the prepared YET walked by catalogue range.
 //
-// Only ~15% of occurrences belong to the union, so drawing where they fall
-// would leave most lanes idle.  Each wavefront appends its union occurrences
-// (offset in the trial, first entry) to a queue in LDS as it streams, and
-// whenever 64 are queued they are drawn in rounds of one draw per lane: a
-// lane takes the next queued occurrence, draws its first ELT and, when
-// further ELTs hold the event, keeps the occurrence and draws one of them
-// per round while the other lanes take new ones; what is left is drawn at
-// the end of the trial.  Each lane sums the losses of the occurrences it
-// finished, in that order; the trial's total is the wavefront sum of those.
+// One workgroup per (block of trials, layer); wavefront g owns trial group g
+// of the block, as in the forward.  The catalogue is walked one range (2^15
+// events) at a time with the range's bitmap words (union ranks) in LDS.  All
+// workgroups walk the ranges in the same order, so the entries of the few
+// ranges in use at any time stay in L2, and the codes and positions stream
+// past it.  Each lane decodes its run of codes (trial advances, event
+// offsets); an occurrence whose event is in the union is appended, with its
+// trial in the block and its position in the trial, to the wavefront's LDS
+// queue, and whenever 64 are queued they are drawn in rounds of one draw per
+// lane: a lane takes the next queued occurrence, draws its first ELT and,
+// when further ELTs hold the event, keeps the occurrence and draws one of
+// them per round while the other lanes take new ones.  A finished
+// occurrence's loss after the occurrence terms (steps two and three) is added
+// to its trial's total in LDS.  The queue carries over from range to range;
+// what is left is drawn after the last range, and the totals then meet the
+// aggregate terms (step four, telescoped).
+//
+// A trial's total is accumulated by one wavefront in an order fixed by the
+// block's code layout (same-address LDS additions of one instruction apply in
+// lane order), so the results depend neither on the trial window nor on the
+// other layers of the call.
 
-constexpr int kSuSlices = 8;        // 64-occurrence slices per step
-constexpr int kSuQueue = 2 * kWave; // queue capacity: < 64 waiting + one slice
+constexpr int kSuChunk = 4;                                 // codes per lane and step (runs are multiples of 4)
+constexpr int kSuQCap = (kWave - 1) + kSuChunk * kWave + 1; // 320: fewer than 64 waiting + one step's codes
+static_assert(kSuThreads == kSrWords / 2, "one bitmap word of a range per thread");
 
 struct SuParams {
-    const int64_t *off;
-    const int32_t *ids;
-    int32_t catalog, n_sr;
+    const uint16_t *code, *pos;
+    const int64_t *seg_base;
+    const int32_t *seg_run;
+    const uint8_t *lane_start;
+    const int64_t *t_off;        // the YET's offsets
+    int64_t n_trials;
+    int32_t tg, tb, n_ranges, n_sr;
+    int32_t b0, nb, n_layers, pad;
     int64_t t0, t1;
-    int64_t occ_begin, occ_count;
     const OccTables *tabs;
-    const uint32_t *filter;      // [n_layers][kFilterWords]
     const uint32_t *ubase;       // [n_layers][n_sr + 1] union-rank bases of the super-ranges
     const uint64_t *eregion;     // [n_layers]
     const uint64_t *ecap;        // [n_layers] entries allocated
@@ -285,175 +300,209 @@ struct SuParams {
     const double *elt_terms, *layer_terms;
     uint64_t seed;
     double *ylt, *s_pre;
-    int32_t *err;
 };
 
+// Workgroup i's block (relative to b0) and layer: with one layer, block i;
+// with several, the layers of one block run back to back on one XCD
+// (workgroups are dealt to the XCDs round-robin; workgroup 8k + x is the
+// k-th on XCD x and takes layer k % L of block 8 (k / L) + x), so that they
+// read the block's codes from HBM once.  -1 past the last block.
+__device__ __forceinline__ int su_item(const SuParams &P, int i, int &layer) {
+    if (P.n_layers == 1) {
+        layer = 0;
+        return i < P.nb ? i : -1;
+    }
+    const int x = i % kXcds, k = i / kXcds;
+    layer = k % P.n_layers;
+    const int bi = (k / P.n_layers) * kXcds + x;
+    return bi < P.nb ? bi : -1;
+}
+
+// SHARED: the workgroups of several layers read the same block's codes, so
+// they are kept in L2; otherwise they stream past it.
+template <bool SHARED>
+__device__ __forceinline__ unsigned long long su_ld4(const uint16_t *p) {
+    if (SHARED) return *reinterpret_cast<const unsigned long long *>(p);
+    return __builtin_nontemporal_load(reinterpret_cast<const unsigned long long *>(p));
+}
+
+template <bool SHARED>
 __global__ __launch_bounds__(kSuThreads) void k_su_fwd(SuParams P) {
-    __shared__ uint32_t filt[kFilterWords];
+    __shared__ uint2 tbr[kSrWords / 2];                  // the range's bitmap words with super-range ranks
+    __shared__ double acc[kMaxTrialsPerBlock + 1];       // per-trial totals (one slot past the trials)
+    __shared__ uint32_t offl[kMaxTrialsPerBlock];        // each trial's first occurrence less the block's
+    __shared__ uint32_t q_e[kGroups][kSuQCap];           // queued occurrence: its event's union index
+    __shared__ uint32_t q_s[kGroups][kSuQCap];           //   its trial in the block << 16 | position in the trial
     __shared__ double ls[kSuMaxJ], lr[kSuMaxJ], ll[kSuMaxJ];
-    __shared__ int32_t q_d[kSuThreads / kWave][kSuQueue];     // occurrence's offset in the trial
-    __shared__ uint32_t q_e[kSuThreads / kWave][kSuQueue];    // its event's union rank = its first entry
-    __shared__ uint32_t ub_s[kSuMaxSr + 1];                   // the layer's union-rank bases
-    const int j = blockIdx.y, tid = threadIdx.x, lane = tid & 63;
+    int j = 0;
+    const int bi = su_item(P, blockIdx.x, j);
+    if (bi < 0) return;   // uniform over the workgroup, before any barrier
     // a layer whose entries did not fit its capacity has none laid out (the
     // call reports ARA_E_LIMIT): nothing of it is read or written
     const uint64_t cap = P.ecap[j];
     if (P.eused[j] > cap) return;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int tb = P.tb, G = P.n_ranges;
+    const int64_t b = static_cast<int64_t>(P.b0) + bi;
+    const int64_t bt0 = b * tb;                                            // the block's first trial
+    const int nbt = static_cast<int>(min<int64_t>(tb, P.n_trials - bt0));  // and its trials
+    const int64_t gt0 = bt0 + static_cast<int64_t>(w) * P.tg;
+    const int64_t gt1 = min(gt0 + P.tg, P.n_trials);
+    const bool active = gt0 < gt1 && gt1 > P.t0 && gt0 < P.t1;            // uniform
+    const size_t seg0 = static_cast<size_t>(b) * G * kGroups + w;
+    const int64_t occ0 = P.t_off[bt0];
+    for (int i = tid; i <= tb; i += kSuThreads) acc[i] = 0.0;
+    for (int i = tid; i < nbt; i += kSuThreads) offl[i] = static_cast<uint32_t>(P.t_off[bt0 + i] - occ0);
     const int a0 = P.elt_off[j], J = P.elt_off[j + 1] - a0;
-    for (int q = tid; q < J; q += blockDim.x) {
+    for (int q = tid; q < J; q += kSuThreads) {
         const int k = P.elt_ids[a0 + q];
         ls[q] = P.elt_terms[3 * k + 0];
         lr[q] = P.elt_terms[3 * k + 1];
         ll[q] = P.elt_terms[3 * k + 2];
     }
-    for (int i = tid; i < kFilterWords; i += blockDim.x) filt[i] = P.filter[static_cast<size_t>(j) * kFilterWords + i];
-    for (int i = tid; i <= P.n_sr; i += blockDim.x) ub_s[i] = P.ubase[static_cast<size_t>(j) * (P.n_sr + 1) + i];
-    __syncthreads();
-    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
-    int32_t *qd = q_d[wv];
-    uint32_t *qe = q_e[wv];
-    const int64_t nw = static_cast<int64_t>(gridDim.x) * (kSuThreads / kWave);
     const OccTables T = P.tabs[j];
+    const uint32_t *ub = P.ubase + static_cast<size_t>(j) * (P.n_sr + 1);
     const SuEntry *E = P.ent + P.eregion[j];
     const double occR = P.layer_terms[4 * j + 0], occL = P.layer_terms[4 * j + 1];
     const double aggR = P.layer_terms[4 * j + 2], aggL = P.layer_terms[4 * j + 3];
-    const int64_t n = P.t1 - P.t0;
+    // thread tid's bitmap word of range r (range r is half r & 1 of super-range r >> 1)
+    auto slice_word = [&](int r) { return T.br[static_cast<size_t>(r >> 1) * kSrWords + (r & 1) * (kSrWords / 2) + tid]; };
+    tbr[tid] = slice_word(0);
+    __syncthreads();
 
-    for (int64_t t = P.t0 + static_cast<int64_t>(blockIdx.x) * (kSuThreads / kWave) + wv; t < P.t1; t += nw) {
-        int64_t a = P.off[t], b = P.off[t + 1];
-        if (a < P.occ_begin || b > P.occ_begin + P.occ_count || b < a) {
-            if (lane == 0) atomicCAS(P.err, 0, ARA_E_RANGE);
-            b = a;
+    uint32_t *qe = q_e[w];
+    uint32_t *qs = q_s[w];
+    int qh = 0, qlen = 0;   // uniform: the queue's head slot and length
+    auto wrap = [](int x) { return x >= kSuQCap ? x - kSuQCap : x; };   // x < 2 kSuQCap
+    // A lane whose occurrence is held by further ELTs keeps it and draws one
+    // further ELT per round, so that no round waits on a few lanes.
+    bool pend = false;
+    uint32_t pe = 0;    // its next entry
+    int pleft = 0;      // entries still to draw, pe included
+    int64_t pi = 0;     // its index in the trial-major YET
+    int ps = 0;         // its trial in the block
+    double px = 0.0;    // its ELTs' losses so far, summed in listed order
+    // one draw per lane: the held occurrences' next ELTs, and the queue's
+    // first entries for the other lanes in lane order
+    auto round = [&]() {
+        const uint64_t freem = __ballot(!pend);
+        const int rank = static_cast<int>(__builtin_amdgcn_mbcnt_hi(
+            static_cast<uint32_t>(freem >> 32), __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(freem), 0u)));
+        const int taken = min(qlen, static_cast<int>(__popcll(freem)));   // uniform
+        const bool first = !pend;
+        bool act = pend;
+        uint32_t ei = pe;
+        int64_t i = pi;
+        int slot = ps;
+        if (first && rank < taken) {
+            const int at = wrap(qh + rank);
+            ei = qe[at];
+            const uint32_t sv = qs[at];
+            slot = static_cast<int>(sv >> 16);
+            i = occ0 + static_cast<int64_t>(offl[slot]) + static_cast<int64_t>(sv & 0xFFFFu);
+            act = ei < cap;   // union indexes lie below the entries used, checked above
         }
-        double acc = 0.0;   // losses of the occurrences this lane finished
-        int qlen = 0;       // uniform
-        // A lane whose occurrence is held by further ELTs keeps it and draws
-        // one further ELT per round, so that no round waits on a few lanes.
-        bool pend = false;
-        uint32_t pe = 0;    // its next entry
-        int pleft = 0;      // entries still to draw, pe included
-        int64_t pi = 0;     // its index in the YET
-        double px = 0.0;    // its ELTs' losses so far, summed in listed order
-        // one draw per lane: the held occurrences' next ELTs, and the queue's
-        // first entries for the other lanes in lane order (at most `avail`);
-        // steps one to three.  Returns the number of queue entries taken.
-        auto draw_round = [&](int avail) {
-            const uint64_t freem = __ballot(!pend);
-            const int rank = static_cast<int>(__builtin_amdgcn_mbcnt_hi(
-                static_cast<uint32_t>(freem >> 32), __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(freem), 0u)));
-            const int taken = min(avail, static_cast<int>(__popcll(freem)));   // uniform
-            const bool first = !pend;
-            bool act = pend;
-            uint32_t ei = pe;
-            int64_t i = pi;
-            if (first && rank < taken && qe[rank] < cap) {
-                act = true;
-                ei = qe[rank];
-                i = a + qd[rank];
+        if (act) {
+            const SuEntry en = E[ei];
+            const double v = su_draw(en, P.seed, i);
+            const double g = xl(ls[en.q] * v, lr[en.q], ll[en.q]);
+            if (first) {
+                px = g;
+                pi = i;
+                ps = slot;
+                pe = en.next;
+                pleft = static_cast<uint64_t>(en.next) + en.more <= cap ? en.more : 0;
+            } else {
+                px = px + g;
+                ++pe;
+                --pleft;
             }
-            if (act) {
-                const SuEntry en = E[ei];
-                const double v = su_draw(en, P.seed, i);
-                const double g = xl(ls[en.q] * v, lr[en.q], ll[en.q]);
-                if (first) {
-                    px = g;
-                    pi = i;
-                    pe = en.next;
-                    pleft = static_cast<uint64_t>(en.next) + en.more <= cap ? en.more : 0;
-                } else {
-                    px = px + g;
-                    ++pe;
-                    --pleft;
+            pend = pleft > 0;
+            if (!pend) atomicAdd(&acc[ps], xl(px, occR, occL));
+        }
+        qh = wrap(qh + taken);
+        qlen -= taken;
+    };
+
+    // ranges 0 .. G-1, then a last pass (r = G) that draws what is left; the
+    // decode and the draw rounds each have one place in the code
+    for (int r = 0; r <= G; ++r) {
+        const bool flush = r == G;   // uniform
+        uint2 nxt = make_uint2(0u, 0u);
+        if (r + 1 < G) nxt = slice_word(r + 1);
+        int R = 0;                   // uniform: this wavefront's codes per lane in range r
+        int slot = 0;                // the lane's trial in the block
+        const uint16_t *cp = nullptr, *pp = nullptr;
+        unsigned long long X = 0, Y = 0;
+        uint32_t ubr = 0;            // union index of the super-range's rank 0
+        if (active && !flush) {
+            const size_t si = seg0 + static_cast<size_t>(r) * kGroups;
+            R = __builtin_amdgcn_readfirstlane(P.seg_run[si]);
+            if (R > 0) {
+                ubr = __builtin_amdgcn_readfirstlane(ub[r >> 1]);
+                const int64_t sb = P.seg_base[si];
+                slot = w * P.tg + static_cast<int>(P.lane_start[si * kWave + lane]);
+                cp = P.code + sb + 4 * lane;
+                pp = P.pos + sb + 4 * lane;
+                X = su_ld4<SHARED>(cp);
+                Y = su_ld4<SHARED>(pp);
+            }
+        }
+        for (int step = 0; step < R || flush; step += kSuChunk) {
+            if (!flush) {
+                const unsigned long long cx = X, cy = Y;
+                if (step + kSuChunk < R) {   // uniform; the next step's codes while this one is decoded
+                    cp += kSuChunk * kWave;
+                    pp += kSuChunk * kWave;
+                    X = su_ld4<SHARED>(cp);
+                    Y = su_ld4<SHARED>(pp);
                 }
-                pend = pleft > 0;
-                if (!pend) acc += xl(px, occR, occL);
-            }
-            return taken;
-        };
-        // drop the first `taken` queue entries (the queue holds at most 127)
-        auto shift = [&](int taken) {
-            const int rest = qlen - taken;   // uniform
-            int32_t d0 = 0, d1 = 0;
-            uint32_t e0 = 0, e1 = 0;
-            if (lane < rest) {
-                d0 = qd[taken + lane];
-                e0 = qe[taken + lane];
-            }
-            if (lane + kWave < rest) {
-                d1 = qd[taken + kWave + lane];
-                e1 = qe[taken + kWave + lane];
-            }
-            __builtin_amdgcn_wave_barrier();
-            if (lane < rest) {
-                qd[lane] = d0;
-                qe[lane] = e0;
-            }
-            if (lane + kWave < rest) {
-                qd[kWave + lane] = d1;
-                qe[kWave + lane] = e1;
-            }
-            __builtin_amdgcn_wave_barrier();
-            qlen = rest;
-        };
-        for (int64_t base = a; base < b; base += kSuSlices * kWave) {
-            // the step's IDs, then the bitmap words of its maybe-set events
-            // and then the counts and first entries of its set events, each
-            // round trip shared by all the step's slices
-            int32_t ev[kSuSlices];
-            bool in[kSuSlices];
+                bool on[kSuChunk];
+                uint32_t eu[kSuChunk], sv[kSuChunk];
 #pragma unroll
-            for (int k = 0; k < kSuSlices; ++k) {
-                const int64_t i = base + k * kWave + lane;
-                in[k] = i < b;
-                ev[k] = in[k] ? P.ids[i] : 0;
-            }
-            uint2 w[kSuSlices];
-#pragma unroll
-            for (int k = 0; k < kSuSlices; ++k) {
-                const int32_t e = ev[k];
-                if (in[k] && (e < 0 || e >= P.catalog)) {
-                    atomicCAS(P.err, 0, ARA_E_RANGE);
-                    in[k] = false;
+                for (int u = 0; u < kSuChunk; ++u) {
+                    const uint32_t c = static_cast<uint32_t>(cx >> (16 * u)) & 0xFFFFu;
+                    slot += static_cast<int>(c >> 15);   // advance before the code
+                    const uint2 q = tbr[(c >> 5) & 1023u];
+                    const uint32_t bit = c & 31u;
+                    on[u] = ((q.x >> bit) & 1u) != 0u && c != 0xFFFFu;
+                    eu[u] = ubr + q.y + __popc(q.x & ((1u << bit) - 1u));
+                    sv[u] = (static_cast<uint32_t>(slot) << 16) | (static_cast<uint32_t>(cy >> (16 * u)) & 0xFFFFu);
                 }
-                const bool maybe = in[k] && ((filt[(static_cast<uint32_t>(e) >> 5) & (kFilterWords - 1)] >> (e & 31)) & 1u);
-                w[k] = make_uint2(0u, 0u);
-                if (maybe) w[k] = T.br[static_cast<uint32_t>(e) >> 5];
-            }
-            uint32_t gr[kSuSlices];   // union rank (first entry) of each set event
-            bool u[kSuSlices];
+                // append the step's union occurrences, code by code in lane order
 #pragma unroll
-            for (int k = 0; k < kSuSlices; ++k) {
-                const uint32_t e = static_cast<uint32_t>(ev[k]), bit = e & 31;
-                u[k] = ((w[k].x >> bit) & 1u) != 0u;   // only for a valid ID (w is 0 otherwise)
-                gr[k] = u[k] ? ub_s[e >> kSrBits] + w[k].y + __popc(w[k].x & ((1u << bit) - 1u)) : 0u;
-            }
-#pragma unroll
-            for (int k = 0; k < kSuSlices; ++k) {
-                // append this slice's union occurrences, in slice order
-                const uint64_t m = __ballot(u[k]);
-                if (u[k]) {
-                    const int pos = qlen + static_cast<int>(__builtin_amdgcn_mbcnt_hi(
-                                               static_cast<uint32_t>(m >> 32),
-                                               __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(m), 0u)));
-                    qd[pos] = static_cast<int32_t>(base - a) + k * kWave + lane;
-                    qe[pos] = gr[k];
+                for (int u = 0; u < kSuChunk; ++u) {
+                    const uint64_t m = __ballot(on[u]);
+                    if (on[u]) {
+                        const int at = wrap(qh + qlen + static_cast<int>(__builtin_amdgcn_mbcnt_hi(
+                                                              static_cast<uint32_t>(m >> 32),
+                                                              __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(m), 0u))));
+                        qe[at] = eu[u];
+                        qs[at] = sv[u];
+                    }
+                    qlen += static_cast<int>(__popcll(m));
                 }
-                qlen += __popcll(m);
                 __builtin_amdgcn_wave_barrier();
-                // every round draws on every lane that has work; a round that
-                // takes no entry still moves the held occurrences on
-                while (qlen >= kWave) shift(draw_round(qlen));
             }
+            while (qlen >= kWave || (flush && (qlen > 0 || __ballot(pend) != 0ull))) round();
+            if (flush) break;
         }
-        while (qlen > 0 || __ballot(pend) != 0ull) shift(draw_round(qlen));
-        // step four, telescoped: the aggregate terms on the trial's total
-        const double S = lane63(wave_inclusive_sum(acc));
-        if (lane == 0) {
+        if (!flush) {
+            __syncthreads();   // every wavefront is done with range r's words
+            tbr[tid] = nxt;
+            __syncthreads();
+        }
+    }
+    if (active) {
+        const int64_t lo = max(gt0, P.t0), hi = min(gt1, P.t1);
+        const size_t n = static_cast<size_t>(P.t1 - P.t0);
+        for (int64_t t = lo + lane; t < hi; t += kWave) {
+            const double S = acc[t - bt0];
             const size_t o = static_cast<size_t>(j) * n + static_cast<size_t>(t - P.t0);
             P.ylt[o] = xl(S, aggR, aggL);
             if (P.s_pre) P.s_pre[o] = S;
         }
-        __builtin_amdgcn_wave_barrier();
     }
 }
 
@@ -503,7 +552,6 @@ static size_t su_workspace(const ara_tables *tables, const ara_layers *layers, c
     b += align256(static_cast<size_t>(std::max(L, 1)) * n_sr * sizeof(uint32_t));     // otot
     b += align256(static_cast<size_t>(std::max(L, 1)) * (n_sr + 1) * sizeof(uint32_t));   // ubase
     b += align256(static_cast<size_t>(std::max(L, 1)) * n_sr * sizeof(uint32_t));     // obase
-    b += align256(static_cast<size_t>(std::max(L, 1)) * kFilterWords * sizeof(uint32_t));
     b += align256(static_cast<size_t>(std::max<uint64_t>(S.n_ent, 1)) * sizeof(SuEntry));
     return b;
 }
@@ -561,23 +609,23 @@ extern "C" int32_t ara_su_workspace_bytes(const ara_tables *tables, const ara_la
     return ARA_OK;
 }
 
-extern "C" int32_t ara_ylt_forward_su(const ara_tables *tables, const float *sigma, const int64_t *offsets,
-                                      const int32_t *ids, int64_t n_trials, const ara_layers *layers,
-                                      const int64_t *elt_records, const double *elt_terms,
+extern "C" int32_t ara_ylt_forward_su(const ara_tables *tables, const float *sigma, const ara_yet *yet,
+                                      const ara_layers *layers, const int64_t *elt_records, const double *elt_terms,
                                       const double *layer_terms, uint64_t seed, int64_t trial_begin,
-                                      int64_t trial_end, int64_t occ_begin, int64_t occ_count, double *ylt,
-                                      double *s_pre, void *ws, size_t ws_bytes, void *stream) {
-    if (!tables || !elt_records) return fail(ARA_E_INVAL, "null tables or record counts");
+                                      int64_t trial_end, double *ylt, double *s_pre, void *ws, size_t ws_bytes,
+                                      void *stream) {
+    if (!tables || !yet || !elt_records) return fail(ARA_E_INVAL, "null tables, YET or record counts");
+    if (tables->catalog != yet->catalog) return fail(ARA_E_INVAL, "tables and YET use different catalogues");
+    if (yet->range_bits != kRangeBits || yet->groups != kGroups) return fail(ARA_E_INVAL, "YET not prepared by this library");
+    if (!yet->pos || !yet->t_off) return fail(ARA_E_INVAL, "YET prepared without ARA_PREP_POSITIONS");
     int32_t rc = check_layers(layers, tables->n_elts);
     if (rc) return rc;
-    if (trial_begin < 0 || trial_end < trial_begin || trial_end > n_trials)
+    if (trial_begin < 0 || trial_end < trial_begin || trial_end > yet->n_trials)
         return fail(ARA_E_RANGE, "trial range outside the YET");
-    if (occ_begin < 0 || occ_count < 0) return fail(ARA_E_RANGE, "negative occurrence range");
     if (!ws) return fail(ARA_E_INVAL, "null workspace");
     const int L = layers->n_layers;
     const int64_t n = trial_end - trial_begin;
-    if (L > 0 && n > 0 && (!offsets || !sigma || !elt_terms || !layer_terms || !ylt || (occ_count > 0 && !ids)))
-        return fail(ARA_E_INVAL, "null input or output");
+    if (L > 0 && n > 0 && (!sigma || !elt_terms || !layer_terms || !ylt)) return fail(ARA_E_INVAL, "null input or output");
     SuLayout S;
     if ((rc = su_layout(tables, layers, elt_records, S))) return rc;
     if (ws_bytes < su_workspace(tables, layers, S)) return fail(ARA_E_NOSPACE, "workspace too small");
@@ -602,7 +650,6 @@ extern "C" int32_t ara_ylt_forward_su(const ara_tables *tables, const float *sig
     uint32_t *otot = c.take<uint32_t>(static_cast<size_t>(L) * n_sr);
     uint32_t *ubase = c.take<uint32_t>(static_cast<size_t>(L) * (n_sr + 1));
     uint32_t *obase = c.take<uint32_t>(static_cast<size_t>(L) * n_sr);
-    uint32_t *filter = c.take<uint32_t>(static_cast<size_t>(L) * kFilterWords);
     SuEntry *ent = c.take<SuEntry>(static_cast<size_t>(std::max<uint64_t>(S.n_ent, 1)));
     HeadImage img(ws);
     img.cover(d_err + kWsHeaderBytes / sizeof(int32_t));
@@ -625,19 +672,30 @@ extern "C" int32_t ara_ylt_forward_su(const ara_tables *tables, const float *sig
             tables->loss, sigma, tables->present, tables->catalog, tables->words, d_off, d_ids, d_tabs, n_sr, ooff,
             ubase, obase, d_cap, d_region, ent);
         ARA_HIP(hipGetLastError());
-        if ((rc = launch_set_filter(d_tabs, n_sr * kSrWords, filter, L, st))) return rc;
     }
+    const int tb = yet->trials_per_block;
+    if (tb < 1 || tb > kMaxTrialsPerBlock || yet->trials_per_group * kGroups != tb)
+        return fail(ARA_E_INVAL, "YET not prepared by this library");
+    const int b0 = static_cast<int>(trial_begin / tb);
+    const int b1 = static_cast<int>((trial_end + tb - 1) / tb);
     SuParams P{};
-    P.off = offsets;
-    P.ids = ids;
-    P.catalog = tables->catalog;
+    P.code = yet->code;
+    P.pos = yet->pos;
+    P.seg_base = yet->seg_base;
+    P.seg_run = yet->seg_run;
+    P.lane_start = yet->lane_start;
+    P.t_off = yet->t_off;
+    P.n_trials = yet->n_trials;
+    P.tg = yet->trials_per_group;
+    P.tb = tb;
+    P.n_ranges = yet->n_ranges;
     P.n_sr = n_sr;
+    P.b0 = b0;
+    P.nb = b1 - b0;
+    P.n_layers = L;
     P.t0 = trial_begin;
     P.t1 = trial_end;
-    P.occ_begin = occ_begin;
-    P.occ_count = occ_count;
     P.tabs = d_tabs;
-    P.filter = filter;
     P.ubase = ubase;
     P.eregion = d_region;
     P.ecap = d_cap;
@@ -650,12 +708,13 @@ extern "C" int32_t ara_ylt_forward_su(const ara_tables *tables, const float *sig
     P.seed = seed;
     P.ylt = ylt;
     P.s_pre = s_pre;
-    P.err = d_err;
-    const int waves_per_wg = kSuThreads / kWave;
-    const int64_t want = (n + waves_per_wg - 1) / waves_per_wg;
-    const unsigned gx = static_cast<unsigned>(std::max<int64_t>(1, std::min<int64_t>(want, device_cu_count())));
+    const int64_t groups = L == 1 ? P.nb : static_cast<int64_t>(kXcds) * ((P.nb + kXcds - 1) / kXcds) * L;
+    if (groups > 0x7FFFFFFF) return fail(ARA_E_LIMIT, "too many workgroups");
     ProfScope prof(ARA_PROF_SU, st);
-    k_su_fwd<<<dim3(gx, static_cast<unsigned>(L)), kSuThreads, 0, st>>>(P);
+    if (L == 1)
+        k_su_fwd<false><<<static_cast<unsigned>(groups), kSuThreads, 0, st>>>(P);
+    else
+        k_su_fwd<true><<<static_cast<unsigned>(groups), kSuThreads, 0, st>>>(P);
     ARA_HIP(hipGetLastError());
     return ARA_OK;
 }

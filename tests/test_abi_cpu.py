@@ -41,7 +41,7 @@ def test_status_strings(ara):
     assert lib.ara_status_string(0) == b"ok"
     assert b"duplicate" in lib.ara_status_string(3)
     assert lib.ara_status_string(99) == b"unknown status"
-    assert lib.ara_abi_version() == 1
+    assert lib.ara_abi_version() == 2
 
 
 def test_profile_controls(ara):
@@ -74,7 +74,10 @@ def test_size_queries(ara):
     assert lib.ara_yet_prepare_bytes(1000, 1_000_000, 200_000, ara.PREP_TRANSPOSED | ara.PREP_TRIAL_MAJOR,
                                      ctypes.byref(nb)) == 0
     assert nb.value >= tr + 4 * 1_000_000 + 8 * 1001
-    assert lib.ara_yet_prepare_bytes(1000, 1_000_000, 200_000, 4, ctypes.byref(nb)) == 1   # unknown flag
+    # positions add one 16-bit word per code slot and a copy of the offsets
+    assert lib.ara_yet_prepare_bytes(1000, 1_000_000, 200_000, ara.PREP_POSITIONS, ctypes.byref(nb)) == 0
+    assert nb.value >= plain + 2 * 1_000_000 + 8 * 1001
+    assert lib.ara_yet_prepare_bytes(1000, 1_000_000, 200_000, 8, ctypes.byref(nb)) == 1   # unknown flag
     assert lib.ara_build_elt_tables_bytes(15, 2_000_000, ctypes.byref(nb)) == 0
     assert nb.value >= 15 * 2_000_000 * 4
     assert lib.ara_metrics_workspace_bytes(2, 1000, ctypes.byref(nb)) == 0
@@ -174,20 +177,27 @@ def test_secondary_uncertainty_queries_and_validation(ara):
     assert lib.ara_su_workspace_bytes(ctypes.byref(tables), ctypes.byref(lay.handle),
                                       bad.ctypes.data_as(ctypes.c_void_p), ctypes.byref(nb)) == 1
     assert lib.ara_su_workspace_bytes(ctypes.byref(tables), ctypes.byref(lay.handle), None, ctypes.byref(nb)) == 1
+    # a YET handle as ara_yet_prepare fills it (host-only stand-in: no device work happens below)
+    fake = ctypes.c_void_p(256)
+    yet = ara.ara_yet(n_trials=10, nnz=100, catalog=200_000, range_bits=15, n_ranges=7, groups=16,
+                      trials_per_group=1, trials_per_block=16, n_blocks=1, code=fake, pos=fake, t_off=fake)
+    recp = rec.ctypes.data_as(ctypes.c_void_p)
+
+    def su(yet_, t0, t1, ws, nbytes, records=recp, ptr=None):
+        return lib.ara_ylt_forward_su(ctypes.byref(tables), ptr, ctypes.byref(yet_), ctypes.byref(lay.handle), records,
+                                      ptr, ptr, 7, t0, t1, ptr, None, ws, nbytes, None)
     # trial range outside the YET, null workspace, null records: all before any device work
-    assert lib.ara_ylt_forward_su(ctypes.byref(tables), None, None, None, 10, ctypes.byref(lay.handle),
-                                  rec.ctypes.data_as(ctypes.c_void_p), None, None, 7, 0, 11, 0, 0, None, None,
-                                  ctypes.c_void_p(256), 1 << 30, None) == 2
-    assert lib.ara_ylt_forward_su(ctypes.byref(tables), None, None, None, 10, ctypes.byref(lay.handle),
-                                  rec.ctypes.data_as(ctypes.c_void_p), None, None, 7, 0, 10, 0, 0, None, None,
-                                  None, 1 << 30, None) == 1
-    assert lib.ara_ylt_forward_su(ctypes.byref(tables), None, None, None, 10, ctypes.byref(lay.handle), None, None,
-                                  None, 7, 0, 10, 0, 0, None, None, ctypes.c_void_p(256), 1 << 30, None) == 1
+    assert su(yet, 0, 11, fake, 1 << 30) == 2
+    assert su(yet, 0, 10, None, 1 << 30) == 1
+    assert su(yet, 0, 10, fake, 1 << 30, records=None) == 1
     # a workspace smaller than the query
-    assert lib.ara_ylt_forward_su(ctypes.byref(tables), ctypes.c_void_p(256), ctypes.c_void_p(256), ctypes.c_void_p(256),
-                                  10, ctypes.byref(lay.handle), rec.ctypes.data_as(ctypes.c_void_p),
-                                  ctypes.c_void_p(256), ctypes.c_void_p(256), 7, 0, 10, 0, 100,
-                                  ctypes.c_void_p(256), None, ctypes.c_void_p(256), 4096, None) == 4
+    assert su(yet, 0, 10, fake, 4096, ptr=fake) == 4
+    # a YET prepared without positions, or over another catalogue
+    nopos = ara.ara_yet(n_trials=10, nnz=100, catalog=200_000, range_bits=15, n_ranges=7, groups=16, code=fake)
+    assert su(nopos, 0, 10, fake, 1 << 30, ptr=fake) == 1
+    other = ara.ara_yet(n_trials=10, nnz=100, catalog=100_000, range_bits=15, n_ranges=4, groups=16, code=fake,
+                        pos=fake, t_off=fake)
+    assert su(other, 0, 10, fake, 1 << 30, ptr=fake) == 1
     assert lib.ara_build_elt_sigma(ctypes.byref(tables), None, None, None, None, None) == 1
 
 

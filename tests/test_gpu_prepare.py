@@ -53,7 +53,8 @@ def expected(yet_np, slice_trials, n_slices):
 def check_codes(py, yet_np):
     """Decode every segment of the 16-bit code stream on the host and compare
     it with the raw trials: same (trial, offset) sequence, in trial order and
-    storage order inside a trial."""
+    storage order inside a trial; with positions, each occurrence's position
+    in its trial beside its code and 0xFFFF beside the other codes."""
     import torch
     h = py.handle
     G, groups, tg, tb = h.n_ranges, h.groups, h.trials_per_group, h.trials_per_block
@@ -68,6 +69,8 @@ def check_codes(py, yet_np):
     key = ((t // tb) * G + (ids >> 15)) * groups + (t % tb) // tg
     order = np.argsort(key, kind="stable")
     key_s, trial_s, local_s = key[order], (t % tb % tg)[order], (ids & 0x7FFF)[order]
+    pos_s = (np.arange(yet_np.nnz, dtype=np.int64) - yet_np.offsets[t])[order]
+    pos = read_dev(py, h.pos, max(h.n_codes, 1), torch.int16).view(np.uint16).astype(np.int64) if h.pos else None
     bounds = np.searchsorted(key_s, np.arange(nseg + 1))
     lanes = np.arange(64)
     for si in range(nseg):
@@ -85,13 +88,17 @@ def check_codes(py, yet_np):
         got_t, got_l = tr[valid], (c & 0x7FFF)[valid]      # row-major: lane by lane, in order
         assert np.array_equal(got_t, trial_s[a:b]), f"segment {si}: trials differ"
         assert np.array_equal(got_l, local_s[a:b]), f"segment {si}: offsets differ"
+        if pos is not None:
+            p = pos[slot]
+            assert np.array_equal(p[valid], pos_s[a:b]), f"segment {si}: positions differ"
+            assert np.all(p[~valid] == 0xFFFF), f"segment {si}: a gap or padding code has a position"
     assert h.n_codes >= yet_np.nnz
 
 
 def check(ara, yet_np):
     import torch
     _say(f"trials {yet_np.n_trials} nnz {yet_np.nnz} catalog {yet_np.catalog}")
-    py = ara.PreparedYet.from_numpy(yet_np, "cuda")
+    py = ara.PreparedYet.from_numpy(yet_np, "cuda", positions=True)
     h = py.handle
     torch.cuda.synchronize()
     check_codes(py, yet_np)

@@ -1,11 +1,13 @@
 """Secondary uncertainty on the GPU (ara_ylt_forward_su) against the oracle:
 every trial at small sizes, sampled trial ranges at 1M x 1000, sigma = 0
-against the deterministic path, determinism, subranges and errors.
+against the deterministic path, determinism, subranges, layers alone and
+together, and errors.
 
 Tolerance: the draws use the device's binary64 log, cos and exp (within an
-ulp or two of the host's), and a trial's occurrence losses are summed in
-wavefront order, so YLT and S agree with the oracle to 1e-9 of the trial's
-total before aggregate terms."""
+ulp or two of the host's), and a trial's occurrence losses are summed in the
+order of the prepared layout (by catalogue range), not in storage order, so
+YLT and S agree with the oracle to 1e-9 of the trial's total before
+aggregate terms."""
 import sys
 
 import numpy as np
@@ -39,14 +41,13 @@ class Su:
         self.tables = ara.EltTables.from_numpy(w.elts)
         self.sigma = ara.SigmaTables.from_numpy(self.tables, rec_sigma)
         self.layers = ara.Layers(w.layers.elt_off, w.layers.elt_ids)
-        self.off = torch.from_numpy(np.ascontiguousarray(w.yet.offsets, np.int64)).cuda()
-        self.ids = torch.from_numpy(np.ascontiguousarray(w.yet.ids, np.int32)).cuda()
+        self.yet = ara.PreparedYet.from_numpy(w.yet, transposed=False, positions=True)
         self.et = torch.tensor(w.elts.terms, dtype=torch.float64, device="cuda")
         self.lt = torch.tensor(w.layers.terms, dtype=torch.float64, device="cuda")
 
-    def run(self, seed, t0=0, t1=None):
-        y, s = self.ara.ylt_forward_su(self.tables, self.sigma, self.off, self.ids, self.layers, self.et, self.lt,
-                                       seed, t0, t1, check=True)
+    def run(self, seed, t0=0, t1=None, layers=None, lt=None):
+        y, s = self.ara.ylt_forward_su(self.tables, self.sigma, self.yet, layers or self.layers, self.et,
+                                       self.lt if lt is None else lt, seed, t0, t1, check=True)
         return y.cpu().numpy(), s.cpu().numpy()
 
 
@@ -118,6 +119,42 @@ def test_run_twice_subranges_and_seeds(ara):
     assert np.mean(s3 != s1) > 0.9
 
 
+def test_layers_alone_and_together(ara):
+    """Each layer run alone gives, bit for bit, its row of the call over all
+    layers (the layers of one block run back to back and share its codes)."""
+    import torch
+    _say("workload 2 prefix: four layers together and one at a time")
+    w = synth.config(2, n_trials=3000)
+    sg = synth.record_sigmas(11, w.elts)
+    e = Su(ara, w, sg)
+    y, s = e.run(3)
+    off, ids = w.layers.elt_off, w.layers.elt_ids
+    for j in range(w.layers.n_layers):
+        lay = ara.Layers(np.array([0, off[j + 1] - off[j]], np.int32), ids[off[j]:off[j + 1]])
+        lt = torch.tensor(np.asarray(w.layers.terms)[j:j + 1], dtype=torch.float64, device="cuda")
+        yj, sj = e.run(3, layers=lay, lt=lt)
+        assert np.array_equal(yj[0], y[j]) and np.array_equal(sj[0], s[j]), j
+
+
+def test_long_trials_and_ragged_blocks(ara):
+    """Trials of up to 20,000 occurrences (positions past 2^14), empty trials,
+    and a trial count that leaves the last block and group ragged."""
+    _say("long and empty trials against the oracle")
+    rng = np.random.default_rng(130825)
+    w = synth.config(0, n_trials=700)
+    lens = rng.integers(0, 3000, size=700)
+    lens[::97] = 0
+    lens[5] = 20_000
+    lens[400] = 12_345
+    off = np.zeros(701, np.int64)
+    off[1:] = np.cumsum(lens)
+    ids = rng.integers(0, w.yet.catalog, size=int(off[-1])).astype(np.int32)
+    w = synth.Workload("long trials", synth.Yet(w.yet.catalog, off, ids), w.elts, w.layers, w.p)
+    sg = synth.record_sigmas(5, w.elts)
+    y, s = Su(ara, w, sg).run(77)
+    assert_close(y, s, oracle_su(w, sg, 77, threads=oracle.num_threads_available()))
+
+
 def test_config1_full_size_sampled(ara):
     """1M x 1000 x 15 with deviations; the oracle on three trial ranges."""
     _say("workload 1: generating 1M x 1000")
@@ -147,12 +184,19 @@ def test_errors(ara):
         e.run(1)
     assert ex.value.status == 6
     e.tables.records[:] = saved
-    # an event ID outside the catalogue
-    ids = e.ids.clone()
-    ids[3] = w.yet.catalog + 5
+    # a YET prepared without positions
+    plain = ara.PreparedYet.from_numpy(w.yet, transposed=False)
     with pytest.raises(ara.AraError) as ex:
-        ara.ylt_forward_su(e.tables, e.sigma, e.off, ids, e.layers, e.et, e.lt, 1, check=True)
-    assert ex.value.status == 2
+        ara.ylt_forward_su(e.tables, e.sigma, plain, e.layers, e.et, e.lt, 1)
+    assert ex.value.status == 1
+    # a trial of more than 65536 occurrences cannot carry positions
+    off = torch.tensor([0, 70_000], dtype=torch.int64, device="cuda")
+    ids = torch.zeros(70_000, dtype=torch.int32, device="cuda")
+    with pytest.raises(ara.AraError) as ex:
+        ara.PreparedYet(off, ids, w.yet.catalog, transposed=False, positions=True)
+    assert ex.value.status == 6
+    ok = torch.tensor([0, 65_536], dtype=torch.int64, device="cuda")   # the longest trial that fits
+    ara.PreparedYet(ok, ids[:65_536], w.yet.catalog, transposed=False, positions=True)
     # a negative standard deviation
     bad = sg.copy()
     bad[0] = -1.0
@@ -160,6 +204,6 @@ def test_errors(ara):
         ara.SigmaTables.from_numpy(e.tables, bad)
     assert ex.value.status == 1
     # empty trial range
-    y, s = ara.ylt_forward_su(e.tables, e.sigma, e.off, e.ids, e.layers, e.et, e.lt, 1, 5, 5)
+    y, s = ara.ylt_forward_su(e.tables, e.sigma, e.yet, e.layers, e.et, e.lt, 1, 5, 5)
     assert y.shape == (1, 0)
     torch.cuda.synchronize()
