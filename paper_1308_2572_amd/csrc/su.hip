@@ -19,11 +19,14 @@
 // The draw: Philox4x32-10 (Salmon, Moraes, Dror and Shaw, SC'11) block of
 // counter words (occurrence low, high, ELT index, 0) under key words (seed
 // low, high); two uniforms from the top 52 bits of the word pairs (w1 w0)
-// and (w3 w2), Box-Muller, x = exp(m + s z).
+// and (w3 w2), Box-Muller, x = exp(m + s z), with the logarithm, cosine and
+// exponential of su_math.h.
 #include "occ.h"
+#include "su_math.h"
 #include "wave.h"
 
 #include <algorithm>
+#include <cstddef>
 #include <vector>
 
 namespace ara {
@@ -44,7 +47,9 @@ struct SuEntry {
     uint8_t exact;     // sigma = 0: the draw is mu itself
     uint8_t more;      // number of further entries (first entry only)
 };
-static_assert(sizeof(SuEntry) == 32, "entry layout");
+static_assert(sizeof(SuEntry) == 32 && offsetof(SuEntry, mu) == 16 && offsetof(SuEntry, next) == 24 &&
+                  offsetof(SuEntry, q) == 28 && offsetof(SuEntry, exact) == 30 && offsetof(SuEntry, more) == 31,
+              "entry layout (read as two 16-byte words)");
 
 // ---------------------------------------------------------------------------
 // Standard-deviation tables.
@@ -238,17 +243,35 @@ __device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32
     }
 }
 
+// One entry as two 16-byte loads issued together.
+__device__ __forceinline__ SuEntry su_entry(const SuEntry *p) {
+    const uint4 *q = reinterpret_cast<const uint4 *>(p);
+    const uint4 a = q[0], b = q[1];
+    SuEntry e;
+    e.m = __hiloint2double(static_cast<int>(a.y), static_cast<int>(a.x));
+    e.s = __hiloint2double(static_cast<int>(a.w), static_cast<int>(a.z));
+    e.mu = __uint_as_float(b.x);
+    e.k = static_cast<int32_t>(b.y);
+    e.next = b.z;
+    e.q = static_cast<uint16_t>(b.w & 0xFFFFu);
+    e.exact = static_cast<uint8_t>((b.w >> 16) & 0xFFu);
+    e.more = static_cast<uint8_t>(b.w >> 24);
+    return e;
+}
+
+// Without a branch on sigma = 0 (such a pair draws mu itself): the lanes of
+// a round draw together either way, and a branch would let the compiler
+// split the entry's loads around it.
 __device__ __forceinline__ double su_draw(const SuEntry &e, uint64_t seed, int64_t occ) {
-    if (e.exact) return static_cast<double>(e.mu);
     const uint64_t o = static_cast<uint64_t>(occ);
     uint32_t c[4] = {static_cast<uint32_t>(o), static_cast<uint32_t>(o >> 32), static_cast<uint32_t>(e.k), 0u};
     philox4x32_10(c, static_cast<uint32_t>(seed), static_cast<uint32_t>(seed >> 32));
     const uint64_t b1 = (static_cast<uint64_t>(c[1]) << 32) | c[0], b2 = (static_cast<uint64_t>(c[3]) << 32) | c[2];
     const double u1 = (static_cast<double>(b1 >> 12) + 0.5) * 0x1p-52;
     const double u2 = (static_cast<double>(b2 >> 12) + 0.5) * 0x1p-52;
-    const double two_pi = 6.283185307179586476925286766559;   // the binary64 nearest 2 pi
-    const double z = sqrt(-2.0 * log(u1)) * cos(two_pi * u2);
-    return exp(e.m + e.s * z);
+    const double z = sqrt(-2.0 * su_log(u1)) * su_cos_2pi(u2);
+    const double x = su_exp(e.m + e.s * z);
+    return e.exact ? static_cast<double>(e.mu) : x;
 }
 
 // ---------------------------------------------------------------------------
@@ -277,7 +300,8 @@ __device__ __forceinline__ double su_draw(const SuEntry &e, uint64_t seed, int64
 // other layers of the call.
 
 constexpr int kSuChunk = 4;                                 // codes per lane and step (runs are multiples of 4)
-constexpr int kSuQCap = (kWave - 1) + kSuChunk * kWave + 1; // 320: fewer than 64 waiting + one step's codes
+constexpr int kSuQCap = 512;                                // a ring: fewer than 64 waiting + one step's codes
+static_assert(kSuQCap >= (kWave - 1) + kSuChunk * kWave && (kSuQCap & (kSuQCap - 1)) == 0, "queue ring");
 static_assert(kSuThreads == kSrWords / 2, "one bitmap word of a range per thread");
 
 struct SuParams {
@@ -331,8 +355,8 @@ __global__ __launch_bounds__(kSuThreads) void k_su_fwd(SuParams P) {
     __shared__ uint2 tbr[kSrWords / 2];                  // the range's bitmap words with super-range ranks
     __shared__ double acc[kMaxTrialsPerBlock + 1];       // per-trial totals (one slot past the trials)
     __shared__ uint32_t offl[kMaxTrialsPerBlock];        // each trial's first occurrence less the block's
-    __shared__ uint32_t q_e[kGroups][kSuQCap];           // queued occurrence: its event's union index
-    __shared__ uint32_t q_s[kGroups][kSuQCap];           //   its trial in the block << 16 | position in the trial
+    __shared__ uint2 q_es[kGroups][kSuQCap];             // queued occurrence: (its event's union index,
+                                                         //   its trial in the block << 16 | position in the trial)
     __shared__ double ls[kSuMaxJ], lr[kSuMaxJ], ll[kSuMaxJ];
     int j = 0;
     const int bi = su_item(P, blockIdx.x, j);
@@ -371,10 +395,9 @@ __global__ __launch_bounds__(kSuThreads) void k_su_fwd(SuParams P) {
     tbr[tid] = slice_word(0);
     __syncthreads();
 
-    uint32_t *qe = q_e[w];
-    uint32_t *qs = q_s[w];
+    uint2 *qes = q_es[w];
     int qh = 0, qlen = 0;   // uniform: the queue's head slot and length
-    auto wrap = [](int x) { return x >= kSuQCap ? x - kSuQCap : x; };   // x < 2 kSuQCap
+    auto wrap = [](int x) { return x & (kSuQCap - 1); };
     // A lane whose occurrence is held by further ELTs keeps it and draws one
     // further ELT per round, so that no round waits on a few lanes.
     bool pend = false;
@@ -396,15 +419,15 @@ __global__ __launch_bounds__(kSuThreads) void k_su_fwd(SuParams P) {
         int64_t i = pi;
         int slot = ps;
         if (first && rank < taken) {
-            const int at = wrap(qh + rank);
-            ei = qe[at];
-            const uint32_t sv = qs[at];
+            const uint2 es = qes[wrap(qh + rank)];
+            ei = es.x;
+            const uint32_t sv = es.y;
             slot = static_cast<int>(sv >> 16);
             i = occ0 + static_cast<int64_t>(offl[slot]) + static_cast<int64_t>(sv & 0xFFFFu);
             act = ei < cap;   // union indexes lie below the entries used, checked above
         }
         if (act) {
-            const SuEntry en = E[ei];
+            const SuEntry en = su_entry(E + ei);
             const double v = su_draw(en, P.seed, i);
             const double g = xl(ls[en.q] * v, lr[en.q], ll[en.q]);
             if (first) {
@@ -478,8 +501,7 @@ __global__ __launch_bounds__(kSuThreads) void k_su_fwd(SuParams P) {
                         const int at = wrap(qh + qlen + static_cast<int>(__builtin_amdgcn_mbcnt_hi(
                                                               static_cast<uint32_t>(m >> 32),
                                                               __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(m), 0u))));
-                        qe[at] = eu[u];
-                        qs[at] = sv[u];
+                        qes[at] = make_uint2(eu[u], sv[u]);
                     }
                     qlen += static_cast<int>(__popcll(m));
                 }
