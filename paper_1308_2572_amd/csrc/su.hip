@@ -27,6 +27,7 @@
 
 #include <algorithm>
 #include <cstddef>
+#include <type_traits>
 #include <vector>
 
 namespace ara {
@@ -413,39 +414,64 @@ __global__ __launch_bounds__(kSuThreads) void k_su_fwd(SuParams P) {
         const int rank = static_cast<int>(__builtin_amdgcn_mbcnt_hi(
             static_cast<uint32_t>(freem >> 32), __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(freem), 0u)));
         const int taken = min(qlen, static_cast<int>(__popcll(freem)));   // uniform
-        const bool first = !pend;
-        bool act = pend;
-        uint32_t ei = pe;
-        int64_t i = pi;
-        int slot = ps;
-        if (first && rank < taken) {
-            const uint2 es = qes[wrap(qh + rank)];
-            ei = es.x;
-            const uint32_t sv = es.y;
-            slot = static_cast<int>(sv >> 16);
-            i = occ0 + static_cast<int64_t>(offl[slot]) + static_cast<int64_t>(sv & 0xFFFFu);
-            act = ei < cap;   // union indexes lie below the entries used, checked above
-        }
-        if (act) {
-            const SuEntry en = su_entry(E + ei);
-            const double v = su_draw(en, P.seed, i);
-            const double g = xl(ls[en.q] * v, lr[en.q], ll[en.q]);
-            if (first) {
-                px = g;
-                pi = i;
-                ps = slot;
-                pe = en.next;
-                pleft = static_cast<uint64_t>(en.next) + en.more <= cap ? en.more : 0;
-            } else {
-                px = px + g;
-                ++pe;
-                --pleft;
-            }
-            pend = pleft > 0;
-            if (!pend) atomicAdd(&acc[ps], xl(px, occR, occL));
-        }
+        const bool take = !pend && rank < taken;
+        const bool act = take || pend;
+        // Every lane runs the draw (no branch, so no state copies between
+        // paths); an idle lane reads entry 0 and a queue slot it ignores, and
+        // keeps its state.  Union indexes lie below the entries used, which
+        // the layer's check above bounds by the entries allocated.
+        const uint2 es = qes[wrap(qh + (take ? rank : 0))];
+        const int slot = take ? static_cast<int>(es.y >> 16) : ps;
+        const int64_t i = take ? occ0 + static_cast<int64_t>(offl[slot]) + static_cast<int64_t>(es.y & 0xFFFFu) : pi;
+        const uint32_t ei = take ? es.x : (pend ? pe : 0u);
+        const SuEntry en = su_entry(E + ei);
+        const double v = su_draw(en, P.seed, i);
+        const double g = xl(ls[en.q] * v, lr[en.q], ll[en.q]);
+        const int left = take ? (static_cast<uint64_t>(en.next) + en.more <= cap ? en.more : 0) : pleft - 1;
+        px = act ? (take ? g : px + g) : px;
+        pi = i;
+        ps = slot;
+        pe = take ? en.next : pe + (act ? 1u : 0u);
+        pleft = act ? left : pleft;
+        const bool done = act && left <= 0;
+        pend = act && left > 0;
+        if (done) atomicAdd(&acc[ps], xl(px, occR, occL));
         qh = wrap(qh + taken);
         qlen -= taken;
+    };
+
+    // One step: four codes per lane (offset bits 5..14 pick the bitmap word,
+    // bits 0..4 the bit; bit 15 advances the lane's trial first), and the
+    // union occurrences among them appended to the queue code by code in
+    // lane order.  Skip codes (0xFFFF) read the range's last bit: only when
+    // that event is in the union must they be told apart from it.
+    auto decode = [&](unsigned long long cx, unsigned long long cy, int &slot, uint32_t ubr, auto tell_tag) {
+        constexpr bool kTell = decltype(tell_tag)::value;
+        const uint32_t cw[2] = {static_cast<uint32_t>(cx), static_cast<uint32_t>(cx >> 32)};
+        const uint32_t pw[2] = {static_cast<uint32_t>(cy), static_cast<uint32_t>(cy >> 32)};
+        bool on[kSuChunk];
+        uint2 ent[kSuChunk];
+#pragma unroll
+        for (int u = 0; u < kSuChunk; ++u) {
+            const uint32_t c = (u & 1) ? (cw[u >> 1] >> 16) : cw[u >> 1];   // bits 16.. are ignored below
+            slot += static_cast<int>(__builtin_amdgcn_ubfe(c, 15, 1));
+            const uint2 q = tbr[__builtin_amdgcn_ubfe(c, 5, 10)];
+            on[u] = __builtin_amdgcn_ubfe(q.x, c, 1) != 0u;   // bit (c & 31) of the word
+            if (kTell) on[u] = on[u] && (c & 0xFFFFu) != 0xFFFFu;
+            const uint32_t pos = (u & 1) ? (pw[u >> 1] >> 16) : (pw[u >> 1] & 0xFFFFu);
+            ent[u] = make_uint2(ubr + q.y + __popc(__builtin_amdgcn_ubfe(q.x, 0, c)),
+                                (static_cast<uint32_t>(slot) << 16) | pos);
+        }
+#pragma unroll
+        for (int u = 0; u < kSuChunk; ++u) {
+            const uint64_t m = __ballot(on[u]);
+            if (on[u])
+                qes[wrap(qh + qlen + static_cast<int>(__builtin_amdgcn_mbcnt_hi(
+                                          static_cast<uint32_t>(m >> 32),
+                                          __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(m), 0u))))] = ent[u];
+            qlen += static_cast<int>(__popcll(m));
+        }
+        __builtin_amdgcn_wave_barrier();
     };
 
     // ranges 0 .. G-1, then a last pass (r = G) that draws what is left; the
@@ -459,6 +485,7 @@ __global__ __launch_bounds__(kSuThreads) void k_su_fwd(SuParams P) {
         const uint16_t *cp = nullptr, *pp = nullptr;
         unsigned long long X = 0, Y = 0;
         uint32_t ubr = 0;            // union index of the super-range's rank 0
+        const bool last_set = (__builtin_amdgcn_readfirstlane(tbr[1023].x) >> 31) != 0u;   // uniform
         if (active && !flush) {
             const size_t si = seg0 + static_cast<size_t>(r) * kGroups;
             R = __builtin_amdgcn_readfirstlane(P.seg_run[si]);
@@ -481,31 +508,10 @@ __global__ __launch_bounds__(kSuThreads) void k_su_fwd(SuParams P) {
                     X = su_ld4<SHARED>(cp);
                     Y = su_ld4<SHARED>(pp);
                 }
-                bool on[kSuChunk];
-                uint32_t eu[kSuChunk], sv[kSuChunk];
-#pragma unroll
-                for (int u = 0; u < kSuChunk; ++u) {
-                    const uint32_t c = static_cast<uint32_t>(cx >> (16 * u)) & 0xFFFFu;
-                    slot += static_cast<int>(c >> 15);   // advance before the code
-                    const uint2 q = tbr[(c >> 5) & 1023u];
-                    const uint32_t bit = c & 31u;
-                    on[u] = ((q.x >> bit) & 1u) != 0u && c != 0xFFFFu;
-                    eu[u] = ubr + q.y + __popc(q.x & ((1u << bit) - 1u));
-                    sv[u] = (static_cast<uint32_t>(slot) << 16) | (static_cast<uint32_t>(cy >> (16 * u)) & 0xFFFFu);
-                }
-                // append the step's union occurrences, code by code in lane order
-#pragma unroll
-                for (int u = 0; u < kSuChunk; ++u) {
-                    const uint64_t m = __ballot(on[u]);
-                    if (on[u]) {
-                        const int at = wrap(qh + qlen + static_cast<int>(__builtin_amdgcn_mbcnt_hi(
-                                                              static_cast<uint32_t>(m >> 32),
-                                                              __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(m), 0u))));
-                        qes[at] = make_uint2(eu[u], sv[u]);
-                    }
-                    qlen += static_cast<int>(__popcll(m));
-                }
-                __builtin_amdgcn_wave_barrier();
+                if (last_set)
+                    decode(cx, cy, slot, ubr, std::true_type{});
+                else
+                    decode(cx, cy, slot, ubr, std::false_type{});
             }
             while (qlen >= kWave || (flush && (qlen > 0 || __ballot(pend) != 0ull))) round();
             if (flush) break;
