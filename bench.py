@@ -35,20 +35,21 @@ def log(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def traffic_from_profiles(kernel_file: str):
-    """HBM bytes per launch of the forward kernel, from the committed rocprofv3
-    counter summary, if it was taken on the current kernel source."""
-    path = os.path.join(HERE, "profiles", "fwd_traffic.md")
+def traffic_from_profiles(profile: str, *kernel_files: str):
+    """HBM bytes per launch of a kernel, from a committed rocprofv3 counter
+    summary under profiles/, if it was taken on the current source of every
+    file given (each one's sha256 on a `source_sha256:` line)."""
+    path = os.path.join(HERE, "profiles", profile)
     if not os.path.exists(path):
         return None
     text = open(path).read()
-    m_sha = re.search(r"source_sha256:\s*([0-9a-f]{64})", text)
+    shas = set(re.findall(r"source_sha256:\s*([0-9a-f]{64})", text))
     m_b = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", text)
-    if not m_sha or not m_b:
+    if not shas or not m_b:
         return None
-    sha = hashlib.sha256(open(kernel_file, "rb").read()).hexdigest()
-    if sha != m_sha.group(1):
-        return None
+    for f in kernel_files:
+        if hashlib.sha256(open(f, "rb").read()).hexdigest() not in shas:
+            return None
     return float(m_b.group(1))
 
 
@@ -189,7 +190,7 @@ def main() -> int:
         f"{occ_ms / max(occ_n, 1):.4f} ms; metrics {met_ms / max(met_n, 1):.4f} ms; AAL {m[0]:.6e} PML {m[1]:.6e} "
         f"TVaR {m[2]:.6e}")
 
-    traffic = traffic_from_profiles(os.path.join(HERE, "paper_1308_2572_amd", "csrc", "forward.hip"))
+    traffic = traffic_from_profiles("fwd_traffic.md", os.path.join(HERE, "paper_1308_2572_amd", "csrc", "forward.hip"))
     result = {
         "metric": "event-ELT lookups/s & %HBM peak (1M×1000×15); fwd+bwd cost; p99 quote latency",
         "value": value,
@@ -392,9 +393,12 @@ def bench_su(ara, tables, yet, layers, et, lt, w, steps, warmup):
     algo = 4.0 * nnz + 8.0 * N + 8.0 * N * w.layers.n_layers
     del y, sigma
     torch.cuda.empty_cache()
+    csrc = os.path.join(HERE, "paper_1308_2572_amd", "csrc")
+    moved = traffic_from_profiles("su_fwd_1Mx1000x15.md", os.path.join(csrc, "su.hip"), os.path.join(csrc, "su_math.h"))
     return {"ms_per_call": ms, "kernel": "k_su_fwd", "kernel_ms": k, "draws": draws,
             "draws_per_s": draws / (k * 1e-3), "lookups_per_s": nnz * J / (ms * 1e-3),
             "algorithmic_bytes": algo, "frac_of_hbm_peak": algo / (k * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "traffic": moved, "traffic_over_algorithmic": None if moved is None else moved / algo,
             "metrics": {"aal": float(mm[0]), "pml": float(mm[1]), "tvar": float(mm[2])}}
 
 
