@@ -148,10 +148,13 @@ __global__ __launch_bounds__(kSuThreads) void k_su_base(const OccTables *__restr
     }
 }
 
-// Per (4096-event chunk, layer): the entries of every union event, in the
-// layer's listed ELT order.
-constexpr int kSuFillWords = 128;                  // 4096 events per workgroup
+// Per (1024-event chunk, layer): the entries of every union event, in the
+// layer's listed ELT order; one event per thread, so that the chains of
+// dependent loads (bitmap word, rank, counts; presence; losses) of many
+// events are in flight at once.
+constexpr int kSuFillWords = kSuThreads / 32;      // 1024 events per workgroup
 constexpr int kSuFillChunks = kSrWords / kSuFillWords;
+constexpr int kSuFillBatch = 8;                    // ELTs whose loads are in flight together
 
 __global__ __launch_bounds__(kSuThreads) void k_su_fill(const float *__restrict__ loss, const float *__restrict__ sigma,
                                                         const uint32_t *__restrict__ present, int32_t catalog,
@@ -178,45 +181,80 @@ __global__ __launch_bounds__(kSuThreads) void k_su_fill(const float *__restrict_
     if (n_union > cap) return;   // flagged by k_su_base
     SuEntry *E = ent + eregion[j];
     const uint32_t *oo = ooff + (static_cast<size_t>(j) * n_sr + s) * kSr;
-    for (int it = 0; it < 4; ++it) {
-        const int local = p * (kSuFillWords * 32) + it * kSuThreads + tid;   // event within the super-range
+    {
+        const int local = p * (kSuFillWords * 32) + tid;   // event within the super-range
         const int64_t ev = static_cast<int64_t>(s) * kSr + local;
-        if (ev >= catalog) continue;
+        if (ev >= catalog) return;
         const uint2 q2 = T.br[static_cast<size_t>(s) * kSrWords + (local >> 5)];
         const int bit = local & 31;
-        if (!((q2.x >> bit) & 1u)) continue;
+        if (!((q2.x >> bit) & 1u)) return;
         const uint32_t r = q2.y + __popc(q2.x & ((1u << bit) - 1u));
         const uint32_t nb = T.cnt[static_cast<size_t>(s) * kSr + r];
         const uint64_t first = static_cast<uint64_t>(ub) + r;
         const uint64_t next = static_cast<uint64_t>(ob) + oo[r];
         uint64_t o = first;
         int h = 0;
-        for (int q = 0; q < J; ++q) {
-            const int k = lk[q];
-            if (!((present[static_cast<size_t>(k) * words + (ev >> 5)] >> (ev & 31)) & 1u)) continue;
-            if (o >= cap) break;   // flagged by k_su_base
-            const float mu = loss[static_cast<size_t>(k) * catalog + ev];
-            const float sg = sigma[static_cast<size_t>(k) * catalog + ev];
-            SuEntry e;
-            e.mu = mu;
-            e.k = k;
-            e.q = static_cast<uint16_t>(q);
-            e.exact = (sg == 0.0f) ? 1 : 0;
-            e.next = h == 0 ? static_cast<uint32_t>(next) : 0u;
-            e.more = h == 0 ? static_cast<uint8_t>(nb - 1) : 0;
-            if (e.exact) {
-                e.m = 0.0;
-                e.s = 0.0;
-            } else {
-                const double rr = static_cast<double>(sg) / static_cast<double>(mu);
-                const double s2 = log1p(rr * rr);
-                e.m = log(static_cast<double>(mu)) - 0.5 * s2;
-                e.s = sqrt(s2);
+        // eight ELTs at a time: their presence words loaded together, then
+        // the losses and deviations of the present ones, then the entries in
+        // listed order
+        for (int q0 = 0; q0 < J; q0 += kSuFillBatch) {
+            bool on[kSuFillBatch];
+            float mu8[kSuFillBatch], sg8[kSuFillBatch];
+#pragma unroll
+            for (int i = 0; i < kSuFillBatch; ++i) {
+                const int k = lk[min(q0 + i, J - 1)];
+                on[i] = q0 + i < J && ((present[static_cast<size_t>(k) * words + (ev >> 5)] >> (ev & 31)) & 1u);
             }
-            E[o] = e;
-            o = (h == 0) ? next : o + 1;
-            ++h;
+#pragma unroll
+            for (int i = 0; i < kSuFillBatch; ++i) {
+                mu8[i] = sg8[i] = 0.0f;
+                if (on[i]) {
+                    const int k = lk[q0 + i];
+                    mu8[i] = loss[static_cast<size_t>(k) * catalog + ev];
+                    sg8[i] = sigma[static_cast<size_t>(k) * catalog + ev];
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < kSuFillBatch; ++i) {
+                // entries past the capacity are not written (flagged by k_su_base)
+                if (!on[i] || o >= cap) continue;
+                const float mu = mu8[i], sg = sg8[i];
+                SuEntry e;
+                e.mu = mu;
+                e.k = lk[q0 + i];
+                e.q = static_cast<uint16_t>(q0 + i);
+                e.exact = (sg == 0.0f) ? 1 : 0;
+                e.next = h == 0 ? static_cast<uint32_t>(next) : 0u;
+                e.more = h == 0 ? static_cast<uint8_t>(nb - 1) : 0;
+                e.m = 0.0;
+                e.s = static_cast<double>(sg);   // k_su_params turns (mu, sigma) into (m, s)
+                E[o] = e;
+                o = (h == 0) ? next : o + 1;
+                ++h;
+            }
         }
+    }
+}
+
+// Per layer: each entry's lognormal parameters from its mean and deviation,
+// s^2 = ln(1 + sigma^2/mu^2), m = ln mu - s^2/2 (0, 0 for an exact entry), one
+// thread per entry so that the binary64 logarithms run on full wavefronts.
+__global__ __launch_bounds__(256) void k_su_params(const uint64_t *__restrict__ eregion,
+                                                   const uint64_t *__restrict__ ecap,
+                                                   const uint64_t *__restrict__ eused, SuEntry *__restrict__ ent) {
+    const int j = blockIdx.y;
+    const uint64_t cap = ecap[j], used = eused[j];
+    if (used > cap) return;   // nothing laid out (flagged by k_su_base)
+    SuEntry *E = ent + eregion[j];
+    for (uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; i < used;
+         i += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
+        SuEntry &e = E[i];
+        if (e.exact) continue;
+        const double mu = static_cast<double>(e.mu);
+        const double rr = e.s / mu;
+        const double s2 = log1p(rr * rr);
+        e.m = log(mu) - 0.5 * s2;
+        e.s = sqrt(s2);
     }
 }
 
@@ -699,6 +737,9 @@ extern "C" int32_t ara_ylt_forward_su(const ara_tables *tables, const float *sig
         k_su_fill<<<dim3(static_cast<unsigned>(n_sr * kSuFillChunks), static_cast<unsigned>(L)), kSuThreads, 0, st>>>(
             tables->loss, sigma, tables->present, tables->catalog, tables->words, d_off, d_ids, d_tabs, n_sr, ooff,
             ubase, obase, d_cap, d_region, ent);
+        const uint64_t most = *std::max_element(S.cap.begin(), S.cap.end());
+        const unsigned px = static_cast<unsigned>(std::max<uint64_t>(1, std::min<uint64_t>((most + 255) / 256, 4096)));
+        k_su_params<<<dim3(px, static_cast<unsigned>(L)), 256, 0, st>>>(d_region, d_cap, d_used, ent);
         ARA_HIP(hipGetLastError());
     }
     const int tb = yet->trials_per_block;
