@@ -521,7 +521,7 @@ __global__ __launch_bounds__(kSuThreads) void k_su_fwd(SuParams P) {
         int R = 0;                   // uniform: this wavefront's codes per lane in range r
         int slot = 0;                // the lane's trial in the block
         const uint16_t *cp = nullptr, *pp = nullptr;
-        unsigned long long X = 0, Y = 0;
+        unsigned long long X = 0, Y = 0, X2 = 0, Y2 = 0;
         uint32_t ubr = 0;            // union index of the super-range's rank 0
         const bool last_set = (__builtin_amdgcn_readfirstlane(tbr[1023].x) >> 31) != 0u;   // uniform
         if (active && !flush) {
@@ -535,16 +535,24 @@ __global__ __launch_bounds__(kSuThreads) void k_su_fwd(SuParams P) {
                 pp = P.pos + sb + 4 * lane;
                 X = su_ld4<SHARED>(cp);
                 Y = su_ld4<SHARED>(pp);
+                if (kSuChunk < R) {
+                    X2 = su_ld4<SHARED>(cp + kSuChunk * kWave);
+                    Y2 = su_ld4<SHARED>(pp + kSuChunk * kWave);
+                }
             }
         }
         for (int step = 0; step < R || flush; step += kSuChunk) {
             if (!flush) {
                 const unsigned long long cx = X, cy = Y;
-                if (step + kSuChunk < R) {   // uniform; the next step's codes while this one is decoded
+                if (step + kSuChunk < R) {   // uniform; the codes two steps ahead load while this one is decoded
+                    X = X2;
+                    Y = Y2;
+                    if (step + 2 * kSuChunk < R) {
+                        X2 = su_ld4<SHARED>(cp + 2 * kSuChunk * kWave);
+                        Y2 = su_ld4<SHARED>(pp + 2 * kSuChunk * kWave);
+                    }
                     cp += kSuChunk * kWave;
                     pp += kSuChunk * kWave;
-                    X = su_ld4<SHARED>(cp);
-                    Y = su_ld4<SHARED>(pp);
                 }
                 if (last_set)
                     decode(cx, cy, slot, ubr, std::true_type{});
