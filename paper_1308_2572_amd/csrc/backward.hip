@@ -34,15 +34,18 @@
 // trials, as the metrics' do (AAL: the same weight wherever the aggregate
 // clamp is linear; PML, TVaR: zero outside the tied or top trials).  With c
 // that common fixed-point value and D the trials whose value differs,
-//   W(e) = c * (occurrences of e) + sum over t in D of (v_t - c) * (occurrences of e in t),
+//   W(e) = c * (occurrences of e in the call's trials)
+//          + sum over t in D of (v_t - c) * (occurrences of e in t),
 // integer arithmetic that gives the gather's result bit for bit.  The
-// occurrence counts come from the event-major offsets, the second term from
-// the trial-major copy of the deviating trials' events; for a call over part
-// of the trials, those outside it count as deviating (weight 0) when c is
-// not zero.  It is used when the trials to walk are at most a sixteenth of
-// all (each walked trial costs about sixteen times its share of the
-// gather's time); the decision is taken on the device from the counts, so
-// both forms are enqueued and the one not chosen returns at once.
+// occurrence counts come from the event-major offsets: over all trials the
+// per-event totals, over part of them the list lengths of the trial slices
+// the range covers whole, plus a count of the in-range entries of the (at
+// most two) slices it cuts; the second term comes from the trial-major copy
+// of the deviating trials' events.  It is used when the trials to walk are
+// at most a sixteenth of all (each walked trial costs about sixteen times
+// its share of the gather's time); the decision is taken on the device from
+// the counts, so both forms are enqueued and the one not chosen returns at
+// once.
 #include "occ.h"
 #include "wave.h"
 
@@ -218,8 +221,9 @@ struct BwdSparse {
     const int64_t *vq;                 // [n_layers][n][cs]
     int64_t n, t0, n_trials;
     int32_t cs, n_cot, catalog, n_sr;
-    int32_t pad;
-    int64_t n_out;                     // trials outside the call's range (weight 0 there)
+    int64_t slice_trials;              // trials of one slice of the event-major copy
+    const int64_t *tr_off;             // event-major copy: list offsets per (slice, event)
+    const uint32_t *tr_ent;            //   and the lists' slice-local trial indices
     unsigned long long *ndev;          // [n_layers] deviating trials
     int64_t *common;                   // [n_layers][kMaxCot] the chosen common value
     int32_t *dev;                      // [n_layers][n] deviating trials (call-relative)
@@ -237,19 +241,29 @@ __device__ __forceinline__ int64_t cand_value(const BwdSparse &P, int j, int c, 
     return P.vq[(static_cast<size_t>(j) * P.n + t) * P.cs + c];
 }
 
-// Whether some row's common value is non-zero: then the trials outside the
-// call's range (weight 0) deviate from it too.
+// Whether some row's common value is non-zero (W then starts from c times
+// the occurrence counts).
 __device__ __forceinline__ bool common_nonzero(const BwdSparse &P, int j) {
     for (int c = 0; c < P.n_cot; ++c)
         if (P.common[static_cast<size_t>(j) * kMaxCot + c] != 0) return true;
     return false;
 }
 
-// Deviating trials the second form walks: those of the range, and the ones
-// outside it when the common value is not zero.
-__device__ __forceinline__ int64_t sparse_walk(const BwdSparse &P, int j) {
-    return static_cast<int64_t>(P.ndev[j]) + (common_nonzero(P, j) ? P.n_out : 0);
+// Trial slice x of the event-major copy holds trials [x S, min((x + 1) S, N)).
+__device__ __forceinline__ bool slice_inside(const BwdSparse &P, int x) {
+    const int64_t lo = static_cast<int64_t>(x) * P.slice_trials;
+    const int64_t hi = min(lo + P.slice_trials, P.n_trials);
+    return lo >= P.t0 && hi <= P.t0 + P.n;
 }
+
+__device__ __forceinline__ bool slice_cut(const BwdSparse &P, int x) {
+    const int64_t lo = static_cast<int64_t>(x) * P.slice_trials;
+    const int64_t hi = min(lo + P.slice_trials, P.n_trials);
+    return max(lo, P.t0) < min(hi, P.t0 + P.n) && !slice_inside(P, x);
+}
+
+// Deviating trials the second form walks: those of the range.
+__device__ __forceinline__ int64_t sparse_walk(const BwdSparse &P, int j) { return static_cast<int64_t>(P.ndev[j]); }
 
 // The second form's condition, the same in every kernel that reads it: at
 // most a sixteenth of all the trials to walk.
@@ -422,17 +436,30 @@ __global__ __launch_bounds__(1024) void k_bwd_dev(BwdSparse P) {
     for (uint32_t i = threadIdx.x; i < nb; i += blockDim.x) dv[i] = buf[i];
 }
 
-// (5c) W(e) = c * (occurrences of e in all trials) for every hot event (when
-// the second form is chosen and c is not zero; the accumulators are zero
-// from step 4 otherwise)
+// (5c) W(e) = c * (occurrences of e in the trial slices the call covers
+// whole; all trials: the per-event totals) for every hot event (when the
+// second form is chosen and c is not zero; the accumulators are zero from
+// step 4 otherwise)
 __global__ __launch_bounds__(256) void k_bwd_winit(BwdSparse P) {
     const int j = blockIdx.y;
     if (!sparse_chosen(P, j) || !common_nonzero(P, j)) return;   // c = 0: W starts at zero
     const int H = P.hot_base[static_cast<size_t>(j) * (P.n_sr + 1) + P.n_sr];
     const int32_t *hev = P.hot_ev + static_cast<size_t>(j) * P.catalog;
     int64_t *Wj = P.W + static_cast<size_t>(j) * P.n_cot * P.catalog;
+    const bool all = P.t0 == 0 && P.n == P.n_trials;   // uniform
     for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < H; g += gridDim.x * blockDim.x) {
-        const int64_t cnt = P.t_cnt[hev[g]];
+        const int e = hev[g];
+        int64_t cnt = 0;
+        if (all) {
+            cnt = P.t_cnt[e];
+        } else {
+#pragma unroll
+            for (int x = 0; x < kSlices; ++x)
+                if (slice_inside(P, x)) {
+                    const int64_t *off = P.tr_off + static_cast<int64_t>(x) * P.catalog;
+                    cnt += off[e + 1] - off[e];
+                }
+        }
 #pragma unroll
         for (int c = 0; c < kMaxCot; ++c)
             if (c < P.n_cot)
@@ -442,15 +469,55 @@ __global__ __launch_bounds__(256) void k_bwd_winit(BwdSparse P) {
     }
 }
 
-// (5d) the deviating trials: a wavefront per trial adds v_t - c to W of each
-// hot event of the trial, one integer atomic per (occurrence, row); the
-// trials outside the call's range (v_t = 0) follow the listed ones
+// (5c') the slices the call's range cuts: for every hot event, c times the
+// entries of its list in the slice that lie in the range.  Workgroup i works
+// on slice i mod 8, as the gather does; G lanes per hot event read its list
+// coalesced and count, and the count meets W in one integer atomic per row.
+template <int G>
+__global__ __launch_bounds__(256) void k_bwd_wcut(BwdSparse P) {
+    constexpr int kU = 4;
+    const int x = blockIdx.x % kSlices, wi = blockIdx.x / kSlices, nw = gridDim.x / kSlices, j = blockIdx.y;
+    if (!sparse_chosen(P, j) || !common_nonzero(P, j) || !slice_cut(P, x)) return;   // uniform
+    const int64_t tx0 = static_cast<int64_t>(x) * P.slice_trials;
+    const int64_t ulo = max<int64_t>(P.t0 - tx0, 0), uhi = min<int64_t>(P.t0 + P.n - tx0, P.slice_trials);
+    const uint32_t u0 = static_cast<uint32_t>(ulo), span = static_cast<uint32_t>(uhi - ulo);
+    const int H = P.hot_base[static_cast<size_t>(j) * (P.n_sr + 1) + P.n_sr];
+    const int32_t *hev = P.hot_ev + static_cast<size_t>(j) * P.catalog;
+    const int64_t *off = P.tr_off + static_cast<int64_t>(x) * P.catalog;
+    int64_t *Wj = P.W + static_cast<size_t>(j) * P.n_cot * P.catalog;
+    const int sub = threadIdx.x & (G - 1);
+    const int ngrp = nw * static_cast<int>(blockDim.x) / G;
+    for (int g = (wi * static_cast<int>(blockDim.x) + static_cast<int>(threadIdx.x)) / G; g < H; g += ngrp) {
+        const int e = hev[g];
+        const int64_t o0 = off[e], o1 = off[e + 1];
+        uint32_t cnt = 0;
+        for (int64_t i = o0 + sub; i < o1; i += G * kU) {
+            uint32_t d[kU];
+#pragma unroll
+            for (int v = 0; v < kU; ++v)
+                d[v] = (i + v * G < o1) ? __builtin_nontemporal_load(P.tr_ent + i + v * G) - u0 : span;   // span = skip
+#pragma unroll
+            for (int v = 0; v < kU; ++v) cnt += d[v] < span ? 1u : 0u;
+        }
+        for (int s2 = G / 2; s2 > 0; s2 >>= 1) cnt += static_cast<uint32_t>(__shfl_xor(static_cast<int>(cnt), s2, G));
+        if (sub == 0 && cnt != 0) {
+#pragma unroll
+            for (int c = 0; c < kMaxCot; ++c)
+                if (c < P.n_cot)
+                    atomicAdd(reinterpret_cast<unsigned long long *>(&Wj[static_cast<size_t>(c) * P.catalog + g]),
+                              static_cast<unsigned long long>(P.common[static_cast<size_t>(j) * kMaxCot + c]) *
+                                  static_cast<unsigned long long>(cnt));
+        }
+    }
+}
+
+// (5d) the deviating trials of the range: a wavefront per trial adds
+// v_t - c to W of each hot event of the trial, one integer atomic per
+// (occurrence, row)
 __global__ __launch_bounds__(256) void k_bwd_wsparse(BwdSparse P) {
     const int j = blockIdx.y, lane = threadIdx.x & 63;
     if (!sparse_chosen(P, j)) return;
-    const int64_t nd = static_cast<int64_t>(P.ndev[j]);
     const int64_t nwalk = sparse_walk(P, j);
-    const int64_t call_end = P.t0 + P.n;
     const OccTables T = P.tabs[j];
     const int32_t *hb = P.hot_base + static_cast<size_t>(j) * (P.n_sr + 1);
     const int64_t *q = P.vq + static_cast<size_t>(j) * P.n * P.cs;
@@ -458,23 +525,13 @@ __global__ __launch_bounds__(256) void k_bwd_wsparse(BwdSparse P) {
     const int waves = gridDim.x * (blockDim.x >> 6);
     for (int64_t i = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); i < nwalk; i += waves) {
         unsigned long long dl[kMaxCot];
-        int64_t t;
-        if (i < nd) {   // a deviating trial of the range
-            const int32_t u = P.dev[static_cast<size_t>(j) * P.n + i];
+        const int32_t u = P.dev[static_cast<size_t>(j) * P.n + i];
 #pragma unroll
-            for (int c = 0; c < kMaxCot; ++c)
-                dl[c] = c < P.n_cot ? static_cast<unsigned long long>(q[static_cast<size_t>(u) * P.cs + c]) -
-                                          static_cast<unsigned long long>(P.common[static_cast<size_t>(j) * kMaxCot + c])
-                                    : 0ull;
-            t = P.t0 + u;
-        } else {        // a trial outside the range: weight 0
-            const int64_t o = i - nd;
-            t = o < P.t0 ? o : call_end + (o - P.t0);
-#pragma unroll
-            for (int c = 0; c < kMaxCot; ++c)
-                dl[c] = c < P.n_cot ? 0ull - static_cast<unsigned long long>(P.common[static_cast<size_t>(j) * kMaxCot + c])
-                                    : 0ull;
-        }
+        for (int c = 0; c < kMaxCot; ++c)
+            dl[c] = c < P.n_cot ? static_cast<unsigned long long>(q[static_cast<size_t>(u) * P.cs + c]) -
+                                      static_cast<unsigned long long>(P.common[static_cast<size_t>(j) * kMaxCot + c])
+                                : 0ull;
+        const int64_t t = P.t0 + u;
         const int64_t a = P.t_off[t], b = P.t_off[t + 1];
         constexpr int kU = 16;   // events per lane in flight: a 1000-event trial in one round
         for (int64_t k0 = a; k0 < b; k0 += 64 * kU) {
@@ -884,7 +941,9 @@ extern "C" int32_t ara_ylt_backward(const ara_tables *tables, const ara_yet *yet
     Q.n_cot = n_cot;
     Q.catalog = tables->catalog;
     Q.n_sr = B.z.n_sr;
-    Q.n_out = yet->n_trials - n;
+    Q.slice_trials = yet->slice_trials;
+    Q.tr_off = yet->tr_off;
+    Q.tr_ent = yet->tr_ent;
     Q.ndev = ndev;
     Q.common = common;
     Q.dev = dev;
@@ -897,21 +956,26 @@ extern "C" int32_t ara_ylt_backward(const ara_tables *tables, const ara_yet *yet
     Q.W = W;
     {
         ProfScope prof(ARA_PROF_BWD, st);
-        if (S.use_sp) {
-            const unsigned gt = static_cast<unsigned>(dev_blocks(n));
-            k_bwd_pick<<<L, kPickSamples, 0, st>>>(Q);
-            k_bwd_dev<<<dim3(gt, L), 1024, 0, st>>>(Q);
-            const unsigned gh = static_cast<unsigned>(std::min<int64_t>((tables->catalog + 255) / 256, 1024));
-            k_bwd_winit<<<dim3(gh, L), 256, 0, st>>>(Q);
-            k_bwd_wsparse<<<dim3(2048, L), 256, 0, st>>>(Q);
-        }
         // four 256-thread workgroups per CU, a multiple of the slice count
         const int cu = device_cu_count();
         const unsigned gx = static_cast<unsigned>(kSlices * std::max(1, (4 * cu) / kSlices));
         const dim3 grid(gx, L);
         // lanes per hot event: about a third of the mean list length, 4 or 16
         const double mean_list = static_cast<double>(yet->nnz) / (static_cast<double>(kSlices) * tables->catalog);
-        if (mean_list >= 24.0) launch_bwd_w<16>(B.cs, grid, st, S);
+        const bool wide = mean_list >= 24.0;
+        if (S.use_sp) {
+            const unsigned gt = static_cast<unsigned>(dev_blocks(n));
+            k_bwd_pick<<<L, kPickSamples, 0, st>>>(Q);
+            k_bwd_dev<<<dim3(gt, L), 1024, 0, st>>>(Q);
+            const unsigned gh = static_cast<unsigned>(std::min<int64_t>((tables->catalog + 255) / 256, 1024));
+            k_bwd_winit<<<dim3(gh, L), 256, 0, st>>>(Q);
+            if (trial_begin != 0 || trial_end != yet->n_trials) {   // some slice may be cut
+                if (wide) k_bwd_wcut<16><<<grid, 256, 0, st>>>(Q);
+                else k_bwd_wcut<4><<<grid, 256, 0, st>>>(Q);
+            }
+            k_bwd_wsparse<<<dim3(2048, L), 256, 0, st>>>(Q);
+        }
+        if (wide) launch_bwd_w<16>(B.cs, grid, st, S);
         else launch_bwd_w<4>(B.cs, grid, st, S);
         ARA_HIP(hipGetLastError());
     }

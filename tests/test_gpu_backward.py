@@ -267,7 +267,9 @@ def _both_forms(ara, w):
         return ge.cpu().numpy(), gl.cpu().numpy()
 
     ylt, s_pre, _ = ara.ylt_forward(tables, with_tm, layers, et, lt, want_s_pre=True)
-    return ylt, s_pre, (lambda *a, **k: run(with_tm, *a, **k)), (lambda *a, **k: run(without, *a, **k))
+    sparse = lambda *a, **k: run(with_tm, *a, **k)   # noqa: E731
+    sparse.slice_trials = int(with_tm.handle.slice_trials)
+    return ylt, s_pre, sparse, (lambda *a, **k: run(without, *a, **k))
 
 
 def test_deviating_trial_form_is_bitwise_the_gather(ara):
@@ -276,7 +278,10 @@ def test_deviating_trial_form_is_bitwise_the_gather(ara):
     gather.  The fixed-point sums are exact, so the results are identical
     bit for bit: metric weights (AAL nearly constant, PML and TVaR nearly
     zero), deviating-trial counts at the sixteenth of the trials and one above,
-    a sub-range with a non-zero common value (gather) and one with zero."""
+    and sub-ranges with a non-zero common value (the occurrence counts then
+    come from the event-major slices the range covers whole and a count over
+    the slices it cuts) and with zero: cutting two slices, one, none (the
+    range on slice boundaries), and lying inside one slice."""
     import torch
     _say("workload 2 prefix (24k trials, 4 layers): both forms of W")
     w = synth.config(2, n_trials=24_000)
@@ -298,8 +303,15 @@ def test_deviating_trial_form_is_bitwise_the_gather(ara):
     four[3, :, :7] = 1.0
     cases.append(("four rows", four, 0, None))
     _, wts_sub = ara.metrics(ylt[:, 5000:17000].contiguous(), 0.95, want_weights=True)
-    cases.append(("sub-range, AAL row (gather)", wts_sub, 5000, 17000))
-    # most of the trials: those outside the range count as deviating (weight 0)
+    cases.append(("sub-range, AAL row", wts_sub, 5000, 17000))
+    st = sparse.slice_trials
+    assert 5000 % st and 17000 % st and 5000 // st != 17000 // st   # two cut slices
+    for a0, a1, label in [(st, 5 * st, "on slice boundaries"), (0, 2 * st + st // 3, "one cut slice"),
+                          (st + 17, 2 * st - 5, "inside one slice"), (3 * st + 1, 3 * st + 3, "two trials")]:
+        a1 = min(a1, n)
+        _, wts_r = ara.metrics(ylt[:, a0:a1].contiguous(), 0.9, want_weights=True)
+        cases.append((f"sub-range {label}, every row", wts_r, a0, a1))
+    # most of the trials
     _, wts_near = ara.metrics(ylt[:, 400:23400].contiguous(), 0.99, want_weights=True)
     cases.append(("near-full sub-range, every row", wts_near, 400, 23400))
     cases.append(("near-full sub-range, AAL row", wts_near[:1].contiguous(), 400, 23400))
@@ -325,7 +337,7 @@ def test_deviating_trial_form_full_size_vs_oracle(ara):
     a = sparse(s_pre, wts)
     b = dense(s_pre, wts)
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
-    # a range over 96% of the trials: the 40,000 outside it join the deviating ones (weight 0)
+    # a range over 96% of the trials: its first and last slices are cut
     t0, t1 = 20_000, w.yet.n_trials - 20_000
     _say("workload 3: both forms over trials [20000, 980000)")
     _, wsub = ara.metrics(ylt[:, t0:t1].contiguous(), w.p, want_weights=True)
