@@ -261,25 +261,21 @@ __global__ __launch_bounds__(256) void k_su_params(const uint64_t *__restrict__ 
 // ---------------------------------------------------------------------------
 // The draw.
 
-__device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
-    constexpr uint32_t kM0 = 0xD2511F53u, kM1 = 0xCD9E8D57u;
-    constexpr uint32_t kW0 = 0x9E3779B9u, kW1 = 0xBB67AE85u;
+// One round of Philox4x32 (Salmon et al., SC'11): the two 32 x 32-bit
+// products A x.x and B x.z, each formed by one 64-bit multiply, their high
+// halves mixed with the other two words and the round key.
+__device__ __forceinline__ uint4 philox_round(uint4 x, uint32_t k0, uint32_t k1) {
+    const uint64_t a = static_cast<uint64_t>(x.x) * 0xD2511F53u;
+    const uint64_t b = static_cast<uint64_t>(x.z) * 0xCD9E8D57u;
+    return make_uint4(static_cast<uint32_t>(b >> 32) ^ x.y ^ k0, static_cast<uint32_t>(b),
+                      static_cast<uint32_t>(a >> 32) ^ x.w ^ k1, static_cast<uint32_t>(a));
+}
+
+// Ten rounds; round r's key is the key plus r times the Weyl constants.
+__device__ __forceinline__ uint4 philox4x32_10(uint4 ctr, uint32_t k0, uint32_t k1) {
 #pragma unroll
-    for (int r = 0; r < 10; ++r) {
-        if (r > 0) {
-            k0 += kW0;
-            k1 += kW1;
-        }
-        // each full 64-bit product in one multiply (high and low words)
-        const uint64_t p0 = static_cast<uint64_t>(kM0) * c[0], p1 = static_cast<uint64_t>(kM1) * c[2];
-        const uint32_t hi0 = static_cast<uint32_t>(p0 >> 32), lo0 = static_cast<uint32_t>(p0);
-        const uint32_t hi1 = static_cast<uint32_t>(p1 >> 32), lo1 = static_cast<uint32_t>(p1);
-        const uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
-        c[0] = n0;
-        c[1] = lo1;
-        c[2] = n2;
-        c[3] = lo0;
-    }
+    for (uint32_t r = 0; r < 10; ++r) ctr = philox_round(ctr, k0 + r * 0x9E3779B9u, k1 + r * 0xBB67AE85u);
+    return ctr;
 }
 
 // One entry as two 16-byte loads issued together.
@@ -303,9 +299,10 @@ __device__ __forceinline__ SuEntry su_entry(const SuEntry *p) {
 // split the entry's loads around it.
 __device__ __forceinline__ double su_draw(const SuEntry &e, uint64_t seed, int64_t occ) {
     const uint64_t o = static_cast<uint64_t>(occ);
-    uint32_t c[4] = {static_cast<uint32_t>(o), static_cast<uint32_t>(o >> 32), static_cast<uint32_t>(e.k), 0u};
-    philox4x32_10(c, static_cast<uint32_t>(seed), static_cast<uint32_t>(seed >> 32));
-    const uint64_t b1 = (static_cast<uint64_t>(c[1]) << 32) | c[0], b2 = (static_cast<uint64_t>(c[3]) << 32) | c[2];
+    const uint4 w = philox4x32_10(make_uint4(static_cast<uint32_t>(o), static_cast<uint32_t>(o >> 32),
+                                             static_cast<uint32_t>(e.k), 0u),
+                                  static_cast<uint32_t>(seed), static_cast<uint32_t>(seed >> 32));
+    const uint64_t b1 = (static_cast<uint64_t>(w.y) << 32) | w.x, b2 = (static_cast<uint64_t>(w.w) << 32) | w.z;
     const double u1 = (static_cast<double>(b1 >> 12) + 0.5) * 0x1p-52;
     const double u2 = (static_cast<double>(b2 >> 12) + 0.5) * 0x1p-52;
     const double z = sqrt(-2.0 * su_log(u1)) * su_cos_2pi(u2);
