@@ -132,7 +132,8 @@ typedef struct ara_yet {
     /* positions (ARA_PREP_POSITIONS; NULL otherwise) */
     uint16_t *pos;               /* device [n_codes + 256]: at each occurrence code's index, the
                                     occurrence's position in its trial (its index in ids less
-                                    offsets[trial]); 0xFFFF at gap codes and padding */
+                                    offsets[trial]); 0xFFFF at gap codes and padding (the code
+                                    itself tells these from an occurrence at position 65535) */
 } ara_yet;
 
 /* prepare flags */
