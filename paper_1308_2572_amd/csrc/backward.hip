@@ -469,14 +469,16 @@ __global__ __launch_bounds__(256) void k_bwd_winit(BwdSparse P) {
     }
 }
 
-// (5c') the slices the call's range cuts: for every hot event, c times the
-// entries of its list in the slice that lie in the range.  Workgroup i works
-// on slice i mod 8, as the gather does; G lanes per hot event read its list
-// coalesced and count, and the count meets W in one integer atomic per row.
+// (5c') the slices the call's range cuts (cut[0 .. ncut), at most two): for
+// every hot event, c times the entries of its list in the slice that lie in
+// the range.  Workgroup i works on cut slice i mod ncut, so that every
+// workgroup has work; G lanes per hot event read its list coalesced and
+// count, and the count meets W in one integer atomic per row.
 template <int G>
-__global__ __launch_bounds__(256) void k_bwd_wcut(BwdSparse P) {
+__global__ __launch_bounds__(256) void k_bwd_wcut(BwdSparse P, int2 cut, int ncut) {
     constexpr int kU = 4;
-    const int x = blockIdx.x % kSlices, wi = blockIdx.x / kSlices, nw = gridDim.x / kSlices, j = blockIdx.y;
+    const int k = blockIdx.x % ncut, wi = blockIdx.x / ncut, nw = gridDim.x / ncut, j = blockIdx.y;
+    const int x = k == 0 ? cut.x : cut.y;
     if (!sparse_chosen(P, j) || !common_nonzero(P, j) || !slice_cut(P, x)) return;   // uniform
     const int64_t tx0 = static_cast<int64_t>(x) * P.slice_trials;
     const int64_t ulo = max<int64_t>(P.t0 - tx0, 0), uhi = min<int64_t>(P.t0 + P.n - tx0, P.slice_trials);
@@ -969,9 +971,20 @@ extern "C" int32_t ara_ylt_backward(const ara_tables *tables, const ara_yet *yet
             k_bwd_dev<<<dim3(gt, L), 1024, 0, st>>>(Q);
             const unsigned gh = static_cast<unsigned>(std::min<int64_t>((tables->catalog + 255) / 256, 1024));
             k_bwd_winit<<<dim3(gh, L), 256, 0, st>>>(Q);
-            if (trial_begin != 0 || trial_end != yet->n_trials) {   // some slice may be cut
-                if (wide) k_bwd_wcut<16><<<grid, 256, 0, st>>>(Q);
-                else k_bwd_wcut<4><<<grid, 256, 0, st>>>(Q);
+            // the slices the range cuts: at most its first and its last
+            int cut[2], ncut = 0;
+            for (int64_t t : {trial_begin, trial_end - 1}) {
+                const int x = static_cast<int>(t / yet->slice_trials);
+                const int64_t lo = static_cast<int64_t>(x) * yet->slice_trials;
+                const int64_t hi = std::min(lo + yet->slice_trials, yet->n_trials);
+                const bool inside = lo >= trial_begin && hi <= trial_end;
+                if (n > 0 && !inside && (ncut == 0 || cut[0] != x)) cut[ncut++] = x;
+            }
+            if (ncut > 0) {
+                const dim3 gc(static_cast<unsigned>(ncut * std::max(1, (4 * cu) / ncut)), L);
+                const int2 cx = make_int2(cut[0], ncut > 1 ? cut[1] : cut[0]);
+                if (wide) k_bwd_wcut<16><<<gc, 256, 0, st>>>(Q, cx, ncut);
+                else k_bwd_wcut<4><<<gc, 256, 0, st>>>(Q, cx, ncut);
             }
             k_bwd_wsparse<<<dim3(2048, L), 256, 0, st>>>(Q);
         }
