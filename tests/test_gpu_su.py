@@ -172,6 +172,33 @@ def test_config1_full_size_sampled(ara):
         assert_close(y[:, t0:t1], s[:, t0:t1], ref)
 
 
+def test_config2_full_size_sampled_and_layers_alone(ara):
+    """1M x Poisson(1000), four layers over 55 ELTs: the layers of a block
+    dealt to one XCD back to back over all blocks; the oracle on three trial
+    windows, and one layer run alone equal to its row bit for bit."""
+    import torch
+    _say("workload 2: generating 1M x Poisson(1000), 4 layers")
+    w = synth.config(2)
+    sg = synth.record_sigmas(synth.SEED_BASE + 22, w.elts)
+    e = Su(ara, w, sg)
+    _say("workload 2: secondary-uncertainty forward, four layers")
+    y, s = e.run(2026)
+    th = oracle.num_threads_available()
+    tb = oracle.build_tables(w.elts)
+    st = oracle.build_sigma_tables(w.elts, sg)
+    for t0, t1 in [(0, 600), (333_000, 333_700), (w.yet.n_trials - 600, w.yet.n_trials)]:
+        _say(f"workload 2: oracle on trials [{t0}, {t1})")
+        ref = oracle.forward_su(tb, st, w.yet, w.layers, w.elts.terms, w.layers.terms, 2026, t0, t1, n_threads=th)
+        assert_close(y[:, t0:t1], s[:, t0:t1], ref)
+    off, ids = w.layers.elt_off, w.layers.elt_ids
+    j = 2
+    lay = ara.Layers(np.array([0, off[j + 1] - off[j]], np.int32), ids[off[j]:off[j + 1]])
+    lt = torch.tensor(np.asarray(w.layers.terms)[j:j + 1], dtype=torch.float64, device="cuda")
+    _say("workload 2: layer 2 alone")
+    yj, sj = e.run(2026, layers=lay, lt=lt)
+    assert np.array_equal(yj[0], y[j]) and np.array_equal(sj[0], s[j])
+
+
 def test_errors(ara):
     import torch
     w = synth.tiny_random(2, n_trials=30, max_events=10, n_layers=1)
