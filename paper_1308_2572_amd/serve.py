@@ -99,3 +99,33 @@ def run_benchmark(tables, yet, elt_terms, requests: List, p: float = 0.99, quote
         "shared_block_item_frac": (stats["shared_block_items"] - base["shared_block_items"]) / max(items, 1),
         "server": stats,
     }
+
+
+def main(argv=None) -> int:
+    """Replay quotes through the server over the resident serving workload
+    (1,000,000 trials x Poisson(1000) events, 200 ELTs) and print one JSON
+    line; by default 600 quotes all arriving at once (a saturating burst)."""
+    import argparse
+    import json
+
+    import synth
+    from . import EltTables, PreparedYet
+    ap = argparse.ArgumentParser(description=main.__doc__)
+    ap.add_argument("--requests", type=int, default=600)
+    ap.add_argument("--rate", type=float, default=1e9, help="Poisson arrivals per second (1e9: all at once)")
+    ap.add_argument("--seed", type=int, default=synth.SEED_BASE + 40)
+    ap.add_argument("--plain-sample", type=int, default=1, help="quotes also timed through the batch entry points")
+    args = ap.parse_args(argv)
+    w = synth.config(4)
+    tables = EltTables.from_numpy(w.elts)
+    yet = PreparedYet.from_numpy(w.yet)
+    et = torch.tensor(w.elts.terms, dtype=torch.float64, device="cuda")
+    reqs = synth.serving_requests(args.requests, w.yet.n_trials, n_elts=w.elts.n_elts, rate_per_s=args.rate,
+                                  seed=args.seed)
+    out = run_benchmark(tables, yet, et, reqs, p=0.99, plain_sample=max(1, args.plain_sample))
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    raise SystemExit(main())
