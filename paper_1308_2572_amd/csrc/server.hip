@@ -55,8 +55,12 @@ class HipExecutor final : public SchedExecutor {
     char *arena_base = nullptr;
     OccLayoutSizes z{};
     size_t res_doubles = 0;                // per slot: 3 metrics + 3*4 layer grads + 3*n_elts*3 ELT grads
-    double *h_res = nullptr;               // pinned host, [max_slots][res_doubles]
-    int32_t *h_status = nullptr;           // pinned host, [max_slots]: each quote's device-side status
+    // A quote's status word and its results sit side by side in its arena
+    // range (the status first, kResOff bytes before the results) and come back
+    // in one copy into its slot of the pinned host stage.
+    static constexpr size_t kResOff = 256;
+    size_t stage_bytes = 0;                // kResOff + res_doubles * 8
+    char *h_stage = nullptr;               // pinned host, [max_slots][stage_bytes]
     hipStream_t st = nullptr;
     FwdItem *d_items[kRing] = {nullptr, nullptr};
     FwdItem *h_items[kRing] = {nullptr, nullptr};
@@ -70,9 +74,10 @@ class HipExecutor final : public SchedExecutor {
         Carver c(nullptr);
         c.take<int32_t>(2);
         c.take<int32_t>(j.elt_ids.size() + 1);
-        c.take<int32_t>(64);   // the quote's device-side status word
         c.take<double>(4);
         c.take<OccTables>(1);
+        c.take<int32_t>(kResOff / sizeof(int32_t));   // the quote's device-side status word
+        c.take<double>(res_doubles);
         size_t b = c.bytes() + z.per_layer;
         Carver d(nullptr);
         d.take<double>(static_cast<size_t>(n));   // ylt
@@ -80,7 +85,6 @@ class HipExecutor final : public SchedExecutor {
         size_t mb = 0;
         ara_metrics_workspace_bytes(1, n, &mb);
         d.take<char>(mb);
-        d.take<double>(res_doubles);
         if (j.q.want_grad) {
             d.take<double>(static_cast<size_t>(3) * n);   // weights
             size_t bb = 0;
@@ -109,15 +113,15 @@ class HipExecutor final : public SchedExecutor {
         Carver c(arena_base + j.mem_off);
         d->d_off = c.take<int32_t>(2);
         d->d_ids = c.take<int32_t>(j.elt_ids.size() + 1);
-        d->d_err = c.take<int32_t>(64);
         d->d_lterm = c.take<double>(4);
         d->d_tab = c.take<OccTables>(1);
+        d->d_err = c.take<int32_t>(kResOff / sizeof(int32_t));
+        d->d_res = c.take<double>(res_doubles);
         d->tab = occ_carve(c, z, false);
         d->ylt = c.take<double>(static_cast<size_t>(n));
         d->s_pre = c.take<double>(static_cast<size_t>(n));
         ara_metrics_workspace_bytes(1, n, &d->met_bytes);
         d->met_ws = c.take<char>(d->met_bytes);
-        d->d_res = c.take<double>(res_doubles);
         d->h_off[1] = static_cast<int32_t>(j.elt_ids.size());
         if (j.q.want_grad) {
             d->weights = c.take<double>(static_cast<size_t>(3) * n);
@@ -132,13 +136,16 @@ class HipExecutor final : public SchedExecutor {
             return ARA_E_HIP;
         }
         ++events_created;
-        int32_t rc = hip_step(hipMemcpyAsync(d->d_off, d->h_off, 2 * sizeof(int32_t), hipMemcpyHostToDevice, st), err);
-        if (!rc && !j.elt_ids.empty())
-            rc = hip_step(hipMemcpyAsync(d->d_ids, j.elt_ids.data(), j.elt_ids.size() * sizeof(int32_t),
-                                         hipMemcpyHostToDevice, st), err);
-        if (!rc) rc = hip_step(hipMemcpyAsync(d->d_lterm, j.q.layer_terms, 4 * sizeof(double), hipMemcpyHostToDevice, st), err);
-        if (!rc) rc = hip_step(hipMemcpyAsync(d->d_tab, &d->tab, sizeof(OccTables), hipMemcpyHostToDevice, st), err);
-        if (!rc) rc = hip_step(hipMemsetAsync(d->d_err, 0, sizeof(int32_t), st), err);
+        // the quote's lists, terms and table descriptor in one copy, which
+        // also clears its status word and results
+        HeadImage img(arena_base + j.mem_off);
+        img.put(d->d_off, d->h_off, 2);
+        img.put(d->d_ids, j.elt_ids.data(), j.elt_ids.size());
+        img.put(d->d_lterm, j.q.layer_terms, 4);
+        img.put(d->d_tab, &d->tab, 1);
+        img.cover(d->d_res + res_doubles);
+        int32_t rc = img.send(st);
+        if (rc) *err = "copy of the quote's head failed";
         // the quote's occurrence table; invalid terms set its own status word
         if (!rc && (rc = launch_occ(&tables, d->d_off, d->d_ids, elt_terms, d->d_lterm, 1, false, false, d->d_tab, z.n_sr,
                                     d->d_err, st)))
@@ -204,10 +211,8 @@ class HipExecutor final : public SchedExecutor {
             }
         }
         const size_t slot = static_cast<size_t>(j.slot);
-        if ((rc = hip_step(hipMemcpyAsync(h_res + slot * res_doubles, d->d_res, res_doubles * sizeof(double),
-                                          hipMemcpyDeviceToHost, st), err)))
-            return rc;
-        if ((rc = hip_step(hipMemcpyAsync(h_status + slot, d->d_err, sizeof(int32_t), hipMemcpyDeviceToHost, st), err)))
+        if ((rc = hip_step(hipMemcpyAsync(h_stage + slot * stage_bytes, d->d_err, stage_bytes, hipMemcpyDeviceToHost, st),
+                           err)))
             return rc;
         return hip_step(hipEventRecord(d->done_ev, st), err);
     }
@@ -220,9 +225,10 @@ class HipExecutor final : public SchedExecutor {
     int32_t collect(SchedJob &j) override {
         const DevJob *d = static_cast<const DevJob *>(j.exec);
         if (hipEventQuery(d->done_ev) != hipSuccess) return ARA_E_HIP;
-        const size_t slot = static_cast<size_t>(j.slot);
-        if (h_status[slot] != ARA_OK) return h_status[slot];
-        const double *r = h_res + slot * res_doubles;
+        const char *stage = h_stage + static_cast<size_t>(j.slot) * stage_bytes;
+        const int32_t status = *reinterpret_cast<const int32_t *>(stage);
+        if (status != ARA_OK) return status;
+        const double *r = reinterpret_cast<const double *>(stage + kResOff);
         const size_t J = j.elt_ids.size();
         j.res.assign(15 + 9 * J, 0.0);
         std::copy(r, r + 15, j.res.begin());
@@ -271,8 +277,7 @@ static void free_host(Server *S) {
         if (S->ex.item_ev[r]) hipEventDestroy(S->ex.item_ev[r]);
         if (S->ex.h_items[r]) hipHostFree(S->ex.h_items[r]);
     }
-    if (S->ex.h_res) hipHostFree(S->ex.h_res);
-    if (S->ex.h_status) hipHostFree(S->ex.h_status);
+    if (S->ex.h_stage) hipHostFree(S->ex.h_stage);
     if (S->ex.st) hipStreamDestroy(S->ex.st);
 }
 
@@ -303,15 +308,13 @@ extern "C" int32_t ara_server_create(const ara_tables *tables, const ara_yet *ye
     X.elt_terms = elt_terms;
     X.z = occ_sizes(tables->catalog, false);
     X.res_doubles = 3 + 12 + static_cast<size_t>(3) * tables->n_elts * 3;
+    X.stage_bytes = HipExecutor::kResOff + X.res_doubles * sizeof(double);
     for (int r = 0; r < HipExecutor::kRing; ++r)
         X.d_items[r] = reinterpret_cast<FwdItem *>(static_cast<char *>(arena) + r * HipExecutor::kMaxItems * sizeof(FwdItem));
     X.arena_base = static_cast<char *>(arena) + ring_bytes();
     hipError_t e = hipStreamCreateWithFlags(&X.st, hipStreamNonBlocking);
     if (e == hipSuccess)
-        e = hipHostMalloc(reinterpret_cast<void **>(&X.h_res), X.res_doubles * max_slots * sizeof(double),
-                          hipHostMallocDefault);
-    if (e == hipSuccess)
-        e = hipHostMalloc(reinterpret_cast<void **>(&X.h_status), max_slots * sizeof(int32_t), hipHostMallocDefault);
+        e = hipHostMalloc(reinterpret_cast<void **>(&X.h_stage), X.stage_bytes * max_slots, hipHostMallocDefault);
     for (int r = 0; e == hipSuccess && r < HipExecutor::kRing; ++r) {
         e = hipHostMalloc(reinterpret_cast<void **>(&X.h_items[r]), HipExecutor::kMaxItems * sizeof(FwdItem),
                           hipHostMallocDefault);
