@@ -101,6 +101,27 @@ class HeadImage {
     std::vector<unsigned char> buf_;
 };
 
+// One YLT row of a metrics launch (the quote server's quotes that finish in
+// one iteration share a launch): its values, its results (AAL, PML, TVaR),
+// its weights ([3] rows wstride apart, or none), its length and rank, and
+// the pieces of its metrics workspace.
+struct MetRow {
+    const double *ylt;
+    double *out;
+    double *w;
+    int64_t wstride, n, r;
+    int32_t nwg, pad;
+    uint32_t *hist;    // [2][2048]
+    void *st, *part;   // the row's selection state and per-workgroup partials
+    uint64_t *cand;    // [n]
+};
+// The row over a workspace of ara_metrics_workspace_bytes(1, n) bytes.
+MetRow metrics_row(void *ws, const double *ylt, int64_t n, double p, double *out, double *w);
+// The metrics (and the weights of the rows that have them) of the n_rows
+// rows listed at d_rows (device memory); their workspaces are cleared here,
+// by a kernel.  max_nwg / max_n: the largest nwg and n among the rows.
+int32_t metrics_rows(const MetRow *d_rows, int n_rows, int max_nwg, int64_t max_n, bool any_weights, hipStream_t st);
+
 // Records a start/stop HIP event pair around the enclosed launches when
 // profiling is enabled (ara_profile_enable); no-op otherwise.
 class ProfScope {

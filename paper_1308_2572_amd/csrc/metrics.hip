@@ -13,6 +13,10 @@
 // in the workgroup that finishes last (a counter per layer), so a call is
 // three kernels whatever the ties.  Sums use a fixed partition of the trials,
 // fixed-order trees and exact integer sums, so every result is deterministic.
+//
+// A launch serves several rows (blockIdx.y): the layers of one call, rows of
+// one length in one workspace, or a list of rows each with its own length,
+// rank and workspace (the quote server's quotes finishing together).
 #include "ara_internal.h"
 #include "wave.h"
 
@@ -50,6 +54,39 @@ struct MetPart {
     uint64_t kmax;     // the largest gathered key of the workgroup
     int64_t n_kmax;    // how many of its gathered keys equal it
 };
+
+// The rows of a launch: `rows` lists rows of their own (MetRow, declared with
+// the internal interface), or, when it is null, n_rows rows of length n laid
+// out one after another in one workspace.
+struct MetCall {
+    const MetRow *rows;
+    const double *ylt;
+    double *out, *w;
+    int64_t n, r;
+    int32_t nwg, n_rows;
+    uint32_t *hist;
+    MetState *st;
+    MetPart *part;
+    uint64_t *cand;
+};
+
+__device__ __forceinline__ MetRow met_row(const MetCall &c, int l) {
+    if (c.rows) return c.rows[l];
+    MetRow m;
+    m.ylt = c.ylt + static_cast<size_t>(l) * c.n;
+    m.out = c.out + 3 * l;
+    m.w = c.w ? c.w + static_cast<size_t>(l) * c.n : nullptr;
+    m.wstride = static_cast<int64_t>(c.n_rows) * c.n;
+    m.n = c.n;
+    m.r = c.r;
+    m.nwg = c.nwg;
+    m.pad = 0;
+    m.hist = c.hist + static_cast<size_t>(l) * 2 * kBins;
+    m.st = reinterpret_cast<char *>(c.st + l);
+    m.part = reinterpret_cast<char *>(c.part + static_cast<size_t>(l) * c.nwg);
+    m.cand = c.cand + static_cast<size_t>(l) * c.n;
+    return m;
+}
 
 __device__ __forceinline__ uint64_t key_of(double y) {
     return (y == 0.0) ? 0ull : static_cast<uint64_t>(__double_as_longlong(y));
@@ -145,15 +182,17 @@ __device__ void find_digit(const uint32_t *h, int bins, int64_t need, FindShared
 // the values whose higher bits equal the prefix selected so far.  Pass 0 also
 // forms the fixed-partition partial sums for the mean.  The last workgroup
 // selects the digit for the next pass.
-__global__ __launch_bounds__(kMetThreads) void k_met_hist(const double *__restrict__ ylt, int64_t n, int nwg, int d,
-                                                         uint32_t *__restrict__ hist, MetState *__restrict__ st,
-                                                         MetPart *__restrict__ part, int64_t r) {
+__global__ __launch_bounds__(kMetThreads) void k_met_hist(MetCall call, int d) {
     __shared__ uint32_t h[kBins];
     __shared__ FindShared fs;
     __shared__ double red[1][16];
     __shared__ int flag;
-    const int l = blockIdx.y, wg = blockIdx.x, tid = threadIdx.x, lane = tid & 63;
-    MetState &S = st[l];
+    const int wg = blockIdx.x, tid = threadIdx.x, lane = tid & 63;
+    const MetRow R = met_row(call, blockIdx.y);
+    if (wg >= R.nwg) return;   // uniform over the workgroup, before any barrier
+    const int64_t n = R.n, r = R.r;
+    const int nwg = R.nwg;
+    MetState &S = *reinterpret_cast<MetState *>(R.st);
     const uint64_t prefix = d ? S.prefix[1] : 0ull;
     for (int i = tid; i < kBins; i += kMetThreads) h[i] = 0;
     __syncthreads();
@@ -161,7 +200,7 @@ __global__ __launch_bounds__(kMetThreads) void k_met_hist(const double *__restri
     const uint32_t mask = (1u << kWidth[d]) - 1u;
     int64_t lo, hi;
     chunk_of(n, nwg, wg, lo, hi);
-    const double *y = ylt + static_cast<size_t>(l) * n;
+    const double *y = R.ylt;
     double s = 0.0;
     for (int64_t i0 = lo; i0 < hi; i0 += kMetSweep) {   // uniform trip count: every lane reaches the ballots
         double v[kMetUnroll];
@@ -193,10 +232,10 @@ __global__ __launch_bounds__(kMetThreads) void k_met_hist(const double *__restri
     if (d == 0) {
         double t[1] = {s};
         block_sums(t, red);
-        if (tid == 0) part[static_cast<size_t>(l) * nwg + wg].sum = t[0];
+        if (tid == 0) reinterpret_cast<MetPart *>(R.part)[wg].sum = t[0];
     }
     __syncthreads();
-    uint32_t *hd = hist + (static_cast<size_t>(d) * gridDim.y + l) * kBins;
+    uint32_t *hd = R.hist + static_cast<size_t>(d) * kBins;
     for (int i = tid; i < kBins; i += kMetThreads)
         if (h[i]) atomicAdd(&hd[i], h[i]);
     if (!finished_last(S, d, nwg, &flag)) return;
@@ -231,9 +270,7 @@ __device__ __forceinline__ void each_cand(bool in_lds, const uint64_t *cs, const
 // Gathers every value whose 23-bit prefix is the selected one (a wavefront
 // reserves its slots with one atomic), with their smallest and largest key.
 // The last workgroup finishes digits 2..5 on them.
-__global__ __launch_bounds__(kMetThreads) void k_met_collect(const double *__restrict__ ylt, int64_t n, int nwg,
-                                                            MetState *__restrict__ st, uint64_t *__restrict__ cand,
-                                                            MetPart *__restrict__ part, double *__restrict__ out) {
+__global__ __launch_bounds__(kMetThreads) void k_met_collect(MetCall call) {
     __shared__ uint64_t cs[kCandCap];
     __shared__ uint32_t h[kBins];
     __shared__ FindShared fs;
@@ -242,16 +279,21 @@ __global__ __launch_bounds__(kMetThreads) void k_met_collect(const double *__res
     __shared__ unsigned long long wkm[kMetThreads / 64];
     __shared__ long long wkn[kMetThreads / 64];
     __shared__ int flag;
-    const int l = blockIdx.y, wg = blockIdx.x, tid = threadIdx.x, lane = tid & 63;
-    MetState &S = st[l];
+    const int wg = blockIdx.x, tid = threadIdx.x, lane = tid & 63;
+    const MetRow R = met_row(call, blockIdx.y);
+    if (wg >= R.nwg) return;   // uniform over the workgroup, before any barrier
+    const int64_t n = R.n;
+    const int nwg = R.nwg;
+    MetState &S = *reinterpret_cast<MetState *>(R.st);
+    MetPart *const part = reinterpret_cast<MetPart *>(R.part);
     const uint64_t prefix = S.prefix[2];
     double s_above = 0.0;   // values above the bin (all above the PML value)
     int64_t n_above = 0;
     const int hb = kShift[1];
     int64_t lo, hi;
     chunk_of(n, nwg, wg, lo, hi);
-    const double *y = ylt + static_cast<size_t>(l) * n;
-    uint64_t *c = cand + static_cast<size_t>(l) * n;
+    const double *y = R.ylt;
+    uint64_t *c = R.cand;
     uint64_t kmin = ~0ull, kmax = 0ull;
     int64_t nkmax = 0;   // this lane's gathered keys equal to its kmax
     for (int64_t i0 = lo; i0 < hi; i0 += kMetSweep) {
@@ -321,7 +363,7 @@ __global__ __launch_bounds__(kMetThreads) void k_met_collect(const double *__res
         double t2[2] = {s_above, static_cast<double>(n_above)};
         block_sums(t2, red);   // also publishes wkm and wkn
         if (tid == 0) {
-            MetPart *pw = part + static_cast<size_t>(l) * nwg + wg;
+            MetPart *pw = part + wg;
             put(&pw->sum_gt, t2[0]);
             put(&pw->cnt_gt, static_cast<int64_t>(t2[1]));
             unsigned long long km = 0ull;
@@ -343,7 +385,7 @@ __global__ __launch_bounds__(kMetThreads) void k_met_collect(const double *__res
     int64_t n_top = 0;
     if (lo_key != hi_key && cn > kCandCap) {   // uniform
         long long v = 0;
-        const MetPart *pl = part + static_cast<size_t>(l) * nwg;
+        const MetPart *pl = part;
         for (int i = tid; i < nwg; i += kMetThreads)
             if (get(&pl[i].kmax) == hi_key) v += get(&pl[i].n_kmax);
         for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
@@ -441,7 +483,7 @@ __global__ __launch_bounds__(kMetThreads) void k_met_collect(const double *__res
         __syncthreads();
     }
     // the sums over the workgroups, in a fixed order
-    MetPart *pl = part + static_cast<size_t>(l) * nwg;
+    MetPart *pl = part;
     double t4[3] = {0.0, 0.0, 0.0};
     for (int i = tid; i < nwg; i += kMetThreads) {
         t4[0] += pl[i].sum;   // written by an earlier kernel
@@ -459,25 +501,25 @@ __global__ __launch_bounds__(kMetThreads) void k_met_collect(const double *__res
         S.thr = thr;
         S.cnt_gt = tgt;
         S.cnt_eq = static_cast<int64_t>(c_eq);
-        out[3 * l + 0] = t4[0] / static_cast<double>(n);
-        out[3 * l + 1] = thr;
-        out[3 * l + 2] = (tsg + static_cast<double>(r - tgt) * thr) / static_cast<double>(r);
+        R.out[0] = t4[0] / static_cast<double>(n);
+        R.out[1] = thr;
+        R.out[2] = (tsg + static_cast<double>(r - tgt) * thr) / static_cast<double>(r);
     }
 }
 
-__global__ void k_met_weights(const double *__restrict__ ylt, int64_t n, int n_layers, const MetState *__restrict__ st,
-                              double *__restrict__ w) {
-    const int l = blockIdx.y;
-    const double thr = st[l].thr;
-    const int64_t r = st[l].r, gt = st[l].cnt_gt, eq = st[l].cnt_eq;
+__global__ void k_met_weights(MetCall call) {
+    const MetRow R = met_row(call, blockIdx.y);
+    if (!R.w) return;
+    const MetState &S = *reinterpret_cast<const MetState *>(R.st);
+    const int64_t n = R.n;
+    const double thr = S.thr;
+    const int64_t r = S.r, gt = S.cnt_gt, eq = S.cnt_eq;
     const double inv_n = 1.0 / static_cast<double>(n);
     const double w_pml = 1.0 / static_cast<double>(eq);
     const double w_gt = 1.0 / static_cast<double>(r);
     const double w_eq = static_cast<double>(r - gt) / (static_cast<double>(r) * static_cast<double>(eq));
-    const double *y = ylt + static_cast<size_t>(l) * n;
-    double *wa = w + (static_cast<size_t>(0) * n_layers + l) * n;
-    double *wp = w + (static_cast<size_t>(1) * n_layers + l) * n;
-    double *wt = w + (static_cast<size_t>(2) * n_layers + l) * n;
+    const double *y = R.ylt;
+    double *wa = R.w, *wp = R.w + R.wstride, *wt = R.w + 2 * R.wstride;
     for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
          i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
         const double v = y[i];
@@ -502,6 +544,30 @@ __global__ void k_met_vjp(const double *__restrict__ w, int64_t n, int n_layers,
 
 static int met_nwg(int64_t n) {
     return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>((n + kMetSweep - 1) / kMetSweep, 1024)));
+}
+
+static int64_t met_rank(int64_t n, double p) {
+    const int64_t r = n - static_cast<int64_t>(std::floor(p * static_cast<double>(n) + 1e-9));
+    return std::max<int64_t>(1, std::min<int64_t>(n, r));
+}
+
+// Clears each listed row's histograms and selection state.
+__global__ __launch_bounds__(256) void k_met_clear(MetCall call) {
+    const MetRow R = met_row(call, blockIdx.y);
+    for (int i = threadIdx.x; i < 2 * kBins; i += blockDim.x) R.hist[i] = 0;
+    uint32_t *sw = reinterpret_cast<uint32_t *>(R.st);
+    for (int i = threadIdx.x; i < static_cast<int>(sizeof(MetState) / 4); i += blockDim.x) sw[i] = 0;
+}
+
+static void met_launch(const MetCall &call, int max_nwg, int64_t max_n, bool weights, hipStream_t st) {
+    const dim3 grid(static_cast<unsigned>(max_nwg), static_cast<unsigned>(call.n_rows));
+    k_met_hist<<<grid, kMetThreads, 0, st>>>(call, 0);
+    k_met_hist<<<grid, kMetThreads, 0, st>>>(call, 1);
+    k_met_collect<<<grid, kMetThreads, 0, st>>>(call);
+    if (weights) {
+        const unsigned gx = static_cast<unsigned>(std::max<int64_t>(1, std::min<int64_t>((max_n + 255) / 256, 4096)));
+        k_met_weights<<<dim3(gx, static_cast<unsigned>(call.n_rows)), 256, 0, st>>>(call);
+    }
 }
 
 static size_t met_bytes(int32_t L, int64_t n) {
@@ -543,20 +609,58 @@ extern "C" int32_t ara_metrics(const double *ylt, int32_t n_layers, int64_t n, d
     const size_t clear = reinterpret_cast<char *>(part) - reinterpret_cast<char *>(hdr);
     ARA_HIP(hipMemsetAsync(hdr, 0, clear, st));
     if (n_layers == 0) return ARA_OK;
-    int64_t r = n - static_cast<int64_t>(std::floor(p * static_cast<double>(n) + 1e-9));
-    r = std::max<int64_t>(1, std::min<int64_t>(n, r));
-    dim3 grid(static_cast<unsigned>(nwg), static_cast<unsigned>(n_layers));
+    MetCall call{};
+    call.ylt = ylt;
+    call.out = out;
+    call.w = weights;
+    call.n = n;
+    call.r = met_rank(n, p);
+    call.nwg = nwg;
+    call.n_rows = n_layers;
+    call.hist = hist;
+    call.st = state;
+    call.part = part;
+    call.cand = cand;
     ProfScope prof(ARA_PROF_METRICS, st);
-    k_met_hist<<<grid, kMetThreads, 0, st>>>(ylt, n, nwg, 0, hist, state, part, r);
-    k_met_hist<<<grid, kMetThreads, 0, st>>>(ylt, n, nwg, 1, hist, state, part, r);
-    k_met_collect<<<grid, kMetThreads, 0, st>>>(ylt, n, nwg, state, cand, part, out);
-    if (weights) {
-        const unsigned gx = static_cast<unsigned>(std::min<int64_t>((n + 255) / 256, 4096));
-        k_met_weights<<<dim3(gx, static_cast<unsigned>(n_layers)), 256, 0, st>>>(ylt, n, n_layers, state, weights);
-    }
+    met_launch(call, nwg, n, weights != nullptr, st);
     ARA_HIP(hipGetLastError());
     return ARA_OK;
 }
+
+namespace ara {
+
+MetRow metrics_row(void *ws, const double *ylt, int64_t n, double p, double *out, double *w) {
+    const int nwg = met_nwg(n);
+    Carver c(ws);   // the layout of a one-row ara_metrics workspace
+    c.take<int32_t>(kWsHeaderBytes / 4);
+    MetRow m{};
+    m.hist = c.take<uint32_t>(static_cast<size_t>(2) * kBins);
+    m.st = c.take<MetState>(1);
+    m.part = c.take<MetPart>(static_cast<size_t>(nwg));
+    m.cand = c.take<uint64_t>(static_cast<size_t>(n));
+    m.ylt = ylt;
+    m.out = out;
+    m.w = w;
+    m.wstride = n;
+    m.n = n;
+    m.r = met_rank(n, p);
+    m.nwg = nwg;
+    return m;
+}
+
+int32_t metrics_rows(const MetRow *d_rows, int n_rows, int max_nwg, int64_t max_n, bool any_weights, hipStream_t st) {
+    if (n_rows <= 0) return ARA_OK;
+    MetCall call{};
+    call.rows = d_rows;
+    call.n_rows = n_rows;
+    ProfScope prof(ARA_PROF_METRICS, st);
+    k_met_clear<<<dim3(1, static_cast<unsigned>(n_rows)), 256, 0, st>>>(call);
+    met_launch(call, max_nwg, max_n, any_weights, st);
+    ARA_HIP(hipGetLastError());
+    return ARA_OK;
+}
+
+}  // namespace ara
 
 extern "C" int32_t ara_metrics_vjp(const double *weights, int32_t n_layers, int64_t n, const double *grad_out,
                                    double *grad_ylt, void *stream) {

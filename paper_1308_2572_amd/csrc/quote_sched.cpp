@@ -288,11 +288,10 @@ void Scheduler::loop() {
                 if (s.job) ++per_block[s.block];
             for (auto &kv : per_block)
                 if (kv.second > 1) n_shared += kv.second;
-            for (SchedJob *j : completed) {
-                if (rc) break;
-                rc = ex_->finish(*j, &err);
+            if (!rc && !completed.empty()) rc = ex_->finish_all(completed, &err);
+            {
                 std::lock_guard<std::mutex> lk(mu_);
-                j->stage = kFinishing;
+                for (SchedJob *j : completed) j->stage = kFinishing;
             }
             std::lock_guard<std::mutex> lk(mu_);
             ++launches_;

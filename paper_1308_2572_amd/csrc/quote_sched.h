@@ -81,6 +81,15 @@ class SchedExecutor {
     virtual int32_t launch(const std::vector<SchedItem> &items, bool shared, std::string *err) = 0;
     // after the launch holding its last block: metrics, backward, result copy
     virtual int32_t finish(SchedJob &j, std::string *err) = 0;
+    // every quote whose last block the launch held; one at a time unless the
+    // executor does better (the device executor shares the metrics launches)
+    virtual int32_t finish_all(const std::vector<SchedJob *> &jobs, std::string *err) {
+        for (SchedJob *j : jobs) {
+            const int32_t rc = finish(*j, err);
+            if (rc) return rc;
+        }
+        return 0;
+    }
     // has the quote's finishing work completed?
     virtual bool done(SchedJob &j) = 0;
     // fills j.res; returns the quote's device-side status (ARA_OK if none)

@@ -9,8 +9,9 @@
 // of the forward kernel, completion and retirement) is the HIP-free core in
 // quote_sched.cpp; this file is its executor on the device: each admitted quote's
 // occurrence table, the packed forward launches (the items of one block dealt
-// to one XCD, their codes loaded through its L2), and each finished quote's
-// metrics, backward and result copy, observed with an event.
+// to one XCD, their codes loaded through its L2), the metrics of the quotes
+// that a launch finishes (one row each, all in one set of launches), and each
+// finished quote's backward and result copy, observed with an event.
 //
 // Per-quote results do not depend on what else is in flight: every block of
 // a quote is computed by the same kernel in the same order, alone or packed.
@@ -41,6 +42,7 @@ struct DevJob {
     double *ylt = nullptr, *s_pre = nullptr, *weights = nullptr, *d_res = nullptr;
     void *met_ws = nullptr, *bwd_ws = nullptr;
     size_t met_bytes = 0, bwd_bytes = 0;
+    MetRow row{};                          // its metrics row over ylt, met_ws, d_res and weights
     hipEvent_t done_ev = nullptr;
 };
 
@@ -48,6 +50,7 @@ class HipExecutor final : public SchedExecutor {
    public:
     static constexpr int kRing = 2;        // forward launches whose item lists may be in flight
     static constexpr int kMaxItems = 4096;
+    static constexpr int kMaxRows = 256;   // quotes finishing together: at most one per slot
 
     ara_tables tables{};
     ara_yet yet{};
@@ -67,6 +70,12 @@ class HipExecutor final : public SchedExecutor {
     hipEvent_t item_ev[kRing] = {nullptr, nullptr};
     bool item_used[kRing] = {false, false};
     int ring = 0;
+    // the metrics rows of the quotes finishing after one launch, same ring scheme
+    MetRow *d_rows[kRing] = {nullptr, nullptr};
+    MetRow *h_rows[kRing] = {nullptr, nullptr};
+    hipEvent_t row_ev[kRing] = {nullptr, nullptr};
+    bool row_used[kRing] = {false, false};
+    int row_ring = 0;
     int64_t events_created = 0, events_destroyed = 0;
 
     size_t bytes_of(const SchedJob &j) const {
@@ -129,6 +138,7 @@ class HipExecutor final : public SchedExecutor {
             ara_ylt_backward_workspace_bytes(&tables, &yet, &L, 3, &d->bwd_bytes);
             d->bwd_ws = c.take<char>(d->bwd_bytes);
         }
+        d->row = metrics_row(d->met_ws, d->ylt, n, j.q.p, d->d_res, d->weights);
         hipError_t e = hipEventCreateWithFlags(&d->done_ev, hipEventDisableTiming);
         if (e != hipSuccess) {
             d->done_ev = nullptr;
@@ -193,28 +203,62 @@ class HipExecutor final : public SchedExecutor {
     }
 
     int32_t finish(SchedJob &j, std::string *err) override {
-        DevJob *d = static_cast<DevJob *>(j.exec);
-        const int64_t n = j.q.trial_end - j.q.trial_begin;
+        SchedJob *one = &j;
+        return finish_all(std::vector<SchedJob *>(1, one), err);
+    }
+
+    // The metrics of all the quotes at once (one row each, in one set of
+    // launches), then each quote's backward and its copy back.
+    int32_t finish_all(const std::vector<SchedJob *> &jobs, std::string *err) override {
+        if (jobs.empty()) return ARA_OK;
+        if (static_cast<int>(jobs.size()) > kMaxRows) {
+            *err = "too many quotes finishing at once";
+            return ARA_E_LIMIT;
+        }
         int32_t rc;
-        if ((rc = ara_metrics(d->ylt, 1, n, j.q.p, d->d_res, d->weights, d->met_ws, d->met_bytes, st))) {
+        if (row_used[row_ring] && (rc = hip_step(hipEventSynchronize(row_ev[row_ring]), err))) return rc;
+        MetRow *hr = h_rows[row_ring];
+        int max_nwg = 1;
+        int64_t max_n = 1;
+        bool any_w = false;
+        for (size_t i = 0; i < jobs.size(); ++i) {
+            const DevJob *d = static_cast<const DevJob *>(jobs[i]->exec);
+            hr[i] = d->row;
+            max_nwg = std::max(max_nwg, static_cast<int>(d->row.nwg));
+            max_n = std::max(max_n, d->row.n);
+            any_w = any_w || d->row.w != nullptr;
+        }
+        if ((rc = hip_step(hipMemcpyAsync(d_rows[row_ring], hr, jobs.size() * sizeof(MetRow), hipMemcpyHostToDevice, st),
+                           err)))
+            return rc;
+        if ((rc = metrics_rows(d_rows[row_ring], static_cast<int>(jobs.size()), max_nwg, max_n, any_w, st))) {
             *err = "metrics failed";
             return rc;
         }
-        if (j.q.want_grad) {
-            ara_layers L = one_layer(d->h_off, j.elt_ids.data());
-            double *ge = d->d_res + 3 + 12;
-            double *gl = d->d_res + 3;
-            if ((rc = ara_ylt_backward(&tables, &yet, &L, elt_terms, d->d_lterm, j.q.trial_begin, j.q.trial_end,
-                                       d->s_pre, 3, d->weights, ge, gl, d->bwd_ws, d->bwd_bytes, st))) {
-                *err = "backward failed";
-                return rc;
+        if ((rc = hip_step(hipEventRecord(row_ev[row_ring], st), err))) return rc;
+        row_used[row_ring] = true;
+        row_ring = (row_ring + 1) % kRing;
+        for (SchedJob *jp : jobs) {
+            SchedJob &j = *jp;
+            DevJob *d = static_cast<DevJob *>(j.exec);
+            if (j.q.want_grad) {
+                ara_layers L = one_layer(d->h_off, j.elt_ids.data());
+                double *ge = d->d_res + 3 + 12;
+                double *gl = d->d_res + 3;
+                if ((rc = ara_ylt_backward(&tables, &yet, &L, elt_terms, d->d_lterm, j.q.trial_begin, j.q.trial_end,
+                                           d->s_pre, 3, d->weights, ge, gl, d->bwd_ws, d->bwd_bytes, st))) {
+                    *err = "backward failed";
+                    return rc;
+                }
             }
+            const size_t slot = static_cast<size_t>(j.slot);
+            if ((rc = hip_step(
+                     hipMemcpyAsync(h_stage + slot * stage_bytes, d->d_err, stage_bytes, hipMemcpyDeviceToHost, st),
+                     err)))
+                return rc;
+            if ((rc = hip_step(hipEventRecord(d->done_ev, st), err))) return rc;
         }
-        const size_t slot = static_cast<size_t>(j.slot);
-        if ((rc = hip_step(hipMemcpyAsync(h_stage + slot * stage_bytes, d->d_err, stage_bytes, hipMemcpyDeviceToHost, st),
-                           err)))
-            return rc;
-        return hip_step(hipEventRecord(d->done_ev, st), err);
+        return ARA_OK;
     }
 
     bool done(SchedJob &j) override {
@@ -255,6 +299,8 @@ class HipExecutor final : public SchedExecutor {
     void settle() override {
         const int last = (ring + kRing - 1) % kRing;
         if (item_used[last]) hipEventSynchronize(item_ev[last]);
+        const int last_rows = (row_ring + kRing - 1) % kRing;
+        if (row_used[last_rows]) hipEventSynchronize(row_ev[last_rows]);
     }
 
    private:
@@ -270,12 +316,18 @@ struct Server {
     std::unique_ptr<Scheduler> sched;
 };
 
-static size_t ring_bytes() { return align256(HipExecutor::kRing * HipExecutor::kMaxItems * sizeof(FwdItem)); }
+// The head of the arena: the two item lists, then the two row lists.
+static size_t items_bytes() { return align256(HipExecutor::kRing * HipExecutor::kMaxItems * sizeof(FwdItem)); }
+static size_t ring_bytes() {
+    return items_bytes() + align256(HipExecutor::kRing * HipExecutor::kMaxRows * sizeof(MetRow));
+}
 
 static void free_host(Server *S) {
     for (int r = 0; r < HipExecutor::kRing; ++r) {
         if (S->ex.item_ev[r]) hipEventDestroy(S->ex.item_ev[r]);
         if (S->ex.h_items[r]) hipHostFree(S->ex.h_items[r]);
+        if (S->ex.row_ev[r]) hipEventDestroy(S->ex.row_ev[r]);
+        if (S->ex.h_rows[r]) hipHostFree(S->ex.h_rows[r]);
     }
     if (S->ex.h_stage) hipHostFree(S->ex.h_stage);
     if (S->ex.st) hipStreamDestroy(S->ex.st);
@@ -311,6 +363,9 @@ extern "C" int32_t ara_server_create(const ara_tables *tables, const ara_yet *ye
     X.stage_bytes = HipExecutor::kResOff + X.res_doubles * sizeof(double);
     for (int r = 0; r < HipExecutor::kRing; ++r)
         X.d_items[r] = reinterpret_cast<FwdItem *>(static_cast<char *>(arena) + r * HipExecutor::kMaxItems * sizeof(FwdItem));
+    for (int r = 0; r < HipExecutor::kRing; ++r)
+        X.d_rows[r] = reinterpret_cast<MetRow *>(static_cast<char *>(arena) + items_bytes() +
+                                                 r * HipExecutor::kMaxRows * sizeof(MetRow));
     X.arena_base = static_cast<char *>(arena) + ring_bytes();
     hipError_t e = hipStreamCreateWithFlags(&X.st, hipStreamNonBlocking);
     if (e == hipSuccess)
@@ -319,6 +374,10 @@ extern "C" int32_t ara_server_create(const ara_tables *tables, const ara_yet *ye
         e = hipHostMalloc(reinterpret_cast<void **>(&X.h_items[r]), HipExecutor::kMaxItems * sizeof(FwdItem),
                           hipHostMallocDefault);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&X.item_ev[r], hipEventDisableTiming);
+        if (e == hipSuccess)
+            e = hipHostMalloc(reinterpret_cast<void **>(&X.h_rows[r]), HipExecutor::kMaxRows * sizeof(MetRow),
+                              hipHostMallocDefault);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&X.row_ev[r], hipEventDisableTiming);
     }
     if (e != hipSuccess) {
         free_host(S);
