@@ -449,9 +449,10 @@ int32_t ara_server_poll(void *server, int64_t ticket, ara_quote_result *out);
 int32_t ara_server_wait(void *server, int64_t ticket, ara_quote_result *out);
 /* Cancels a quote still in the queue (ARA_E_BUSY once it is on the device). */
 int32_t ara_server_cancel(void *server, int64_t ticket);
-/* stats[8] = iterations, packed forward launches, most quotes in one launch,
+/* stats[9] = iterations, packed forward launches, most quotes in one launch,
  * queued, active, free arena bytes, work items launched, items on a block
- * that other items of the same launch share. */
+ * that other items of the same launch share, most quotes finished after one
+ * launch (their metrics share one set of launches). */
 int32_t ara_server_stats(void *server, int64_t *stats);
 /* Stops admitting, drains the active quotes, frees host resources. */
 int32_t ara_server_destroy(void *server);

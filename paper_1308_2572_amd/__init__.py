@@ -518,10 +518,10 @@ class QuoteServer:
         return True
 
     def stats(self):
-        st = (_c_i64 * 8)()
+        st = (_c_i64 * 9)()
         _check(library().ara_server_stats(self.handle, st), "ara_server_stats")
         keys = ["iterations", "packed_launches", "max_quotes_per_launch", "queued", "active", "free_arena_bytes",
-                "items", "shared_block_items"]
+                "items", "shared_block_items", "max_finished_per_launch"]
         return dict(zip(keys, list(st)))
 
     def close(self):

@@ -161,6 +161,7 @@ void Scheduler::stats(int64_t *s) {
     s[5] = static_cast<int64_t>(arena_.free_bytes());
     s[6] = items_;
     s[7] = shared_items_;
+    s[8] = max_finished_;
 }
 
 void Scheduler::stop() {
@@ -289,6 +290,7 @@ void Scheduler::loop() {
             for (auto &kv : per_block)
                 if (kv.second > 1) n_shared += kv.second;
             if (!rc && !completed.empty()) rc = ex_->finish_all(completed, &err);
+            const int64_t n_finished = static_cast<int64_t>(completed.size());
             {
                 std::lock_guard<std::mutex> lk(mu_);
                 for (SchedJob *j : completed) j->stage = kFinishing;
@@ -298,6 +300,7 @@ void Scheduler::loop() {
             items_ += n_items;
             shared_items_ += n_shared;
             max_quotes_ = std::max(max_quotes_, n_quotes);
+            max_finished_ = std::max(max_finished_, n_finished);
         }
         bool waiting = false, launchable = false;
         {

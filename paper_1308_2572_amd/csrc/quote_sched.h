@@ -135,8 +135,9 @@ class Scheduler {
     int32_t wait(int64_t ticket, std::shared_ptr<SchedJob> *out, std::string *err);
     int32_t cancel(int64_t ticket, std::string *err);
     // iterations, launches, most quotes in one launch, queued, active, free
-    // arena bytes, items launched, items of shared blocks
-    void stats(int64_t *s8);
+    // arena bytes, items launched, items of shared blocks, most quotes
+    // finished after one launch
+    void stats(int64_t *s9);
     // stops admitting, cancels what is queued, drains the active quotes and
     // joins the scheduler thread; idempotent
     void stop();
@@ -162,7 +163,7 @@ class Scheduler {
     std::thread th_;
     int scan_pos_ = 0;   // scheduler thread only
     // statistics (under mu_)
-    int64_t iterations_ = 0, launches_ = 0, max_quotes_ = 0, items_ = 0, shared_items_ = 0;
+    int64_t iterations_ = 0, launches_ = 0, max_quotes_ = 0, items_ = 0, shared_items_ = 0, max_finished_ = 0;
 };
 
 }  // namespace ara

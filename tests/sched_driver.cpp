@@ -371,7 +371,7 @@ static void alone_vs_mix(const World &w) {
             CHECK(s.wait(tk[i], &j, &err) == ARA_OK);
             std::copy(j->res.begin(), j->res.begin() + 3, mix[i].begin());
         }
-        int64_t st[8];
+        int64_t st[9];
         s.stats(st);
         CHECK(st[2] >= 2);           // several quotes shared a launch
         CHECK(st[7] > 0);            // and some blocks
@@ -448,7 +448,7 @@ static void mid_flight_admission(const World &w) {
     ara_quote a = to_abi(quotes[0]);
     CHECK(s.submit(a, &ta, &err) == ARA_OK);
     for (int i = 0; i < 2000; ++i) {   // until the first launch of the long quote is out
-        int64_t st[8];
+        int64_t st[9];
         s.stats(st);
         if (st[1] >= 1) break;
         std::this_thread::sleep_for(std::chrono::microseconds(200));
@@ -489,7 +489,7 @@ static void cancellation(const World &w) {
         CHECK(s.submit(a, &t[i], &err) == ARA_OK);
     }
     for (int i = 0; i < 2000; ++i) {
-        int64_t st[8];
+        int64_t st[9];
         s.stats(st);
         if (st[4] == 1) break;
         std::this_thread::sleep_for(std::chrono::microseconds(100));

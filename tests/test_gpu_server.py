@@ -72,6 +72,34 @@ def test_alone_and_in_mix_equal_direct_calls(env):
         same(a, direct(ara, tables, yet, et, r, 0.99))
 
 
+def test_quotes_finishing_together_equal_direct_calls(env):
+    """Quotes admitted together whose trial ranges all end in the YET's last
+    block finish after the same forward launch, and their metrics then run
+    as rows of one set of launches: rows of different lengths (one block to
+    the whole YET), tail probabilities and ranks, with and without weights.
+    Every quote equals its direct calls bit for bit."""
+    import dataclasses
+    ara, w, tables, yet, et, reqs = env
+    N = w.yet.n_trials
+    starts = [0, 1, N // 3, N // 2 + 7, N - 2_500, N - 100, 3, N - 1, N // 4, 17, N - 40, N // 5]
+    ps = [0.5, 0.9, 0.99, 0.995, 0.999, 0.99, 0.75, 0.99, 0.95, 0.999, 0.5, 0.99]
+    qs = [dataclasses.replace(r, trial_begin=b, trial_end=N, want_grad=(i % 3 == 0))
+          for i, (r, b) in enumerate(zip(reqs, starts))]
+    srv = ara.QuoteServer(tables, yet, et, quotes_with_grad=4, max_slots=16)
+    try:
+        _say("12 quotes ending in the last block, submitted at once")
+        tickets = [srv.submit(r.elt_ids, r.layer_terms, r.trial_begin, r.trial_end, p, r.want_grad)
+                   for r, p in zip(qs, ps)]
+        got = [srv.wait(t) for t in tickets]
+        st = srv.stats()
+    finally:
+        srv.close()
+    _say(f"stats {st}")
+    assert st["max_finished_per_launch"] >= 2, st     # metrics rows really ran together
+    for r, p, g in zip(qs, ps, got):
+        same(g, direct(ara, tables, yet, et, r, p))
+
+
 def test_results_survive_slot_reuse(env):
     """Two result slots, eight quotes, results collected last-first: every
     quote's result must be its own even after later quotes reused its slot."""
