@@ -245,6 +245,35 @@ class FakeExec final : public SchedExecutor {
         });
         return ARA_OK;
     }
+    // the quotes a launch finished, handed over together: each must have had
+    // every one of its blocks launched; their metrics run as one device task
+    int32_t finish_all(const std::vector<SchedJob *> &jobs, std::string *) override {
+        std::vector<FJob *> fs;
+        std::vector<int64_t> tickets;
+        {
+            std::lock_guard<std::mutex> lk(log_mu_);
+            for (SchedJob *j : jobs) {
+                const int b0 = static_cast<int>(j->q.trial_begin / w_.tb);
+                const int b1 = static_cast<int>((j->q.trial_end + w_.tb - 1) / w_.tb);
+                std::set<int> seen;
+                for (auto &l : log_)
+                    for (auto &x : l)
+                        if (x.ticket == j->ticket) seen.insert(x.block);
+                CHECK(static_cast<int>(seen.size()) == b1 - b0 && *seen.begin() == b0 && *seen.rbegin() == b1 - 1);
+                fs.push_back(static_cast<FJob *>(j->exec));
+                tickets.push_back(j->ticket);
+            }
+            batches_.push_back(tickets);
+        }
+        enqueue([fs] {
+            for (FJob *f : fs) {
+                f->res.assign(3, 0.0);
+                CHECK(oracle_metrics(f->ylt.data(), 1, f->q.t1 - f->q.t0, f->q.p, f->res.data()) == 0);
+            }
+            for (FJob *f : fs) f->finished.store(true, std::memory_order_release);
+        });
+        return ARA_OK;
+    }
     bool done(SchedJob &j) override { return static_cast<FJob *>(j.exec)->finished.load(std::memory_order_acquire); }
     int32_t collect(SchedJob &j) override {
         FJob *f = static_cast<FJob *>(j.exec);
@@ -271,6 +300,10 @@ class FakeExec final : public SchedExecutor {
     std::vector<bool> shared_flags() {
         std::lock_guard<std::mutex> lk(log_mu_);
         return shared_flags_;
+    }
+    std::vector<std::vector<int64_t>> batches() {
+        std::lock_guard<std::mutex> lk(log_mu_);
+        return batches_;
     }
 
     std::atomic<int64_t> created{0}, destroyed{0};
@@ -308,6 +341,7 @@ class FakeExec final : public SchedExecutor {
     int in_flight_ = 0;
     std::vector<std::vector<Logged>> log_;
     std::vector<bool> shared_flags_;
+    std::vector<std::vector<int64_t>> batches_;
 };
 
 static SchedConfig config_for(const World &w, size_t arena, int slots) {
@@ -388,6 +422,46 @@ static void alone_vs_mix(const World &w) {
     CHECK(some_shared);
     CHECK(ex.created == ex.destroyed && ex.created == static_cast<int64_t>(2 * quotes.size()));
     std::printf("ok alone == mix == direct for %zu quotes; %zu launches\n", quotes.size(), ex.log().size());
+}
+
+// Quotes queued before the scheduler starts are admitted in its first
+// iteration; when their ranges all end in the last block they finish after
+// the same launch and reach the executor in one batch.
+static void finished_together(const World &w) {
+    auto quotes = make_quotes(w, 16, 9);
+    const int64_t starts[9] = {0, 1, 63, 64, 300, 511, 700, 960, 999};
+    for (size_t i = 0; i < quotes.size(); ++i) {
+        quotes[i].t0 = starts[i];
+        quotes[i].t1 = w.n_trials;
+    }
+    FakeExec ex(w);
+    Scheduler s(&ex, config_for(w, 1 << 30, 16));
+    std::string err;
+    std::vector<int64_t> tk(quotes.size());
+    for (size_t i = 0; i < quotes.size(); ++i) {
+        ara_quote a = to_abi(quotes[i]);
+        CHECK(s.submit(a, &tk[i], &err) == ARA_OK);
+    }
+    s.start();
+    for (size_t i = 0; i < quotes.size(); ++i) {
+        std::shared_ptr<SchedJob> j;
+        CHECK(s.wait(tk[i], &j, &err) == ARA_OK);
+        double d[3];
+        direct_metrics(w, quotes[i], d);
+        CHECK(same_bits(d, j->res.data(), 3));
+    }
+    int64_t st[9];
+    s.stats(st);
+    s.stop();
+    const auto b = ex.batches();
+    size_t total = 0, most = 0;
+    for (auto &x : b) {
+        total += x.size();
+        most = std::max(most, x.size());
+    }
+    CHECK(total == quotes.size());
+    CHECK(most == quotes.size() && st[8] == static_cast<int64_t>(quotes.size()));
+    std::printf("ok %zu quotes ending in the last block finished after one launch, in one batch\n", most);
 }
 
 static void admission_by_memory(const World &w) {
@@ -565,6 +639,7 @@ int main() {
     const World w = make_world(7);
     deal_property();
     alone_vs_mix(w);
+    finished_together(w);
     admission_by_memory(w);
     mid_flight_admission(w);
     cancellation(w);

@@ -96,7 +96,8 @@ def test_scheduler_under_thread_sanitizer(tmp_path):
     of one block dealt to one XCD, completion, cancellation, stop) driven by
     a stand-in executor whose "device" thread computes each item with the
     oracle: results alone == in the mix == the oracle over the whole range,
-    bit for bit; built with -fsanitize=thread, which fails the run on any
+    bit for bit; quotes that a launch finishes reach the executor in one
+    batch, each with every block launched; built with -fsanitize=thread, which fails the run on any
     data race between the scheduler, submitting and device threads."""
     csrc = os.path.join(ROOT, "paper_1308_2572_amd", "csrc")
     obj = str(tmp_path / "oracle.o")
