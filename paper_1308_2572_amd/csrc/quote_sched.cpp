@@ -257,6 +257,7 @@ bool Scheduler::next_launch(std::vector<SchedItem> *slots, bool *shared, std::ve
 }
 
 void Scheduler::loop() {
+    int idle_polls = 0;   // iterations in a row that only waited for finishing quotes
     for (;;) {
         std::vector<std::shared_ptr<SchedJob>> admitted;
         {
@@ -340,10 +341,17 @@ void Scheduler::loop() {
             launchable = launchable || (!queue_.empty() && !free_slots_.empty());
         }
         if (launched && rc == ARA_OK) {
+            idle_polls = 0;
             ex_->settle();
         } else if (waiting && !launchable) {
-            // results pending and nothing to launch: wait briefly instead of spinning
-            std::this_thread::sleep_for(std::chrono::microseconds(20));
+            // results pending and nothing to launch: poll again at once for a
+            // while (a finishing quote's last kernels and copy take tens to
+            // hundreds of microseconds, and a sleep overshoots by about as
+            // much), then back off to short sleeps
+            if (++idle_polls < kSpinPolls) std::this_thread::yield();
+            else std::this_thread::sleep_for(std::chrono::microseconds(20));
+        } else {
+            idle_polls = 0;
         }
     }
 }

@@ -143,6 +143,7 @@ class Scheduler {
     void stop();
 
    private:
+    static constexpr int kSpinPolls = 256;   // polls before the scheduler sleeps between them
     void loop();
     void admit(std::vector<std::shared_ptr<SchedJob>> *admitted);
     bool next_launch(std::vector<SchedItem> *slots, bool *shared, std::vector<SchedJob *> *completed);
