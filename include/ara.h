@@ -67,6 +67,7 @@ extern "C" {
 #define ARA_MAX_CATALOG       (1 << 26)   /* events in the catalogue */
 #define ARA_MAX_ELTS_PER_LAYER 128
 #define ARA_MAX_COTANGENTS     4
+#define ARA_MAX_LAYERS         65535      /* layers per call (each layer is one row of a launch grid) */
 
 const char *ara_status_string(int32_t status);
 const char *ara_last_error(void);

@@ -28,6 +28,7 @@ PREP_TRANSPOSED = 1          # ARA_PREP_TRANSPOSED
 PREP_TRIAL_MAJOR = 2         # ARA_PREP_TRIAL_MAJOR
 PREP_POSITIONS = 4           # ARA_PREP_POSITIONS
 ARA_MAX_COTANGENTS = 4
+ARA_MAX_LAYERS = 65535
 
 _c_i32, _c_i64, _c_u32, _c_f64, _c_p, _c_sz = (ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_double,
                                                ctypes.c_void_p, ctypes.c_size_t)

@@ -594,6 +594,7 @@ extern "C" int32_t ara_metrics_workspace_bytes(int32_t n_layers, int64_t n, size
 extern "C" int32_t ara_metrics(const double *ylt, int32_t n_layers, int64_t n, double p, double *out, double *weights,
                                void *ws, size_t ws_bytes, void *stream) {
     if (n_layers < 0 || n <= 0) return fail(ARA_E_INVAL, "ara_metrics: need n > 0 trials");
+    if (n_layers > ARA_MAX_LAYERS) return fail(ARA_E_LIMIT, "ara_metrics: more than ARA_MAX_LAYERS rows");
     if (!(p > 0.0 && p < 1.0)) return fail(ARA_E_INVAL, "ara_metrics: p must lie in (0, 1)");
     if (!ws || (n_layers > 0 && (!ylt || !out))) return fail(ARA_E_INVAL, "ara_metrics: null pointer");
     if (ws_bytes < met_bytes(n_layers, n)) return fail(ARA_E_NOSPACE, "ara_metrics: workspace too small");
@@ -665,6 +666,7 @@ int32_t metrics_rows(const MetRow *d_rows, int n_rows, int max_nwg, int64_t max_
 extern "C" int32_t ara_metrics_vjp(const double *weights, int32_t n_layers, int64_t n, const double *grad_out,
                                    double *grad_ylt, void *stream) {
     if (n_layers < 0 || n < 0) return fail(ARA_E_INVAL, "ara_metrics_vjp: bad size");
+    if (n_layers > ARA_MAX_LAYERS) return fail(ARA_E_LIMIT, "ara_metrics_vjp: more than ARA_MAX_LAYERS rows");
     if (n_layers == 0 || n == 0) return ARA_OK;
     if (!weights || !grad_out || !grad_ylt) return fail(ARA_E_INVAL, "ara_metrics_vjp: null pointer");
     hipStream_t st = static_cast<hipStream_t>(stream);

@@ -195,6 +195,7 @@ __global__ __launch_bounds__(1024) void k_occ_rank(const OccTables *__restrict__
 int32_t check_layers(const ara_layers *layers, int32_t n_elts) {
     if (!layers) return fail(ARA_E_INVAL, "null layers");
     if (layers->n_layers < 0) return fail(ARA_E_INVAL, "negative layer count");
+    if (layers->n_layers > ARA_MAX_LAYERS) return fail(ARA_E_LIMIT, "more than ARA_MAX_LAYERS layers in one call");
     if (layers->n_layers == 0) return ARA_OK;
     if (!layers->elt_off || !layers->elt_ids) return fail(ARA_E_INVAL, "null layer arrays");
     if (layers->elt_off[0] != 0) return fail(ARA_E_RANGE, "elt_off[0] must be 0");

@@ -102,6 +102,14 @@ def test_argument_validation_before_device_work(ara):
     lay = ara.Layers([0, 130], np.zeros(130, np.int32))
     assert lib.ara_ylt_workspace_bytes(ctypes.byref(tables), ctypes.byref(yet), ctypes.byref(lay.handle), 0,
                                        ctypes.byref(nb)) == 6
+    # more layers than one launch grid holds rows for
+    L = ara.ARA_MAX_LAYERS + 1
+    lay = ara.Layers(np.arange(L + 1, dtype=np.int32), np.zeros(L, np.int32))
+    assert lib.ara_ylt_workspace_bytes(ctypes.byref(tables), ctypes.byref(yet), ctypes.byref(lay.handle), 0,
+                                       ctypes.byref(nb)) == 6
+    assert b"ARA_MAX_LAYERS" in lib.ara_last_error()
+    assert lib.ara_metrics(None, L, 10, 0.99, None, None, None, 0, None) == 6
+    assert lib.ara_metrics_vjp(None, L, 10, None, None, None) == 6
     # mismatched catalogues
     yet2 = ara.ara_yet(n_trials=10, catalog=101, range_bits=15, groups=16)
     lay = ara.Layers([0, 1], [0])
