@@ -226,10 +226,11 @@ bool Scheduler::next_launch(std::vector<SchedItem> *slots, bool *shared, std::ve
     W = std::min(W, nb);
     std::vector<SchedItem> items;
     std::vector<int> order;
-    for (;;) {
+    // the items of the window's first w blocks, dealt to the XCDs
+    auto window = [&](int w) {
         items.clear();
         std::vector<int> blk;
-        for (int d = 0; d < W; ++d) {
+        for (int d = 0; d < w; ++d) {
             const int b = (p + d) % nb;
             for (SchedJob *j : fw)
                 if (wanted(j, b)) {
@@ -238,8 +239,22 @@ bool Scheduler::next_launch(std::vector<SchedItem> *slots, bool *shared, std::ve
                 }
         }
         order = deal_to_xcds(blk, cfg_.n_xcd);
-        if (static_cast<int>(order.size()) <= cfg_.max_items || W == 1) break;
-        W = std::max(1, W / 2);
+        return static_cast<int>(order.size()) / std::max(cfg_.n_xcd, 1);   // workgroups per XCD
+    };
+    int depth = window(W);
+    while (static_cast<int>(order.size()) > cfg_.max_items && W > 1) depth = window(W = std::max(1, W / 2));
+    const int S = cfg_.xcd_slots;
+    if (S > 0 && depth > S && depth % S != 0 && depth % S <= S / 2) {
+        // the largest window whose XCDs run whole rounds (the depth grows with w)
+        const int full = depth / S * S;
+        int lo = 0, hi = W;   // window(lo) fits (or lo = 0), window(hi) does not
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) / 2;
+            if (window(mid) <= full) lo = mid;
+            else hi = mid;
+        }
+        if (lo >= 1) W = lo;
+        depth = window(W);
     }
     slots->clear();
     *shared = false;

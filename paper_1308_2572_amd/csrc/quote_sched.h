@@ -120,6 +120,10 @@ struct SchedConfig {
     int items_per_launch = 2048;   // the scan window is about this many items over the active quotes
     int min_window = 64;           // blocks
     int n_xcd = 8;
+    // forward workgroups that run at once on one XCD (0: unknown).  A launch
+    // whose last round of workgroups would be at most half full is cut back
+    // by whole blocks to full rounds; the blocks cut go to the next launch.
+    int xcd_slots = 0;
 };
 
 class Scheduler {

@@ -393,6 +393,7 @@ extern "C" int32_t ara_server_create(const ara_tables *tables, const ara_yet *ye
     cfg.max_slots = max_slots;
     cfg.max_items = HipExecutor::kMaxItems;
     cfg.n_xcd = kXcds;
+    cfg.xcd_slots = 2 * device_cu_count() / kXcds;   // two forward workgroups per CU
     S->sched.reset(new Scheduler(&S->ex, cfg));
     S->sched->start();
     *server = S;

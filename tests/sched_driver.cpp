@@ -464,6 +464,44 @@ static void finished_together(const World &w) {
     std::printf("ok %zu quotes ending in the last block finished after one launch, in one batch\n", most);
 }
 
+// With the XCD's concurrent workgroups known, no launch ends in a round of
+// workgroups that is at most half full, unless the window could not be cut
+// back to whole rounds; the results do not change.
+static void whole_rounds(const World &w) {
+    auto quotes = make_quotes(w, 17, 12);
+    FakeExec ex(w);
+    SchedConfig cfg = config_for(w, 1 << 30, 16);
+    cfg.xcd_slots = 3;
+    cfg.items_per_launch = 60;
+    cfg.min_window = 1;
+    Scheduler s(&ex, cfg);
+    std::string err;
+    std::vector<int64_t> tk(quotes.size());
+    for (size_t i = 0; i < quotes.size(); ++i) {
+        ara_quote a = to_abi(quotes[i]);
+        CHECK(s.submit(a, &tk[i], &err) == ARA_OK);
+    }
+    s.start();
+    for (size_t i = 0; i < quotes.size(); ++i) {
+        std::shared_ptr<SchedJob> j;
+        CHECK(s.wait(tk[i], &j, &err) == ARA_OK);
+        double d[3];
+        direct_metrics(w, quotes[i], d);
+        CHECK(same_bits(d, j->res.data(), 3));
+    }
+    s.stop();
+    int cut = 0, ragged = 0;
+    for (auto &l : ex.log()) {
+        check_grouping(l, 8);
+        const int depth = static_cast<int>(l.size()) / 8;
+        if (depth > 3 && depth % 3 != 0 && depth % 3 <= 1) ++ragged;
+        if (depth > 3 && depth % 3 == 0) ++cut;
+    }
+    CHECK(ragged == 0 && cut > 0);
+    std::printf("ok launches in whole rounds of workgroups: %d of %zu launches at a multiple of the XCD's slots\n", cut,
+                ex.log().size());
+}
+
 static void admission_by_memory(const World &w) {
     auto quotes = make_quotes(w, 12, 10);
     for (auto &q : quotes) {   // the same size, so the arena holds exactly two
@@ -640,6 +678,7 @@ int main() {
     deal_property();
     alone_vs_mix(w);
     finished_together(w);
+    whole_rounds(w);
     admission_by_memory(w);
     mid_flight_admission(w);
     cancellation(w);
