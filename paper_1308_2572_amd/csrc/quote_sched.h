@@ -116,8 +116,8 @@ struct SchedConfig {
     int32_t n_elts = 0;
     size_t arena_bytes = 0;
     int max_slots = 1;
-    int max_items = 4096;          // slots of one launch
-    int items_per_launch = 2048;   // the scan window is about this many items over the active quotes
+    int max_items = 8192;          // slots of one launch
+    int items_per_launch = 6144;   // the scan window is about this many items over the active quotes
     int min_window = 64;           // blocks
     int n_xcd = 8;
     // forward workgroups that run at once on one XCD (0: unknown).  A launch

@@ -49,7 +49,7 @@ struct DevJob {
 class HipExecutor final : public SchedExecutor {
    public:
     static constexpr int kRing = 2;        // forward launches whose item lists may be in flight
-    static constexpr int kMaxItems = 4096;
+    static constexpr int kMaxItems = 8192;
     static constexpr int kMaxRows = 256;   // quotes finishing together: at most one per slot
 
     ara_tables tables{};
