@@ -115,6 +115,9 @@ def main(argv=None) -> int:
     ap.add_argument("--rate", type=float, default=1e9, help="Poisson arrivals per second (1e9: all at once)")
     ap.add_argument("--seed", type=int, default=synth.SEED_BASE + 40)
     ap.add_argument("--plain-sample", type=int, default=1, help="quotes also timed through the batch entry points")
+    ap.add_argument("--quotes-with-grad", type=int, default=16,
+                    help="the server's arena is sized for this many gradient quotes at once")
+    ap.add_argument("--max-slots", type=int, default=64, help="quotes active at once (1..256)")
     args = ap.parse_args(argv)
     w = synth.config(4)
     tables = EltTables.from_numpy(w.elts)
@@ -122,7 +125,8 @@ def main(argv=None) -> int:
     et = torch.tensor(w.elts.terms, dtype=torch.float64, device="cuda")
     reqs = synth.serving_requests(args.requests, w.yet.n_trials, n_elts=w.elts.n_elts, rate_per_s=args.rate,
                                   seed=args.seed)
-    out = run_benchmark(tables, yet, et, reqs, p=0.99, plain_sample=max(1, args.plain_sample))
+    out = run_benchmark(tables, yet, et, reqs, p=0.99, quotes_with_grad=args.quotes_with_grad, max_slots=args.max_slots,
+                        plain_sample=max(1, args.plain_sample))
     print(json.dumps(out), flush=True)
     return 0
 
