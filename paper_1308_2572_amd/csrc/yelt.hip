@@ -5,7 +5,7 @@
 // of a trial's increments is its year loss; their maximum is the occurrence
 // loss behind occurrence-exceedance metrics.
 //
-// One wavefront per trial, 512 consecutive occurrences per step: the event
+// One wavefront per trial, 1024 consecutive occurrences per step: the event
 // IDs stream from the caller's trial-major YET (storage order is needed
 // here, so the bucketed layout cannot serve).  Each workgroup first loads a
 // 1-Mbit filter of the layer's set events into LDS (the set-event bitmap
@@ -27,7 +27,7 @@
 namespace ara {
 
 constexpr int kYeltThreads = 1024;
-constexpr int kYeltSteps = 8;           // 64-occurrence slices per step
+constexpr int kYeltSteps = 16;          // 64-occurrence slices per step (8 and 20 measured slower)
 constexpr int kYeltGroup = 4;           // slices per transposed scan
 
 struct YeltParams {
