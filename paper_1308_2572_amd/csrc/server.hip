@@ -65,6 +65,13 @@ class HipExecutor final : public SchedExecutor {
     size_t stage_bytes = 0;                // kResOff + res_doubles * 8
     char *h_stage = nullptr;               // pinned host, [max_slots][stage_bytes]
     hipStream_t st = nullptr;
+    // Gradient quotes' backward passes (short chains of small kernels) run on
+    // a few streams of their own after the metrics, so that those of the
+    // quotes finishing together overlap; default priority like st.
+    static constexpr int kFinStreams = 4;
+    hipStream_t fst[kFinStreams] = {nullptr, nullptr, nullptr, nullptr};
+    hipEvent_t met_ev = nullptr;           // the metrics of the latest finishing set are done
+    int fin_next = 0;
     FwdItem *d_items[kRing] = {nullptr, nullptr};
     FwdItem *h_items[kRing] = {nullptr, nullptr};
     hipEvent_t item_ev[kRing] = {nullptr, nullptr};
@@ -238,25 +245,31 @@ class HipExecutor final : public SchedExecutor {
         if ((rc = hip_step(hipEventRecord(row_ev[row_ring], st), err))) return rc;
         row_used[row_ring] = true;
         row_ring = (row_ring + 1) % kRing;
+        if ((rc = hip_step(hipEventRecord(met_ev, st), err))) return rc;
         for (SchedJob *jp : jobs) {
             SchedJob &j = *jp;
             DevJob *d = static_cast<DevJob *>(j.exec);
+            hipStream_t s = st;   // a quote without gradients only copies its results back
             if (j.q.want_grad) {
+                // after the metrics (its weights), on the next backward stream
+                s = fst[fin_next];
+                fin_next = (fin_next + 1) % kFinStreams;
+                if ((rc = hip_step(hipStreamWaitEvent(s, met_ev, 0), err))) return rc;
                 ara_layers L = one_layer(d->h_off, j.elt_ids.data());
                 double *ge = d->d_res + 3 + 12;
                 double *gl = d->d_res + 3;
                 if ((rc = ara_ylt_backward(&tables, &yet, &L, elt_terms, d->d_lterm, j.q.trial_begin, j.q.trial_end,
-                                           d->s_pre, 3, d->weights, ge, gl, d->bwd_ws, d->bwd_bytes, st))) {
+                                           d->s_pre, 3, d->weights, ge, gl, d->bwd_ws, d->bwd_bytes, s))) {
                     *err = "backward failed";
                     return rc;
                 }
             }
             const size_t slot = static_cast<size_t>(j.slot);
             if ((rc = hip_step(
-                     hipMemcpyAsync(h_stage + slot * stage_bytes, d->d_err, stage_bytes, hipMemcpyDeviceToHost, st),
+                     hipMemcpyAsync(h_stage + slot * stage_bytes, d->d_err, stage_bytes, hipMemcpyDeviceToHost, s),
                      err)))
                 return rc;
-            if ((rc = hip_step(hipEventRecord(d->done_ev, st), err))) return rc;
+            if ((rc = hip_step(hipEventRecord(d->done_ev, s), err))) return rc;
         }
         return ARA_OK;
     }
@@ -330,6 +343,9 @@ static void free_host(Server *S) {
         if (S->ex.h_rows[r]) hipHostFree(S->ex.h_rows[r]);
     }
     if (S->ex.h_stage) hipHostFree(S->ex.h_stage);
+    for (int i = 0; i < HipExecutor::kFinStreams; ++i)
+        if (S->ex.fst[i]) hipStreamDestroy(S->ex.fst[i]);
+    if (S->ex.met_ev) hipEventDestroy(S->ex.met_ev);
     if (S->ex.st) hipStreamDestroy(S->ex.st);
 }
 
@@ -368,6 +384,9 @@ extern "C" int32_t ara_server_create(const ara_tables *tables, const ara_yet *ye
                                                  r * HipExecutor::kMaxRows * sizeof(MetRow));
     X.arena_base = static_cast<char *>(arena) + ring_bytes();
     hipError_t e = hipStreamCreateWithFlags(&X.st, hipStreamNonBlocking);
+    for (int i = 0; e == hipSuccess && i < HipExecutor::kFinStreams; ++i)
+        e = hipStreamCreateWithFlags(&X.fst[i], hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&X.met_ev, hipEventDisableTiming);
     if (e == hipSuccess)
         e = hipHostMalloc(reinterpret_cast<void **>(&X.h_stage), X.stage_bytes * max_slots, hipHostMallocDefault);
     for (int r = 0; e == hipSuccess && r < HipExecutor::kRing; ++r) {
